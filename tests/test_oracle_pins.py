@@ -1,0 +1,398 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+The paper prints no numerical values for rho, chi0 or eps^-1, so every pin is a
+brute-force evaluation of a definition, an identity, a closed form or a special
+case (free electrons), each chosen so that a dropped term, a wrong sign or index,
+a transposed operand or a wrong normalisation fails at least one of them.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from synth import crystal_for
+from synth.crystal import (fcc_lattice, hamiltonian, make_crystal, shell_potential,
+                           kgrid_gamma, ecut_for_npw)
+from synth.configs import FCC4, A_FCC
+from oracle.rho import rho_direct, rho_fft, rho_head_q0
+from oracle.chi0 import chi0_from_rho, pole_weights
+from oracle.epsinv import epsinv_sym, epsinv_nonsym, eps_tilde
+from oracle.pipeline import rho_pair, rho_all_pairs, chi0_crystal
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def c1s():
+    return crystal_for("c1_small")
+
+
+@pytest.fixture(scope="module")
+def c1s_all():
+    # every plane wave is a band: closure relations hold exactly in the finite basis
+    return crystal_for("c1_small", nb_all=True)
+
+
+# --------------------------------------------------------------------------
+# P1: rho from the FFT route equals brute-force evaluations of the definition
+# --------------------------------------------------------------------------
+
+def test_p1_fft_equals_direct_sum_all_pairs(c1s):
+    # includes the umklapp pairs G0 = (-1,-1,0), (-1,0,0), (0,-1,0)
+    assert any(np.any(g0 != 0) for _, _, g0 in c1s.pairs)
+    for ip in range(len(c1s.pairs)):
+        a, _ = rho_pair(c1s, ip, "fft")
+        b, _ = rho_pair(c1s, ip, "direct")
+        assert np.abs(a - b).max() < TOL
+
+
+def _psi_on_grid(cr, ik, bands, kc, pts):
+    """psi_nk(r) = sum_G c(G) exp(i (k+G).r) at Cartesian points, explicit exponentials."""
+    kg = kc[None, :] + cr.mill[ik].astype(float) @ cr.lat.bvec
+    ph = np.exp(1j * pts @ kg.T)                       # (npts, npw)
+    return ph @ cr.coef[ik][bands].T                    # (npts, nb)
+
+
+def test_p1_realspace_bruteforce_of_definition(c1s):
+    """<c k| exp(i(q+G).r) |v k-q> as a literal cell average of full Bloch functions.
+
+    Uses Cartesian k, k - q and q directly (no FFT, no Miller index arithmetic, no
+    G0 bookkeeping): the integrand is lattice periodic and band limited below the
+    grid's Nyquist reach, so the grid average is the exact cell integral.
+    """
+    cr = c1s
+    n = cr.grid
+    j = np.stack(np.meshgrid(*[np.arange(x) for x in n], indexing="ij"), -1).reshape(-1, 3)
+    pts = (j / np.array(n)) @ cr.lat.avec
+    q = cr.qcart()
+    for ip in (0, 1):  # both are umklapp pairs
+        ik, ikp, g0 = cr.pairs[ip]
+        kc = cr.kcart(ik)
+        kmq = kc - q                                     # the literal k - q
+        # psi_{v,k-q} is the stored state at k' (same Bloch function): evaluate it
+        # with its own k' phases, then compare to exp(i(k-q).r) times a periodic part
+        psi_v = _psi_on_grid(cr, ikp, slice(0, 3), cr.kcart(ikp), pts)
+        psi_c = _psi_on_grid(cr, ik, slice(cr.nocc, cr.nocc + 3), kc, pts)
+        r_ref, _ = rho_pair(cr, ip, "fft")
+        nc = cr.coef[ik].shape[0] - cr.nocc
+        r_ref = r_ref.reshape(cr.nocc, nc, -1)
+        for ig in (0, 1, 7, 30, 58):
+            G = cr.gmill[ig].astype(float) @ cr.lat.bvec
+            X = np.exp(1j * pts @ (q + G))
+            val = (np.conj(psi_c).T * X[None, :]) @ psi_v / pts.shape[0]   # [c, v]
+            assert np.abs(val.T - r_ref[:3, :3, ig]).max() < 1e-12
+        # and the k - q label really is k' + G0
+        assert np.allclose(kmq, cr.kcart(ikp) + g0 @ cr.lat.bvec)
+
+
+def test_p1_umklapp_equals_unfolded_basis():
+    """Orbitals diagonalised directly at k - q (no G0 shift) give the same chi0.
+
+    chi0 is gauge invariant, so the independent diagonalisation's phases and
+    degenerate-subspace rotations do not matter.
+    """
+    lat = fcc_lattice(A_FCC)
+    pot = shell_potential(lat, 11)
+    q = np.array([.5, .5, 0.])
+    ecut = ecut_for_npw(lat, 200)
+    cr = make_crystal(lat, pot, FCC4, q, (16,) * 3, ecut, 8, 20, 27, 2, 11, scissor_min=None)
+    M, dE = rho_all_pairs(cr, "fft")
+    ref = chi0_from_rho(M, dE, cr.omegas, cr.pref)
+    # unfolded: for each k build the k - q orbitals on their own sphere, G0 = 0
+    Ms, dEs = [], []
+    for ik in range(cr.nk):
+        kmq = cr.kf[ik] - q
+        cru = make_crystal(lat, pot, np.stack([cr.kf[ik], kmq]), np.zeros(3), (16,) * 3,
+                           ecut, 8, 20, 27, 2, 99, scissor_min=None, check_alias=False)
+        r = rho_direct(cru.coef[0][8:], cru.mill[0], cru.coef[1][:8], cru.mill[1],
+                       cru.gmill, np.zeros(3, np.int32))
+        Ms.append(r.reshape(-1, r.shape[-1]))
+        dEs.append((cru.eps[0][8:][None, :] - cru.eps[1][:8][:, None]).reshape(-1))
+    alt = chi0_from_rho(np.concatenate(Ms), np.concatenate(dEs), cr.omegas, cr.pref)
+    assert np.abs(alt - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------
+# P2: rho_nm(q = 0, G = 0) = delta_nm (orthonormality, unit-cell normalisation)
+# --------------------------------------------------------------------------
+
+def test_p2_rho_q0_g0_is_identity():
+    lat = fcc_lattice(A_FCC)
+    cr = make_crystal(lat, shell_potential(lat, 3), FCC4, np.zeros(3), (16,) * 3,
+                      ecut_for_npw(lat, 200), 6, 14, 27, 2, 3, scissor_min=None)
+    for ik in range(cr.nk):
+        c = cr.coef[ik]
+        r = rho_fft(c, cr.mill[ik], c, cr.mill[ik], cr.gmill, np.zeros(3, np.int64), cr.grid)
+        assert np.all(cr.gmill[0] == 0)
+        assert np.abs(r[:, :, 0] - np.eye(c.shape[0])).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P3: band-phase gauge
+# --------------------------------------------------------------------------
+
+def test_p3_gauge(c1s):
+    ip = 0
+    ik, ikp, g0 = c1s.pairs[ip]
+    g = np.random.default_rng(5)
+    cc = c1s.coef[ik][c1s.nocc:]
+    cv = c1s.coef[ikp][:c1s.nocc]
+    pc = np.exp(1j * g.uniform(0, 6.3, cc.shape[0]))
+    pv = np.exp(1j * g.uniform(0, 6.3, cv.shape[0]))
+    a = rho_fft(cc, c1s.mill[ik], cv, c1s.mill[ikp], c1s.gmill, g0, c1s.grid)
+    b = rho_fft(cc * pc[:, None], c1s.mill[ik], cv * pv[:, None], c1s.mill[ikp], c1s.gmill, g0, c1s.grid)
+    expect = a * (pv[:, None, None] * np.conj(pc)[None, :, None])
+    assert np.abs(b - expect).max() < TOL
+    dE = np.ones(a.shape[0] * a.shape[1])
+    ca = chi0_from_rho(a.reshape(-1, a.shape[-1]), dE, [0.3], 1.0)
+    cb = chi0_from_rho(b.reshape(-1, b.shape[-1]), dE, [0.3], 1.0)
+    assert np.abs(ca - cb).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P4: chi0(i w) Hermitian and negative semidefinite
+# --------------------------------------------------------------------------
+
+def test_p4_hermitian_nsd(c1s):
+    chi = chi0_crystal(c1s)
+    for j in range(chi.shape[0]):
+        assert np.abs(chi[j] - chi[j].conj().T).max() < 1e-15
+        ev = np.linalg.eigvalsh(chi[j])
+        assert ev.max() < 1e-13 * abs(ev.min())
+        assert np.all(np.diag(chi[j]).real < 0)
+    # magnitude falls with frequency at every diagonal entry
+    assert np.all(np.abs(np.diag(chi[1])) < np.abs(np.diag(chi[0])))
+
+
+def test_weights_and_sign_closed_form():
+    # one transition, one G: chi0 = -pref * 2 D / (w^2 + D^2) |rho|^2
+    M = np.array([[0.3 + 0.4j]])
+    for w in (0.0, 0.5, 2.0):
+        c = chi0_from_rho(M, np.array([0.7]), [w], 2.0)
+        assert abs(c[0, 0, 0] - (-2.0 * 2 * 0.7 / (w * w + 0.49) * 0.25)) < 1e-15
+    assert np.allclose(pole_weights(np.array([1.0]), 0.0), 2.0)
+
+
+# --------------------------------------------------------------------------
+# P5: f-sum rule
+# --------------------------------------------------------------------------
+
+def _fsum_terms(cr, ip, igs):
+    """sum_n (e_n - e_v) |rho_nv(G)|^2 over every band n at k, for each occupied v."""
+    ik, ikp, g0 = cr.pairs[ip]
+    nocc = cr.nocc_at(ikp)
+    r, dE = rho_pair(cr, ip, "fft", band_lo=0)
+    nall = cr.coef[ik].shape[0]
+    r = r.reshape(nocc, nall, -1)
+    return np.einsum("vc,vcg->vg", dE.reshape(nocc, nall), np.abs(r[:, :, igs]) ** 2)
+
+
+def test_p5_fsum_closure_exact(c1s_all):
+    """Finite-basis closure: sum_n (e_n - e_v)|<n|X|v>|^2 = <Xv|P(H_k - e_v)P|Xv>."""
+    cr = c1s_all
+    nocc = cr.nocc
+    igs = [0, 3, 10, 40]
+    for ip, (ik, ikp, g0) in enumerate(cr.pairs):
+        lhs = _fsum_terms(cr, ip, igs)
+        H = hamiltonian(cr.lat, cr.kf[ik], cr.mill[ik], _pot(cr))
+        look = {tuple(m): i for i, m in enumerate(cr.mill[ik])}
+        for j, ig in enumerate(igs):
+            # X|v> on the k sphere: coefficient at G1 is c_v(G1 - G + G0)
+            Xv = np.zeros((nocc, cr.mill[ik].shape[0]), complex)
+            for i2, m2 in enumerate(cr.mill[ikp]):
+                t = tuple(int(x) for x in (m2 + cr.gmill[ig] - g0))
+                if t in look:
+                    Xv[:, look[t]] = cr.coef[ikp][:nocc, i2]
+            ev = cr.eps[ikp][:nocc]
+            closure = (np.einsum("vi,ij,vj->v", Xv.conj(), H, Xv).real
+                       - ev * np.einsum("vi,vi->v", Xv.conj(), Xv).real)
+            assert np.abs(lhs[:, j] - closure).max() < 1e-10
+
+
+def test_p5_fsum_physical_free_electrons():
+    """V = 0: sum_n (e_n - e_v)|rho|^2 = |q+G|^2/2 + (q+G).(k'+G_v) exactly; the k-set sum
+    over a set closed under k -> -k gives N_k N_v |q+G|^2 / 2."""
+    lat = fcc_lattice(A_FCC)
+    q = np.array([.5, .5, 0.])
+    cr = make_crystal(lat, shell_potential(lat, 0, zero=True), FCC4, q, (16,) * 3,
+                      ecut_for_npw(lat, 230), 9, None, 27, 2, 21, scissor_min=None,
+                      nocc_k=[9, 6, 6, 6])
+    igs = list(range(15))
+    qc = cr.qcart()
+    total = np.zeros(len(igs))
+    nv_tot = 0
+    for ip, (ik, ikp, g0) in enumerate(cr.pairs):
+        lhs = _fsum_terms(cr, ip, igs)
+        nv = cr.nocc_at(ikp)
+        kgv = cr.kcart(ikp)[None, :] + cr.mill[ikp] @ lat.bvec
+        pv = np.einsum("vi,ix->vx", np.abs(cr.coef[ikp][:nv]) ** 2, kgv)
+        for j, ig in enumerate(igs):
+            qg = qc + cr.gmill[ig] @ lat.bvec
+            assert np.abs(lhs[:, j] - (0.5 * qg @ qg + pv @ qg)).max() < 1e-12
+        total += lhs.sum(0)
+        nv_tot += nv
+    qg = qc[None, :] + cr.gmill[igs] @ lat.bvec
+    assert np.abs(total - nv_tot * 0.5 * np.einsum("gi,gi->g", qg, qg)).max() < 1e-11
+
+
+def test_p5_fsum_physical_model_crystal_truncation():
+    """With the model potential the physical f-sum holds up to basis truncation."""
+    cr = crystal_for("c1_small", nb_all=True, npw=800, grid=24)
+    igs = [0, 3, 10]
+    qc = cr.qcart()
+    total = np.zeros(len(igs))
+    for ip in range(len(cr.pairs)):
+        total += _fsum_terms(cr, ip, igs).sum(0)
+    qg = qc[None, :] + cr.gmill[igs] @ cr.lat.bvec
+    expect = cr.nk * cr.nocc * 0.5 * np.einsum("gi,gi->g", qg, qg)
+    dev = np.abs(total - expect) / expect
+    assert dev.max() < 0.05, dev
+
+
+def _pot(cr):
+    return shell_potential(cr.lat, cr.seed)
+
+
+# --------------------------------------------------------------------------
+# P6: free electrons -> Lindhard closed form, chi0 diagonal in G
+# --------------------------------------------------------------------------
+
+def test_p6_free_electron_lindhard():
+    lat = fcc_lattice(A_FCC)
+    q = np.array([.5, .5, 0.])
+    ecut = ecut_for_npw(lat, 230)
+    pot = shell_potential(lat, 0, zero=True)
+    # E_F between free-electron levels: 9 states below at Gamma, 6 at each X
+    nocc_k = [9, 6, 6, 6]
+    cr = make_crystal(lat, pot, FCC4, q, (16,) * 3, ecut, 9, None, 27, 3, 21,
+                      scissor_min=None, nocc_k=nocc_k)
+    chi = chi0_crystal(cr)
+    # closed form from plane-wave kinematics only
+    u = lat.unit
+    EF = 0.5 * 3.5 * u * u
+    qc = q @ lat.bvec
+    ref = np.zeros((len(cr.omegas), 27))
+    for ik, ikp, g0 in cr.pairs:
+        kp = cr.kcart(ikp)
+        m = cr.mill[ikp]
+        kgv = kp[None, :] + m @ lat.bvec
+        ev = 0.5 * np.einsum("ij,ij->i", kgv, kgv)
+        occ = ev < EF
+        for ig, mg in enumerate(cr.gmill):
+            kgc = kgv + qc + mg @ lat.bvec
+            ec = 0.5 * np.einsum("ij,ij->i", kgc, kgc)
+            ok = occ & (ec > EF) & (ec <= ecut)
+            d = ec[ok] - ev[ok]
+            for j, w in enumerate(cr.omegas):
+                ref[j, ig] += -cr.pref * np.sum(2 * d / (w * w + d * d))
+    for j in range(len(cr.omegas)):
+        off = chi[j] - np.diag(np.diag(chi[j]))
+        assert np.abs(off).max() < 1e-12
+        assert np.abs(np.diag(chi[j]) - ref[j]).max() < 1e-12 * np.abs(ref[j]).max()
+
+
+# --------------------------------------------------------------------------
+# P7, P10: eps~^-1 spectrum, inverse identity, symmetric / non-symmetric relation
+# --------------------------------------------------------------------------
+
+def test_p7_p10_epsinv(c1s):
+    chi = chi0_crystal(c1s)
+    qpg = c1s.qpg()
+    E = epsinv_sym(chi, qpg)
+    et = eps_tilde(chi, qpg)
+    s = np.sqrt(4 * np.pi) / qpg
+    En = epsinv_nonsym(chi, qpg)
+    for j in range(chi.shape[0]):
+        assert np.abs(et[j] @ E[j] - np.eye(len(qpg))).max() < 1e-12
+        ev = np.linalg.eigvalsh(E[j])
+        assert ev.min() > 0 and ev.max() <= 1 + 1e-12
+        assert np.abs(En[j] - s[:, None] * E[j] / s[None, :]).max() < 1e-12
+        assert np.abs(np.diag(En[j]) - np.diag(E[j])).max() < 1e-12
+        # (I - v chi0) En = I with v multiplying from the left
+        v = 4 * np.pi / qpg ** 2
+        assert np.abs((np.eye(len(qpg)) - v[:, None] * chi[j]) @ En[j] - np.eye(len(qpg))).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P8: time reversal chi0_GG'(q) = chi0_{-G',-G}(-q)
+# --------------------------------------------------------------------------
+
+def test_p8_time_reversal():
+    lat = fcc_lattice(A_FCC)
+    pot = shell_potential(lat, 8)
+    kf = kgrid_gamma(3)
+    ecut = ecut_for_npw(lat, 120)
+    q = np.array([1 / 3, 0, 0])
+    nocc, nb = 8, 12
+    # the occupied/empty split and the band cut must not split a degenerate level,
+    # else the included subspace depends on the arbitrary basis eigh picks
+    probe = make_crystal(lat, pot, kf, q, (16,) * 3, ecut, nocc, nb + 1, 27, 2, 8, scissor_min=None)
+    for e in probe.eps:
+        assert e[nocc] - e[nocc - 1] > 1e-6 and e[nb] - e[nb - 1] > 1e-6
+    a = make_crystal(lat, pot, kf, q, (16,) * 3, ecut, nocc, nb, 27, 2, 8, scissor_min=None)
+    b = make_crystal(lat, pot, kf, -q, (16,) * 3, ecut, nocc, nb, 27, 2, 8, scissor_min=None)
+    ca, cb = chi0_crystal(a), chi0_crystal(b)
+    look = {tuple(m): i for i, m in enumerate(a.gmill)}
+    neg = np.array([look[tuple(-m)] for m in a.gmill])   # the G-set is closed under G -> -G
+    for j in range(2):
+        assert np.abs(ca[j] - cb[j][np.ix_(neg, neg)].T).max() < 1e-12 * np.abs(ca[j]).max()
+        # and the relation is not trivially satisfied: chi0 is not symmetric under G -> -G alone
+        assert np.abs(ca[j] - ca[j][np.ix_(neg, neg)]).max() > 1e-6 * np.abs(ca[j]).max()
+
+
+# --------------------------------------------------------------------------
+# P9: q -> 0 head from velocities vs finite small q
+# --------------------------------------------------------------------------
+
+def test_p9_head_velocity_vs_finite_q():
+    lat = fcc_lattice(A_FCC)
+    pot = shell_potential(lat, 4)
+    ecut = ecut_for_npw(lat, 180)
+    k = np.array([[0.1, 0.2, -0.05]])
+    qhat_c = np.array([1.0, 0.0, 0.0])
+    cr0 = make_crystal(lat, pot, k, np.zeros(3), (16,) * 3, ecut, 4, 12, 27, 2, 4, scissor_min=None)
+    cc, ec = cr0.coef[0][4:], cr0.eps[0][4:]
+    cv, ev = cr0.coef[0][:4], cr0.eps[0][:4]
+    rh = rho_head_q0(cc, ec, cv, ev, cr0.mill[0], cr0.kcart(0), lat.bvec, qhat_c)
+    w = pole_weights((ec[None, :] - ev[:, None]).reshape(-1), 0.0)
+    T0 = np.sum(w * np.abs(rh.reshape(-1)) ** 2)
+    errs = []
+    for qe in (2e-3, 1e-3):
+        qf = np.linalg.solve(lat.bvec.T, qe * qhat_c)
+        two = np.stack([k[0], k[0] - qf])
+        cr = make_crystal(lat, pot, two, np.zeros(3), (16,) * 3, ecut, 4, 12, 27, 2, 4,
+                          scissor_min=None, check_alias=False)
+        r = rho_direct(cr.coef[0][4:], cr.mill[0], cr.coef[1][:4], cr.mill[1], cr.gmill,
+                       np.zeros(3, np.int64))[:, :, 0] / qe
+        T = np.sum(w * np.abs(r.reshape(-1)) ** 2)
+        errs.append(abs(T - T0) / T0)
+    assert errs[1] < 1e-3
+    assert errs[1] < 0.6 * errs[0]     # converges at least linearly in q
+
+
+# --------------------------------------------------------------------------
+# P11: Appendix A grouping of degenerate poles is the same sum
+# --------------------------------------------------------------------------
+
+def test_p11_degenerate_pole_grouping(c1s):
+    M, dE = rho_all_pairs(c1s)
+    ref = chi0_from_rho(M, dE, c1s.omegas, c1s.pref)
+    thr = 1e-5
+    order = np.argsort(dE)
+    groups, cur = [], [order[0]]
+    for t in order[1:]:
+        if dE[t] - dE[cur[0]] < thr:
+            cur.append(t)
+        else:
+            groups.append(cur)
+            cur = [t]
+    groups.append(cur)
+    assert len(groups) < len(dE)   # the symmetric crystal has degenerate poles
+    out = np.zeros_like(ref)
+    for gidx in groups:
+        R = c1s.pref * M[gidx].T @ np.conj(M[gidx])        # internal frequency-free sum
+        for j, w in enumerate(c1s.omegas):
+            out[j] += -pole_weights(dE[gidx[0]], w) * R    # one F per group
+    spread = max(dE[g].max() - dE[g].min() for g in groups)
+    bound = spread * 2.0 / min(dE) ** 2 * c1s.pref * np.sum(np.abs(M) ** 2)
+    assert np.abs(out - ref).max() <= bound + 1e-14
