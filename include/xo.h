@@ -1,0 +1,178 @@
+/*
+ * xo -- independent-particle response chi0 and inverse dielectric matrix on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yambo 2019 (arXiv:1902.03837), Linear Response section.
+ *   rho_{cv k}(q,G) = < c k | exp(i(q+G).r) | v k-q >                 Eq. (rhotw)
+ *   chi0_GG'(q, i w) = -pref sum_t [2 D_t/(w^2 + D_t^2)] rho_t(G) rho_t*(G')
+ *                                                   Eq. (X_IP), App. A split
+ *   eps~ = I - s chi0 s,  s_G = sqrt(4 pi)/|q+G|     Eq. (X_rpa_inv), Eq. (W_def)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Array arguments marked [device] are device pointers allocated and owned by
+ *   the caller. The library never frees them and keeps no reference to them
+ *   after the call returns. Arguments marked [host] are host memory, read
+ *   during the call only.
+ * - Every compute call is asynchronous on the given stream (hipStream_t passed
+ *   as void*; NULL means the default stream) unless its comment says it
+ *   synchronises.
+ * - Complex numbers are interleaved (re, im). Precision XO_FP64 uses complex128
+ *   (two doubles); XO_FP32 and XO_BF16X3 use complex64 (two floats) for rho and
+ *   orbital coefficients. chi0 and eps^-1 are always complex128.
+ * - Miller triples are int32 [n][3]; the reciprocal vector is m . (b1,b2,b3).
+ *   The FFT index of m on an N1 x N2 x N3 grid is m mod N.
+ * - Return values: XO_OK or an error code; xo_last_error() then holds a
+ *   thread-local message. No call aborts or exits. Arguments are validated on
+ *   the host before anything is launched; on an argument error nothing is
+ *   enqueued.
+ * - Library workspace is device memory cached per (device, stream) and grown
+ *   on demand; xo_release_workspace() frees it (synchronising the device).
+ *   Calls on distinct streams may run concurrently from distinct threads.
+ */
+#ifndef XO_H
+#define XO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  XO_OK = 0,
+  XO_ERR_ARG = 1,          /* invalid argument (message says which)            */
+  XO_ERR_ALLOC = 2,        /* device allocation failed                         */
+  XO_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed       */
+  XO_ERR_NOTPD = 4,        /* eps~ not positive definite at some frequency     */
+  XO_ERR_UNSUPPORTED = 5   /* size or option outside what the kernels handle   */
+};
+
+enum { XO_FP64 = 0, XO_FP32 = 1, XO_BF16X3 = 2 };
+
+/* Thread-local message describing the last error of this thread ("" if none). */
+const char* xo_last_error(void);
+/* Library version string. */
+const char* xo_version(void);
+/* Free all cached workspace and geometry tables on every device (synchronises). */
+int xo_release_workspace(void);
+
+/* ------------------------------------------------------------------------- */
+/* Oscillator strengths, Eq. (rhotw): the Fourier transform of the real-space
+ * product conj(psi_c,k(r)) psi_v,k-q(r), evaluated for one k-pair and all
+ * (v, c) of the given band sets.
+ *
+ * The conduction (empty) states c are at k; the valence (occupied) states v at
+ * k - q = k' + G0 are stored at k' with Miller lists relative to k'. Output
+ *   rho[v][c][g] = rho_{c v k}(q, G_g),  transition index t = v*nc + c,
+ *   dE[v][c]     = e_c - e_v  (the pole energy of Eq. X_IP, Ha).
+ * For q0 != 0 (q = 0 exactly, k' = k, G0 = 0) the G = 0 column holds the q -> 0
+ * limit divided by |q| along qhat from velocity matrix elements (Eq. dip, the
+ * G-space v approach for a local Hamiltonian):
+ *   rho^_cv = qhat . sum_G conj(c_c(G)) (k+G) c_v(G) / (e_c - e_v),
+ * and requires |e_c - e_v| >= 1e-8 Ha for every pair (checked on the device
+ * data only by the caller; the library does not read device energies).
+ *
+ * Layout: coef_c [nc][npw_c], coef_v [nv][npw_v] complex (precision per prec);
+ * rho [nv][nc][ng] complex of the same precision.
+ * Errors (XO_ERR_ARG): sizes <= 0; a Miller list that wraps onto itself on the
+ * grid; a grid too small for an alias-free product (per axis the reach
+ * max|m_c - m_v - (m_G - G0)| must stay below N); q0 set with G = 0 missing
+ * from the G-set. XO_ERR_UNSUPPORTED: grid axis > 128, or a plane-wave sphere
+ * wider than 32 Miller steps along z.
+ */
+typedef struct {
+  int n[3];                 /* FFT grid                                        */
+  double bvec[9];           /* [host] rows b1,b2,b3 in 1/bohr (q0 velocities)  */
+  int prec;                 /* XO_FP64 / XO_FP32 (XO_BF16X3 computes as FP32)   */
+  /* bra: conduction bands at k */
+  int npw_c;
+  const int32_t* mill_c;    /* [host] [npw_c][3]                               */
+  int nc;
+  const void* coef_c;       /* [device] [nc][npw_c] complex                    */
+  const double* e_c;        /* [device] [nc] band energies, Ha                 */
+  double kcart[3];          /* k in 1/bohr (q0 velocities only)                */
+  /* ket: valence bands at k' (k - q = k' + G0) */
+  int npw_v;
+  const int32_t* mill_v;    /* [host] [npw_v][3]                               */
+  int nv;
+  const void* coef_v;       /* [device] [nv][npw_v] complex                    */
+  const double* e_v;        /* [device] [nv]                                   */
+  int g0[3];                /* umklapp G0 (Miller)                             */
+  /* chi0 G-set */
+  int ng;
+  const int32_t* mill_g;    /* [host] [ng][3]                                  */
+  int q0;                   /* nonzero: q = 0 head from velocities             */
+  double qhat[3];           /* Cartesian direction of q -> 0                   */
+  /* outputs */
+  void* rho;                /* [device] [nv][nc][ng] complex                   */
+  double* dE;               /* [device] [nv][nc] or NULL                       */
+} xo_rho_args;
+
+int xo_rho(const xo_rho_args* a, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* chi0 at imaginary frequencies, Eq. (X_IP) with the App. A split into the
+ * frequency-free outer products and one frequency factor per transition:
+ *   chi0[w][G][G'] (+)= -pref sum_t [2 dE_t / (w^2 + dE_t^2)] rho[t][G] conj(rho[t][G'])
+ * A weighted Hermitian rank-nt update; only G-blocks i <= j are computed and
+ * the lower triangle is written as the conjugate, so the result is exactly
+ * Hermitian with a real diagonal.
+ *
+ * rho: [device] [nt][ng] complex (complex128 for XO_FP64, complex64 otherwise).
+ * dE:  [device] [nt] pole energies, must be > 0 (with check_dE set the call
+ *      synchronises the stream and returns XO_ERR_ARG if any is <= 0 or NaN).
+ * w:   [host] [nw] imaginary frequencies (Ha), w >= 0, nw <= 64.
+ * chi0: [device] [nw][ng][ng] complex128; accumulate = 0 overwrites, 1 adds
+ *      (so chunks of transitions can be streamed).
+ * prec: XO_FP64 (FP64 MFMA), XO_FP32 (FP32 MFMA, FP32 accumulation within a
+ *      transition chunk, FP64 across chunks), XO_BF16X3 (each operand split
+ *      into bf16 hi + lo, three bf16 MFMA products hi*hi + hi*lo + lo*hi,
+ *      FP32 accumulation within a chunk, FP64 across chunks).
+ */
+typedef struct {
+  int nt, ng, nw;
+  int prec;
+  const void* rho;
+  const double* dE;
+  const double* w;
+  double pref;
+  int accumulate;
+  int check_dE;
+  double* chi0;
+} xo_chi0_args;
+
+int xo_chi0(const xo_chi0_args* a, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Inverse dielectric matrix by the Dyson equation in matrix form, Eq. (X_rpa_inv):
+ *   eps~ = I - diag(s) chi0 diag(s),  s_G = sqrt(4 pi)/|q+G|,
+ *   out  = eps~^-1                       (XO_EPS_SYM, default; the matrix that
+ *                                          Eq. (W_def) scales by 4pi/(|q+G||q+G'|))
+ *   out  = (I - v chi0)^-1 = diag(s) eps~^-1 diag(1/s)   (XO_EPS_NONSYM)
+ * Always FP64. eps~ is Hermitian positive definite at imaginary frequencies;
+ * the inversion is a blocked Gauss-Jordan without pivoting whose pivots are
+ * the LDL^H diagonal, so a non-positive pivot proves eps~ is not PD: the call
+ * then returns XO_ERR_NOTPD naming the first such frequency. With
+ * XO_EPS_LU_FALLBACK the sign test is skipped (an exactly zero pivot still
+ * fails). The call synchronises the stream to read the pivot flags.
+ * qpg: [host] [ng] |q+G| (at q = 0 the G = 0 entry is 1 and chi0's G = 0 row and
+ *      column are the q-normalised head and wings).
+ * chi0: [device] [nw][ng][ng] complex128 (read only); out: [device] same shape.
+ */
+enum { XO_EPS_SYM = 0, XO_EPS_NONSYM = 1, XO_EPS_LU_FALLBACK = 2 };
+
+typedef struct {
+  int ng, nw;
+  const double* qpg;
+  const double* chi0;
+  int flags;
+  double* out;
+} xo_eps_args;
+
+int xo_epsinv(const xo_eps_args* a, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XO_H */

@@ -1,0 +1,168 @@
+// C-ABI plumbing: error state, version, workspace and device-table caches.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "xo_common.h"
+
+namespace xo {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+static std::mutex g_mu;
+
+struct Buf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+static std::map<std::tuple<int, hipStream_t, int>, Buf> g_ws;
+static std::map<std::tuple<int, hipStream_t>, Buf> g_hostflags;
+
+struct Table {
+  std::vector<unsigned char> host;
+  void* dev = nullptr;
+};
+static std::map<std::tuple<int, uint64_t, size_t>, std::vector<Table>> g_tables;
+
+static bool fault_alloc() {
+  const char* f = getenv("XO_FAULT");
+  return f && strcmp(f, "alloc") == 0;
+}
+
+static int dev_alloc(void** p, size_t bytes) {
+  if (fault_alloc()) {
+    set_error("device allocation of %zu bytes failed (forced by XO_FAULT=alloc)", bytes);
+    return XO_ERR_ALLOC;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    *p = nullptr;
+    return XO_ERR_ALLOC;
+  }
+  return XO_OK;
+}
+
+int workspace(hipStream_t s, int slot, size_t bytes, void** out) {
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  bytes = align_up(bytes < 256 ? 256 : bytes, 256);
+  std::lock_guard<std::mutex> lk(g_mu);
+  Buf& b = g_ws[std::make_tuple(dev, s, slot)];
+  if (b.n < bytes) {
+    if (b.p) {
+      XO_TRY_HIP(hipStreamSynchronize(s));
+      XO_TRY_HIP(hipFree(b.p));
+      b.p = nullptr;
+      b.n = 0;
+    }
+    size_t want = bytes + bytes / 8;  // headroom so small growth does not re-allocate
+    XO_RET(dev_alloc(&b.p, want));
+    b.n = want;
+  }
+  *out = b.p;
+  return XO_OK;
+}
+
+int host_flags(hipStream_t s, size_t bytes, void** out) {
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  Buf& b = g_hostflags[std::make_tuple(dev, s)];
+  if (b.n < bytes) {
+    if (b.p) {
+      XO_TRY_HIP(hipStreamSynchronize(s));
+      XO_TRY_HIP(hipHostFree(b.p));
+      b.p = nullptr;
+      b.n = 0;
+    }
+    XO_TRY_HIP(hipHostMalloc(&b.p, bytes));
+    b.n = bytes;
+  }
+  *out = b.p;
+  return XO_OK;
+}
+
+static uint64_t fnv1a(const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int device_table(const void* host, size_t bytes, hipStream_t s, const void** out) {
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  uint64_t h = fnv1a(host, bytes);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto& bucket = g_tables[std::make_tuple(dev, h, bytes)];
+  for (auto& t : bucket) {
+    if (memcmp(t.host.data(), host, bytes) == 0) {
+      *out = t.dev;
+      return XO_OK;
+    }
+  }
+  Table t;
+  t.host.assign(static_cast<const unsigned char*>(host),
+                static_cast<const unsigned char*>(host) + bytes);
+  XO_RET(dev_alloc(&t.dev, bytes < 256 ? 256 : bytes));
+  hipError_t e = hipMemcpyAsync(t.dev, t.host.data(), bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(t.dev);
+    set_error("table upload failed: %s", hipGetErrorString(e));
+    return XO_ERR_HIP;
+  }
+  *out = t.dev;
+  bucket.push_back(std::move(t));
+  return XO_OK;
+}
+
+}  // namespace xo
+
+extern "C" {
+
+const char* xo_last_error(void) { return xo::g_err; }
+
+const char* xo_version(void) { return "xo 0.1.0 (gfx950)"; }
+
+int xo_release_workspace(void) {
+  std::lock_guard<std::mutex> lk(xo::g_mu);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    xo::set_error("hipDeviceSynchronize failed: %s", hipGetErrorString(e));
+    return XO_ERR_HIP;
+  }
+  for (auto& kv : xo::g_ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  xo::g_ws.clear();
+  for (auto& kv : xo::g_hostflags)
+    if (kv.second.p) (void)hipHostFree(kv.second.p);
+  xo::g_hostflags.clear();
+  for (auto& kv : xo::g_tables)
+    for (auto& t : kv.second)
+      if (t.dev) (void)hipFree(t.dev);
+  xo::g_tables.clear();
+  return XO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+"""ctypes binding of libxo.so (argument marshalling only).
+
+Every compute step runs in the library's HIP kernels. PyTorch provides device
+memory and the current stream. If the library is missing the calls raise: there
+is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxo.so")
+
+XO_OK, XO_ERR_ARG, XO_ERR_ALLOC, XO_ERR_HIP, XO_ERR_NOTPD, XO_ERR_UNSUPPORTED = range(6)
+XO_FP64, XO_FP32, XO_BF16X3 = 0, 1, 2
+XO_EPS_SYM, XO_EPS_NONSYM, XO_EPS_LU_FALLBACK = 0, 1, 2
+
+PREC = {"fp64": XO_FP64, "fp32": XO_FP32, "bf16x3": XO_BF16X3}
+ERRNAME = {1: "XO_ERR_ARG", 2: "XO_ERR_ALLOC", 3: "XO_ERR_HIP", 4: "XO_ERR_NOTPD", 5: "XO_ERR_UNSUPPORTED"}
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+
+
+class RhoArgs(C.Structure):
+    _fields_ = [
+        ("n", C.c_int * 3), ("bvec", C.c_double * 9), ("prec", C.c_int),
+        ("npw_c", C.c_int), ("mill_c", _i32p), ("nc", C.c_int), ("coef_c", C.c_void_p),
+        ("e_c", C.c_void_p), ("kcart", C.c_double * 3),
+        ("npw_v", C.c_int), ("mill_v", _i32p), ("nv", C.c_int), ("coef_v", C.c_void_p),
+        ("e_v", C.c_void_p), ("g0", C.c_int * 3),
+        ("ng", C.c_int), ("mill_g", _i32p), ("q0", C.c_int), ("qhat", C.c_double * 3),
+        ("rho", C.c_void_p), ("dE", C.c_void_p),
+    ]
+
+
+class Chi0Args(C.Structure):
+    _fields_ = [
+        ("nt", C.c_int), ("ng", C.c_int), ("nw", C.c_int), ("prec", C.c_int),
+        ("rho", C.c_void_p), ("dE", C.c_void_p), ("w", _f64p), ("pref", C.c_double),
+        ("accumulate", C.c_int), ("check_dE", C.c_int), ("chi0", C.c_void_p),
+    ]
+
+
+class EpsArgs(C.Structure):
+    _fields_ = [
+        ("ng", C.c_int), ("nw", C.c_int), ("qpg", _f64p), ("chi0", C.c_void_p),
+        ("flags", C.c_int), ("out", C.c_void_p),
+    ]
+
+
+class XoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRNAME.get(code, code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_rho", "xo_chi0", "xo_epsinv")
+
+
+def lib():
+    """Load libxo.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1902_03837_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.xo_last_error.restype = C.c_char_p
+        L.xo_version.restype = C.c_char_p
+        for name, argt in (("xo_rho", RhoArgs), ("xo_chi0", Chi0Args), ("xo_epsinv", EpsArgs)):
+            fn = getattr(L, name)
+            fn.argtypes = [C.POINTER(argt), C.c_void_p]
+            fn.restype = C.c_int
+        L.xo_release_workspace.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != XO_OK:
+        raise XoError(rc, lib().xo_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return t.data_ptr()
+
+
+def version() -> str:
+    return lib().xo_version().decode()
+
+
+def release_workspace():
+    _check(lib().xo_release_workspace())
+
+
+def _cdtype(prec):
+    import torch
+    return torch.complex128 if (PREC[prec] if isinstance(prec, str) else int(prec)) == XO_FP64 else torch.complex64
+
+
+def rho(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=None,
+        prec="fp64", kcart=(0., 0., 0.), bvec=None, q0=False, qhat=(1., 0., 0.), stream=None):
+    """xo_rho for one k-pair: out[nv][nc][ng] (and dE[nv][nc] if given)."""
+    import torch
+    mc, mv, mg = _host_i32(mill_c), _host_i32(mill_v), _host_i32(gmill)
+    cdt = _cdtype(prec)
+    nc, nv, ng = coef_c.shape[0], coef_v.shape[0], mg.shape[0]
+    # host-side shape checks: the kernels trust these extents
+    assert mc.ndim == 2 and mc.shape[1] == 3 and mv.ndim == 2 and mv.shape[1] == 3 and mg.shape[1] == 3
+    assert tuple(coef_c.shape) == (nc, mc.shape[0]) and coef_c.dtype == cdt, (coef_c.shape, coef_c.dtype)
+    assert tuple(coef_v.shape) == (nv, mv.shape[0]) and coef_v.dtype == cdt, (coef_v.shape, coef_v.dtype)
+    assert tuple(out.shape) == (nv, nc, ng) and out.dtype == cdt, (out.shape, out.dtype)
+    if dE is not None:
+        assert dE.numel() == nv * nc and dE.dtype == torch.float64
+    if dE is not None or q0:
+        assert e_c is not None and e_v is not None
+        assert e_c.numel() >= nc and e_v.numel() >= nv and e_c.dtype == e_v.dtype == torch.float64
+    a = RhoArgs()
+    a.n[:] = [int(x) for x in grid]
+    a.bvec[:] = list(np.asarray(bvec if bvec is not None else np.eye(3), float).reshape(9))
+    a.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    a.npw_c, a.mill_c, a.nc = mc.shape[0], mc.ctypes.data_as(_i32p), coef_c.shape[0]
+    a.coef_c, a.e_c = _ptr(coef_c), _ptr(e_c)
+    a.kcart[:] = [float(x) for x in kcart]
+    a.npw_v, a.mill_v, a.nv = mv.shape[0], mv.ctypes.data_as(_i32p), coef_v.shape[0]
+    a.coef_v, a.e_v = _ptr(coef_v), _ptr(e_v)
+    a.g0[:] = [int(x) for x in g0]
+    a.ng, a.mill_g = mg.shape[0], mg.ctypes.data_as(_i32p)
+    a.q0 = 1 if q0 else 0
+    a.qhat[:] = [float(x) for x in qhat]
+    a.rho, a.dE = _ptr(out), _ptr(dE)
+    _check(lib().xo_rho(C.byref(a), _stream(stream)))
+    return out
+
+
+def chi0(rho_m, dE, omegas: Sequence[float], pref: float, *, out, prec="fp64", accumulate=False,
+         check_dE=True, stream=None):
+    """xo_chi0: out[nw][ng][ng] complex128 (+)= -pref sum_t W_t(w) rho_t rho_t^H."""
+    import torch
+    w = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    assert rho_m.ndim == 2 and rho_m.dtype == _cdtype(prec), (rho_m.shape, rho_m.dtype)
+    assert dE.numel() == rho_m.shape[0] and dE.dtype == torch.float64
+    assert tuple(out.shape) == (w.shape[0], rho_m.shape[1], rho_m.shape[1]) and out.dtype == torch.complex128
+    a = Chi0Args()
+    a.nt, a.ng, a.nw = rho_m.shape[0], rho_m.shape[1], w.shape[0]
+    a.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    a.rho, a.dE, a.w, a.pref = _ptr(rho_m), _ptr(dE), w.ctypes.data_as(_f64p), float(pref)
+    a.accumulate, a.check_dE, a.chi0 = int(bool(accumulate)), int(bool(check_dE)), _ptr(out)
+    _check(lib().xo_chi0(C.byref(a), _stream(stream)))
+    return out
+
+
+def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, stream=None):
+    """xo_epsinv: out = eps~^-1 (or (I - v chi0)^-1 with XO_EPS_NONSYM), complex128."""
+    import torch
+    q = np.ascontiguousarray(np.asarray(qpg, dtype=np.float64))
+    assert chi0_m.ndim == 3 and chi0_m.shape[1] == chi0_m.shape[2] == q.shape[0]
+    assert chi0_m.dtype == torch.complex128 and out.dtype == torch.complex128
+    assert tuple(out.shape) == tuple(chi0_m.shape)
+    a = EpsArgs()
+    a.ng, a.nw = chi0_m.shape[-1], chi0_m.shape[0]
+    a.qpg, a.chi0, a.flags, a.out = q.ctypes.data_as(_f64p), _ptr(chi0_m), int(flags), _ptr(out)
+    _check(lib().xo_epsinv(C.byref(a), _stream(stream)))
+    return out

@@ -1,0 +1,115 @@
+"""C-ABI library: loads, exports every declared symbol, validates arguments on the host.
+
+CPU only: no call here reaches a kernel launch (each fails validation first).
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1902_03837_amd import xo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "xo.h")).read()
+    return sorted(set(re.findall(r"\b(xo_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = xo.lib()
+    names = _declared()
+    assert {"xo_rho", "xo_chi0", "xo_epsinv", "xo_last_error", "xo_version"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(xo.EXPORTS) <= set(names)
+    assert xo.version().startswith("xo ")
+
+
+def test_struct_layouts_match_header_sizes():
+    # field counts of the ctypes mirrors track the header structs
+    src = open(os.path.join(ROOT, "include", "xo.h")).read()
+    assert "xo_rho_args" in src and "xo_chi0_args" in src and "xo_eps_args" in src
+    assert C.sizeof(xo.Chi0Args) == 4 * 4 + 3 * 8 + 8 + 4 + 4 + 8
+    assert C.sizeof(xo.EpsArgs) == 8 + 8 + 8 + 8 + 8
+
+
+def _rc(fn, a):
+    rc = fn(C.byref(a), None)
+    return rc, xo.lib().xo_last_error().decode()
+
+
+def test_chi0_argument_errors():
+    L = xo.lib()
+    a = xo.Chi0Args()
+    rc, msg = _rc(L.xo_chi0, a)
+    assert rc == xo.XO_ERR_ARG and "positive" in msg
+    w = np.array([0.0, -1.0])
+    a.nt, a.ng, a.nw, a.prec = 4, 3, 2, 0
+    a.rho, a.dE, a.chi0 = 8, 8, 8   # never dereferenced: validation fails first
+    a.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    a.pref = 1.0
+    rc, msg = _rc(L.xo_chi0, a)
+    assert rc == xo.XO_ERR_ARG and "negative" in msg
+    w[1] = 1.0
+    a.prec = 7
+    rc, msg = _rc(L.xo_chi0, a)
+    assert rc == xo.XO_ERR_ARG and "precision" in msg
+    a.prec = 0
+    a.nw = 65
+    rc, msg = _rc(L.xo_chi0, a)
+    assert rc == xo.XO_ERR_ARG
+
+
+def _rho_args(mc, mv, mg, grid, g0=(0, 0, 0)):
+    a = xo.RhoArgs()
+    a.n[:] = grid
+    keep = [np.ascontiguousarray(x, dtype=np.int32) for x in (mc, mv, mg)]
+    a.npw_c, a.mill_c = len(mc), keep[0].ctypes.data_as(C.POINTER(C.c_int32))
+    a.npw_v, a.mill_v = len(mv), keep[1].ctypes.data_as(C.POINTER(C.c_int32))
+    a.ng, a.mill_g = len(mg), keep[2].ctypes.data_as(C.POINTER(C.c_int32))
+    a.nc = a.nv = 2
+    a.coef_c = a.coef_v = a.rho = 8
+    a.g0[:] = g0
+    return a, keep
+
+
+def test_rho_alias_and_wrap_checks():
+    L = xo.lib()
+    sphere = np.array([[i, j, k] for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)])
+    gs = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0]])
+    # reach along x: 3 - (-3) - (-1) = 7 -> needs N >= 8; the sphere spans 7 -> N >= 7
+    a, keep = _rho_args(sphere, sphere, gs, [7, 16, 16])
+    rc, msg = _rc(L.xo_rho, a)
+    assert rc == xo.XO_ERR_ARG and "aliases" in msg
+    a, keep = _rho_args(sphere, sphere, gs, [6, 16, 16])
+    rc, msg = _rc(L.xo_rho, a)
+    assert rc == xo.XO_ERR_ARG and "wraps" in msg
+    a, keep = _rho_args(sphere, sphere, gs, [200, 16, 16])
+    rc, msg = _rc(L.xo_rho, a)
+    assert rc == xo.XO_ERR_UNSUPPORTED
+    # q0 needs G = 0 in the G-set
+    a, keep = _rho_args(sphere, sphere, gs[1:], [16, 16, 16])
+    a.q0 = 1
+    a.qhat[:] = [1, 0, 0]
+    a.e_c = a.e_v = 8
+    rc, msg = _rc(L.xo_rho, a)
+    assert rc == xo.XO_ERR_ARG and "G = 0" in msg
+
+
+def test_epsinv_argument_errors():
+    L = xo.lib()
+    q = np.array([1.0, 0.0, 2.0])
+    a = xo.EpsArgs()
+    a.ng, a.nw = 3, 1
+    a.qpg = q.ctypes.data_as(C.POINTER(C.c_double))
+    a.chi0, a.out = 8, 16
+    rc, msg = _rc(L.xo_epsinv, a)
+    assert rc == xo.XO_ERR_ARG and "|q+G|" in msg
+    a.flags = 64
+    rc, msg = _rc(L.xo_epsinv, a)
+    assert rc == xo.XO_ERR_ARG and "flags" in msg

@@ -1,0 +1,230 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, element by element."""
+
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import crystal_for  # noqa: E402
+from synth.crystal import fcc_lattice, make_crystal, shell_potential, ecut_for_npw, kgrid_gamma  # noqa: E402
+from synth.configs import A_FCC  # noqa: E402
+from synth.rand import random_complex, random_positive  # noqa: E402
+from oracle.pipeline import rho_pair, rho_all_pairs, chi0_crystal  # noqa: E402
+from oracle.chi0 import chi0_from_rho  # noqa: E402
+from oracle.epsinv import epsinv_sym, epsinv_nonsym  # noqa: E402
+from oracle.metrics import err_table, rel_fro  # noqa: E402
+from paper_1902_03837_amd import xo  # noqa: E402
+from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal, rho_all, ntrans  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+
+
+def _to(a, dt=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dt)
+
+
+# ----------------------------------------------------------------------------- rho
+
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+def test_rho_parity(name, prec, tol):
+    cr = crystal_for(name)
+    say(f"rho parity {name} {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    K = ntrans(cr)
+    ng = cr.gmill.shape[0]
+    M = torch.empty((K, ng), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
+    dE = torch.empty(K, dtype=torch.float64, device=DEV)
+    rho_all(dc, M, dE)
+    torch.cuda.synchronize()
+    Mr, dEr = rho_all_pairs(cr, "fft")
+    Mg = M.cpu().numpy().astype(np.complex128)
+    err = np.abs(Mg - Mr).max() / np.abs(Mr).max()
+    say(f"  max rel err {err:.3e}")
+    assert err < tol
+    assert np.array_equal(dE.cpu().numpy(), dEr)
+
+
+def test_rho_q0_head_parity():
+    lat = fcc_lattice(A_FCC)
+    cr = make_crystal(lat, shell_potential(lat, 31), kgrid_gamma(2), np.zeros(3), (16,) * 3,
+                      ecut_for_npw(lat, 160), 4, 12, 27, 2, 31)
+    say("rho q0 head parity")
+    assert cr.q0
+    dc = DeviceCrystal.upload(cr, "fp64")
+    K = ntrans(cr)
+    M = torch.empty((K, 27), dtype=torch.complex128, device=DEV)
+    dE = torch.empty(K, dtype=torch.float64, device=DEV)
+    rho_all(dc, M, dE)
+    Mr, _ = rho_all_pairs(cr, "fft")
+    Mg = M.cpu().numpy()
+    assert np.abs(Mg[:, 0] - Mr[:, 0]).max() < 1e-12 * np.abs(Mr[:, 0]).max()
+    assert np.abs(Mg - Mr).max() < 1e-12 * np.abs(Mr).max()
+
+
+# ---------------------------------------------------------------------------- chi0
+
+@pytest.mark.parametrize("nt,ng,nw", [(1, 1, 1), (37, 17, 2), (1000, 33, 3), (777, 59, 8), (300, 40, 11)])
+def test_chi0_fp64_random(nt, ng, nw):
+    say(f"chi0 fp64 random nt={nt} ng={ng} nw={nw}")
+    M = random_complex(100 + nt, (nt, ng))
+    dE = random_positive(200 + nt, nt, 0.05, 3.0)
+    w = np.linspace(0.0, 2.0, nw)
+    ref = chi0_from_rho(M, dE, w, 0.37)
+    out = torch.empty((nw, ng, ng), dtype=torch.complex128, device=DEV)
+    xo.chi0(_to(M), _to(dE, torch.float64), w, 0.37, out=out, prec="fp64")
+    got = out.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+    for j in range(nw):
+        assert np.array_equal(got[j], got[j].conj().T)   # exactly Hermitian by construction
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16x3", 2e-4)])
+def test_chi0_reduced_precision_random(prec, tol):
+    nt, ng, nw = 5000, 45, 4
+    say(f"chi0 {prec} random")
+    M = random_complex(7, (nt, ng))
+    dE = random_positive(8, nt, 0.05, 3.0)
+    w = np.linspace(0.0, 2.0, nw)
+    ref = chi0_from_rho(M.astype(np.complex64).astype(np.complex128), dE, w, 1.0)
+    out = torch.empty((nw, ng, ng), dtype=torch.complex128, device=DEV)
+    xo.chi0(_to(M, torch.complex64), _to(dE, torch.float64), w, 1.0, out=out, prec=prec)
+    got = out.cpu().numpy()
+    err = rel_fro(got, ref)
+    say(f"  rel Frobenius err {err:.3e}")
+    assert err < tol
+
+
+def test_chi0_accumulate_and_determinism():
+    nt, ng, nw = 3000, 50, 3
+    M = random_complex(11, (nt, ng))
+    dE = random_positive(12, nt, 0.1, 2.0)
+    w = [0.0, 0.5, 1.5]
+    Md, dEd = _to(M), _to(dE, torch.float64)
+    full = torch.empty((nw, ng, ng), dtype=torch.complex128, device=DEV)
+    full2 = torch.empty_like(full)
+    xo.chi0(Md, dEd, w, 1.0, out=full)
+    xo.chi0(Md, dEd, w, 1.0, out=full2)
+    assert torch.equal(full, full2)                       # fixed-order reduction
+    part = torch.empty_like(full)
+    xo.chi0(Md[:1200], dEd[:1200], w, 1.0, out=part)
+    xo.chi0(Md[1200:], dEd[1200:], w, 1.0, out=part, accumulate=True)
+    a, b = part.cpu().numpy(), full.cpu().numpy()
+    assert np.abs(a - b).max() < 1e-13 * np.abs(b).max()  # sharding invariance
+
+
+def test_chi0_rejects_nonpositive_pole():
+    M = random_complex(1, (10, 4))
+    dE = np.ones(10)
+    dE[3] = -0.1
+    out = torch.empty((1, 4, 4), dtype=torch.complex128, device=DEV)
+    with pytest.raises(xo.XoError) as e:
+        xo.chi0(_to(M), _to(dE, torch.float64), [0.0], 1.0, out=out)
+    assert e.value.code == xo.XO_ERR_ARG
+
+
+# -------------------------------------------------------------------------- epsinv
+
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+def test_epsinv_parity(name):
+    cr = crystal_for(name)
+    say(f"epsinv parity {name}")
+    chi = chi0_crystal(cr)
+    qpg = cr.qpg()
+    ref = epsinv_sym(chi, qpg)
+    out = torch.empty(chi.shape, dtype=torch.complex128, device=DEV)
+    xo.epsinv(_to(chi), qpg, out=out)
+    got = out.cpu().numpy()
+    assert rel_fro(got, ref) < 1e-12
+    refn = epsinv_nonsym(chi, qpg)
+    xo.epsinv(_to(chi), qpg, out=out, flags=xo.XO_EPS_NONSYM)
+    assert rel_fro(out.cpu().numpy(), refn) < 1e-12
+
+
+@pytest.mark.parametrize("ng", [1, 31, 32, 33, 97])
+def test_epsinv_sizes_random_hpd(ng):
+    say(f"epsinv random HPD ng={ng}")
+    X = random_complex(ng, (3 * ng + 2, ng))
+    chi = -(X.conj().T @ X)[None] / (3 * ng)
+    chi = np.concatenate([chi, 0.5 * chi])
+    qpg = np.linspace(0.5, 3.0, ng)
+    ref = epsinv_sym(chi, qpg)
+    out = torch.empty(chi.shape, dtype=torch.complex128, device=DEV)
+    xo.epsinv(_to(chi), qpg, out=out)
+    assert rel_fro(out.cpu().numpy(), ref) < 1e-12
+
+
+def test_epsinv_not_positive_definite():
+    ng = 40
+    X = random_complex(3, (50, ng))
+    chi = (X.conj().T @ X)[None] * 0.5          # positive: eps~ = I - s chi s is indefinite
+    qpg = np.ones(ng)
+    out = torch.empty(chi.shape, dtype=torch.complex128, device=DEV)
+    with pytest.raises(xo.XoError) as e:
+        xo.epsinv(_to(chi), qpg, out=out)
+    assert e.value.code == xo.XO_ERR_NOTPD
+    xo.epsinv(_to(chi), qpg, out=out, flags=xo.XO_EPS_LU_FALLBACK)
+    s = np.sqrt(4 * np.pi) / qpg
+    ref = np.linalg.inv(np.eye(ng) - s[:, None] * chi[0] * s[None, :])
+    assert np.abs(out.cpu().numpy()[0] - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------- end to end
+
+@pytest.mark.parametrize("name,prec,gate", [("c1", "fp64", 1e-6), ("c2_small", "fp64", 1e-6),
+                                            ("c1", "fp32", 1e-4), ("c2_small", "fp32", 1e-4),
+                                            ("c2_small", "bf16x3", 1e-4)])
+def test_end_to_end(name, prec, gate):
+    cr = crystal_for(name)
+    say(f"end to end {name} {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    M, dE, chi, E = run_crystal(dc)
+    torch.cuda.synchronize()
+    Eref, chiref = _oracle_eps(name)
+    t = err_table(E.cpu().numpy(), Eref, chi.cpu().numpy(), chiref)
+    say(f"  {t}")
+    assert t["e_F"] <= gate
+    if prec == "fp64":
+        assert t["e_F"] < 1e-11
+
+
+_ORC = {}
+
+
+def _oracle_eps(name):
+    if name not in _ORC:
+        cr = crystal_for(name)
+        chi = chi0_crystal(cr)
+        _ORC[name] = (epsinv_sym(chi, cr.qpg()), chi)
+    return _ORC[name]
+
+
+def test_alloc_failure_is_reported_and_recovers():
+    cr = crystal_for("c1_small")
+    dc = DeviceCrystal.upload(cr, "fp64")
+    xo.release_workspace()
+    os.environ["XO_FAULT"] = "alloc"
+    try:
+        with pytest.raises(xo.XoError) as e:
+            run_crystal(dc)
+        assert e.value.code == xo.XO_ERR_ALLOC
+    finally:
+        del os.environ["XO_FAULT"]
+    M, dE, chi, E = run_crystal(dc)
+    Eref = epsinv_sym(chi0_crystal(cr), cr.qpg())
+    assert rel_fro(E.cpu().numpy(), Eref) < 1e-11
