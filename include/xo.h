@@ -57,6 +57,13 @@ const char* xo_version(void);
 /* Free all cached workspace and geometry tables on every device (synchronises). */
 int xo_release_workspace(void);
 
+/* Kernel timing for benchmarks: with timing on, every kernel the library launches
+ * is bracketed by HIP events recorded on its launch stream. xo_timing_report
+ * synchronises those events, writes one line "name launches total_ms" per kernel
+ * into buf (NUL-terminated, truncated to len bytes) and clears the counters. */
+int xo_timing_enable(int on);
+int xo_timing_report(char* buf, int len);
+
 /* ------------------------------------------------------------------------- */
 /* Oscillator strengths, Eq. (rhotw): the Fourier transform of the real-space
  * product conj(psi_c,k(r)) psi_v,k-q(r), evaluated for one k-pair and all

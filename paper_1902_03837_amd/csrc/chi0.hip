@@ -272,15 +272,24 @@ static int run_group(const TileArgs& base, int nslice_wg, hipStream_t s, int pre
   dim3 grid(A.ntiles, nslice_wg);
   if (prec == XO_BF16X3) {
     if constexpr (std::is_same<T, float>::value) {
-      hipLaunchKernelGGL((chi0_tiles_bf16x3<NWG>), grid, dim3(256), 0, s, A);
+      {
+        KernelTimer kt_("chi0_tiles_bf16x3", s);
+        hipLaunchKernelGGL((chi0_tiles_bf16x3<NWG>), grid, dim3(256), 0, s, A);
+      }
     }
   } else {
-    hipLaunchKernelGGL((chi0_tiles<T, NWG>), grid, dim3(256), 0, s, A);
+    {
+      KernelTimer kt_("chi0_tiles", s);
+      hipLaunchKernelGGL((chi0_tiles<T, NWG>), grid, dim3(256), 0, s, A);
+    }
   }
   XO_CHECK_LAUNCH();
-  hipLaunchKernelGGL((chi0_reduce<T, NWG>), dim3(A.ntiles, NWG), dim3(256), 0, s,
-                     static_cast<const T*>(A.part), nslice_wg * kWaves, A.ntiles, A.tiles, A.ng, w0, nw, pref,
-                     accumulate, chi0);
+  {
+    KernelTimer kt_("chi0_reduce", s);
+    hipLaunchKernelGGL((chi0_reduce<T, NWG>), dim3(A.ntiles, NWG), dim3(256), 0, s,
+                       static_cast<const T*>(A.part), nslice_wg * kWaves, A.ntiles, A.tiles, A.ng, w0, nw, pref,
+                       accumulate, chi0);
+  }
   XO_CHECK_LAUNCH();
   return XO_OK;
 }
@@ -318,8 +327,11 @@ static int chi0_run(const xo_chi0_args* a, hipStream_t s) {
   void* part = static_cast<char*>(ws) + wbytes;
   int* bad = reinterpret_cast<int*>(static_cast<char*>(ws) + wbytes + pbytes);
   if (a->check_dE) XO_TRY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-  hipLaunchKernelGGL((pole_factors<T>), dim3((a->nt + 255) / 256), dim3(256), 0, s, a->dE, a->nt,
-                     static_cast<const double*>(dw), a->nw, nwpad, W, a->check_dE ? bad : nullptr);
+  {
+    KernelTimer kt_("pole_factors", s);
+    hipLaunchKernelGGL((pole_factors<T>), dim3((a->nt + 255) / 256), dim3(256), 0, s, a->dE, a->nt,
+                       static_cast<const double*>(dw), a->nw, nwpad, W, a->check_dE ? bad : nullptr);
+  }
   XO_CHECK_LAUNCH();
   if (a->check_dE) {
     int* hb = nullptr;

@@ -208,28 +208,46 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   int* flag = static_cast<int*>(ws);
   XO_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int) * a->nw, st));
   const size_t nn = (size_t)n * n;
-  hipLaunchKernelGGL(build_eps, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->chi0,
-                     static_cast<const double*>(ds), n, a->out);
+  {
+    KernelTimer kt_("eps_build", st);
+    hipLaunchKernelGGL(build_eps, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->chi0,
+                       static_cast<const double*>(ds), n, a->out);
+  }
   XO_CHECK_LAUNCH();
   const int nblk = (n + kB - 1) / kB;
   const int check_sign = (a->flags & XO_EPS_LU_FALLBACK) ? 0 : 1;
   for (int K = 0; K < nblk; ++K) {
     const int kb = std::min(kB, n - K * kB);
-    hipLaunchKernelGGL(diag_inverse, dim3(a->nw), dim3(256), 0, st, a->out, n, K, kb, check_sign, flag);
+    {
+      KernelTimer kt_("eps_diag_inverse", st);
+      hipLaunchKernelGGL(diag_inverse, dim3(a->nw), dim3(256), 0, st, a->out, n, K, kb, check_sign, flag);
+    }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
-      hipLaunchKernelGGL(row_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+      {
+        KernelTimer kt_("eps_row_block", st);
+        hipLaunchKernelGGL(row_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+      }
       XO_CHECK_LAUNCH();
-      hipLaunchKernelGGL(rank_update, dim3((n + 31) / 32, (n + 31) / 32, a->nw), dim3(256), 0, st, a->out, n,
-                         K, kb);
+      {
+        KernelTimer kt_("eps_rank_update", st);
+        hipLaunchKernelGGL(rank_update, dim3((n + 31) / 32, (n + 31) / 32, a->nw), dim3(256), 0, st, a->out, n,
+                           K, kb);
+      }
       XO_CHECK_LAUNCH();
-      hipLaunchKernelGGL(col_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+      {
+        KernelTimer kt_("eps_col_block", st);
+        hipLaunchKernelGGL(col_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+      }
       XO_CHECK_LAUNCH();
     }
   }
   if (a->flags & XO_EPS_NONSYM) {
-    hipLaunchKernelGGL(unsymmetrise, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->out,
-                       static_cast<const double*>(ds), n);
+    {
+      KernelTimer kt_("eps_unsymmetrise", st);
+      hipLaunchKernelGGL(unsymmetrise, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->out,
+                         static_cast<const double*>(ds), n);
+    }
     XO_CHECK_LAUNCH();
   }
   int* hf = nullptr;

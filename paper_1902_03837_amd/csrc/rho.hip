@@ -40,47 +40,66 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw, int n) {
 
 struct SphereEntry {
   int src;  // index of the plane wave in the caller's coefficient row
-  int ix;   // m_x mod Nx
-  int iy;   // m_y mod Ny
+  int bx;   // m_x - min m_x over the sphere
+  int by;   // m_y - min m_y over the sphere
 };
 
-// U[b][x][y][s] = sum_{PW in z-slot s} c_b(PW) exp(2 pi i (m_x x/Nx + m_y y/Ny))
+// U[b][x][y][s] = sum_{PW with m_z = zlo + s} c_b(PW) exp(2 pi i (m_x x/Nx + m_y y/Ny)).
+// One workgroup per (band, z-slot): scatter the slot's plane waves into a dense
+// (m_y, m_x) box in LDS, transform along x, then along y; slots past the sphere's
+// z-extent are written as zeros.
 template <typename T, int NO>
 __global__ void __launch_bounds__(kBlock) orb_mixed(const cplx<T>* __restrict__ coef, int npw,
                                                      const SphereEntry* __restrict__ ent,
-                                                     const int* __restrict__ zoff, int nslot, int Nx,
-                                                     int Ny, cplx<T>* __restrict__ U) {
+                                                     const int* __restrict__ zoff, int nslot, int Nx, int Ny,
+                                                     int xlo, int nbx, int ylo, int nby,
+                                                     cplx<T>* __restrict__ U) {
   extern __shared__ unsigned char smem[];
   cplx<T>* twx = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* twy = twx + Nx;
-  cplx<T>* cs = twy + Ny;
-  int2* ixy = reinterpret_cast<int2*>(cs + npw);
+  cplx<T>* box = twy + Ny;        // [nby][nbx]
+  cplx<T>* V = box + nby * nbx;   // [nby][Nx]
   const int b = blockIdx.x;
+  const int s = blockIdx.y;
+  cplx<T>* ub = U + (size_t)b * Nx * Ny * NO + s;
+  if (s >= nslot) {
+    for (int xy = threadIdx.x; xy < Nx * Ny; xy += blockDim.x) ub[(size_t)xy * NO] = {T(0), T(0)};
+    return;
+  }
   load_twiddles(twx, Nx);
   load_twiddles(twy, Ny);
-  for (int p = threadIdx.x; p < npw; p += blockDim.x) {
-    SphereEntry e = ent[p];
-    cs[p] = coef[(size_t)b * npw + e.src];
-    ixy[p] = make_int2(e.ix, e.iy);
+  for (int e = threadIdx.x; e < nby * nbx; e += blockDim.x) box[e] = {T(0), T(0)};
+  __syncthreads();
+  const int p0 = zoff[s], p1 = zoff[s + 1];
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    const SphereEntry e = ent[p];
+    box[e.by * nbx + e.bx] = coef[(size_t)b * npw + e.src];
   }
   __syncthreads();
-  cplx<T>* ub = U + (size_t)b * Nx * Ny * NO;
+  // x transform: V[by][x] = sum_bx box[by][bx] exp(2 pi i (xlo + bx) x / Nx)
+  for (int it = threadIdx.x; it < nby * Nx; it += blockDim.x) {
+    const int by = it / Nx, x = it - (it / Nx) * Nx;
+    int k = pmod(xlo * x, Nx);
+    cplx<T> acc = {T(0), T(0)};
+    for (int bx = 0; bx < nbx; ++bx) {
+      cfma(acc, box[by * nbx + bx], twx[k]);
+      k += x;
+      if (k >= Nx) k -= Nx;
+    }
+    V[it] = acc;
+  }
+  __syncthreads();
+  // y transform: U[x][y][s] = sum_by V[by][x] exp(2 pi i (ylo + by) y / Ny)
   for (int xy = threadIdx.x; xy < Nx * Ny; xy += blockDim.x) {
     const int x = xy / Ny, y = xy - (xy / Ny) * Ny;
-    cplx<T>* out = ub + (size_t)xy * NO;
-#pragma unroll 1
-    for (int s = 0; s < NO; ++s) {
-      cplx<T> acc = {T(0), T(0)};
-      if (s < nslot) {
-        const int p1 = zoff[s + 1];
-        for (int p = zoff[s]; p < p1; ++p) {
-          int2 q = ixy[p];
-          cplx<T> ph = cmul(twx[(q.x * x) % Nx], twy[(q.y * y) % Ny]);
-          cfma(acc, cs[p], ph);
-        }
-      }
-      out[s] = acc;
+    int k = pmod(ylo * y, Ny);
+    cplx<T> acc = {T(0), T(0)};
+    for (int by = 0; by < nby; ++by) {
+      cfma(acc, V[by * Nx + x], twy[k]);
+      k += y;
+      if (k >= Ny) k -= Ny;
     }
+    ub[(size_t)xy * NO] = acc;
   }
 }
 
@@ -252,12 +271,12 @@ struct SphereTable {
   int nslot = 0;
 };
 
-static SphereTable sphere_table(const int32_t* m, int npw, const Extent& ex, int Nx, int Ny) {
+static SphereTable sphere_table(const int32_t* m, int npw, const Extent& ex) {
   SphereTable t;
   t.nslot = ex.hi[2] - ex.lo[2] + 1;
   std::vector<std::vector<SphereEntry>> by(t.nslot);
   for (int i = 0; i < npw; ++i)
-    by[m[3 * i + 2] - ex.lo[2]].push_back({i, pmod(m[3 * i], Nx), pmod(m[3 * i + 1], Ny)});
+    by[m[3 * i + 2] - ex.lo[2]].push_back({i, m[3 * i] - ex.lo[0], m[3 * i + 1] - ex.lo[1]});
   t.zoff.push_back(0);
   for (auto& v : by) {
     t.ent.insert(t.ent.end(), v.begin(), v.end());
@@ -267,13 +286,14 @@ static SphereTable sphere_table(const int32_t* m, int npw, const Extent& ex, int
 }
 
 template <typename T, int NO>
-static int launch_orb(const void* coef, int npw, int nb, const SphereTable& st, hipStream_t s,
-                      int Nx, int Ny, void* U) {
+static int launch_orb(const void* coef, int npw, int nb, const SphereTable& st, const Extent& ex,
+                      hipStream_t s, int Nx, int Ny, void* U) {
   const void* dent = nullptr;
   const void* dzoff = nullptr;
   XO_RET(device_table(st.ent.data(), st.ent.size() * sizeof(SphereEntry), s, &dent));
   XO_RET(device_table(st.zoff.data(), st.zoff.size() * sizeof(int), s, &dzoff));
-  size_t lds = (size_t)(Nx + Ny + npw) * sizeof(cplx<T>) + (size_t)npw * sizeof(int2);
+  const int nbx = ex.hi[0] - ex.lo[0] + 1, nby = ex.hi[1] - ex.lo[1] + 1;
+  size_t lds = (size_t)(Nx + Ny + nby * nbx + nby * Nx) * sizeof(cplx<T>);
   if (lds > 160 * 1024) {
     set_error("plane-wave sphere of %d coefficients does not fit in LDS", npw);
     return XO_ERR_UNSUPPORTED;
@@ -281,9 +301,13 @@ static int launch_orb(const void* coef, int npw, int nb, const SphereTable& st, 
   if (lds > 64 * 1024)
     XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&orb_mixed<T, NO>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((orb_mixed<T, NO>), dim3(nb), dim3(kBlock), lds, s,
-                     static_cast<const cplx<T>*>(coef), npw, static_cast<const SphereEntry*>(dent),
-                     static_cast<const int*>(dzoff), st.nslot, Nx, Ny, static_cast<cplx<T>*>(U));
+  {
+    KernelTimer kt_("orb_mixed", s);
+    hipLaunchKernelGGL((orb_mixed<T, NO>), dim3(nb, NO), dim3(kBlock), lds, s,
+                       static_cast<const cplx<T>*>(coef), npw, static_cast<const SphereEntry*>(dent),
+                       static_cast<const int*>(dzoff), st.nslot, Nx, Ny, ex.lo[0], nbx, ex.lo[1], nby,
+                       static_cast<cplx<T>*>(U));
+  }
   XO_CHECK_LAUNCH();
   return XO_OK;
 }
@@ -292,8 +316,8 @@ template <typename T, int NO>
 static int rho_run(const xo_rho_args* a, hipStream_t s, const Extent& xc, const Extent& xv,
                    const Extent& xe) {
   const int Nx = a->n[0], Ny = a->n[1];
-  SphereTable tc = sphere_table(a->mill_c, a->npw_c, xc, Nx, Ny);
-  SphereTable tv = sphere_table(a->mill_v, a->npw_v, xv, Nx, Ny);
+  SphereTable tc = sphere_table(a->mill_c, a->npw_c, xc);
+  SphereTable tv = sphere_table(a->mill_v, a->npw_v, xv);
 
   // needed (e_y, e_z) pairs and per-G selectors
   const int ezmin = xe.lo[2];
@@ -333,8 +357,8 @@ static int rho_run(const xo_rho_args* a, hipStream_t s, const Extent& xc, const 
   void* Uv = base + uc_bytes;
   void* S2 = base + uc_bytes + uv_bytes;
 
-  XO_RET((launch_orb<T, NO>(a->coef_c, a->npw_c, a->nc, tc, s, Nx, Ny, Uc)));
-  XO_RET((launch_orb<T, NO>(a->coef_v, a->npw_v, a->nv, tv, s, Nx, Ny, Uv)));
+  XO_RET((launch_orb<T, NO>(a->coef_c, a->npw_c, a->nc, tc, xc, s, Nx, Ny, Uc)));
+  XO_RET((launch_orb<T, NO>(a->coef_v, a->npw_v, a->nv, tv, xv, s, Nx, Ny, Uv)));
 
   int TV = std::min(a->nv, 8);
   auto lds_of = [&](int tvv) { return (size_t)(Ny + (size_t)tvv * Ny * nz4) * sizeof(cplx<T>); };
@@ -363,12 +387,18 @@ static int rho_run(const xo_rho_args* a, hipStream_t s, const Extent& xc, const 
     P.c0 = c0;
     P.ncc = n;
     P.S2 = S2;
-    hipLaunchKernelGGL((rho_zy<T, NO>), dim3((a->nv + TV - 1) / TV, n), dim3(kBlock), lds_of(TV), s, P);
+    {
+      KernelTimer kt_("rho_zy", s);
+      hipLaunchKernelGGL((rho_zy<T, NO>), dim3((a->nv + TV - 1) / TV, n), dim3(kBlock), lds_of(TV), s, P);
+    }
     XO_CHECK_LAUNCH();
-    hipLaunchKernelGGL((rho_x<T>), dim3((a->ng + kBlock - 1) / kBlock, n, a->nv), dim3(kBlock), 0, s,
-                       static_cast<const cplx<T>*>(S2), Nx, nyz, a->ng,
-                       static_cast<const int2*>(dgsel), n, c0, a->nc, (T)scale,
-                       static_cast<cplx<T>*>(a->rho));
+    {
+      KernelTimer kt_("rho_x", s);
+      hipLaunchKernelGGL((rho_x<T>), dim3((a->ng + kBlock - 1) / kBlock, n, a->nv), dim3(kBlock), 0, s,
+                         static_cast<const cplx<T>*>(S2), Nx, nyz, a->ng,
+                         static_cast<const int2*>(dgsel), n, c0, a->nc, (T)scale,
+                         static_cast<cplx<T>*>(a->rho));
+    }
     XO_CHECK_LAUNCH();
   }
 
@@ -388,16 +418,22 @@ static int rho_run(const xo_rho_args* a, hipStream_t s, const Extent& xc, const 
     const void* dproj = nullptr;
     XO_RET(device_table(proj.data(), proj.size() * sizeof(double), s, &dproj));
     const int n = a->nc * a->nv;
-    hipLaunchKernelGGL((rho_head_q0<T>), dim3((n + 255) / 256), dim3(256), 0, s,
-                       static_cast<const cplx<T>*>(a->coef_c), static_cast<const cplx<T>*>(a->coef_v),
-                       a->npw_c, static_cast<const double*>(dproj), a->e_c, a->e_v, a->nc, a->nv, a->ng,
-                       g0idx, static_cast<cplx<T>*>(a->rho));
+    {
+      KernelTimer kt_("rho_head_q0", s);
+      hipLaunchKernelGGL((rho_head_q0<T>), dim3((n + 255) / 256), dim3(256), 0, s,
+                         static_cast<const cplx<T>*>(a->coef_c), static_cast<const cplx<T>*>(a->coef_v),
+                         a->npw_c, static_cast<const double*>(dproj), a->e_c, a->e_v, a->nc, a->nv, a->ng,
+                         g0idx, static_cast<cplx<T>*>(a->rho));
+    }
     XO_CHECK_LAUNCH();
   }
   if (a->dE) {
     const int n = a->nc * a->nv;
-    hipLaunchKernelGGL(pole_energies, dim3((n + 255) / 256), dim3(256), 0, s, a->e_c, a->e_v, a->nc,
-                       a->nv, a->dE);
+    {
+      KernelTimer kt_("pole_energies", s);
+      hipLaunchKernelGGL(pole_energies, dim3((n + 255) / 256), dim3(256), 0, s, a->e_c, a->e_v, a->nc,
+                         a->nv, a->dE);
+    }
     XO_CHECK_LAUNCH();
   }
   return XO_OK;

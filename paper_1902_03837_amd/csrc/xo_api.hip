@@ -137,9 +137,79 @@ int device_table(const void* host, size_t bytes, hipStream_t s, const void** out
   return XO_OK;
 }
 
+static bool g_timing = false;
+struct TimedEvent {
+  std::string name;
+  hipEvent_t a, b;
+};
+static std::vector<TimedEvent> g_events;
+static std::vector<hipEvent_t> g_pool;
+
+static hipEvent_t pool_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+KernelTimer::KernelTimer(const char* n, hipStream_t st) : name(n), s(st) {
+  if (!g_timing) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  a = pool_get();
+  b = pool_get();
+  if (a) (void)hipEventRecord(a, s);
+}
+
+KernelTimer::~KernelTimer() {
+  if (!a || !b) return;
+  (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_events.push_back({name, a, b});
+}
+
 }  // namespace xo
 
 extern "C" {
+
+int xo_timing_enable(int on) {
+  xo::g_timing = on != 0;
+  return XO_OK;
+}
+
+int xo_timing_report(char* buf, int len) {
+  std::lock_guard<std::mutex> lk(xo::g_mu);
+  std::map<std::string, std::pair<int, double>> acc;
+  std::vector<std::string> order;
+  for (auto& e : xo::g_events) {
+    float ms = 0.f;
+    hipError_t r = hipEventSynchronize(e.b);
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.a, e.b);
+    if (r != hipSuccess) {
+      xo::set_error("timing event failed: %s", hipGetErrorString(r));
+      return XO_ERR_HIP;
+    }
+    if (!acc.count(e.name)) order.push_back(e.name);
+    acc[e.name].first += 1;
+    acc[e.name].second += ms;
+    xo::g_pool.push_back(e.a);
+    xo::g_pool.push_back(e.b);
+  }
+  xo::g_events.clear();
+  std::string out;
+  for (auto& n : order) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s %d %.6f\n", n.c_str(), acc[n].first, acc[n].second);
+    out += line;
+  }
+  if (buf && len > 0) {
+    snprintf(buf, (size_t)len, "%s", out.c_str());
+  }
+  return XO_OK;
+}
 
 const char* xo_last_error(void) { return xo::g_err; }
 

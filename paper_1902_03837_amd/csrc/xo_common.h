@@ -66,6 +66,15 @@ int host_flags(hipStream_t s, size_t bytes, void** out);
 // keyed by content. Returned pointer stays valid until xo_release_workspace.
 int device_table(const void* host, size_t bytes, hipStream_t s, const void** out);
 
+// Event bracket around one kernel launch when timing is enabled (no-op otherwise).
+struct KernelTimer {
+  KernelTimer(const char* name, hipStream_t s);
+  ~KernelTimer();
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ----------------------------------------------------------- device math --

@@ -62,7 +62,8 @@ class XoError(RuntimeError):
 
 _LIB = None
 
-EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_rho", "xo_chi0", "xo_epsinv")
+EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
+           "xo_rho", "xo_chi0", "xo_epsinv")
 
 
 def lib():
@@ -79,6 +80,10 @@ def lib():
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
         L.xo_release_workspace.restype = C.c_int
+        L.xo_timing_enable.argtypes = [C.c_int]
+        L.xo_timing_enable.restype = C.c_int
+        L.xo_timing_report.argtypes = [C.c_char_p, C.c_int]
+        L.xo_timing_report.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -112,6 +117,21 @@ def version() -> str:
 
 def release_workspace():
     _check(lib().xo_release_workspace())
+
+
+def timing_enable(on: bool = True):
+    _check(lib().xo_timing_enable(1 if on else 0))
+
+
+def timing_report() -> dict:
+    """{kernel: (launches, total_ms)} since the last report (synchronises)."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().xo_timing_report(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
+    return out
 
 
 def _cdtype(prec):
