@@ -91,7 +91,7 @@ int xo_timing_report(char* buf, int len);
 typedef struct {
   int n[3];                 /* FFT grid                                        */
   double bvec[9];           /* [host] rows b1,b2,b3 in 1/bohr (q0 velocities)  */
-  int prec;                 /* XO_FP64 / XO_FP32 (XO_BF16X3 computes as FP32)   */
+  int prec;                 /* XO_FP64 / XO_FP32 / XO_BF16X3 (see xo_rho_batch) */
   /* bra: conduction bands at k */
   int npw_c;
   const int32_t* mill_c;    /* [host] [npw_c][3]                               */
@@ -117,6 +117,17 @@ typedef struct {
 } xo_rho_args;
 
 int xo_rho(const xo_rho_args* a, void* stream);
+
+/* Several k-pairs in one call, with the same semantics as calling xo_rho on each
+ * pair in order (each pair's output slice is written exactly as xo_rho writes
+ * it). pairs: [host] array of npairs argument blocks. With prec XO_BF16X3 and
+ * no q0 pair, pairs that share the grid and the G-set run in one MFMA launch:
+ * orbitals become split bf16 (hi + lo) in real space along x and y, and the
+ * z-correlation and pruned y-transform are bf16 x 3 matrix products with FP32
+ * accumulation; the x-transform accumulates in FP32 (G-sets up to 1024 vectors,
+ * x axis up to 72 points, sphere z-extent up to 32). Other batches, and
+ * XO_BF16X3 batches outside those limits, run the FP32 path pair by pair. */
+int xo_rho_batch(const xo_rho_args* pairs, int npairs, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* chi0 at imaginary frequencies, Eq. (X_IP) with the App. A split into the

@@ -21,13 +21,12 @@
 #include <cmath>
 #include <vector>
 
-#include "xo_common.h"
+#include "rho_geom.h"
 
 namespace xo {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxAxis = 128;
 
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw, int n) {
@@ -38,11 +37,7 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw, int n) {
   }
 }
 
-struct SphereEntry {
-  int src;  // index of the plane wave in the caller's coefficient row
-  int bx;   // m_x - min m_x over the sphere
-  int by;   // m_y - min m_y over the sphere
-};
+
 
 // U[b][x][y][s] = sum_{PW with m_z = zlo + s} c_b(PW) exp(2 pi i (m_x x/Nx + m_y y/Ny)).
 // One workgroup per (band, z-slot): scatter the slot's plane waves into a dense
@@ -246,45 +241,6 @@ __global__ void rho_head_q0(const cplx<T>* __restrict__ cc, const cplx<T>* __res
 
 // ------------------------------------------------------------------ host side
 
-struct Extent {
-  int lo[3], hi[3];
-};
-
-static Extent extent_of(const int32_t* m, int n, const int* shift) {
-  Extent e;
-  for (int a = 0; a < 3; ++a) {
-    e.lo[a] = 1 << 30;
-    e.hi[a] = -(1 << 30);
-  }
-  for (int i = 0; i < n; ++i)
-    for (int a = 0; a < 3; ++a) {
-      int v = m[3 * i + a] - (shift ? shift[a] : 0);
-      e.lo[a] = std::min(e.lo[a], v);
-      e.hi[a] = std::max(e.hi[a], v);
-    }
-  return e;
-}
-
-struct SphereTable {
-  std::vector<SphereEntry> ent;
-  std::vector<int> zoff;
-  int nslot = 0;
-};
-
-static SphereTable sphere_table(const int32_t* m, int npw, const Extent& ex) {
-  SphereTable t;
-  t.nslot = ex.hi[2] - ex.lo[2] + 1;
-  std::vector<std::vector<SphereEntry>> by(t.nslot);
-  for (int i = 0; i < npw; ++i)
-    by[m[3 * i + 2] - ex.lo[2]].push_back({i, m[3 * i] - ex.lo[0], m[3 * i + 1] - ex.lo[1]});
-  t.zoff.push_back(0);
-  for (auto& v : by) {
-    t.ent.insert(t.ent.end(), v.begin(), v.end());
-    t.zoff.push_back((int)t.ent.size());
-  }
-  return t;
-}
-
 template <typename T, int NO>
 static int launch_orb(const void* coef, int npw, int nb, const SphereTable& st, const Extent& ex,
                       hipStream_t s, int Nx, int Ny, void* U) {
@@ -453,11 +409,10 @@ static int rho_dispatch(const xo_rho_args* a, hipStream_t s, const Extent& xc, c
 }  // namespace
 }  // namespace xo
 
-extern "C" int xo_rho(const xo_rho_args* a, void* stream) {
-  using namespace xo;
-  clear_error();
+namespace xo {
+
+int validate_rho(const xo_rho_args* a, Extent* pxc, Extent* pxv, Extent* pxe) {
   XO_ARG(a, "xo_rho: null argument block");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   for (int i = 0; i < 3; ++i) {
     XO_ARG(a->n[i] > 0, "xo_rho: grid axis %d is %d", i, a->n[i]);
     if (a->n[i] > kMaxAxis) {
@@ -497,6 +452,18 @@ extern "C" int xo_rho(const xo_rho_args* a, void* stream) {
     double qn = a->qhat[0] * a->qhat[0] + a->qhat[1] * a->qhat[1] + a->qhat[2] * a->qhat[2];
     XO_ARG(qn > 0, "xo_rho: q0 requires a nonzero qhat");
   }
+  *pxc = xc;
+  *pxv = xv;
+  *pxe = xe;
+  return XO_OK;
+}
+
+// VALU path for one pair (FP64 and FP32).
+int rho_valu(const xo_rho_args* a, hipStream_t s) {
+  Extent xc, xv, xe;
+  XO_RET(validate_rho(a, &xc, &xv, &xe));
   if (a->prec == XO_FP64) return rho_dispatch<double>(a, s, xc, xv, xe);
   return rho_dispatch<float>(a, s, xc, xv, xe);
 }
+
+}  // namespace xo

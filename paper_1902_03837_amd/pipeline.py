@@ -48,20 +48,29 @@ def ntrans(cr, nempty=None, band_lo=None) -> int:
 
 
 def rho_all(dc: DeviceCrystal, M: torch.Tensor, dE: torch.Tensor, nempty=None, band_lo=None,
-            qhat=(1.0, 0.0, 0.0), rho_prec=None, stream=None):
-    """Fill M[K][ng] and dE[K] for every pair (transition t = v * nc + c within a pair)."""
+            qhat=(1.0, 0.0, 0.0), rho_prec=None, stream=None, batch=True):
+    """Fill M[K][ng] and dE[K] for every pair (transition t = v * nc + c within a pair).
+
+    batch=True passes every pair to one xo_rho_batch call; batch=False calls xo_rho per pair.
+    """
     cr = dc.cr
     ng = cr.gmill.shape[0]
     off = 0
+    calls = []
     for ik, ikp, g0, lo, hi, nv in band_ranges(cr, nempty, band_lo):
         nc = hi - lo
         n = nc * nv
-        xo.rho(dc.coef[ik][lo:hi], cr.mill[ik], dc.eps[ik][lo:hi],
-               dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv],
-               cr.gmill, g0, cr.grid, out=M[off:off + n].view(nv, nc, ng), dE=dE[off:off + n],
-               prec=rho_prec or dc.prec, kcart=cr.kcart(ik), bvec=cr.lat.bvec, q0=cr.q0, qhat=qhat,
-               stream=stream)
+        calls.append(dict(coef_c=dc.coef[ik][lo:hi], mill_c=cr.mill[ik], e_c=dc.eps[ik][lo:hi],
+                          coef_v=dc.coef[ikp][:nv], mill_v=cr.mill[ikp], e_v=dc.eps[ikp][:nv],
+                          gmill=cr.gmill, g0=g0, grid=cr.grid, out=M[off:off + n].view(nv, nc, ng),
+                          dE=dE[off:off + n], prec=rho_prec or dc.prec, kcart=cr.kcart(ik), bvec=cr.lat.bvec,
+                          q0=cr.q0, qhat=qhat))
         off += n
+    if batch:
+        xo.rho_batch(calls, stream=stream)
+    else:
+        for kw in calls:
+            xo.rho(**kw, stream=stream)
     return off
 
 

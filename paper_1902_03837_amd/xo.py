@@ -63,7 +63,7 @@ class XoError(RuntimeError):
 _LIB = None
 
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
-           "xo_rho", "xo_chi0", "xo_epsinv")
+           "xo_rho", "xo_rho_batch", "xo_chi0", "xo_epsinv")
 
 
 def lib():
@@ -79,6 +79,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
+        L.xo_rho_batch.argtypes = [C.POINTER(RhoArgs), C.c_int, C.c_void_p]
+        L.xo_rho_batch.restype = C.c_int
         L.xo_release_workspace.restype = C.c_int
         L.xo_timing_enable.argtypes = [C.c_int]
         L.xo_timing_enable.restype = C.c_int
@@ -139,9 +141,9 @@ def _cdtype(prec):
     return torch.complex128 if (PREC[prec] if isinstance(prec, str) else int(prec)) == XO_FP64 else torch.complex64
 
 
-def rho(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=None,
-        prec="fp64", kcart=(0., 0., 0.), bvec=None, q0=False, qhat=(1., 0., 0.), stream=None):
-    """xo_rho for one k-pair: out[nv][nc][ng] (and dE[nv][nc] if given)."""
+def _rho_args(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=None,
+              prec="fp64", kcart=(0., 0., 0.), bvec=None, q0=False, qhat=(1., 0., 0.)):
+    """Checked argument block for one k-pair (returns it with the host arrays it points to)."""
     import torch
     mc, mv, mg = _host_i32(mill_c), _host_i32(mill_v), _host_i32(gmill)
     cdt = _cdtype(prec)
@@ -170,8 +172,23 @@ def rho(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=No
     a.q0 = 1 if q0 else 0
     a.qhat[:] = [float(x) for x in qhat]
     a.rho, a.dE = _ptr(out), _ptr(dE)
+    return a, (mc, mv, mg)
+
+
+def rho(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=None,
+        prec="fp64", kcart=(0., 0., 0.), bvec=None, q0=False, qhat=(1., 0., 0.), stream=None):
+    """xo_rho for one k-pair: out[nv][nc][ng] (and dE[nv][nc] if given)."""
+    a, keep = _rho_args(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, out=out, dE=dE,
+                        prec=prec, kcart=kcart, bvec=bvec, q0=q0, qhat=qhat)
     _check(lib().xo_rho(C.byref(a), _stream(stream)))
     return out
+
+
+def rho_batch(pairs, stream=None):
+    """xo_rho_batch over a list of keyword dicts, each as for rho()."""
+    built = [_rho_args(**kw) for kw in pairs]
+    arr = (RhoArgs * len(built))(*[b[0] for b in built])
+    _check(lib().xo_rho_batch(arr, len(built), _stream(stream)))
 
 
 def chi0(rho_m, dE, omegas: Sequence[float], pref: float, *, out, prec="fp64", accumulate=False,

@@ -41,7 +41,7 @@ def _to(a, dt=torch.complex128):
 # ----------------------------------------------------------------------------- rho
 
 @pytest.mark.parametrize("name", ["c1", "c2_small"])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6), ("bf16x3", 5e-5)])
 def test_rho_parity(name, prec, tol):
     cr = crystal_for(name)
     say(f"rho parity {name} {prec}")
@@ -58,6 +58,23 @@ def test_rho_parity(name, prec, tol):
     say(f"  max rel err {err:.3e}")
     assert err < tol
     assert np.array_equal(dE.cpu().numpy(), dEr)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_rho_batch_equals_per_pair(prec):
+    cr = crystal_for("c2_small")
+    say(f"rho batch vs per-pair {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    K = ntrans(cr)
+    ng = cr.gmill.shape[0]
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    M1 = torch.empty((K, ng), dtype=cdt, device=DEV)
+    M2 = torch.empty_like(M1)
+    d1 = torch.empty(K, dtype=torch.float64, device=DEV)
+    d2 = torch.empty_like(d1)
+    rho_all(dc, M1, d1, batch=True)
+    rho_all(dc, M2, d2, batch=False)
+    assert torch.equal(M1, M2) and torch.equal(d1, d2)
 
 
 def test_rho_q0_head_parity():
