@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "rho_geom.h"
@@ -75,67 +76,88 @@ struct OrbSide {
   int xlo, nbx, ylo, nby;
 };
 
-// U[b][x][y][s] as split bf16 pairs; one workgroup per (band, z-slot, side).
+// U[b][x][y][s] as split bf16 pairs. One workgroup per (band, side): for z-slots
+// in chunks of 8, scatter the plane waves into dense (m_y, m_x) boxes in LDS,
+// transform along x, then along y, and write each (x, y)'s chunk contiguously.
+constexpr int kSC = 8;
+
 template <int NO>
-__global__ void __launch_bounds__(kBlock) orb_split(const OrbSide* __restrict__ sides, int Nx, int Ny) {
+__global__ void __launch_bounds__(kBlock) orb_split(const OrbSide* __restrict__ sides, int Nx, int Ny,
+                                                    const float2* __restrict__ twt) {
   extern __shared__ unsigned char smem[];
-  const OrbSide S = sides[blockIdx.z];
-  const int b = blockIdx.x, s = blockIdx.y;
+  const OrbSide S = sides[blockIdx.y];
+  const int b = blockIdx.x;
   if (b >= S.nb) return;
-  float2* twx = reinterpret_cast<float2*>(smem);
+  float2* twx = reinterpret_cast<float2*>(smem);  // [Nx] then [Ny]
   float2* twy = twx + Nx;
-  float2* box = twy + Ny;
-  float2* V = box + S.nby * S.nbx;
-  const size_t ub = (size_t)b * Nx * Ny * NO + s;
-  if (s >= S.nslot) {
+  float2* box = twy + Ny;                        // [kSC][nby][nbx]
+  float2* V = box + kSC * S.nby * S.nbx;         // [kSC][nby][Nx]
+  const int nbb = S.nby * S.nbx;
+  for (int k = threadIdx.x; k < Nx + Ny; k += blockDim.x) twx[k] = twt[k];
+  uint32_t* uh = S.Uhi + (size_t)b * Nx * Ny * NO;
+  uint32_t* ul = S.Ulo + (size_t)b * Nx * Ny * NO;
+  for (int s0 = 0; s0 < NO; s0 += kSC) {
+    if (s0 >= S.nslot) {
+      for (int i = threadIdx.x; i < Nx * Ny * kSC; i += blockDim.x) {
+        const int xy = i / kSC, j = i - (i / kSC) * kSC;
+        uh[(size_t)xy * NO + s0 + j] = 0u;
+        ul[(size_t)xy * NO + s0 + j] = 0u;
+      }
+      continue;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kSC * nbb; e += blockDim.x) box[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const int s1 = min(s0 + kSC, S.nslot);
+    for (int p = S.zoff[s0] + threadIdx.x; p < S.zoff[s1]; p += blockDim.x) {
+      const SphereEntry e = S.ent[p];
+      // slot of plane wave p: the z-slot whose [zoff[s], zoff[s+1]) range holds p
+      int j = 0;
+      while (S.zoff[s0 + j + 1] <= p) ++j;
+      box[j * nbb + e.by * S.nbx + e.bx] = S.coef[(size_t)b * S.npw + e.src];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < kSC * S.nby * Nx; it += blockDim.x) {
+      const int x = it % Nx, jb = it / Nx;           // jb = j * nby + by
+      int k = pmod(S.xlo * x, Nx);
+      const float2* row = box + jb * S.nbx;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int bx = 0; bx < S.nbx; ++bx) {
+        const float2 c = row[bx], w = twx[k];
+        acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
+        acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
+        k += x;
+        if (k >= Nx) k -= Nx;
+      }
+      V[jb * Nx + x] = acc;
+    }
+    __syncthreads();
     for (int xy = threadIdx.x; xy < Nx * Ny; xy += blockDim.x) {
-      S.Uhi[ub + (size_t)xy * NO] = 0u;
-      S.Ulo[ub + (size_t)xy * NO] = 0u;
+      const int x = xy / Ny, y = xy - (xy / Ny) * Ny;
+      const int k0 = pmod(S.ylo * y, Ny);
+      uint32_t hv[kSC], lv[kSC];
+#pragma unroll
+      for (int j = 0; j < kSC; ++j) {
+        int k = k0;
+        float2 acc = make_float2(0.f, 0.f);
+        if (s0 + j < S.nslot) {
+          for (int by = 0; by < S.nby; ++by) {
+            const float2 c = V[(j * S.nby + by) * Nx + x], w = twy[k];
+            acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
+            acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
+            k += y;
+            if (k >= Ny) k -= Ny;
+          }
+        }
+        split2(acc.x, acc.y, hv[j], lv[j]);
+      }
+      u4* dh = reinterpret_cast<u4*>(uh + (size_t)xy * NO + s0);
+      u4* dl = reinterpret_cast<u4*>(ul + (size_t)xy * NO + s0);
+      dh[0] = u4{hv[0], hv[1], hv[2], hv[3]};
+      dh[1] = u4{hv[4], hv[5], hv[6], hv[7]};
+      dl[0] = u4{lv[0], lv[1], lv[2], lv[3]};
+      dl[1] = u4{lv[4], lv[5], lv[6], lv[7]};
     }
-    return;
-  }
-  for (int k = threadIdx.x; k < Nx + Ny; k += blockDim.x) {
-    const int n = k < Nx ? Nx : Ny, kk = k < Nx ? k : k - Nx;
-    double sn, cs;
-    sincospi(2.0 * kk / n, &sn, &cs);
-    twx[k] = make_float2((float)cs, (float)sn);
-  }
-  for (int e = threadIdx.x; e < S.nby * S.nbx; e += blockDim.x) box[e] = make_float2(0.f, 0.f);
-  __syncthreads();
-  for (int p = S.zoff[s] + threadIdx.x; p < S.zoff[s + 1]; p += blockDim.x) {
-    const SphereEntry e = S.ent[p];
-    box[e.by * S.nbx + e.bx] = S.coef[(size_t)b * S.npw + e.src];
-  }
-  __syncthreads();
-  for (int it = threadIdx.x; it < S.nby * Nx; it += blockDim.x) {
-    const int by = it / Nx, x = it - (it / Nx) * Nx;
-    int k = pmod(S.xlo * x, Nx);
-    float2 acc = make_float2(0.f, 0.f);
-    for (int bx = 0; bx < S.nbx; ++bx) {
-      const float2 c = box[by * S.nbx + bx], w = twx[k];
-      acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
-      acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
-      k += x;
-      if (k >= Nx) k -= Nx;
-    }
-    V[it] = acc;
-  }
-  __syncthreads();
-  for (int xy = threadIdx.x; xy < Nx * Ny; xy += blockDim.x) {
-    const int x = xy / Ny, y = xy - (xy / Ny) * Ny;
-    int k = pmod(S.ylo * y, Ny);
-    float2 acc = make_float2(0.f, 0.f);
-    for (int by = 0; by < S.nby; ++by) {
-      const float2 c = V[by * Nx + x], w = twy[k];
-      acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
-      acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
-      k += y;
-      if (k >= Ny) k -= Ny;
-    }
-    uint32_t hi, lo;
-    split2(acc.x, acc.y, hi, lo);
-    S.Uhi[ub + (size_t)xy * NO] = hi;
-    S.Ulo[ub + (size_t)xy * NO] = lo;
   }
 }
 
@@ -152,9 +174,9 @@ struct PairDesc {
 };
 
 template <int NK, int GPT>
-__global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ pairs, int npairs, int Nx,
-                                                   int Ny, int Nyp, int ng, const float2* __restrict__ twtab,
-                                                   float scale) {
+__global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ pairs, int npairs, int nwg,
+                                                   int Nx, int Ny, int Nyp, int ng,
+                                                   const float2* __restrict__ twtab, float scale) {
   constexpr int NO = 16 * NK;
   constexpr int LW = NO + 2 * kLP;
   extern __shared__ uint32_t lds[];
@@ -166,13 +188,19 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
   float2* twx = reinterpret_cast<float2*>(S1lo + 4096);  // [Nx e][Nx x]
   int* gt = reinterpret_cast<int*>(twx + Nx * Nx);       // [ng]
 
+  // XCD-aware order: hardware dispatches workgroup b to XCD b % 8, so XCD x gets
+  // the contiguous logical range [x * per, (x + 1) * per) and works through whole
+  // k-pairs, keeping each pair's valence orbitals resident in that XCD's L2.
+  const int per = (nwg + 7) >> 3;
+  const int L = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (L >= nwg) return;
   int lo = 0, hi = npairs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (pairs[mid].wg0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    if (pairs[mid].wg0 <= L) lo = mid; else hi = mid - 1;
   }
   const PairDesc P = pairs[lo];
-  const int local = blockIdx.x - P.wg0;
+  const int local = L - P.wg0;
   const int c = local / P.nvt, vt = local - (local / P.nvt) * P.nvt;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, l16 = l & 15, q = l >> 4;
   const int vo = tid & 15, gq = tid >> 4;
@@ -297,12 +325,20 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
   }
 }
 
-__global__ void pole_energies_b(const double* __restrict__ ec, const double* __restrict__ ev, int nc, int nv,
-                                double* __restrict__ dE) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc * nv) return;
-  const int v = i / nc, c = i - (i / nc) * nc;
-  dE[i] = ec[c] - ev[v];
+struct PoleDesc {
+  const double* ec;
+  const double* ev;
+  double* dE;
+  int nc, nv;
+};
+
+// dE[v][c] = e_c - e_v for every pair of the batch (blockIdx.y = pair).
+__global__ void pole_energies_b(const PoleDesc* __restrict__ pd) {
+  const PoleDesc P = pd[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.nc * P.nv; i += gridDim.x * blockDim.x) {
+    const int v = i / P.nc, c = i - (i / P.nc) * P.nc;
+    P.dE[i] = P.ec[c] - P.ev[v];
+  }
 }
 
 // ------------------------------------------------------------------ host --
@@ -381,6 +417,39 @@ static Geo make_geo(const xo_rho_args* a, int Nx, int Ny, int Nyp) {
   return g;
 }
 
+// Device geometry per (grid, G-set, G0), built once per process and device.
+struct DevGeo {
+  const void* F = nullptr;
+  const void* gtab = nullptr;
+  int nz = 0;
+};
+
+static int dev_geo(const xo_rho_args* a, int Nx, int Ny, int Nyp, hipStream_t s, const DevGeo** out) {
+  static std::mutex mu;
+  static std::map<std::vector<int>, DevGeo> cache;
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  std::vector<int> key = {dev, Nx, Ny, a->g0[0], a->g0[1], a->g0[2]};
+  key.insert(key.end(), a->mill_g, a->mill_g + 3 * a->ng);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    *out = it->second.nz ? &it->second : nullptr;
+    return XO_OK;
+  }
+  Geo g = make_geo(a, Nx, Ny, Nyp);
+  DevGeo d;
+  if (g.ok) {
+    XO_RET(device_table(g.F.data(), g.F.size() * sizeof(uint32_t), s, &d.F));
+    XO_RET(device_table(g.gtab.data(), g.gtab.size() * sizeof(int), s, &d.gtab));
+    d.nz = g.nz;
+  }
+  auto& slot = cache[key];
+  slot = d;
+  *out = d.nz ? &slot : nullptr;
+  return XO_OK;
+}
+
 template <int NK, int GPT>
 static int launch_rho(const void* dpairs, int npairs, int nwg, int Nx, int Ny, int Nyp, int ng, const void* dtw,
                       hipStream_t s, size_t lds) {
@@ -389,8 +458,8 @@ static int launch_rho(const void* dpairs, int npairs, int nwg, int Nx, int Ny, i
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
     KernelTimer kt_("rho_mfma", s);
-    hipLaunchKernelGGL((rho_mfma<NK, GPT>), dim3(nwg), dim3(kBlock), lds, s,
-                       static_cast<const PairDesc*>(dpairs), npairs, Nx, Ny, Nyp, ng,
+    hipLaunchKernelGGL((rho_mfma<NK, GPT>), dim3(8 * ((nwg + 7) / 8)), dim3(kBlock), lds, s,
+                       static_cast<const PairDesc*>(dpairs), npairs, nwg, Nx, Ny, Nyp, ng,
                        static_cast<const float2*>(dtw), (float)(1.0 / ((double)Nx * Ny)));
   }
   XO_CHECK_LAUNCH();
@@ -436,14 +505,11 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   for (int i = 0; i < n; ++i) {
     auto key = std::make_tuple(p[i].g0[0], p[i].g0[1], p[i].g0[2]);
     if (geos.count(key)) continue;
-    Geo g = make_geo(&p[i], Nx, Ny, Nyp);
-    if (!g.ok) return XO_ERR_UNSUPPORTED;
-    const void* dF = nullptr;
-    const void* dg = nullptr;
-    XO_RET(device_table(g.F.data(), g.F.size() * sizeof(uint32_t), s, &dF));
-    XO_RET(device_table(g.gtab.data(), g.gtab.size() * sizeof(int), s, &dg));
-    geos[key] = {dF, dg};
-    nzs[key] = g.nz;
+    const DevGeo* dg = nullptr;
+    XO_RET(dev_geo(&p[i], Nx, Ny, Nyp, s, &dg));
+    if (!dg) return XO_ERR_UNSUPPORTED;
+    geos[key] = {dg->F, dg->gtab};
+    nzs[key] = dg->nz;
   }
   std::vector<float2> tw((size_t)Nx * Nx);
   for (int e = 0; e < Nx; ++e)
@@ -453,6 +519,14 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     }
   const void* dtw = nullptr;
   XO_RET(device_table(tw.data(), tw.size() * sizeof(float2), s, &dtw));
+  std::vector<float2> twxy(Nx + Ny);
+  for (int k = 0; k < Nx + Ny; ++k) {
+    const int nn = k < Nx ? Nx : Ny, kk = k < Nx ? k : k - Nx;
+    const double th = 2.0 * M_PI * kk / nn;
+    twxy[k] = make_float2((float)std::cos(th), (float)std::sin(th));
+  }
+  const void* dtwxy = nullptr;
+  XO_RET(device_table(twxy.data(), twxy.size() * sizeof(float2), s, &dtwxy));
 
   // workspace: split orbitals of every pair
   const size_t plane = (size_t)Nx * Ny * NO;
@@ -491,7 +565,7 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
       o.ylo = ex.lo[1];
       o.nby = ex.hi[1] - ex.lo[1] + 1;
       maxnb = std::max(maxnb, o.nb);
-      orb_lds = std::max(orb_lds, (size_t)(Nx + Ny + o.nby * o.nbx + o.nby * Nx) * sizeof(float2));
+      orb_lds = std::max(orb_lds, (size_t)(Nx + Ny + kSC * (o.nby * o.nbx + o.nby * Nx)) * sizeof(float2));
     }
   }
   const void* dsides = nullptr;
@@ -503,11 +577,11 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
       XO_TRY_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)orb_lds));
     KernelTimer kt_("orb_split", s);
     if (NO == 16)
-      hipLaunchKernelGGL(orb_split<16>, dim3(maxnb, NO, 2 * n), dim3(kBlock), orb_lds, s,
-                         static_cast<const OrbSide*>(dsides), Nx, Ny);
+      hipLaunchKernelGGL(orb_split<16>, dim3(maxnb, 2 * n), dim3(kBlock), orb_lds, s,
+                         static_cast<const OrbSide*>(dsides), Nx, Ny, static_cast<const float2*>(dtwxy));
     else
-      hipLaunchKernelGGL(orb_split<32>, dim3(maxnb, NO, 2 * n), dim3(kBlock), orb_lds, s,
-                         static_cast<const OrbSide*>(dsides), Nx, Ny);
+      hipLaunchKernelGGL(orb_split<32>, dim3(maxnb, 2 * n), dim3(kBlock), orb_lds, s,
+                         static_cast<const OrbSide*>(dsides), Nx, Ny, static_cast<const float2*>(dtwxy));
   }
   XO_CHECK_LAUNCH();
 
@@ -541,13 +615,20 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   else
     XO_RET(launch_rho_g<2>(dpairs, n, nwg, Nx, Ny, Nyp, ng, dtw, s, lds));
 
+  std::vector<PoleDesc> poles;
+  int maxm = 0;
   for (int i = 0; i < n; ++i) {
     if (!p[i].dE) continue;
-    const int m = p[i].nc * p[i].nv;
+    poles.push_back({p[i].e_c, p[i].e_v, p[i].dE, p[i].nc, p[i].nv});
+    maxm = std::max(maxm, p[i].nc * p[i].nv);
+  }
+  if (!poles.empty()) {
+    const void* dpoles = nullptr;
+    XO_RET(device_table(poles.data(), poles.size() * sizeof(PoleDesc), s, &dpoles));
     {
       KernelTimer kt_("pole_energies", s);
-      hipLaunchKernelGGL(pole_energies_b, dim3((m + 255) / 256), dim3(256), 0, s, p[i].e_c, p[i].e_v, p[i].nc,
-                         p[i].nv, p[i].dE);
+      hipLaunchKernelGGL(pole_energies_b, dim3(std::min(64, (maxm + 255) / 256), (unsigned)poles.size()),
+                         dim3(256), 0, s, static_cast<const PoleDesc*>(dpoles));
     }
     XO_CHECK_LAUNCH();
   }

@@ -99,12 +99,22 @@ int host_flags(hipStream_t s, size_t bytes, void** out) {
   return XO_OK;
 }
 
-static uint64_t fnv1a(const void* p, size_t n) {
+// Content hash for the table cache: 64-bit multiply-xorshift over 8-byte words
+// (a mismatch only costs a memcmp, equality is always checked in full).
+static uint64_t content_hash(const void* p, size_t n) {
   const unsigned char* c = static_cast<const unsigned char*>(p);
-  uint64_t h = 1469598103934665603ull;
-  for (size_t i = 0; i < n; ++i) {
+  uint64_t h = 0x9e3779b97f4a7c15ull ^ n;
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    memcpy(&w, c + i, 8);
+    h ^= w;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 32;
+  }
+  for (; i < n; ++i) {
     h ^= c[i];
-    h *= 1099511628211ull;
+    h *= 0xc4ceb9fe1a85ec53ull;
   }
   return h;
 }
@@ -112,7 +122,7 @@ static uint64_t fnv1a(const void* p, size_t n) {
 int device_table(const void* host, size_t bytes, hipStream_t s, const void** out) {
   int dev = 0;
   XO_TRY_HIP(hipGetDevice(&dev));
-  uint64_t h = fnv1a(host, bytes);
+  uint64_t h = content_hash(host, bytes);
   std::lock_guard<std::mutex> lk(g_mu);
   auto& bucket = g_tables[std::make_tuple(dev, h, bytes)];
   for (auto& t : bucket) {

@@ -24,6 +24,11 @@ class DeviceCrystal:
     prec: str
     coef: List[torch.Tensor]
     eps: List[torch.Tensor]
+    plans: dict = None
+
+    def __post_init__(self):
+        if self.plans is None:
+            self.plans = {}
 
     @classmethod
     def upload(cls, cr, prec="fp64", device="cuda"):
@@ -55,6 +60,11 @@ def rho_all(dc: DeviceCrystal, M: torch.Tensor, dE: torch.Tensor, nempty=None, b
     """
     cr = dc.cr
     ng = cr.gmill.shape[0]
+    key = (M.data_ptr(), dE.data_ptr(), nempty, band_lo, tuple(qhat), rho_prec, batch)
+    plan = dc.plans.get(key)
+    if plan is not None:
+        xo.launch_plan(plan, stream=stream)
+        return plan.ntrans
     off = 0
     calls = []
     for ik, ikp, g0, lo, hi, nv in band_ranges(cr, nempty, band_lo):
@@ -66,11 +76,9 @@ def rho_all(dc: DeviceCrystal, M: torch.Tensor, dE: torch.Tensor, nempty=None, b
                           dE=dE[off:off + n], prec=rho_prec or dc.prec, kcart=cr.kcart(ik), bvec=cr.lat.bvec,
                           q0=cr.q0, qhat=qhat))
         off += n
-    if batch:
-        xo.rho_batch(calls, stream=stream)
-    else:
-        for kw in calls:
-            xo.rho(**kw, stream=stream)
+    plan = xo.RhoPlan(calls, batch, off)
+    dc.plans[key] = plan
+    xo.launch_plan(plan, stream=stream)
     return off
 
 

@@ -184,6 +184,25 @@ def rho(coef_c, mill_c, e_c, coef_v, mill_v, e_v, gmill, g0, grid, *, out, dE=No
     return out
 
 
+class RhoPlan:
+    """Checked argument blocks for a fixed set of pairs and buffers, reusable across calls."""
+
+    def __init__(self, pairs, batch=True, ntrans=0):
+        self.built = [_rho_args(**kw) for kw in pairs]
+        self.arr = (RhoArgs * len(self.built))(*[b[0] for b in self.built])
+        self.batch = batch
+        self.ntrans = ntrans
+
+
+def launch_plan(plan: RhoPlan, stream=None):
+    st = _stream(stream)
+    if plan.batch:
+        _check(lib().xo_rho_batch(plan.arr, len(plan.built), st))
+    else:
+        for i in range(len(plan.built)):
+            _check(lib().xo_rho(C.byref(plan.arr[i]), st))
+
+
 def rho_batch(pairs, stream=None):
     """xo_rho_batch over a list of keyword dicts, each as for rho()."""
     built = [_rho_args(**kw) for kw in pairs]
