@@ -25,14 +25,13 @@
 #include <type_traits>
 #include <vector>
 
+#include "bf16x3.h"
 #include "xo_common.h"
 
 namespace xo {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTile = 16;
 constexpr int kWaves = 4;
@@ -135,14 +134,10 @@ __global__ void __launch_bounds__(256) chi0_tiles(TileArgs A) {
       for (int e = 0; e < 4; ++e) out[(w * 2 + r) * 256 + Acc<T>::row(kk, e) * 16 + i] = acc[w][r][e];
 }
 
-// BF16 x 3: every operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
-// is hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-16 relative, is dropped).
-// 16 transitions (32 real columns) per MFMA step; FP32 accumulation.
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
+// BF16 x 3 (split-bf16 products, FP32 accumulation): 16 transitions (32 real
+// columns) per MFMA step. The weighted left operand of the Re row is split once
+// per frequency; the Im row's operand (w rho_im, -w rho_re) is the same bits
+// with the halves swapped and one sign flipped.
 template <int NWG>
 __global__ void __launch_bounds__(256) chi0_tiles_bf16x3(TileArgs A) {
   const int wave = threadIdx.x >> 6;
@@ -166,52 +161,30 @@ __global__ void __launch_bounds__(256) chi0_tiles_bf16x3(TileArgs A) {
   const int t_end = min(A.nt, t_begin + A.kper);
   const bool gi_ok = Gi < A.ng, gj_ok = Gj < A.ng;
   for (int s = t_begin; s < t_end; s += 16) {
-    cplx<float> ra[4], rb[4];
-    bool tv[4];
+    cplx<float> ra[4];
+    float wt[4][NWG];
+    uint32_t bhh[4], bll[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = s + 4 * q + u;
-      tv[u] = t < t_end;
-      ra[u] = (tv[u] && gi_ok) ? rho[(size_t)t * A.ng + Gi] : cplx<float>{0.f, 0.f};
-      rb[u] = (tv[u] && gj_ok) ? rho[(size_t)t * A.ng + Gj] : cplx<float>{0.f, 0.f};
-    }
-    bf8 bh, bl;
+      const bool tv = t < t_end;
+      ra[u] = (tv && gi_ok) ? rho[(size_t)t * A.ng + Gi] : cplx<float>{0.f, 0.f};
+      const cplx<float> rb = (tv && gj_ok) ? rho[(size_t)t * A.ng + Gj] : cplx<float>{0.f, 0.f};
+      split2(rb.x, rb.y, bhh[u], bll[u]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      __bf16 h, l;
-      split_bf16(rb[u].x, h, l);
-      bh[2 * u] = h;
-      bl[2 * u] = l;
-      split_bf16(rb[u].y, h, l);
-      bh[2 * u + 1] = h;
-      bl[2 * u + 1] = l;
+      for (int w = 0; w < NWG; ++w) wt[u][w] = tv ? W[(size_t)t * A.nwpad + w] : 0.f;
     }
+    const u4 bh = u4{bhh[0], bhh[1], bhh[2], bhh[3]}, bl = u4{bll[0], bll[1], bll[2], bll[3]};
 #pragma unroll
     for (int w = 0; w < NWG; ++w) {
-      bf8 reh, rel, imh, iml;
+      uint32_t h[4], l[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float wt = tv[u] ? W[(size_t)(s + 4 * q + u) * A.nwpad + w] : 0.f;
-        __bf16 h, l;
-        split_bf16(wt * ra[u].x, h, l);
-        reh[2 * u] = h;
-        rel[2 * u] = l;
-        split_bf16(wt * ra[u].y, h, l);
-        reh[2 * u + 1] = h;
-        rel[2 * u + 1] = l;
-        split_bf16(wt * ra[u].y, h, l);
-        imh[2 * u] = h;
-        iml[2 * u] = l;
-        split_bf16(-wt * ra[u].x, h, l);
-        imh[2 * u + 1] = h;
-        iml[2 * u + 1] = l;
-      }
-      acc[w][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(reh, bh, acc[w][0], 0, 0, 0);
-      acc[w][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(reh, bl, acc[w][0], 0, 0, 0);
-      acc[w][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rel, bh, acc[w][0], 0, 0, 0);
-      acc[w][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(imh, bh, acc[w][1], 0, 0, 0);
-      acc[w][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(imh, bl, acc[w][1], 0, 0, 0);
-      acc[w][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(iml, bh, acc[w][1], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) split2(wt[u][w] * ra[u].x, wt[u][w] * ra[u].y, h[u], l[u]);
+      const u4 reh = u4{h[0], h[1], h[2], h[3]}, rel = u4{l[0], l[1], l[2], l[3]};
+      const u4 imh = u4{rot_pos(h[0]), rot_pos(h[1]), rot_pos(h[2]), rot_pos(h[3])};
+      const u4 iml = u4{rot_pos(l[0]), rot_pos(l[1]), rot_pos(l[2]), rot_pos(l[3])};
+      acc[w][0] = mma3(reh, rel, bh, bl, acc[w][0]);
+      acc[w][1] = mma3(imh, iml, bh, bl, acc[w][1]);
     }
   }
   float* out = static_cast<float*>(A.part) + ((size_t)slice * A.ntiles + tile) * NWG * 2 * 256;

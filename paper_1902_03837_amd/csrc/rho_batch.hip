@@ -26,6 +26,7 @@
 #include <mutex>
 #include <vector>
 
+#include "bf16x3.h"
 #include "rho_geom.h"
 
 namespace xo {
@@ -34,36 +35,8 @@ int rho_valu(const xo_rho_args* a, hipStream_t s);
 
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-
 constexpr int kBlock = 256;
 constexpr int kLP = 32;  // zero padding on each side of an orbital line in LDS
-
-__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
-  return (uint32_t)__builtin_bit_cast(unsigned short, h);
-}
-// (re, im) -> packed hi pair and lo pair
-__device__ __forceinline__ void split2(float re, float im, uint32_t& hi, uint32_t& lo) {
-  const __bf16 rh = (__bf16)re, ih = (__bf16)im;
-  const __bf16 rl = (__bf16)(re - (float)rh), il = (__bf16)(im - (float)ih);
-  hi = bf16_bits(rh) | (bf16_bits(ih) << 16);
-  lo = bf16_bits(rl) | (bf16_bits(il) << 16);
-}
-// (re, im) -> (-im, re) on a packed bf16 pair
-__device__ __forceinline__ uint32_t rot_neg(uint32_t x) { return ((x >> 16) ^ 0x8000u) | (x << 16); }
-
-__device__ __forceinline__ f4 mma(u4 a, u4 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
-                                                 0);
-}
-__device__ __forceinline__ f4 mma3(u4 ah, u4 al, u4 bh, u4 bl, f4 c) {
-  c = mma(ah, bh, c);
-  c = mma(ah, bl, c);
-  c = mma(al, bh, c);
-  return c;
-}
 
 // --------------------------------------------------------------- orbitals --
 struct OrbSide {
@@ -182,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
   extern __shared__ uint32_t lds[];
   uint32_t* Ahi = lds;                 // [Ny][LW]
   uint32_t* Alo = Ahi + Ny * LW;       // [Ny][LW]
-  uint32_t* S1hi = Alo + Ny * LW;      // [16 iz][16 v][16 y]
+  uint32_t* S1hi = Alo + Ny * LW;      // [16 iz][4 yq][16 v][4 y]
   uint32_t* S1lo = S1hi + 4096;
   float2* S2p = reinterpret_cast<float2*>(S1hi);  // [16 iz][16 slot][16 v], aliases S1
   float2* twx = reinterpret_cast<float2*>(S1lo + 4096);  // [Nx e][Nx x]
@@ -203,15 +176,17 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
   const int local = L - P.wg0;
   const int c = local / P.nvt, vt = local - (local / P.nvt) * P.nvt;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, l16 = l & 15, q = l >> 4;
-  const int vo = tid & 15, gq = tid >> 4;
+  const int vq = tid & 3, gq4 = tid >> 2;  // stage 3 ownership
 
   for (int i = tid; i < 2 * Ny * LW; i += kBlock) Ahi[i] = 0u;
   for (int i = tid; i < Nx * Nx; i += kBlock) twx[i] = twtab[i];
   for (int i = tid; i < ng; i += kBlock) gt[i] = P.gtab[i];
 
-  float2 acc[GPT];
+  float2 acc[GPT][4];
 #pragma unroll
-  for (int i = 0; i < GPT; ++i) acc[i] = make_float2(0.f, 0.f);
+  for (int i = 0; i < GPT; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[i][u] = make_float2(0.f, 0.f);
   const int vb = vt * 16 + l16;
   const bool vok = vb < P.nv;
   const size_t VS = (size_t)16 * 16 * Nyp;  // stride between the four F variants
@@ -234,12 +209,13 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
       s2i[j] = f4{0.f, 0.f, 0.f, 0.f};
     }
     for (int ch = 0; ch < Nyp / 16; ++ch) {
-      // ---- stage 1: this wave's four y values of the chunk
+      // ---- stage 1: this wave's four y values of the chunk (y = ch*16 + 4*wave + j)
+      f4 cr[4], ci[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int yl = wave * 4 + j;
-        const int y = ch * 16 + yl;
-        f4 cr = f4{0.f, 0.f, 0.f, 0.f}, ci = f4{0.f, 0.f, 0.f, 0.f};
+        const int y = ch * 16 + wave * 4 + j;
+        cr[j] = f4{0.f, 0.f, 0.f, 0.f};
+        ci[j] = f4{0.f, 0.f, 0.f, 0.f};
         if (y < Ny) {
 #pragma unroll
           for (int kk = 0; kk < NK; ++kk) {
@@ -258,18 +234,21 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
               bh = *reinterpret_cast<const u4*>(P.Uv_hi + o);
               bl = *reinterpret_cast<const u4*>(P.Uv_lo + o);
             }
-            cr = mma3(arh, arl, bh, bl, cr);
-            ci = mma3(aih, ail, bh, bl, ci);
+            cr[j] = mma3(arh, arl, bh, bl, cr[j]);
+            ci[j] = mma3(aih, ail, bh, bl, ci[j]);
           }
         }
+      }
+      // S1 layout [iz][yq][v][4 y]: lane (q, v) holds rows iz = 4q + r for its 4 y values
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          uint32_t h, lw;
-          split2(cr[r], ci[r], h, lw);
-          const int idx = ((4 * q + r) * 16 + l16) * 16 + yl;
-          S1hi[idx] = h;
-          S1lo[idx] = lw;
-        }
+      for (int r = 0; r < 4; ++r) {
+        uint32_t hh[4], ll[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) split2(cr[j][r], ci[j][r], hh[j], ll[j]);
+        const u4 h = u4{hh[0], hh[1], hh[2], hh[3]}, lw = u4{ll[0], ll[1], ll[2], ll[3]};
+        const int idx = (((4 * q + r) * 4 + wave) * 16 + l16) * 4;
+        *reinterpret_cast<u4*>(S1hi + idx) = h;
+        *reinterpret_cast<u4*>(S1lo + idx) = lw;
       }
       __syncthreads();
       // ---- stage 2: this wave's e_z rows
@@ -282,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
           const u4 frl = *reinterpret_cast<const u4*>(P.F + VS + fb);
           const u4 fih = *reinterpret_cast<const u4*>(P.F + 2 * VS + fb);
           const u4 fil = *reinterpret_cast<const u4*>(P.F + 3 * VS + fb);
-          const int so = (iz * 16 + l16) * 16 + 4 * q;
+          const int so = ((iz * 4 + q) * 16 + l16) * 4;
           const u4 sh = *reinterpret_cast<const u4*>(S1hi + so);
           const u4 sl = *reinterpret_cast<const u4*>(S1lo + so);
           s2r[j] = mma3(frh, frl, sh, sl, s2r[j]);
@@ -301,30 +280,39 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
       }
     }
     __syncthreads();
-    // ---- stage 3: x transform into the owned rho entries
+    // ---- stage 3: x transform into the owned rho entries (G = gq4 + 64 i, v = 4 vq .. 4 vq + 3)
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
-      const int G = gq + 16 * i;
+      const int G = gq4 + 64 * i;
       if (G < ng) {
         const int t = gt[G];
-        const float2 sv = S2p[((t & 31) * 16 + ((t >> 5) & 31)) * 16 + vo];
+        const float4* sp = reinterpret_cast<const float4*>(S2p + ((t & 31) * 16 + ((t >> 5) & 31)) * 16 + 4 * vq);
+        const float4 s01 = sp[0], s23 = sp[1];
         const float2 w = twx[(t >> 10) * Nx + x];
-        acc[i].x = fmaf(sv.x, w.x, fmaf(-sv.y, w.y, acc[i].x));
-        acc[i].y = fmaf(sv.x, w.y, fmaf(sv.y, w.x, acc[i].y));
+        acc[i][0].x = fmaf(s01.x, w.x, fmaf(-s01.y, w.y, acc[i][0].x));
+        acc[i][0].y = fmaf(s01.x, w.y, fmaf(s01.y, w.x, acc[i][0].y));
+        acc[i][1].x = fmaf(s01.z, w.x, fmaf(-s01.w, w.y, acc[i][1].x));
+        acc[i][1].y = fmaf(s01.z, w.y, fmaf(s01.w, w.x, acc[i][1].y));
+        acc[i][2].x = fmaf(s23.x, w.x, fmaf(-s23.y, w.y, acc[i][2].x));
+        acc[i][2].y = fmaf(s23.x, w.y, fmaf(s23.y, w.x, acc[i][2].y));
+        acc[i][3].x = fmaf(s23.z, w.x, fmaf(-s23.w, w.y, acc[i][3].x));
+        acc[i][3].y = fmaf(s23.z, w.y, fmaf(s23.w, w.x, acc[i][3].y));
       }
     }
   }
-  const int v = vt * 16 + vo;
-  if (v < P.nv) {
-    float2* out = P.rho + ((size_t)v * P.nc + c) * ng;
 #pragma unroll
-    for (int i = 0; i < GPT; ++i) {
-      const int G = gq + 16 * i;
-      if (G < ng) out[G] = make_float2(acc[i].x * scale, acc[i].y * scale);
+  for (int u = 0; u < 4; ++u) {
+    const int v = vt * 16 + 4 * vq + u;
+    if (v < P.nv) {
+      float2* out = P.rho + ((size_t)v * P.nc + c) * ng;
+#pragma unroll
+      for (int i = 0; i < GPT; ++i) {
+        const int G = gq4 + 64 * i;
+        if (G < ng) out[G] = make_float2(acc[i][u].x * scale, acc[i][u].y * scale);
+      }
     }
   }
 }
-
 struct PoleDesc {
   const double* ec;
   const double* ev;
@@ -469,10 +457,10 @@ static int launch_rho(const void* dpairs, int npairs, int nwg, int Nx, int Ny, i
 template <int NK>
 static int launch_rho_g(const void* dpairs, int npairs, int nwg, int Nx, int Ny, int Nyp, int ng, const void* dtw,
                         hipStream_t s, size_t lds) {
-  if (ng <= 16 * 8) return launch_rho<NK, 8>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  if (ng <= 16 * 16) return launch_rho<NK, 16>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  if (ng <= 16 * 32) return launch_rho<NK, 32>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  return launch_rho<NK, 64>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
+  if (ng <= 64 * 2) return launch_rho<NK, 2>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
+  if (ng <= 64 * 4) return launch_rho<NK, 4>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
+  if (ng <= 64 * 8) return launch_rho<NK, 8>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
+  return launch_rho<NK, 16>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
 }
 
 // Whether a batch can take the MFMA path (else each pair runs the VALU path in FP32).
