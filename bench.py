@@ -141,6 +141,30 @@ def cpu_baseline(cr, npairs):
                        f"numpy FFT single-threaded, BLAS on all cores")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch (read + write) from the committed counter summary, or None.
+
+    Only used when the kernel's source file still has the hash recorded with the
+    counters; otherwise the figures describe an older kernel and are not reported.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c2_bf16x3_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src, tr = {}, {}
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and f[0] == "source":
+            src[f[1]] = (f[2], f[3])
+        elif len(f) == 4 and f[0] == "traffic_GB":
+            tr[f[1]] = (float(f[2]) + float(f[3])) * 1e9
+    if kernel not in src or kernel not in tr:
+        return None
+    fname, h = src[kernel]
+    cur = hashlib.sha256(open(os.path.join(ROOT, fname), "rb").read()).hexdigest()[:16]
+    return tr[kernel] if cur == h else None
+
+
 def roofline(cr, form, K, nw, ng):
     kern = form["kernels"]
     name = max(kern, key=lambda k: kern[k]["ms_per_step"])
@@ -151,7 +175,7 @@ def roofline(cr, form, K, nw, ng):
         fl = chi0_flops(K, ng, min(nw, 8))          # one launch covers one group of <= 8 frequencies
         peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                    frac=fl / t / peak, traffic=None,
+                    frac=fl / t / peak, traffic=measured_traffic(name),
                     note="algorithmic flops 4 NG^2 K per frequency (Hermitian half)")
     if name == "rho_zy":
         per_t = np.mean([rho_zy_flops(cr, p) for p in cr.pairs])
@@ -165,7 +189,7 @@ def roofline(cr, form, K, nw, ng):
         nr = float(np.prod(cr.grid))
         fl = 5.0 * nr * np.log2(nr) * K / k["launches"]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=PEAK["bf16_mfma"] / 1e12,
-                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=None,
+                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name),
                     note="algorithmic flops 5 N_r log2 N_r per transition (FFT-equivalent) over the bf16 "
                          "dense peak; the kernel executes split-bf16 (x3) padded 16x16 tiles")
     return dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None)
