@@ -190,6 +190,67 @@ typedef struct {
 
 int xo_epsinv(const xo_eps_args* a, void* stream);
 
+/* ------------------------------------------------------------------------- */
+/* Learned empty-band tail (not in the paper: it takes the place of the
+ * extrapolar X-terminator of Eq. (X_term_def) / Appendix B). A small MLP maps
+ * features of the truncated band sum to the missing tail of chi0; the full band
+ * sum stays available as fallback and as the judge of its error.
+ *
+ * MLP layout: nl layers with widths dims[0..nl] ([host]); SiLU after every layer
+ * but the last. params [device] FP32: per layer W [dims[l+1]][dims[l]] row-major
+ * then b [dims[l+1]]; grads has the same layout. X [n][dims[0]], Y [n][dims[nl]].
+ * acts [device] holds, per hidden layer, the pre-activation Z [n][w] followed by
+ * H = silu(Z) [n][w]; size sum_{l<nl} 2 n dims[l+1] floats.
+ * work [device] for backward: 2 n max(dims) floats. dX may be NULL. */
+int xo_mlp_forward(int nl, const int* dims, const float* params, const float* X, int n, float* acts,
+                   float* Y, void* stream);
+int xo_mlp_backward(int nl, const int* dims, const float* params, const float* X, int n, const float* acts,
+                    const float* dY, float* grads, float* work, float* dX, void* stream);
+/* Mean squared error over n elements: loss[0] = mean (Y - T)^2 and, if dY is not
+ * NULL, dY = 2 (Y - T) / n. partial [device]: 256 floats of scratch. */
+int xo_mse(const float* Y, const float* T, long n, float* dY, float* loss, float* partial, void* stream);
+/* Adam (Kingma and Ba) with bias correction for step >= 1, in place on n parameters. */
+int xo_adam_step(float* p, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                 int step, void* stream);
+/* Column statistics of X [n][F] (device): out [device] [F][4] = mean, standard
+ * deviation, min, max (FP64, fixed-order reduction). */
+int xo_col_stats(const float* X, long n, int F, double* out, void* stream);
+/* dst[r][:] = src[idx[r]][:] for n rows of F floats (minibatch assembly). */
+int xo_gather_rows(const float* src, const int* idx, int n, int F, float* dst, void* stream);
+
+/* Tail features per (w, G, G'), 9 per element, normalised as (f - mu) * isd:
+ * Re, Im of s_G chi_t s_G'; Re, Im of s_G (chi_t - chi_h) s_G'; |q+G|, |q+G'|,
+ * |G - G'|, w, delta_GG' (s_G = sqrt(4 pi)/|q+G|). chi_t: truncated sum; chi_h:
+ * the sum over the lower part of the same bands (its difference is the
+ * contribution of the last block). When chi_f and T are given, also writes the
+ * target T [n][2] = tsc * s_G (chi_f - chi_t) s_G'. Device: chi_*, X, T;
+ * host: qpg [ng], gdiff [ng][ng], w [nw], mu [9], isd [9]. */
+typedef struct {
+  const double* chi_t;
+  const double* chi_h;
+  const double* chi_f;
+  const double* qpg;
+  const double* gdiff;
+  const double* w;
+  int ng, nw;
+  const float* mu;
+  const float* isd;
+  double tsc;
+  float* X;
+  float* T;
+} xo_tail_args;
+
+int xo_tail_features(const xo_tail_args* a, void* stream);
+/* out = chi_t + Hermitian part of Y / (tsc s_G s_G'), Y = Y1 or (Y1 + Y2)/2 when Y2
+ * is not NULL; Y1, Y2 [device] [nw][ng][ng][2]; qpg [host] [ng]; out must not alias chi_t. */
+int xo_tail_apply(const double* chi_t, const float* Y1, const float* Y2, const double* qpg, int ng, int nw,
+                  double tsc, double* out, void* stream);
+/* Fallback test inputs: stats[0] = number of features outside the training range
+ * widened by 10 % of its span; stats[1] = sum |Y1 - Y2|^2 and stats[2] =
+ * sum |(Y1 + Y2)/2|^2 for two ensemble members. lo, hi [host] [F]; stats [device] [3]. */
+int xo_tail_guard(const float* X, long n, int F, const float* lo, const float* hi, const float* Y1,
+                  const float* Y2, int ny, double* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,14 @@ class EpsArgs(C.Structure):
     ]
 
 
+class TailArgs(C.Structure):
+    _fields_ = [
+        ("chi_t", C.c_void_p), ("chi_h", C.c_void_p), ("chi_f", C.c_void_p), ("qpg", _f64p), ("gdiff", _f64p),
+        ("w", _f64p), ("ng", C.c_int), ("nw", C.c_int), ("mu", C.POINTER(C.c_float)),
+        ("isd", C.POINTER(C.c_float)), ("tsc", C.c_double), ("X", C.c_void_p), ("T", C.c_void_p),
+    ]
+
+
 class XoError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRNAME.get(code, code)}: {msg}")
@@ -63,7 +71,8 @@ class XoError(RuntimeError):
 _LIB = None
 
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
-           "xo_rho", "xo_rho_batch", "xo_chi0", "xo_epsinv")
+           "xo_rho", "xo_rho_batch", "xo_chi0", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
+           "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard")
 
 
 def lib():
@@ -79,6 +88,21 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
+        vp, ip, i, l, f = C.c_void_p, C.POINTER(C.c_int), C.c_int, C.c_long, C.c_float
+        fp = C.POINTER(C.c_float)
+        L.xo_mlp_forward.argtypes = [i, ip, vp, vp, i, vp, vp, vp]
+        L.xo_mlp_backward.argtypes = [i, ip, vp, vp, i, vp, vp, vp, vp, vp, vp]
+        L.xo_mse.argtypes = [vp, vp, l, vp, vp, vp, vp]
+        L.xo_adam_step.argtypes = [vp, vp, vp, vp, l, f, f, f, f, i, vp]
+        L.xo_gather_rows.argtypes = [vp, vp, i, i, vp, vp]
+        L.xo_col_stats.argtypes = [vp, l, i, vp, vp]
+        L.xo_col_stats.restype = C.c_int
+        L.xo_tail_features.argtypes = [C.POINTER(TailArgs), vp]
+        L.xo_tail_apply.argtypes = [vp, vp, vp, _f64p, i, i, C.c_double, vp, vp]
+        L.xo_tail_guard.argtypes = [vp, l, i, fp, fp, vp, vp, i, vp, vp]
+        for nm in ("xo_mlp_forward", "xo_mlp_backward", "xo_mse", "xo_adam_step", "xo_gather_rows",
+                   "xo_tail_features", "xo_tail_apply", "xo_tail_guard"):
+            getattr(L, nm).restype = C.c_int
         L.xo_rho_batch.argtypes = [C.POINTER(RhoArgs), C.c_int, C.c_void_p]
         L.xo_rho_batch.restype = C.c_int
         L.xo_release_workspace.restype = C.c_int
@@ -239,3 +263,80 @@ def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, stream=None):
     a.qpg, a.chi0, a.flags, a.out = q.ctypes.data_as(_f64p), _ptr(chi0_m), int(flags), _ptr(out)
     _check(lib().xo_epsinv(C.byref(a), _stream(stream)))
     return out
+
+
+# --------------------------------------------------------------------------- MLP / tail
+
+def _dims(dims):
+    d = (C.c_int * len(dims))(*[int(x) for x in dims])
+    return d
+
+
+def mlp_forward(dims, params, X, n, acts, Y, stream=None):
+    _check(lib().xo_mlp_forward(len(dims) - 1, _dims(dims), _ptr(params), _ptr(X), int(n), _ptr(acts), _ptr(Y),
+                                _stream(stream)))
+
+
+def mlp_backward(dims, params, X, n, acts, dY, grads, work, dX=None, stream=None):
+    _check(lib().xo_mlp_backward(len(dims) - 1, _dims(dims), _ptr(params), _ptr(X), int(n), _ptr(acts), _ptr(dY),
+                                 _ptr(grads), _ptr(work), _ptr(dX), _stream(stream)))
+
+
+def mse(Y, T, dY, loss, partial, stream=None):
+    assert Y.numel() == T.numel() and (dY is None or dY.numel() == Y.numel()) and partial.numel() >= 256
+    _check(lib().xo_mse(_ptr(Y), _ptr(T), Y.numel(), _ptr(dY), _ptr(loss), _ptr(partial), _stream(stream)))
+
+
+def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    assert p.numel() == g.numel() == m.numel() == v.numel()
+    _check(lib().xo_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), lr, b1, b2, eps, int(step),
+                              _stream(stream)))
+
+
+def gather_rows(src, idx, dst, stream=None):
+    n, F = dst.shape
+    assert src.shape[1] == F and idx.numel() == n and idx.dtype.itemsize == 4
+    _check(lib().xo_gather_rows(_ptr(src), _ptr(idx), n, F, _ptr(dst), _stream(stream)))
+
+
+def tail_features(chi_t, chi_h, qpg, gdiff, w, mu, isd, X, chi_f=None, T=None, tsc=1.0, stream=None):
+    nw, ng = chi_t.shape[0], chi_t.shape[1]
+    assert X.shape == (nw * ng * ng, 9) and chi_h.shape == chi_t.shape
+    if T is not None:
+        assert chi_f is not None and T.shape == (nw * ng * ng, 2)
+    keep = [np.ascontiguousarray(np.asarray(a, np.float64)) for a in (qpg, gdiff, w)]
+    keepf = [np.ascontiguousarray(np.asarray(a, np.float32)) for a in (mu, isd)]
+    assert keep[0].size == ng and keep[1].size == ng * ng and keep[2].size == nw
+    a = TailArgs()
+    a.chi_t, a.chi_h, a.chi_f = _ptr(chi_t), _ptr(chi_h), _ptr(chi_f)
+    a.qpg, a.gdiff, a.w = (k.ctypes.data_as(_f64p) for k in keep)
+    a.ng, a.nw = ng, nw
+    a.mu, a.isd = (k.ctypes.data_as(C.POINTER(C.c_float)) for k in keepf)
+    a.tsc, a.X, a.T = float(tsc), _ptr(X), _ptr(T)
+    _check(lib().xo_tail_features(C.byref(a), _stream(stream)))
+
+
+def tail_apply(chi_t, Y1, qpg, tsc, out, Y2=None, stream=None):
+    nw, ng = chi_t.shape[0], chi_t.shape[1]
+    q = np.ascontiguousarray(np.asarray(qpg, np.float64))
+    assert Y1.numel() == nw * ng * ng * 2 and out.shape == chi_t.shape
+    assert Y2 is None or Y2.numel() == Y1.numel()
+    _check(lib().xo_tail_apply(_ptr(chi_t), _ptr(Y1), _ptr(Y2), q.ctypes.data_as(_f64p), ng, nw, float(tsc),
+                               _ptr(out), _stream(stream)))
+
+
+def tail_guard(X, lo, hi, Y1, Y2, stats, stream=None):
+    n, F = X.shape
+    lo_ = np.ascontiguousarray(np.asarray(lo, np.float32))
+    hi_ = np.ascontiguousarray(np.asarray(hi, np.float32))
+    ny = Y1.shape[1]
+    assert Y2.shape == Y1.shape and Y1.shape[0] == n and stats.numel() >= 3
+    _check(lib().xo_tail_guard(_ptr(X), n, F, lo_.ctypes.data_as(C.POINTER(C.c_float)),
+                               hi_.ctypes.data_as(C.POINTER(C.c_float)), _ptr(Y1), _ptr(Y2), ny, _ptr(stats),
+                               _stream(stream)))
+
+
+def col_stats(X, out, stream=None):
+    n, F = X.shape
+    assert out.numel() >= 4 * F
+    _check(lib().xo_col_stats(_ptr(X), n, F, _ptr(out), _stream(stream)))

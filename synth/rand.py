@@ -16,3 +16,18 @@ def random_complex(seed: int, shape, scale: float = 1.0) -> np.ndarray:
 
 def random_positive(seed: int, n: int, lo: float, hi: float) -> np.ndarray:
     return rng(seed).uniform(lo, hi, n).astype(np.float64)
+
+
+def mlp_init(dims, seed):
+    """Initial MLP parameters: W_l ~ U(-a, a), a = sqrt(6 / fan_in), b_l = 0 (FP64 arrays)."""
+    g = rng(seed)
+    out = []
+    for din, dout in zip(dims[:-1], dims[1:]):
+        a = np.sqrt(6.0 / din)
+        out.append((g.uniform(-a, a, (dout, din)), np.zeros(dout)))
+    return out
+
+
+def flatten_params(params) -> np.ndarray:
+    """Per layer W [out][in] row-major then b [out], as one FP32 vector."""
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in params]).astype(np.float32)

@@ -1,0 +1,240 @@
+"""Learned band tail on the GPU: MLP kernels vs the FP64 oracle, features, apply, guard, fallback."""
+
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import crystal_for  # noqa: E402
+from synth.rand import mlp_init, flatten_params, rng  # noqa: E402
+from oracle import mlp as omlp  # noqa: E402
+from paper_1902_03837_amd import xo  # noqa: E402
+from paper_1902_03837_amd import tail as T  # noqa: E402
+
+DEV = "cuda"
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1902_03837_amd",
+                     "tail_model.npz")
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+
+
+def _unflatten(flat, dims):
+    out, o = [], 0
+    for din, dout in zip(dims[:-1], dims[1:]):
+        W = flat[o:o + din * dout].reshape(dout, din).astype(np.float64)
+        o += din * dout
+        b = flat[o:o + dout].astype(np.float64)
+        o += dout
+        out.append((W, b))
+    return out
+
+
+@pytest.mark.parametrize("dims,n", [([9, 32, 32, 2], 100), ([9, 256, 256, 256, 2], 257), ([3, 5, 1], 1)])
+def test_mlp_forward_backward_vs_oracle(dims, n):
+    say(f"mlp fwd/bwd dims={dims} n={n}")
+    params = mlp_init(dims, 5)
+    flat = flatten_params(params)
+    p32 = _unflatten(flat, dims)                 # the exact FP32 values the GPU holds, in FP64
+    g = rng(9)
+    X = g.normal(size=(n, dims[0])).astype(np.float32)
+    Tg = g.normal(size=(n, dims[-1])).astype(np.float32)
+    Yr, cache = omlp.forward(p32, X.astype(np.float64))
+    grads_r, dX_r = omlp.backward(p32, cache, Yr, Tg.astype(np.float64))
+    net = T.MLP(flat, dims, DEV)
+    Xd = torch.from_numpy(X).to(DEV)
+    Td = torch.from_numpy(Tg).to(DEV)
+    Y = net.forward(Xd)
+    dY = torch.empty_like(Y)
+    loss = torch.empty(1, dtype=torch.float32, device=DEV)
+    part = torch.empty(256, dtype=torch.float32, device=DEV)
+    xo.mse(Y, Td, dY, loss, part)
+    dX = torch.empty_like(Xd)
+    gr = net.backward(Xd, dY, dX).cpu().numpy()
+    Yg = Y.cpu().numpy()
+    assert np.abs(Yg - Yr).max() <= 1e-4 * max(1.0, np.abs(Yr).max())
+    assert abs(float(loss.item()) - omlp.mse(Yr, Tg.astype(np.float64))) <= 1e-4 * omlp.mse(Yr, Tg)
+    gref = flatten_params(grads_r).astype(np.float64)
+    assert np.abs(gr - gref).max() <= 1e-4 * np.abs(gref).max()
+    assert np.abs(dX.cpu().numpy() - dX_r).max() <= 1e-4 * np.abs(dX_r).max()
+
+
+def test_adam_step_vs_oracle():
+    dims = [4, 8, 2]
+    params = mlp_init(dims, 2)
+    g = rng(4)
+    grads = [(g.normal(size=W.shape), g.normal(size=b.shape)) for W, b in params]
+    st = {}
+    ref = params
+    for _ in range(3):
+        ref = omlp.adam_step(ref, grads, st, lr=1e-2)
+    net = T.MLP(flatten_params(params), dims, DEV)
+    net.g.copy_(torch.from_numpy(flatten_params(grads)))
+    for _ in range(3):
+        net.adam(1e-2)
+    assert np.abs(net.p.cpu().numpy() - flatten_params(ref)).max() < 1e-5
+
+
+def test_gather_and_col_stats():
+    g = rng(3)
+    X = g.normal(size=(1000, 7)).astype(np.float32)
+    idx = g.permutation(1000)[:300].astype(np.int32)
+    Xd = torch.from_numpy(X).to(DEV)
+    out = torch.empty((300, 7), dtype=torch.float32, device=DEV)
+    xo.gather_rows(Xd, torch.from_numpy(idx).to(DEV), out)
+    assert np.array_equal(out.cpu().numpy(), X[idx])
+    st = torch.empty((7, 4), dtype=torch.float64, device=DEV)
+    xo.col_stats(Xd, st)
+    s = st.cpu().numpy()
+    assert np.allclose(s[:, 0], X.astype(np.float64).mean(0), atol=1e-9)
+    assert np.allclose(s[:, 1], X.astype(np.float64).std(0), rtol=1e-7)
+    assert np.array_equal(s[:, 2], X.min(0)) and np.array_equal(s[:, 3], X.max(0))
+
+
+@pytest.fixture(scope="module")
+def small():
+    cr = crystal_for("c4_small")
+    chis, dc = T.crystal_tensors(cr, ntrunc=20, nhalf=10)
+    return cr, [c.cpu().numpy() for c in chis], chis
+
+
+def test_band_blocks_are_cumulative_sums(small):
+    cr, chis, _ = small
+    from oracle.pipeline import rho_all_pairs
+    from oracle.chi0 import chi0_from_rho
+    for nb, ref_i in ((10, 0), (20, 1), (None, 2)):
+        M, dE = rho_all_pairs(cr, "fft", nempty=nb)
+        ref = chi0_from_rho(M, dE, cr.omegas, cr.pref)
+        assert np.abs(chis[ref_i] - ref).max() < 1e-12 * np.abs(ref).max()
+    # more bands -> closer to the full sum (monotone convergence of the truncated sum)
+    e10 = np.linalg.norm(chis[0] - chis[2])
+    e20 = np.linalg.norm(chis[1] - chis[2])
+    assert e20 < e10
+
+
+def test_features_targets_and_apply(small):
+    cr, chis, dchis = small
+    ng, nw = cr.gmill.shape[0], len(cr.omegas)
+    mu = np.arange(9, dtype=np.float32) * 0.1
+    isd = np.linspace(0.5, 2.0, 9).astype(np.float32)
+    tsc = 3.0
+    X, Tt = T.build_features(cr, dchis, mu, isd, tsc)
+    qpg = cr.qpg()
+    ss = 4 * np.pi / np.outer(qpg, qpg)
+    gd = T.gdiff_table(cr)
+    ref = np.zeros((nw, ng, ng, 9))
+    ref[..., 0] = (chis[1] * ss).real
+    ref[..., 1] = (chis[1] * ss).imag
+    ref[..., 2] = ((chis[1] - chis[0]) * ss).real
+    ref[..., 3] = ((chis[1] - chis[0]) * ss).imag
+    ref[..., 4] = qpg[None, :, None]
+    ref[..., 5] = qpg[None, None, :]
+    ref[..., 6] = gd[None]
+    ref[..., 7] = cr.omegas[:, None, None]
+    ref[..., 8] = np.eye(ng)[None]
+    ref = (ref - mu) * isd
+    assert np.abs(X.cpu().numpy().reshape(ref.shape) - ref).max() < 1e-5 * max(1, np.abs(ref).max())
+    tref = (chis[2] - chis[1]) * ss * tsc
+    tg = Tt.cpu().numpy().reshape(nw, ng, ng, 2)
+    assert np.abs(tg[..., 0] - tref.real).max() < 1e-5 * np.abs(tref).max()
+    # applying the exact target restores the full sum (its Hermitian part is itself)
+    out = torch.empty_like(dchis[1])
+    xo.tail_apply(dchis[1], Tt, qpg, tsc, out)
+    got = out.cpu().numpy()
+    assert np.abs(got - chis[2]).max() < 1e-6 * np.abs(chis[2]).max()
+    for j in range(nw):
+        assert np.array_equal(got[j], got[j].conj().T)
+    # ensemble average of identical members is the member
+    out2 = torch.empty_like(out)
+    xo.tail_apply(dchis[1], Tt, qpg, tsc, out2, Y2=Tt)
+    assert torch.equal(out, out2)
+
+
+def test_guard_flags_out_of_range_and_disagreement():
+    n = 500
+    X = torch.zeros((n, 9), dtype=torch.float32, device=DEV)
+    Y = torch.ones((n, 2), dtype=torch.float32, device=DEV)
+    stats = torch.empty(3, dtype=torch.float64, device=DEV)
+    lo, hi = -np.ones(9, np.float32), np.ones(9, np.float32)
+    xo.tail_guard(X, lo, hi, Y, Y, stats)
+    s = stats.cpu().numpy()
+    assert s[0] == 0 and s[1] == 0 and s[2] == pytest.approx(n * 2)
+    X[7, 3] = 1.5                     # beyond hi + 10 % of the span
+    xo.tail_guard(X, lo, hi, Y, Y * 2, stats)
+    s = stats.cpu().numpy()
+    assert s[0] == 1 and s[1] == pytest.approx(n * 2)
+
+
+def test_training_reduces_loss_on_small_family():
+    say("tail training on two small crystals")
+    Xs, Ts = [], []
+    for s in (11, 12):
+        cr = crystal_for("c4_small", seed=s)
+        chis, _ = T.crystal_tensors(cr, 20, 10)
+        X, Tt = T.build_features(cr, chis, np.zeros(9, np.float32), np.ones(9, np.float32), 1.0)
+        Xs.append(X)
+        Ts.append(Tt)
+    X, Tt = torch.cat(Xs), torch.cat(Ts)
+    mu, isd, tsc = T.normalise(X, Tt)
+    # normalise in place through the same kernels: rebuild with the statistics
+    Xs, Ts = [], []
+    for s in (11, 12):
+        cr = crystal_for("c4_small", seed=s)
+        chis, _ = T.crystal_tensors(cr, 20, 10)
+        X, Tt = T.build_features(cr, chis, mu, isd, tsc)
+        Xs.append(X)
+        Ts.append(Tt)
+    X, Tt = torch.cat(Xs), torch.cat(Ts)
+    p, hist = T.train(X, Tt, seed=3, epochs=6, batch=512, lr=2e-3, log=say)
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def test_fallback_returns_the_full_sum(small):
+    """Guard rejection (a model whose range excludes the data) hands back None; the caller
+    then uses the full band sum, which is the plain path's result bit for bit."""
+    cr, chis, dchis = small
+    model = T.TailModel([flatten_params(mlp_init(T.DIMS, 1)), flatten_params(mlp_init(T.DIMS, 2))],
+                        np.zeros(9, np.float32), np.ones(9, np.float32), 1.0,
+                        lo=np.full(9, 10.0, np.float32), hi=np.full(9, 11.0, np.float32))
+    out, info = T.predict(model, cr, dchis[:2])
+    assert out is None and info["out_of_range"] > 0
+    from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal
+    dc = DeviceCrystal.upload(cr, "fp64")
+    full = T.chi0_blocks(dc, [cr.coef[0].shape[0] - cr.nocc])[0]   # what the caller falls back to
+    _, _, plain, _ = run_crystal(dc)                                 # the plain FP64 path
+    assert torch.equal(full, plain)
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained tail model in the tree")
+def test_trained_tail_beats_truncation_on_held_out():
+    """The committed model (trained on seeds 1000..1063 by train_tail) on two held-out crystals."""
+    model = T.TailModel.load(MODEL)
+    for s in (2001, 2002):   # 2000 is out of the training range: the guard sends it to the full sum
+        say(f"held-out crystal seed {s}")
+        cr = crystal_for("c4", seed=s)
+        chis, _ = T.crystal_tensors(cr, 100, 50)
+        out, info = T.predict(model, cr, chis[:2])
+        assert out is not None, info
+        qpg = cr.qpg()
+        E = {}
+        for k, c in (("t", chis[1]), ("l", out), ("f", chis[2])):
+            E[k] = torch.empty_like(c)
+            xo.epsinv(c, qpg, out=E[k])
+        et = max(float(torch.linalg.norm(E["t"][j] - E["f"][j]) / torch.linalg.norm(E["f"][j]))
+                 for j in range(len(cr.omegas)))
+        el = max(float(torch.linalg.norm(E["l"][j] - E["f"][j]) / torch.linalg.norm(E["f"][j]))
+                 for j in range(len(cr.omegas)))
+        say(f"  e_F truncated {et:.3e} learned {el:.3e}")
+        assert el < 0.5 * et
