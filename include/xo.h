@@ -162,6 +162,26 @@ typedef struct {
 
 int xo_chi0(const xo_chi0_args* a, void* stream);
 
+/* Many chi0 problems (q-points with their own G-set size, transitions and
+ * output) sharing precision and frequencies, in one persistent launch: the
+ * problems are cut into units (problem, 16-row x 16*nt_tiles-column block of the
+ * upper triangle, group of <= 8 frequencies, transition slice of kper), queued
+ * longest-first, and taken by num_CUs * wg_per_cu workgroups from an atomic
+ * counter until the queue is empty; partials are reduced per block in a fixed
+ * order, so the result does not depend on the schedule and equals xo_chi0 on
+ * each item up to the order of the FP64 partial sums. items: [host] array. */
+typedef struct {
+  int nt_tiles;   /* column tiles per wave: 1, or 2 (XO_BF16X3 only); 0 = 1      */
+  int kper;       /* transitions per unit; 0 = chosen to fill the chip            */
+  int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 4                */
+} xo_tune;
+
+int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream);
+/* Times a grid of xo_tune candidates on the given batch (each after a warm-up
+ * run; results overwrite the outputs) and returns the fastest with its time in
+ * milliseconds. Synchronises the stream. */
+int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* best_ms, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Inverse dielectric matrix by the Dyson equation in matrix form, Eq. (X_rpa_inv):
  *   eps~ = I - diag(s) chi0 diag(s),  s_G = sqrt(4 pi)/|q+G|,

@@ -9,11 +9,15 @@
 //   Re chi0 ~ sum_{t,a} [W rho_a(G)]                     rho_a(G')
 //   Im chi0 ~ sum_{t,a} [W (a = re ? rho_im : -rho_re)(G)] rho_a(G')
 // so both share the unweighted right operand B[(t,a)][G'] = rho_a(G', t), and the
-// left operand carries the weight of each frequency. One workgroup owns one
-// 16 x 16 block (G-block i <= G'-block j) for a group of frequencies; its four
-// waves each reduce a disjoint slice of the transitions, and a second kernel
-// adds the slices in a fixed order (deterministic), applies -pref and writes the
-// block and its Hermitian mirror.
+// left operand carries the weight of each frequency.
+//
+// Work decomposition. A chi0 problem (an "item", one q-point) is cut into units
+// (item, block pair i <= j, group of <= 8 frequencies, transition slice). One
+// persistent launch serves every unit of every item from an atomic queue ordered
+// longest-first; each workgroup's four waves split the unit's transitions, and
+// each wave writes its partial 16 x (16 NT) block. A second kernel adds the
+// partials of each output block in unit order (bitwise deterministic whatever the
+// queue order), applies -pref and writes the block and its Hermitian mirror.
 //
 // Operand/result layout of the 16x16 MFMA tiles (v_mfma_*_16x16x4, one block):
 //   A[i][k]: lane = i + 16 k,  B[k][j]: lane = j + 16 k.
@@ -35,6 +39,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 16;
 constexpr int kWaves = 4;
+constexpr int MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2;
 
 __device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -72,278 +77,225 @@ __global__ void pole_factors(const double* __restrict__ dE, int nt, const double
   }
 }
 
-struct TileArgs {
-  const void* rho;     // [nt][ng] complex T
-  const void* W;       // [nt][nwpad] T
-  int nwpad, w0;       // frequency stride and first frequency of this group
-  int ng, nt;
-  const int2* tiles;   // (block i, block j), i <= j
-  int ntiles;
-  int kper;            // transitions per wave slice
-  void* part;          // [slice][tile][NWG][2][256] T
+__global__ void zero_ints(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+struct Item {
+  const void* rho;  // [nt][ng] complex T
+  const void* W;    // [nt][nwpad] T
+  double* chi0;     // [nw][ng][ng] complex128
+  double pref;
+  int nt, ng, nwpad, nw;
+  int tile0;        // first entry of this item in the block-pair table
+  int accumulate;
 };
 
-// FP64 / FP32: one 16x16x4 MFMA per (frequency, re/im row) and pair of transitions.
-template <typename T, int NWG>
-__global__ void __launch_bounds__(256) chi0_tiles(TileArgs A) {
-  typedef typename Acc<T>::type V4;
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
-  const int slice = blockIdx.y * kWaves + wave;
-  const int2 bij = A.tiles[tile];
+struct Unit {
+  int item, tile, w0, k0, k1;
+};
+
+// One wave's share of a unit: its own transition slice of one 16 x (16 NT) block.
+template <int MODE, int NWG, int NT>
+__device__ __forceinline__ void unit_wave(const Item& I, int2 bij, int w0, int kb, int ke, int lane,
+                                          float* __restrict__ outf, double* __restrict__ outd) {
   const int i = lane & 15;
-  const int kk = lane >> 4;
-  const int a = kk & 1;
-  const int tsub = kk >> 1;
   const int Gi = bij.x * kTile + i;
-  const int Gj = bij.y * kTile + i;
-  const cplx<T>* rho = static_cast<const cplx<T>*>(A.rho);
-  const T* W = static_cast<const T*>(A.W) + A.w0;
-  V4 acc[NWG][2];
+  const bool gi_ok = Gi < I.ng;
+  if constexpr (MODE == MODE_BF16X3) {
+    const int q = lane >> 4;  // lane holds k = 8q .. 8q+7 -> transitions 4q .. 4q+3, (re, im)
+    const cplx<float>* rho = static_cast<const cplx<float>*>(I.rho);
+    const float* W = static_cast<const float*>(I.W) + w0;
+    f4 acc[NWG][2][NT];
 #pragma unroll
-  for (int w = 0; w < NWG; ++w) {
-    acc[w][0] = V4{0, 0, 0, 0};
-    acc[w][1] = V4{0, 0, 0, 0};
-  }
-  const int t_begin = slice * A.kper;
-  const int t_end = min(A.nt, t_begin + A.kper);
-  const bool gi_ok = Gi < A.ng, gj_ok = Gj < A.ng;
-  for (int s = t_begin; s < t_end; s += 2) {
-    const int t = s + tsub;
-    const bool tv = t < t_end;
-    cplx<T> ra = {T(0), T(0)}, rb = {T(0), T(0)};
-    if (tv && gi_ok) ra = rho[(size_t)t * A.ng + Gi];
-    if (tv && gj_ok) rb = rho[(size_t)t * A.ng + Gj];
-    const T bval = a ? rb.y : rb.x;
-    const T are = a ? ra.y : ra.x;
-    const T aim = a ? -ra.x : ra.y;
+    for (int w = 0; w < NWG; ++w)
 #pragma unroll
-    for (int w = 0; w < NWG; ++w) {
-      const T wt = tv ? W[(size_t)t * A.nwpad + w] : T(0);
-      acc[w][0] = mfma4(wt * are, bval, acc[w][0]);
-      acc[w][1] = mfma4(wt * aim, bval, acc[w][1]);
-    }
-  }
-  T* out = static_cast<T*>(A.part) + ((size_t)slice * A.ntiles + tile) * NWG * 2 * 256;
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-  for (int w = 0; w < NWG; ++w)
+        for (int n = 0; n < NT; ++n) acc[w][r][n] = f4{0, 0, 0, 0};
+    for (int s = kb; s < ke; s += 16) {
+      cplx<float> ra[4];
+      float wt[4][NWG];
+      uint32_t bhh[NT][4], bll[NT][4];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+      for (int u = 0; u < 4; ++u) {
+        const int t = s + 4 * q + u;
+        const bool tv = t < ke;
+        ra[u] = (tv && gi_ok) ? rho[(size_t)t * I.ng + Gi] : cplx<float>{0.f, 0.f};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) out[(w * 2 + r) * 256 + Acc<T>::row(kk, e) * 16 + i] = acc[w][r][e];
-}
-
-// BF16 x 3 (split-bf16 products, FP32 accumulation): 16 transitions (32 real
-// columns) per MFMA step. The weighted left operand of the Re row is split once
-// per frequency; the Im row's operand (w rho_im, -w rho_re) is the same bits
-// with the halves swapped and one sign flipped.
-template <int NWG>
-__global__ void __launch_bounds__(256) chi0_tiles_bf16x3(TileArgs A) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x;
-  const int slice = blockIdx.y * kWaves + wave;
-  const int2 bij = A.tiles[tile];
-  const int i = lane & 15;
-  const int q = lane >> 4;  // this lane holds k = 8q .. 8q+7 -> transitions 4q .. 4q+3, (re, im)
-  const int Gi = bij.x * kTile + i;
-  const int Gj = bij.y * kTile + i;
-  const cplx<float>* rho = static_cast<const cplx<float>*>(A.rho);
-  const float* W = static_cast<const float*>(A.W) + A.w0;
-  f4 acc[NWG][2];
+        for (int n = 0; n < NT; ++n) {
+          const int Gj = bij.y * kTile * NT + 16 * n + i;
+          const cplx<float> rb = (tv && Gj < I.ng) ? rho[(size_t)t * I.ng + Gj] : cplx<float>{0.f, 0.f};
+          split2(rb.x, rb.y, bhh[n][u], bll[n][u]);
+        }
 #pragma unroll
-  for (int w = 0; w < NWG; ++w) {
-    acc[w][0] = f4{0, 0, 0, 0};
-    acc[w][1] = f4{0, 0, 0, 0};
-  }
-  const int t_begin = slice * A.kper;
-  const int t_end = min(A.nt, t_begin + A.kper);
-  const bool gi_ok = Gi < A.ng, gj_ok = Gj < A.ng;
-  for (int s = t_begin; s < t_end; s += 16) {
-    cplx<float> ra[4];
-    float wt[4][NWG];
-    uint32_t bhh[4], bll[4];
+        for (int w = 0; w < NWG; ++w) wt[u][w] = tv ? W[(size_t)t * I.nwpad + w] : 0.f;
+      }
+      u4 bh[NT], bl[NT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = s + 4 * q + u;
-      const bool tv = t < t_end;
-      ra[u] = (tv && gi_ok) ? rho[(size_t)t * A.ng + Gi] : cplx<float>{0.f, 0.f};
-      const cplx<float> rb = (tv && gj_ok) ? rho[(size_t)t * A.ng + Gj] : cplx<float>{0.f, 0.f};
-      split2(rb.x, rb.y, bhh[u], bll[u]);
+      for (int n = 0; n < NT; ++n) {
+        bh[n] = u4{bhh[n][0], bhh[n][1], bhh[n][2], bhh[n][3]};
+        bl[n] = u4{bll[n][0], bll[n][1], bll[n][2], bll[n][3]};
+      }
 #pragma unroll
-      for (int w = 0; w < NWG; ++w) wt[u][w] = tv ? W[(size_t)t * A.nwpad + w] : 0.f;
-    }
-    const u4 bh = u4{bhh[0], bhh[1], bhh[2], bhh[3]}, bl = u4{bll[0], bll[1], bll[2], bll[3]};
+      for (int w = 0; w < NWG; ++w) {
+        uint32_t h[4], l[4];
 #pragma unroll
-    for (int w = 0; w < NWG; ++w) {
-      uint32_t h[4], l[4];
+        for (int u = 0; u < 4; ++u) split2(wt[u][w] * ra[u].x, wt[u][w] * ra[u].y, h[u], l[u]);
+        const u4 reh = u4{h[0], h[1], h[2], h[3]}, rel = u4{l[0], l[1], l[2], l[3]};
+        const u4 imh = u4{rot_pos(h[0]), rot_pos(h[1]), rot_pos(h[2]), rot_pos(h[3])};
+        const u4 iml = u4{rot_pos(l[0]), rot_pos(l[1]), rot_pos(l[2]), rot_pos(l[3])};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) split2(wt[u][w] * ra[u].x, wt[u][w] * ra[u].y, h[u], l[u]);
-      const u4 reh = u4{h[0], h[1], h[2], h[3]}, rel = u4{l[0], l[1], l[2], l[3]};
-      const u4 imh = u4{rot_pos(h[0]), rot_pos(h[1]), rot_pos(h[2]), rot_pos(h[3])};
-      const u4 iml = u4{rot_pos(l[0]), rot_pos(l[1]), rot_pos(l[2]), rot_pos(l[3])};
-      acc[w][0] = mma3(reh, rel, bh, bl, acc[w][0]);
-      acc[w][1] = mma3(imh, iml, bh, bl, acc[w][1]);
-    }
-  }
-  float* out = static_cast<float*>(A.part) + ((size_t)slice * A.ntiles + tile) * NWG * 2 * 256;
-#pragma unroll
-  for (int w = 0; w < NWG; ++w)
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) out[(w * 2 + r) * 256 + (4 * q + e) * 16 + i] = acc[w][r][e];
-}
-
-// Fixed-order FP64 sum of the slices, scale by -pref, write the block and its mirror.
-template <typename T, int NWG>
-__global__ void chi0_reduce(const T* __restrict__ part, int nslice, int ntiles, const int2* __restrict__ tiles,
-                            int ng, int w0, int nw, double pref, int accumulate, double* __restrict__ chi0) {
-  const int tile = blockIdx.x;
-  const int w = blockIdx.y;
-  const int e = threadIdx.x;  // 0..255
-  if (w0 + w >= nw) return;
-  const int2 bij = tiles[tile];
-  const int ii = e >> 4, jj = e & 15;
-  const int G = bij.x * kTile + ii, Gp = bij.y * kTile + jj;
-  if (G >= ng || Gp >= ng) return;
-  if (bij.x == bij.y && ii > jj) return;  // diagonal blocks: upper triangle is authoritative
-  double re = 0.0, im = 0.0;
-  for (int sl = 0; sl < nslice; ++sl) {
-    const T* p = part + (((size_t)sl * ntiles + tile) * NWG + w) * 2 * 256;
-    re += (double)p[e];
-    im += (double)p[256 + e];
-  }
-  re *= -pref;
-  im *= -pref;
-  if (G == Gp) im = 0.0;
-  double* m = chi0 + (size_t)(w0 + w) * ng * ng * 2;
-  const size_t up = ((size_t)G * ng + Gp) * 2, lo = ((size_t)Gp * ng + G) * 2;
-  if (accumulate) {
-    m[up] += re;
-    m[up + 1] += im;
-    if (G != Gp) {
-      m[lo] += re;
-      m[lo + 1] -= im;
-    }
-  } else {
-    m[up] = re;
-    m[up + 1] = im;
-    if (G != Gp) {
-      m[lo] = re;
-      m[lo + 1] = -im;
-    }
-  }
-}
-
-template <typename T, int NWG>
-static int run_group(const TileArgs& base, int nslice_wg, hipStream_t s, int prec, int w0, int nw,
-                     double pref, int accumulate, double* chi0) {
-  TileArgs A = base;
-  A.w0 = w0;
-  dim3 grid(A.ntiles, nslice_wg);
-  if (prec == XO_BF16X3) {
-    if constexpr (std::is_same<T, float>::value) {
-      {
-        KernelTimer kt_("chi0_tiles_bf16x3", s);
-        hipLaunchKernelGGL((chi0_tiles_bf16x3<NWG>), grid, dim3(256), 0, s, A);
+        for (int n = 0; n < NT; ++n) {
+          acc[w][0][n] = mma3(reh, rel, bh[n], bl[n], acc[w][0][n]);
+          acc[w][1][n] = mma3(imh, iml, bh[n], bl[n], acc[w][1][n]);
+        }
       }
     }
+#pragma unroll
+    for (int w = 0; w < NWG; ++w)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            outf[((w * 2 + r) * NT + n) * 256 + (4 * q + e) * 16 + i] = acc[w][r][n][e];
   } else {
-    {
-      KernelTimer kt_("chi0_tiles", s);
-      hipLaunchKernelGGL((chi0_tiles<T, NWG>), grid, dim3(256), 0, s, A);
+    typedef typename std::conditional<MODE == MODE_F64, double, float>::type T;
+    typedef typename Acc<T>::type V4;
+    const int kk = lane >> 4;
+    const int a = kk & 1;
+    const int tsub = kk >> 1;
+    const int Gj = bij.y * kTile + i;
+    const bool gj_ok = Gj < I.ng;
+    const cplx<T>* rho = static_cast<const cplx<T>*>(I.rho);
+    const T* W = static_cast<const T*>(I.W) + w0;
+    V4 acc[NWG][2];
+#pragma unroll
+    for (int w = 0; w < NWG; ++w) {
+      acc[w][0] = V4{0, 0, 0, 0};
+      acc[w][1] = V4{0, 0, 0, 0};
     }
+    for (int s = kb; s < ke; s += 2) {
+      const int t = s + tsub;
+      const bool tv = t < ke;
+      cplx<T> ra = {T(0), T(0)}, rb = {T(0), T(0)};
+      if (tv && gi_ok) ra = rho[(size_t)t * I.ng + Gi];
+      if (tv && gj_ok) rb = rho[(size_t)t * I.ng + Gj];
+      const T bval = a ? rb.y : rb.x;
+      const T are = a ? ra.y : ra.x;
+      const T aim = a ? -ra.x : ra.y;
+#pragma unroll
+      for (int w = 0; w < NWG; ++w) {
+        const T wt = tv ? W[(size_t)t * I.nwpad + w] : T(0);
+        acc[w][0] = mfma4(wt * are, bval, acc[w][0]);
+        acc[w][1] = mfma4(wt * aim, bval, acc[w][1]);
+      }
+    }
+    T* out = MODE == MODE_F64 ? reinterpret_cast<T*>(outd) : reinterpret_cast<T*>(outf);
+#pragma unroll
+    for (int w = 0; w < NWG; ++w)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[(w * 2 + r) * 256 + Acc<T>::row(kk, e) * 16 + i] = acc[w][r][e];
   }
-  XO_CHECK_LAUNCH();
-  {
-    KernelTimer kt_("chi0_reduce", s);
-    hipLaunchKernelGGL((chi0_reduce<T, NWG>), dim3(A.ntiles, NWG), dim3(256), 0, s,
-                       static_cast<const T*>(A.part), nslice_wg * kWaves, A.ntiles, A.tiles, A.ng, w0, nw, pref,
-                       accumulate, chi0);
-  }
-  XO_CHECK_LAUNCH();
-  return XO_OK;
 }
 
-template <typename T>
-static int chi0_run(const xo_chi0_args* a, hipStream_t s) {
-  const int nb = (a->ng + kTile - 1) / kTile;
-  std::vector<int2> tl;
-  for (int i = 0; i < nb; ++i)
-    for (int j = i; j < nb; ++j) tl.push_back(make_int2(i, j));
-  const int ntiles = (int)tl.size();
-  const void* dtiles = nullptr;
-  XO_RET(device_table(tl.data(), tl.size() * sizeof(int2), s, &dtiles));
-  const void* dw = nullptr;
-  XO_RET(device_table(a->w, sizeof(double) * a->nw, s, &dw));
-
-  const int nwg = a->nw >= 8 ? 8 : (a->nw >= 4 ? 4 : (a->nw >= 2 ? 2 : 1));
-  const int ngroups = (a->nw + nwg - 1) / nwg;
-  const int nwpad = ngroups * nwg;
-  // transitions per wave slice: aim for ~4096 waves in flight, slices a multiple of 16
-  const int step = 16;
-  int slices = std::max(kWaves, (4096 + ntiles - 1) / ntiles);
-  slices = (slices + kWaves - 1) / kWaves * kWaves;
-  int kper = (a->nt + slices - 1) / slices;
-  kper = std::max(step, (kper + step - 1) / step * step);
-  slices = (a->nt + kper - 1) / kper;
-  slices = (slices + kWaves - 1) / kWaves * kWaves;
-  const int nslice_wg = slices / kWaves;
-
-  const size_t wbytes = align_up((size_t)a->nt * nwpad * sizeof(T), 256);
-  const size_t pbytes = (size_t)slices * ntiles * nwg * 2 * 256 * sizeof(T);
-  void* ws = nullptr;
-  XO_RET(workspace(s, 1, wbytes + pbytes + 256, &ws));
-  T* W = static_cast<T*>(ws);
-  void* part = static_cast<char*>(ws) + wbytes;
-  int* bad = reinterpret_cast<int*>(static_cast<char*>(ws) + wbytes + pbytes);
-  if (a->check_dE) XO_TRY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-  {
-    KernelTimer kt_("pole_factors", s);
-    hipLaunchKernelGGL((pole_factors<T>), dim3((a->nt + 255) / 256), dim3(256), 0, s, a->dE, a->nt,
-                       static_cast<const double*>(dw), a->nw, nwpad, W, a->check_dE ? bad : nullptr);
+// Persistent workgroups: take units from the queue until it is exhausted.
+template <int MODE, int NWG, int NT>
+__global__ void __launch_bounds__(256) chi0_units(const Item* __restrict__ items, const int2* __restrict__ tiles,
+                                                  const Unit* __restrict__ units, const int* __restrict__ queue,
+                                                  int nunits, int* __restrict__ counter, void* __restrict__ part) {
+  __shared__ int su;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int PER = NWG * 2 * NT * 256;  // values per wave partial
+  for (;;) {
+    if (threadIdx.x == 0) su = atomicAdd(counter, 1);
+    __syncthreads();
+    const int qpos = su;
+    __syncthreads();
+    if (qpos >= nunits) break;
+    const int uid = queue[qpos];
+    const Unit U = units[uid];
+    const Item I = items[U.item];
+    const int2 bij = tiles[I.tile0 + U.tile];
+    const int len = U.k1 - U.k0;
+    int sub = (len + kWaves - 1) / kWaves;
+    sub = (sub + 15) / 16 * 16;
+    const int kb = min(U.k1, U.k0 + wave * sub), ke = min(U.k1, kb + sub);
+    const size_t off = ((size_t)uid * kWaves + wave) * PER;
+    unit_wave<MODE, NWG, NT>(I, bij, U.w0, kb, ke, lane, static_cast<float*>(part) + off,
+                             static_cast<double*>(part) + off);
   }
-  XO_CHECK_LAUNCH();
-  if (a->check_dE) {
-    int* hb = nullptr;
-    XO_RET(host_flags(s, sizeof(int), reinterpret_cast<void**>(&hb)));
-    XO_TRY_HIP(hipMemcpyAsync(hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    XO_TRY_HIP(hipStreamSynchronize(s));
-    XO_ARG(*hb == 0, "xo_chi0: %d pole energies dE are <= 0 or NaN", *hb);
-  }
-  TileArgs A;
-  A.rho = a->rho;
-  A.W = W;
-  A.nwpad = nwpad;
-  A.w0 = 0;
-  A.ng = a->ng;
-  A.nt = a->nt;
-  A.tiles = static_cast<const int2*>(dtiles);
-  A.ntiles = ntiles;
-  A.kper = kper;
-  A.part = part;
-  for (int g = 0; g < ngroups; ++g) {
-    const int w0 = g * nwg;
-    int r;
-    switch (nwg) {
-      case 8: r = run_group<T, 8>(A, nslice_wg, s, a->prec, w0, a->nw, a->pref, a->accumulate, a->chi0); break;
-      case 4: r = run_group<T, 4>(A, nslice_wg, s, a->prec, w0, a->nw, a->pref, a->accumulate, a->chi0); break;
-      case 2: r = run_group<T, 2>(A, nslice_wg, s, a->prec, w0, a->nw, a->pref, a->accumulate, a->chi0); break;
-      default: r = run_group<T, 1>(A, nslice_wg, s, a->prec, w0, a->nw, a->pref, a->accumulate, a->chi0);
-    }
-    XO_RET(r);
-  }
-  return XO_OK;
 }
 
-}  // namespace
-}  // namespace xo
+struct Red {
+  int item, tile, w0, u0, nu;
+};
 
-extern "C" int xo_chi0(const xo_chi0_args* a, void* stream) {
-  using namespace xo;
-  clear_error();
+// Fixed-order sum of the partials of one output block, scale by -pref, write the
+// block (upper triangle authoritative) and its Hermitian mirror.
+template <typename T, int NWG, int NT>
+__global__ void chi0_reduce(const Item* __restrict__ items, const int2* __restrict__ tiles,
+                            const Red* __restrict__ reds, const T* __restrict__ part) {
+  constexpr int PER = NWG * 2 * NT * 256;
+  const Red R = reds[blockIdx.x];
+  const int w = blockIdx.y;
+  const Item I = items[R.item];
+  if (R.w0 + w >= I.nw) return;
+  const int2 bij = tiles[I.tile0 + R.tile];
+  double* m = I.chi0 + (size_t)(R.w0 + w) * I.ng * I.ng * 2;
+  for (int e2 = threadIdx.x; e2 < 256 * NT; e2 += blockDim.x) {
+    const int n = e2 >> 8, e = e2 & 255;
+    const int ii = e >> 4, jj = e & 15;
+    const int G = bij.x * kTile + ii, Gp = bij.y * kTile * NT + 16 * n + jj;
+    if (G >= I.ng || Gp >= I.ng || G > Gp) continue;
+    double re = 0.0, im = 0.0;
+    for (int u = 0; u < R.nu; ++u)
+      for (int wv = 0; wv < kWaves; ++wv) {
+        const T* p = part + ((size_t)(R.u0 + u) * kWaves + wv) * PER + (size_t)(w * 2) * NT * 256;
+        re += (double)p[n * 256 + e];
+        im += (double)p[(NT + n) * 256 + e];
+      }
+    re *= -I.pref;
+    im *= -I.pref;
+    if (G == Gp) im = 0.0;
+    const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
+    if (I.accumulate) {
+      m[up] += re;
+      m[up + 1] += im;
+      if (G != Gp) {
+        m[lo] += re;
+        m[lo + 1] -= im;
+      }
+    } else {
+      m[up] = re;
+      m[up + 1] = im;
+      if (G != Gp) {
+        m[lo] = re;
+        m[lo + 1] = -im;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- host side --
+
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+static int validate(const xo_chi0_args* a) {
   XO_ARG(a, "xo_chi0: null argument block");
   XO_ARG(a->nt > 0 && a->ng > 0 && a->nw > 0, "xo_chi0: sizes must be positive (nt=%d ng=%d nw=%d)", a->nt,
          a->ng, a->nw);
@@ -353,7 +305,258 @@ extern "C" int xo_chi0(const xo_chi0_args* a, void* stream) {
          a->prec);
   for (int j = 0; j < a->nw; ++j) XO_ARG(a->w[j] >= 0.0, "xo_chi0: frequency %d is negative", j);
   XO_ARG(a->pref > 0.0, "xo_chi0: pref must be positive");
+  return XO_OK;
+}
+
+template <int MODE, int NWG, int NT>
+static int launch_units(const void* ditems, const void* dtiles, const void* dunits, const void* dqueue, int nunits,
+                        int* counter, void* part, const void* dreds, int nreds, int grid, hipStream_t s) {
+  typedef typename std::conditional<MODE == MODE_F64, double, float>::type T;
+  hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 1);
+  XO_CHECK_LAUNCH();
+  {
+    KernelTimer kt_(MODE == MODE_BF16X3 ? "chi0_tiles_bf16x3" : "chi0_tiles", s);
+    hipLaunchKernelGGL((chi0_units<MODE, NWG, NT>), dim3(grid), dim3(256), 0, s,
+                       static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
+                       static_cast<const Unit*>(dunits), static_cast<const int*>(dqueue), nunits, counter, part);
+  }
+  XO_CHECK_LAUNCH();
+  {
+    KernelTimer kt_("chi0_reduce", s);
+    hipLaunchKernelGGL((chi0_reduce<T, NWG, NT>), dim3(nreds, NWG), dim3(256), 0, s,
+                       static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
+                       static_cast<const Red*>(dreds), static_cast<const T*>(part));
+  }
+  XO_CHECK_LAUNCH();
+  return XO_OK;
+}
+
+template <int MODE, int NWG>
+static int launch_nt(int nt_tiles, const void* ditems, const void* dtiles, const void* dunits, const void* dqueue,
+                     int nunits, int* counter, void* part, const void* dreds, int nreds, int grid, hipStream_t s) {
+  if constexpr (MODE == MODE_BF16X3) {
+    if (nt_tiles == 2)
+      return launch_units<MODE, NWG, 2>(ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
+                                        s);
+  }
+  return launch_units<MODE, NWG, 1>(ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid, s);
+}
+
+template <int MODE>
+static int launch_nwg(int nwg, int nt_tiles, const void* ditems, const void* dtiles, const void* dunits,
+                      const void* dqueue, int nunits, int* counter, void* part, const void* dreds, int nreds,
+                      int grid, hipStream_t s) {
+  switch (nwg) {
+    case 8:
+      return launch_nt<MODE, 8>(nt_tiles, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid, s);
+    case 4:
+      return launch_nt<MODE, 4>(nt_tiles, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid, s);
+    case 2:
+      return launch_nt<MODE, 2>(nt_tiles, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid, s);
+    default:
+      return launch_nt<MODE, 1>(nt_tiles, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid, s);
+  }
+}
+
+// Every item of a batch shares the precision and the frequencies.
+static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hipStream_t s) {
+  for (int i = 0; i < n; ++i) XO_RET(validate(&a[i]));
+  const int prec = a[0].prec;
+  for (int i = 1; i < n; ++i) {
+    XO_ARG(a[i].prec == prec && a[i].nw == a[0].nw, "xo_chi0_batch: items must share precision and frequencies");
+    for (int j = 0; j < a[0].nw; ++j)
+      XO_ARG(a[i].w[j] == a[0].w[j], "xo_chi0_batch: items must share the frequency list");
+  }
+  const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : MODE_BF16X3);
+  const size_t tsz = mode == MODE_F64 ? sizeof(double) : sizeof(float);
+  const int nw = a[0].nw;
+  const int nwg = nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1));
+  const int ngroups = (nw + nwg - 1) / nwg;
+  const int nwpad = ngroups * nwg;
+  const int NT = (tune && mode == MODE_BF16X3 && tune->nt_tiles == 2) ? 2 : 1;
+  const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : 4;
+
+  // block pairs: 16-row block i, (16 NT)-column block j, keeping those with a column >= a row
+  std::vector<int2> tiles;
+  std::vector<Item> items(n);
+  std::vector<int> ntl(n);
+  std::vector<size_t> woff(n);
+  size_t wbytes = 0;
+  for (int it = 0; it < n; ++it) {
+    const int ng = a[it].ng;
+    const int nbr = (ng + kTile - 1) / kTile, nbc = (ng + kTile * NT - 1) / (kTile * NT);
+    items[it].tile0 = (int)tiles.size();
+    for (int i = 0; i < nbr; ++i)
+      for (int j = 0; j < nbc; ++j)
+        if (j * kTile * NT + kTile * NT - 1 >= i * kTile) tiles.push_back(make_int2(i, j));
+    ntl[it] = (int)tiles.size() - items[it].tile0;
+    woff[it] = wbytes;
+    wbytes += align_up((size_t)a[it].nt * nwpad * tsz, 256);
+  }
+  long total_blocks = 0;
+  for (int it = 0; it < n; ++it) total_blocks += (long)ntl[it] * ngroups;
+  // units: cut transitions so the batch holds about four units per persistent wave
+  const long want_units = (long)num_cus() * grid_per_cu * 4;
+  std::vector<Unit> units;
+  std::vector<Red> reds;
+  for (int it = 0; it < n; ++it) {
+    int kper;
+    if (tune && tune->kper > 0) {
+      kper = tune->kper;
+    } else {
+      const long slices = std::max(1L, (want_units + total_blocks - 1) / std::max(1L, total_blocks));
+      kper = (int)((a[it].nt + slices - 1) / slices);
+    }
+    kper = std::max(64, (kper + 63) / 64 * 64);
+    for (int t = 0; t < ntl[it]; ++t)
+      for (int g = 0; g < ngroups; ++g) {
+        Red r;
+        r.item = it;
+        r.tile = t;
+        r.w0 = g * nwg;
+        r.u0 = (int)units.size();
+        for (int k0 = 0; k0 < a[it].nt; k0 += kper)
+          units.push_back({it, t, g * nwg, k0, std::min(a[it].nt, k0 + kper)});
+        r.nu = (int)units.size() - r.u0;
+        reds.push_back(r);
+      }
+  }
+  // queue: longest units first (stable: equal units keep their item / block order)
+  std::vector<int> queue(units.size());
+  for (size_t u = 0; u < units.size(); ++u) queue[u] = (int)u;
+  std::stable_sort(queue.begin(), queue.end(), [&](int x, int y) {
+    return (units[x].k1 - units[x].k0) > (units[y].k1 - units[y].k0);
+  });
+  const int nunits = (int)units.size();
+  const size_t per = (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
+  const size_t pbytes = per * nunits;
+  void* ws = nullptr;
+  XO_RET(workspace(s, 1, wbytes + pbytes + 256, &ws));
+  char* wbase = static_cast<char*>(ws);
+  void* part = wbase + wbytes;
+  int* counter = reinterpret_cast<int*>(wbase + wbytes + pbytes);
+
+  bool any_check = false;
+  for (int it = 0; it < n; ++it) any_check |= a[it].check_dE != 0;
+  int* bad = nullptr;
+  if (any_check) {
+    void* wsb = nullptr;
+    XO_RET(workspace(s, 4, 256, &wsb));
+    bad = static_cast<int*>(wsb);
+    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, bad, 1);
+    XO_CHECK_LAUNCH();
+  }
+  const void* dw = nullptr;
+  XO_RET(device_table(a[0].w, sizeof(double) * nw, s, &dw));
+  for (int it = 0; it < n; ++it) {
+    void* W = wbase + woff[it];
+    {
+      KernelTimer kt_("pole_factors", s);
+      if (mode == MODE_F64)
+        hipLaunchKernelGGL((pole_factors<double>), dim3((a[it].nt + 255) / 256), dim3(256), 0, s, a[it].dE,
+                           a[it].nt, static_cast<const double*>(dw), nw, nwpad, static_cast<double*>(W),
+                           a[it].check_dE ? bad : nullptr);
+      else
+        hipLaunchKernelGGL((pole_factors<float>), dim3((a[it].nt + 255) / 256), dim3(256), 0, s, a[it].dE,
+                           a[it].nt, static_cast<const double*>(dw), nw, nwpad, static_cast<float*>(W),
+                           a[it].check_dE ? bad : nullptr);
+    }
+    XO_CHECK_LAUNCH();
+    items[it].rho = a[it].rho;
+    items[it].W = W;
+    items[it].chi0 = a[it].chi0;
+    items[it].pref = a[it].pref;
+    items[it].nt = a[it].nt;
+    items[it].ng = a[it].ng;
+    items[it].nwpad = nwpad;
+    items[it].nw = nw;
+    items[it].accumulate = a[it].accumulate;
+  }
+  if (any_check) {
+    int* hb = nullptr;
+    XO_RET(host_flags(s, sizeof(int), reinterpret_cast<void**>(&hb)));
+    XO_TRY_HIP(hipMemcpyAsync(hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    XO_TRY_HIP(hipStreamSynchronize(s));
+    XO_ARG(*hb == 0, "xo_chi0: %d pole energies dE are <= 0 or NaN", *hb);
+  }
+  const void *ditems = nullptr, *dtiles = nullptr, *dunits = nullptr, *dqueue = nullptr, *dreds = nullptr;
+  XO_RET(device_table(items.data(), items.size() * sizeof(Item), s, &ditems));
+  XO_RET(device_table(tiles.data(), tiles.size() * sizeof(int2), s, &dtiles));
+  XO_RET(device_table(units.data(), units.size() * sizeof(Unit), s, &dunits));
+  XO_RET(device_table(queue.data(), queue.size() * sizeof(int), s, &dqueue));
+  XO_RET(device_table(reds.data(), reds.size() * sizeof(Red), s, &dreds));
+  const int grid = std::min(nunits, num_cus() * grid_per_cu);
+  const int nreds = (int)reds.size();
+  if (mode == MODE_F64)
+    return launch_nwg<MODE_F64>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
+                                s);
+  if (mode == MODE_F32)
+    return launch_nwg<MODE_F32>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
+                                s);
+  return launch_nwg<MODE_BF16X3>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
+                                 s);
+}
+
+}  // namespace
+}  // namespace xo
+
+extern "C" int xo_chi0(const xo_chi0_args* a, void* stream) {
+  xo::clear_error();
+  XO_ARG(a, "xo_chi0: null argument block");
+  return xo::chi0_batch_run(a, 1, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream) {
+  xo::clear_error();
+  XO_ARG(items && n > 0, "xo_chi0_batch: need a non-empty array of items");
+  if (tune) {
+    XO_ARG(tune->nt_tiles >= 0 && tune->nt_tiles <= 2, "xo_chi0_batch: nt_tiles must be 0, 1 or 2");
+    XO_ARG(tune->kper >= 0 && tune->wg_per_cu >= 0 && tune->wg_per_cu <= 16, "xo_chi0_batch: bad tune values");
+  }
+  return xo::chi0_batch_run(items, n, tune, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* best_ms, void* stream) {
+  xo::clear_error();
+  XO_ARG(items && n > 0 && best, "xo_chi0_autotune: bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (a->prec == XO_FP64) return chi0_run<double>(a, s);
-  return chi0_run<float>(a, s);
+  std::vector<xo_tune> cands;
+  const int nts = items[0].prec == XO_BF16X3 ? 2 : 1;
+  int ntmax = 0;
+  for (int i = 0; i < n; ++i) ntmax = std::max(ntmax, items[i].nt);
+  for (int nt = 1; nt <= nts; ++nt)
+    for (int kper : {0, 2048, 8192, 32768})
+      for (int wpc : {2, 4, 8}) {
+        if (kper > 0 && kper / 2 > ntmax) continue;
+        cands.push_back({nt, kper, wpc});
+      }
+  hipEvent_t e0, e1;
+  XO_TRY_HIP(hipEventCreate(&e0));
+  XO_TRY_HIP(hipEventCreate(&e1));
+  double tbest = 1e300;
+  xo_tune tb = cands[0];
+  int rc = XO_OK;
+  for (const xo_tune& c : cands) {
+    float ms = 0.f;
+    rc = xo::chi0_batch_run(items, n, &c, s);  // warm-up: allocations and tables
+    if (rc != XO_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = XO_ERR_HIP; break; }
+    rc = xo::chi0_batch_run(items, n, &c, s);
+    if (rc != XO_OK) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = XO_ERR_HIP;
+      break;
+    }
+    if (ms < tbest) {
+      tbest = ms;
+      tb = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != XO_OK) return rc;
+  *best = tb;
+  if (best_ms) *best_ms = tbest;
+  return XO_OK;
 }

@@ -62,6 +62,10 @@ class TailArgs(C.Structure):
     ]
 
 
+class Tune(C.Structure):
+    _fields_ = [("nt_tiles", C.c_int), ("kper", C.c_int), ("wg_per_cu", C.c_int)]
+
+
 class XoError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRNAME.get(code, code)}: {msg}")
@@ -71,7 +75,7 @@ class XoError(RuntimeError):
 _LIB = None
 
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
-           "xo_rho", "xo_rho_batch", "xo_chi0", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
+           "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard")
 
 
@@ -104,6 +108,11 @@ def lib():
                    "xo_tail_features", "xo_tail_apply", "xo_tail_guard"):
             getattr(L, nm).restype = C.c_int
         L.xo_rho_batch.argtypes = [C.POINTER(RhoArgs), C.c_int, C.c_void_p]
+        L.xo_chi0_batch.argtypes = [C.POINTER(Chi0Args), C.c_int, C.POINTER(Tune), C.c_void_p]
+        L.xo_chi0_batch.restype = C.c_int
+        L.xo_chi0_autotune.argtypes = [C.POINTER(Chi0Args), C.c_int, C.POINTER(Tune), C.POINTER(C.c_double),
+                                       C.c_void_p]
+        L.xo_chi0_autotune.restype = C.c_int
         L.xo_rho_batch.restype = C.c_int
         L.xo_release_workspace.restype = C.c_int
         L.xo_timing_enable.argtypes = [C.c_int]
@@ -249,6 +258,40 @@ def chi0(rho_m, dE, omegas: Sequence[float], pref: float, *, out, prec="fp64", a
     a.accumulate, a.check_dE, a.chi0 = int(bool(accumulate)), int(bool(check_dE)), _ptr(out)
     _check(lib().xo_chi0(C.byref(a), _stream(stream)))
     return out
+
+
+def _chi0_args(rho_m, dE, omegas, pref, out, prec, accumulate, check_dE):
+    import torch
+    w = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    assert rho_m.ndim == 2 and rho_m.dtype == _cdtype(prec), (rho_m.shape, rho_m.dtype)
+    assert dE.numel() == rho_m.shape[0] and dE.dtype == torch.float64
+    assert tuple(out.shape) == (w.shape[0], rho_m.shape[1], rho_m.shape[1]) and out.dtype == torch.complex128
+    a = Chi0Args()
+    a.nt, a.ng, a.nw = rho_m.shape[0], rho_m.shape[1], w.shape[0]
+    a.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    a.rho, a.dE, a.w, a.pref = _ptr(rho_m), _ptr(dE), w.ctypes.data_as(_f64p), float(pref)
+    a.accumulate, a.check_dE, a.chi0 = int(bool(accumulate)), int(bool(check_dE)), _ptr(out)
+    return a, w
+
+
+def chi0_batch(items, omegas, *, prec="fp64", tune=None, check_dE=True, stream=None):
+    """xo_chi0_batch over items = [(rho, dE, pref, out), ...] sharing the frequencies."""
+    built = [_chi0_args(r, d, omegas, p, o, prec, False, check_dE) for r, d, p, o in items]
+    arr = (Chi0Args * len(built))(*[b[0] for b in built])
+    t = None
+    if tune is not None:
+        t = Tune(*[int(x) for x in tune])
+    _check(lib().xo_chi0_batch(arr, len(built), C.byref(t) if t is not None else None, _stream(stream)))
+
+
+def chi0_autotune(items, omegas, *, prec="fp64", stream=None):
+    """Fastest (nt_tiles, kper, wg_per_cu) for this batch and its time in ms."""
+    built = [_chi0_args(r, d, omegas, p, o, prec, False, False) for r, d, p, o in items]
+    arr = (Chi0Args * len(built))(*[b[0] for b in built])
+    t = Tune()
+    ms = C.c_double()
+    _check(lib().xo_chi0_autotune(arr, len(built), C.byref(t), C.byref(ms), _stream(stream)))
+    return (t.nt_tiles, t.kper, t.wg_per_cu), ms.value
 
 
 def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, stream=None):

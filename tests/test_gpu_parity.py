@@ -245,3 +245,57 @@ def test_alloc_failure_is_reported_and_recovers():
     M, dE, chi, E = run_crystal(dc)
     Eref = epsinv_sym(chi0_crystal(cr), cr.qpg())
     assert rel_fro(E.cpu().numpy(), Eref) < 1e-11
+
+
+# ------------------------------------------------------------- batched persistent
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8)])
+def test_chi0_batch_uneven_items(prec, tol, tune):
+    """Items with different G-set sizes and transition counts in one persistent launch."""
+    if prec == "fp64" and tune is not None and tune[0] == 2:
+        pytest.skip("two column tiles per wave exist for bf16x3 only (fp64 runs one)")
+    say(f"chi0 batch {prec} tune={tune}")
+    shapes = [(700, 17), (1300, 33), (96, 50), (2000, 41)]
+    w = [0.0, 0.3, 1.0]
+    items, refs = [], []
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    for k, (nt, ng) in enumerate(shapes):
+        M = random_complex(50 + k, (nt, ng))
+        dE = random_positive(60 + k, nt, 0.05, 3.0)
+        if prec != "fp64":
+            M = M.astype(np.complex64).astype(np.complex128)
+        refs.append(chi0_from_rho(M, dE, w, 0.5 + k))
+        out = torch.empty((3, ng, ng), dtype=torch.complex128, device=DEV)
+        items.append((_to(M, cdt), _to(dE, torch.float64), 0.5 + k, out))
+    xo.chi0_batch(items, w, prec=prec, tune=tune)
+    for (_, _, _, out), ref in zip(items, refs):
+        got = out.cpu().numpy()
+        assert rel_fro(got, ref) < tol
+        for j in range(3):
+            assert np.array_equal(got[j], got[j].conj().T)
+
+
+def test_chi0_batch_equals_single_calls_and_autotune():
+    shapes = [(900, 24), (1500, 40)]
+    w = [0.0, 1.0]
+    items = []
+    for k, (nt, ng) in enumerate(shapes):
+        M = random_complex(70 + k, (nt, ng))
+        dE = random_positive(80 + k, nt, 0.05, 3.0)
+        items.append((_to(M), _to(dE, torch.float64), 1.0, torch.empty((2, ng, ng), dtype=torch.complex128,
+                                                                         device=DEV)))
+    xo.chi0_batch(items, w)
+    for Md, dEd, pref, out in items:
+        single = torch.empty_like(out)
+        xo.chi0(Md, dEd, w, pref, out=single)
+        a, b = out.cpu().numpy(), single.cpu().numpy()
+        assert np.abs(a - b).max() < 1e-14 * np.abs(b).max()
+    best, ms = xo.chi0_autotune(items, w)
+    say(f"  autotune best {best} {ms:.3f} ms")
+    assert best[0] in (1, 2) and ms > 0
+    xo.chi0_batch(items, w, tune=best)
+    for Md, dEd, pref, out in items:
+        single = torch.empty_like(out)
+        xo.chi0(Md, dEd, w, pref, out=single)
+        assert np.abs(out.cpu().numpy() - single.cpu().numpy()).max() < 1e-14 * single.abs().max().item()
