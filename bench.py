@@ -195,6 +195,110 @@ def roofline(cr, form, K, nw, ng):
     return dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None)
 
 
+def run_c3(args):
+    """Batched persistent workload: 3x3x3 k-grid, all 27 q-points, uneven G-sets (169..893),
+    32 occupied + 400 empty bands, 48^3 grid, 16 frequencies; bf16x3 rho and chi0 with one
+    persistent chi0 launch over all q (tiles autotuned), FP64 eps^-1 per q."""
+    import torch
+    from synth.configs import crystal_q_set
+    from paper_1902_03837_amd import xo, tune
+    from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE
+
+    t0 = time.perf_counter()
+    crs = crystal_q_set("c3", nq=args.nq)
+    t_fix = time.perf_counter() - t0
+    print(f"[bench] c3 fixture: {len(crs)} q-points, NG {[c.gmill.shape[0] for c in crs]}, {t_fix:.1f} s",
+          file=sys.stderr, flush=True)
+    nw = len(crs[0].omegas)
+
+    def build(prec):
+        base = DeviceCrystal.upload(crs[0], prec)
+        dcs = [DeviceCrystal(cr, prec, base.coef, base.eps) for cr in crs]
+        bufs = []
+        for cr in crs:
+            ng, K = cr.gmill.shape[0], ntrans(cr)
+            bufs.append(dict(M=torch.empty((K, ng), dtype=CDTYPE[prec], device="cuda"),
+                             dE=torch.empty(K, dtype=torch.float64, device="cuda"),
+                             chi=torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda"),
+                             E=torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda")))
+        return dcs, bufs
+
+    def step(dcs, bufs, prec, tn, ev=None):
+        st = torch.cuda.current_stream()
+        if ev:
+            ev[0].record(st)
+        for dc, b in zip(dcs, bufs):
+            rho_all(dc, b["M"], b["dE"])
+        if ev:
+            ev[1].record(st)
+        xo.chi0_batch([(b["M"], b["dE"], dc.cr.pref, b["chi"]) for dc, b in zip(dcs, bufs)], crs[0].omegas,
+                      prec=prec, tune=tn, check_dE=False)
+        if ev:
+            ev[2].record(st)
+        for dc, b in zip(dcs, bufs):
+            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"])
+        if ev:
+            ev[3].record(st)
+
+    out = {}
+    Eall = {}
+    for prec in args.c3_forms.split(","):
+        dcs, bufs = build(prec)
+        tn = None
+        if prec != "fp64":
+            for dc, b in zip(dcs, bufs):
+                rho_all(dc, b["M"], b["dE"])
+            items = [(b["M"], b["dE"], dc.cr.pref, b["chi"]) for dc, b in zip(dcs, bufs)]
+            tn, tms, cached = tune.tuned(items, crs[0].omegas, prec, path=args.tune_cache)
+            print(f"[bench] c3 {prec}: tuned chi0 launch {tn} ({tms:.2f} ms on a sample, cached={cached})",
+                  file=sys.stderr, flush=True)
+        nsteps = args.steps if prec != "fp64" else 1
+        for _ in range(args.warmup if prec != "fp64" else 0):
+            step(dcs, bufs, prec, tn)
+        torch.cuda.synchronize()
+        xo.timing_report()
+        xo.timing_enable(True)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nsteps)]
+        for i in range(nsteps):
+            step(dcs, bufs, prec, tn, evs[i])
+        torch.cuda.synchronize()
+        xo.timing_enable(False)
+        kern = xo.timing_report()
+        ms = float(np.median([evs[i][0].elapsed_time(evs[i][3]) for i in range(nsteps)]))
+        st = [float(np.median([evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(nsteps)])) for j in range(3)]
+        Ks = [b["M"].shape[0] for b in bufs]
+        ngs = [b["M"].shape[1] for b in bufs]
+        fl = sum(4.0 * ng * ng * K * nw for ng, K in zip(ngs, Ks))
+        res = dict(ms_per_step=ms, stage_ms=dict(rho=st[0], chi0=st[1], eps=st[2]),
+                   chi0_GFLOPs=fl / (ms * 1e-3) / 1e9, chi0_kernel_TFLOPs=None,
+                   transitions_per_s_per_qw=sum(Ks) * nw / (ms * 1e-3), tune=tn,
+                   kernels={k: dict(launches=v[0] // nsteps, ms_per_step=v[1] / nsteps) for k, v in kern.items()})
+        ck = [k for k in kern if k.startswith("chi0_tiles")]
+        if ck:
+            res["chi0_kernel_TFLOPs"] = fl / (kern[ck[0]][1] / nsteps * 1e-3) / 1e12
+        Eall[prec] = [b["E"].cpu().numpy() for b in bufs]
+        out[prec] = res
+        print(f"[bench] c3 {prec}: {ms:.1f} ms/step (rho {st[0]:.1f}, chi0 {st[1]:.1f}, eps {st[2]:.1f}), "
+              f"chi0 {res['chi0_GFLOPs']:.0f} GFLOP/s over the step", file=sys.stderr, flush=True)
+        del dcs, bufs
+        torch.cuda.empty_cache()
+    if "fp64" in Eall:
+        for prec in out:
+            if prec != "fp64":
+                out[prec]["e_F_vs_fp64"] = max(float(np.linalg.norm(E[j] - R[j]) / np.linalg.norm(R[j]))
+                                               for E, R in zip(Eall[prec], Eall["fp64"]) for j in range(nw))
+                print(f"[bench] c3 {prec}: e_F vs fp64 {out[prec]['e_F_vs_fp64']:.3e}", file=sys.stderr,
+                      flush=True)
+    res = {"metric": "chi0 GFLOP/s + transitions/s per q,w (batched persistent workload)",
+           "workload": f"c3: fcc 3x3x3 k, {len(crs)} q-points, NG {min(c.gmill.shape[0] for c in crs)}.."
+                       f"{max(c.gmill.shape[0] for c in crs)}, 32 occ + 400 empty bands, FFT 48^3, {nw} freqs",
+           "forms": out, "fixture_s": t_fix}
+    if args.detail:
+        with open(args.detail, "w") as fh:
+            json.dump(res, fh, indent=1)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +309,9 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--detail", default=None, help="write the per-form detail JSON here")
+    ap.add_argument("--nq", type=int, default=27, help="c3: number of q-points")
+    ap.add_argument("--c3-forms", default="bf16x3,fp64", help="c3: forms to time (fp64 is the reference)")
+    ap.add_argument("--tune-cache", default=None, help="c3: JSON file for autotuned launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -216,6 +323,8 @@ def main():
     import torch
     from synth import crystal_for
 
+    if args.workload == "c3":
+        return run_c3(args)
     t0 = time.perf_counter()
     cr = crystal_for(args.workload)
     t_fix = time.perf_counter() - t0

@@ -83,3 +83,34 @@ def crystal_for(name: str, seed: int = None, q=None, potential_zero: bool = Fals
                       scissor_min=None if nb_all else 0.05)
     cr.meta = dict(name=name, spec=spec)
     return cr
+
+
+def crystal_q_set(name: str = "c3", seed: int = None, nq: int = None, **over):
+    """One crystal per q of the k-grid (all q = k-differences), sharing the orbitals.
+
+    The G-set size of each q is a closed-shell count drawn with seed + iq from the
+    configured range, so the set has uneven G-set sizes.
+    """
+    from dataclasses import replace
+    from .crystal import find_pairs, qpg_norms
+    spec = dict(CONFIGS[name], **over)
+    seed = spec["seed"] if seed is None else seed
+    kf = _kset(spec)
+    qs = kf.copy() if spec["q"] == "all" else np.array([spec["q"]], float)
+    if nq is not None:
+        qs = qs[:nq]
+    base = crystal_for(name, seed=seed, q=qs[0], **over)
+    lo, hi = spec["ng"] if not np.isscalar(spec["ng"]) else (spec["ng"], spec["ng"])
+    choices = closed_shell_counts(lo, hi) if lo != hi else [lo]
+    from .crystal import alias_extents
+    out = []
+    for iq, q in enumerate(qs):
+        ng = int(choices[np.random.default_rng(seed + iq).integers(len(choices))])
+        cr = replace(base, qf=np.asarray(q, float), pairs=find_pairs(base.kf, np.asarray(q, float)),
+                     gmill=gset_sorted(base.lat, ng), meta=dict(base.meta, iq=iq))
+        for ik, ikp, g0 in cr.pairs:
+            ext = alias_extents(cr.grid, cr.mill[ik], cr.mill[ikp], cr.gmill, g0)
+            if np.any(ext >= np.array(cr.grid)):
+                raise ValueError(f"q #{iq}: grid {cr.grid} aliases (reach {ext})")
+        out.append(cr)
+    return out

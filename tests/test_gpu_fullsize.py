@@ -1,0 +1,65 @@
+"""The benchmark workload at full size (c2: 64 k-pairs, 16 + 200 bands, 36^3, NG = 400, 8
+frequencies, K = 204 800), in the launch configuration bench.py times: sampled columns of
+rho and of chi0 against the oracle computed column by column, and properties of eps~^-1
+that hold at any size."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import crystal_for  # noqa: E402
+from oracle.rho import rho_direct  # noqa: E402
+from oracle.chi0 import chi0_from_rho  # noqa: E402
+from oracle.epsinv import eps_tilde  # noqa: E402
+from paper_1902_03837_amd import xo  # noqa: E402
+from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal  # noqa: E402
+
+SAMPLE = [0, 1, 7, 58, 211, 399]
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+    cr = crystal_for("c2")
+    # oracle: the sampled G columns of rho for every pair, by the direct plane-wave sum
+    Ms, dEs = [], []
+    for ik, ikp, g0 in cr.pairs:
+        cc, cv = cr.coef[ik][cr.nocc:], cr.coef[ikp][:cr.nocc]
+        r = rho_direct(cc, cr.mill[ik], cv, cr.mill[ikp], cr.gmill[SAMPLE], g0)
+        Ms.append(r.reshape(-1, len(SAMPLE)))
+        dEs.append((cr.eps[ik][cr.nocc:][None, :] - cr.eps[ikp][:cr.nocc][:, None]).reshape(-1))
+    Mref, dEref = np.concatenate(Ms), np.concatenate(dEs)
+    chiref = chi0_from_rho(Mref, dEref, cr.omegas, cr.pref)
+    return cr, Mref, chiref
+
+
+@pytest.mark.parametrize("prec,rtol_rho,rtol_chi", [("fp64", 1e-12, 1e-12), ("bf16x3", 5e-5, 5e-5)])
+def test_c2_full_size_sampled(c2, prec, rtol_rho, rtol_chi):
+    cr, Mref, chiref = c2
+    say(f"c2 full size {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    M, dE, chi, E = run_crystal(dc, check_dE=False)
+    torch.cuda.synchronize()
+    Mg = M[:, SAMPLE].cpu().numpy().astype(np.complex128)
+    erho = np.abs(Mg - Mref).max() / np.abs(Mref).max()
+    chig = chi.cpu().numpy()[:, SAMPLE][:, :, SAMPLE]
+    echi = np.abs(chig - chiref).max() / np.abs(chiref).max()
+    say(f"  sampled rho err {erho:.2e}, sampled chi0 err {echi:.2e}")
+    assert erho < rtol_rho and echi < rtol_chi
+    # eps~^-1 at full size: inverse of the eps~ built from the returned chi0, Hermitian, spectrum in (0, 1]
+    chi_h, E_h = chi.cpu().numpy(), E.cpu().numpy()
+    et = eps_tilde(chi_h, cr.qpg())
+    for j in range(len(cr.omegas)):
+        assert np.abs(et[j] @ E_h[j] - np.eye(et.shape[-1])).max() < 1e-10
+        assert np.abs(E_h[j] - E_h[j].conj().T).max() < 1e-10
+        ev = np.linalg.eigvalsh(0.5 * (E_h[j] + E_h[j].conj().T))
+        assert ev.min() > 0 and ev.max() <= 1 + 1e-10
