@@ -184,14 +184,14 @@ def roofline(cr, form, K, nw, ng):
         return dict(kernel=name, bound="alu", achieved=fl / t / 1e12, peak=PEAK["valu"] / 1e12,
                     unit="TFLOP/s", frac=fl / t / PEAK["valu"], traffic=None,
                     note="useful complex MACs of the z-correlation and pruned y-DFT, 8 flops each")
-    if name == "rho_mfma":
+    if name == "rho_yz":
         # algorithmic count: an FFT of the product grid per transition, 5 N_r log2 N_r
         nr = float(np.prod(cr.grid))
         fl = 5.0 * nr * np.log2(nr) * K / k["launches"]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=PEAK["bf16_mfma"] / 1e12,
                     unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name),
                     note="algorithmic flops 5 N_r log2 N_r per transition (FFT-equivalent) over the bf16 "
-                         "dense peak; the kernel executes split-bf16 (x3) padded 16x16 tiles")
+                         "dense peak; the kernel executes the y-z correlation as split-bf16 (x3) 16x16x32 tiles")
     return dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None)
 
 

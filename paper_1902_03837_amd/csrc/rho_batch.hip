@@ -1,29 +1,35 @@
 // Oscillator strengths on MFMA (split bf16, FP32 accumulation), many k-pairs per
-// launch. Same factorisation as the VALU path (rho.hip):
+// launch.
 //
-//   U(x, y, m_z)  orbitals, real space in x and y, Miller index in z
-//   S1(x,y,e_z)   = sum_m conj(U_c(x,y,m)) U_v(x,y,m - e_z)      stage 1
-//   S2(x,e_y,e_z) = sum_y exp(2 pi i e_y y/Ny) S1(x,y,e_z)       stage 2
-//   rho(G)        = 1/(Nx Ny) sum_x exp(2 pi i e_x x/Nx) S2(x,e_y,e_z)
+// The transform of the real-space product conj(psi_c) psi_v (Eq. rhotw) is
+// factorised by axis. Orbitals are carried real-space along x and as plane-wave
+// (Miller) coefficients along y and z:
 //
-// but stages 1 and 2 run as 16x16 complex matrix products on
-// v_mfma_f32_16x16x32_bf16 and stage 3 is fused into the same workgroup:
+//   U(x, m_y, m_z) = sum_{m_x} c(m) exp(2 pi i m_x x / Nx)                (orb_x)
 //
-//   stage 1, per (c, x, y): Toeplitz(conj U_c)[e_z][m] x U_v[m][v]   (16 v per tile)
-//   stage 2, per (c, x, e_z): F[e_y][y] x S1[y][v]                     (y in chunks of 16)
-//   stage 3: every workgroup owns rho[v][c][G] for its 16 valence bands and
-//            accumulates exp(2 pi i e_x x/Nx) S2 over its x-planes.
+// For one x-plane the y and z part of the transform of the product is then the
+// correlation of the two orbitals' (m_y, m_z) spectra, exact with no grid along
+// those axes; the x part is a DFT of the plane values over the real-space grid:
 //
-// Complex operands use interleaved real K (k = 2n + a): for C = conj(A)^T B,
-// the left operand of Re C is the raw (re, im) pair of A and that of Im C is
-// (-im, re). Every FP32 value x enters as hi = bf16(x) and lo = bf16(x - hi);
-// each product is hi*hi + hi*lo + lo*hi, accumulated in FP32.
+//   P_x(e_y, e_z) = sum_b conj(U_c(x, b + e)) U_v(x, b)      b over the valence (m_y, m_z)
+//   rho(e)        = 1/Nx sum_x exp(2 pi i e_x x / Nx) P_x(e_y, e_z)
+//
+// with e = m_G - G0 and rho_cv(e) = sum_a conj(c_c(a)) c_v(a - e), the same
+// quantity as the 3D FFT of the product on any alias-free grid. Per x-plane the
+// correlation is a complex matrix product: rows are the (e_y, e_z) columns of the
+// G-set, the contraction runs over the valence (m_y, m_z) support, and the 16
+// valence bands of a workgroup form the columns. The left operand is a 2D Toeplitz
+// gather from the conduction orbital's plane, held in LDS.
+//
+// Complex operands use interleaved real K (k = 2b + a): the left operand is the
+// raw (re, im) pair of U_c, the right operand of Re P is (re, im) of U_v and that
+// of Im P is (im, -re). Every FP32 value x enters as hi = bf16(x) and lo =
+// bf16(x - hi); each product is hi*hi + hi*lo + lo*hi, accumulated in FP32.
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <vector>
 
 #include "bf16x3.h"
@@ -36,134 +42,85 @@ int rho_valu(const xo_rho_args* a, hipStream_t s);
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kLP = 32;  // zero padding on each side of an orbital line in LDS
 
 // --------------------------------------------------------------- orbitals --
-struct OrbSide {
-  const float2* coef;
-  const SphereEntry* ent;
-  const int* zoff;
-  uint32_t* Uhi;
+struct OrbX {
+  const float2* coef;   // [nb][npw]
+  const int* boxidx;    // [npw] (col * nbx + bx) of each plane wave, col = by * nbz + bz
+  const int* outcol;    // [nout] box column written at each output position, or -1
+  uint32_t* Uhi;        // [nb][Nx][nout] split bf16 (re, im) pairs
   uint32_t* Ulo;
-  int npw, nb, nslot;
-  int xlo, nbx, ylo, nby;
+  int npw, nb, nout, nbx, ncol, xlo;
 };
 
-// U[b][x][y][s] as split bf16 pairs. One workgroup per (band, side): for z-slots
-// in chunks of 8, scatter the plane waves into dense (m_y, m_x) boxes in LDS,
-// transform along x, then along y, and write each (x, y)'s chunk contiguously.
-constexpr int kSC = 8;
-
-template <int NO>
-__global__ void __launch_bounds__(kBlock) orb_split(const OrbSide* __restrict__ sides, int Nx, int Ny,
-                                                    const float2* __restrict__ twt) {
+// One workgroup per (band, side): scatter the plane waves into a dense
+// (column, m_x) box in LDS, transform every needed column along x and write
+// the split values in the layout the rho kernel reads.
+__global__ void __launch_bounds__(kBlock) orb_x(const OrbX* __restrict__ sides, int Nx,
+                                                const float2* __restrict__ twt) {
   extern __shared__ unsigned char smem[];
-  const OrbSide S = sides[blockIdx.y];
+  const OrbX S = sides[blockIdx.y];
   const int b = blockIdx.x;
   if (b >= S.nb) return;
-  float2* twx = reinterpret_cast<float2*>(smem);  // [Nx] then [Ny]
-  float2* twy = twx + Nx;
-  float2* box = twy + Ny;                        // [kSC][nby][nbx]
-  float2* V = box + kSC * S.nby * S.nbx;         // [kSC][nby][Nx]
-  const int nbb = S.nby * S.nbx;
-  for (int k = threadIdx.x; k < Nx + Ny; k += blockDim.x) twx[k] = twt[k];
-  uint32_t* uh = S.Uhi + (size_t)b * Nx * Ny * NO;
-  uint32_t* ul = S.Ulo + (size_t)b * Nx * Ny * NO;
-  for (int s0 = 0; s0 < NO; s0 += kSC) {
-    if (s0 >= S.nslot) {
-      for (int i = threadIdx.x; i < Nx * Ny * kSC; i += blockDim.x) {
-        const int xy = i / kSC, j = i - (i / kSC) * kSC;
-        uh[(size_t)xy * NO + s0 + j] = 0u;
-        ul[(size_t)xy * NO + s0 + j] = 0u;
-      }
-      continue;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kSC * nbb; e += blockDim.x) box[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const int s1 = min(s0 + kSC, S.nslot);
-    for (int p = S.zoff[s0] + threadIdx.x; p < S.zoff[s1]; p += blockDim.x) {
-      const SphereEntry e = S.ent[p];
-      // slot of plane wave p: the z-slot whose [zoff[s], zoff[s+1]) range holds p
-      int j = 0;
-      while (S.zoff[s0 + j + 1] <= p) ++j;
-      box[j * nbb + e.by * S.nbx + e.bx] = S.coef[(size_t)b * S.npw + e.src];
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < kSC * S.nby * Nx; it += blockDim.x) {
-      const int x = it % Nx, jb = it / Nx;           // jb = j * nby + by
+  float2* tw = reinterpret_cast<float2*>(smem);  // [Nx]
+  float2* box = tw + Nx;                         // [ncol][nbx]
+  for (int k = threadIdx.x; k < Nx; k += kBlock) tw[k] = twt[k];
+  for (int e = threadIdx.x; e < S.ncol * S.nbx; e += kBlock) box[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int p = threadIdx.x; p < S.npw; p += kBlock) box[S.boxidx[p]] = S.coef[(size_t)b * S.npw + p];
+  __syncthreads();
+  uint32_t* uh = S.Uhi + (size_t)b * Nx * S.nout;
+  uint32_t* ul = S.Ulo + (size_t)b * Nx * S.nout;
+  for (int it = threadIdx.x; it < Nx * S.nout; it += kBlock) {
+    const int x = it / S.nout, j = it - (it / S.nout) * S.nout;
+    const int col = S.outcol[j];
+    float2 acc = make_float2(0.f, 0.f);
+    if (col >= 0) {
+      const float2* row = box + col * S.nbx;
       int k = pmod(S.xlo * x, Nx);
-      const float2* row = box + jb * S.nbx;
-      float2 acc = make_float2(0.f, 0.f);
       for (int bx = 0; bx < S.nbx; ++bx) {
-        const float2 c = row[bx], w = twx[k];
+        const float2 c = row[bx], w = tw[k];
         acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
         acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
         k += x;
         if (k >= Nx) k -= Nx;
       }
-      V[jb * Nx + x] = acc;
     }
-    __syncthreads();
-    for (int xy = threadIdx.x; xy < Nx * Ny; xy += blockDim.x) {
-      const int x = xy / Ny, y = xy - (xy / Ny) * Ny;
-      const int k0 = pmod(S.ylo * y, Ny);
-      uint32_t hv[kSC], lv[kSC];
-#pragma unroll
-      for (int j = 0; j < kSC; ++j) {
-        int k = k0;
-        float2 acc = make_float2(0.f, 0.f);
-        if (s0 + j < S.nslot) {
-          for (int by = 0; by < S.nby; ++by) {
-            const float2 c = V[(j * S.nby + by) * Nx + x], w = twy[k];
-            acc.x = fmaf(c.x, w.x, fmaf(-c.y, w.y, acc.x));
-            acc.y = fmaf(c.x, w.y, fmaf(c.y, w.x, acc.y));
-            k += y;
-            if (k >= Ny) k -= Ny;
-          }
-        }
-        split2(acc.x, acc.y, hv[j], lv[j]);
-      }
-      u4* dh = reinterpret_cast<u4*>(uh + (size_t)xy * NO + s0);
-      u4* dl = reinterpret_cast<u4*>(ul + (size_t)xy * NO + s0);
-      dh[0] = u4{hv[0], hv[1], hv[2], hv[3]};
-      dh[1] = u4{hv[4], hv[5], hv[6], hv[7]};
-      dl[0] = u4{lv[0], lv[1], lv[2], lv[3]};
-      dl[1] = u4{lv[4], lv[5], lv[6], lv[7]};
-    }
+    uint32_t h, l;
+    split2(acc.x, acc.y, h, l);
+    uh[it] = h;
+    ul[it] = l;
   }
 }
 
 // ------------------------------------------------------------------- rho --
+// Per-pair geometry tables, one int array (offsets below are into it):
+//   cpos[ncb]          extended-box position of each conduction box entry, or -1
+//   kg[Kp/4]           box offset of each valence K-group (4 consecutive m_z)
+//   oe[nE][MT*16]      box offset of each (e_y, e_z) row of each e-group
+//   gl[nE][GPT*64]     owned G entries: G | row << 16 | (e_x mod Nx) << 24, or -1
 struct PairDesc {
-  const uint32_t* Uc_hi;
+  const uint32_t* Uc_hi;  // [nc][Nx][ncb]
   const uint32_t* Uc_lo;
-  const uint32_t* Uv_hi;
+  const uint32_t* Uv_hi;  // [nv][Nx][Kp]
   const uint32_t* Uv_lo;
-  float2* rho;          // [nv][nc][ng]
-  const uint32_t* F;    // [4][16 iz][16 slot][Nyp]: (re hi, re lo, im hi, im lo)
-  const int* gtab;      // [ng]: iz | srow << 5 | (e_x mod Nx) << 10
-  int nc, nv, nvt, d0, nz, wg0;
+  float2* rho;            // [nv][nc][ng]
+  const int* tab;
+  int cpos, kg, oe, gl;   // offsets into tab
+  int nc, nv, nvt, nE, ncb, Kp, CS, wg0;
+  int mte[8];             // M-tiles used by each e-group (at most 8 groups)
 };
 
-template <int NK, int GPT>
-__global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ pairs, int npairs, int nwg,
-                                                   int Nx, int Ny, int Nyp, int ng,
-                                                   const float2* __restrict__ twtab, float scale) {
-  constexpr int NO = 16 * NK;
-  constexpr int LW = NO + 2 * kLP;
-  extern __shared__ uint32_t lds[];
-  uint32_t* Ahi = lds;                 // [Ny][LW]
-  uint32_t* Alo = Ahi + Ny * LW;       // [Ny][LW]
-  uint32_t* S1hi = Alo + Ny * LW;      // [16 iz][4 yq][16 v][4 y]
-  uint32_t* S1lo = S1hi + 4096;
-  float2* S2p = reinterpret_cast<float2*>(S1hi);  // [16 iz][16 slot][16 v], aliases S1
-  float2* twx = reinterpret_cast<float2*>(S1lo + 4096);  // [Nx e][Nx x]
-  int* gt = reinterpret_cast<int*>(twx + Nx * Nx);       // [ng]
+constexpr int kMaxGroups = 8;
+constexpr int kMaxPF = 2;  // conduction box entries per thread per plane
 
-  // XCD-aware order: hardware dispatches workgroup b to XCD b % 8, so XCD x gets
-  // the contiguous logical range [x * per, (x + 1) * per) and works through whole
-  // k-pairs, keeping each pair's valence orbitals resident in that XCD's L2.
+template <int MT, int GPT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) rho_yz(const PairDesc* __restrict__ pairs, int npairs, int nwg, int Nx,
+                                                  int ng, const float2* __restrict__ twt, float scale) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+  // XCD-aware order: workgroup b runs on XCD b % 8; XCD x gets the contiguous
+  // logical range [x * per, (x + 1) * per), so a pair's valence orbitals stay in
+  // that XCD's L2 while its conduction bands stream through.
   const int per = (nwg + 7) >> 3;
   const int L = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
   if (L >= nwg) return;
@@ -172,147 +129,175 @@ __global__ void __launch_bounds__(kBlock) rho_mfma(const PairDesc* __restrict__ 
     const int mid = (lo + hi + 1) >> 1;
     if (pairs[mid].wg0 <= L) lo = mid; else hi = mid - 1;
   }
-  const PairDesc P = pairs[lo];
+  const PairDesc& P = pairs[lo];
+  const int nE = P.nE, nvt = P.nvt, Kp = P.Kp, CS = P.CS, ncb = P.ncb;
   const int local = L - P.wg0;
-  const int c = local / P.nvt, vt = local - (local / P.nvt) * P.nvt;
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, l16 = l & 15, q = l >> 4;
-  const int vq = tid & 3, gq4 = tid >> 2;  // stage 3 ownership
+  const int c = local / (nvt * nE);
+  const int rem = local - c * (nvt * nE);
+  const int vt = rem / nE, eg = rem - (rem / nE) * nE;
+  const int mte = P.mte[eg];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, l16 = l & 15, q = l >> 4;
+  const int* tab = P.tab;
 
-  for (int i = tid; i < 2 * Ny * LW; i += kBlock) Ahi[i] = 0u;
-  for (int i = tid; i < Nx * Nx; i += kBlock) twx[i] = twtab[i];
-  for (int i = tid; i < ng; i += kBlock) gt[i] = P.gtab[i];
+  const int NxP = (Nx + 1) & ~1;
+  float2* tw = reinterpret_cast<float2*>(lds);                 // [Nx] exp(2 pi i k / Nx)
+  float2* twp = tw + NxP;                                       // [2][Nx] this plane's exp(2 pi i e_x x / Nx)
+  int* kg = reinterpret_cast<int*>(twp + 2 * NxP);              // [Kp/4], padded to a multiple of 4
+  uint32_t* cb = reinterpret_cast<uint32_t*>(kg + ((Kp / 4 + 3) & ~3));  // [2][4][CS]: hi copies, lo copies
+  float2* Pp = reinterpret_cast<float2*>(cb + 8 * CS);          // [4][MT*16][16]
 
+  for (int k = tid; k < Nx; k += kBlock) tw[k] = twt[k];
+  for (int k = tid; k < Kp / 4; k += kBlock) kg[k] = tab[P.kg + k];
+  for (int k = tid; k < 8 * CS; k += kBlock) cb[k] = 0u;
+
+  // A-operand row offsets of this lane (row l16 of every M-tile)
+  int oe[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) oe[mt] = tab[P.oe + (eg * MT + mt) * 16 + l16];
+  // owned outputs: G entries l + 64 i, valence bands 4w .. 4w+3 of the tile
+  int gi[GPT];
   float2 acc[GPT][4];
 #pragma unroll
-  for (int i = 0; i < GPT; ++i)
+  for (int i = 0; i < GPT; ++i) {
+    gi[i] = tab[P.gl + eg * GPT * 64 + l + 64 * i];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = make_float2(0.f, 0.f);
-  const int vb = vt * 16 + l16;
-  const bool vok = vb < P.nv;
-  const size_t VS = (size_t)16 * 16 * Nyp;  // stride between the four F variants
+  }
+  // conduction entries this thread moves into LDS each plane
+  int cp[kMaxPF];
+  uint32_t ph[kMaxPF], pl[kMaxPF];
+  const size_t cbase = (size_t)c * Nx * ncb;
+#pragma unroll
+  for (int f = 0; f < kMaxPF; ++f) {
+    const int j = tid + kBlock * f;
+    cp[f] = j < ncb ? tab[P.cpos + j] : -1;
+    ph[f] = cp[f] >= 0 ? P.Uc_hi[cbase + j] : 0u;
+    pl[f] = cp[f] >= 0 ? P.Uc_lo[cbase + j] : 0u;
+  }
+  __syncthreads();  // boxes zeroed and twiddles loaded before the first plane
+  // work items (K-chunk, M-tile), K-chunk major; wave w takes a contiguous share
+  const int nK = Kp / 16;
+  const int nit = nK * mte;
+  const int it0 = (w * nit) >> 2, it1 = ((w + 1) * nit) >> 2;
+  const int v = vt * 16 + l16;
+  const bool vok = v < P.nv;
+  const size_t vrow = (size_t)(vok ? v : 0) * Nx;
 
   for (int x = 0; x < Nx; ++x) {
-    __syncthreads();  // previous plane finished with A and S2p
-    {
-      const size_t cb = ((size_t)c * Nx + x) * Ny * NO;
-      for (int i = tid; i < Ny * NO; i += kBlock) {
-        const int y = i / NO, n = i - (i / NO) * NO;
-        Ahi[y * LW + kLP + n] = P.Uc_hi[cb + i];
-        Alo[y * LW + kLP + n] = P.Uc_lo[cb + i];
-      }
-    }
-    __syncthreads();
-    f4 s2r[4], s2i[4];
+    // ---- conduction plane into the four shifted copies: copy s holds box[j + s] at j
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      s2r[j] = f4{0.f, 0.f, 0.f, 0.f};
-      s2i[j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int ch = 0; ch < Nyp / 16; ++ch) {
-      // ---- stage 1: this wave's four y values of the chunk (y = ch*16 + 4*wave + j)
-      f4 cr[4], ci[4];
+    for (int f = 0; f < kMaxPF; ++f) {
+      const int p = cp[f];
+      if (p >= 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int y = ch * 16 + wave * 4 + j;
-        cr[j] = f4{0.f, 0.f, 0.f, 0.f};
-        ci[j] = f4{0.f, 0.f, 0.f, 0.f};
-        if (y < Ny) {
-#pragma unroll
-          for (int kk = 0; kk < NK; ++kk) {
-            const int ab = y * LW + kLP + kk * 16 + 4 * q + l16 - P.d0;
-            u4 arh, arl, aih, ail;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              arh[m] = Ahi[ab + m];
-              arl[m] = Alo[ab + m];
-              aih[m] = rot_neg(arh[m]);
-              ail[m] = rot_neg(arl[m]);
-            }
-            u4 bh = u4{0u, 0u, 0u, 0u}, bl = u4{0u, 0u, 0u, 0u};
-            if (vok) {
-              const size_t o = (((size_t)vb * Nx + x) * Ny + y) * NO + kk * 16 + 4 * q;
-              bh = *reinterpret_cast<const u4*>(P.Uv_hi + o);
-              bl = *reinterpret_cast<const u4*>(P.Uv_lo + o);
-            }
-            cr[j] = mma3(arh, arl, bh, bl, cr[j]);
-            ci[j] = mma3(aih, ail, bh, bl, ci[j]);
+        for (int s = 0; s < 4; ++s) {
+          if (p >= s) {
+            cb[s * CS + p - s] = ph[f];
+            cb[(4 + s) * CS + p - s] = pl[f];
           }
         }
       }
-      // S1 layout [iz][yq][v][4 y]: lane (q, v) holds rows iz = 4q + r for its 4 y values
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        uint32_t hh[4], ll[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) split2(cr[j][r], ci[j][r], hh[j], ll[j]);
-        const u4 h = u4{hh[0], hh[1], hh[2], hh[3]}, lw = u4{ll[0], ll[1], ll[2], ll[3]};
-        const int idx = (((4 * q + r) * 4 + wave) * 16 + l16) * 4;
-        *reinterpret_cast<u4*>(S1hi + idx) = h;
-        *reinterpret_cast<u4*>(S1lo + idx) = lw;
-      }
-      __syncthreads();
-      // ---- stage 2: this wave's e_z rows
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int iz = wave + 4 * j;
-        if (iz < P.nz) {
-          const size_t fb = ((size_t)iz * 16 + l16) * Nyp + ch * 16 + 4 * q;
-          const u4 frh = *reinterpret_cast<const u4*>(P.F + fb);
-          const u4 frl = *reinterpret_cast<const u4*>(P.F + VS + fb);
-          const u4 fih = *reinterpret_cast<const u4*>(P.F + 2 * VS + fb);
-          const u4 fil = *reinterpret_cast<const u4*>(P.F + 3 * VS + fb);
-          const int so = ((iz * 4 + q) * 16 + l16) * 4;
-          const u4 sh = *reinterpret_cast<const u4*>(S1hi + so);
-          const u4 sl = *reinterpret_cast<const u4*>(S1lo + so);
-          s2r[j] = mma3(frh, frl, sh, sl, s2r[j]);
-          s2i[j] = mma3(fih, fil, sh, sl, s2i[j]);
-        }
-      }
-      __syncthreads();
     }
-    // ---- S2 plane to LDS (reuses the S1 space)
+    // twiddle row of this plane (double buffered: the previous row may still be read)
+    for (int e = tid; e < Nx; e += kBlock) twp[(x & 1) * NxP + e] = tw[(e * x) % Nx];
+    if (x + 1 < Nx) {
+      const size_t o = cbase + (size_t)(x + 1) * ncb;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int iz = wave + 4 * j;
-      if (iz < P.nz) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) S2p[(iz * 16 + 4 * q + r) * 16 + l16] = make_float2(s2r[j][r], s2i[j][r]);
+      for (int f = 0; f < kMaxPF; ++f) {
+        if (cp[f] >= 0) {
+          ph[f] = P.Uc_hi[o + tid + kBlock * f];
+          pl[f] = P.Uc_lo[o + tid + kBlock * f];
+        }
       }
     }
     __syncthreads();
-    // ---- stage 3: x transform into the owned rho entries (G = gq4 + 64 i, v = 4 vq .. 4 vq + 3)
+    // ---- correlation on MFMA
+    f4 re[MT], im[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      re[mt] = f4{0.f, 0.f, 0.f, 0.f};
+      im[mt] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (it0 < it1) {
+      const int kc0 = it0 / mte, kc1 = (it1 - 1) / mte;
+      const uint32_t* vh = P.Uv_hi + (vrow + x) * Kp + 4 * q;
+      const uint32_t* vl = P.Uv_lo + (vrow + x) * Kp + 4 * q;
+      u4 nbh = vok ? *reinterpret_cast<const u4*>(vh + kc0 * 16) : u4{0u, 0u, 0u, 0u};
+      u4 nbl = vok ? *reinterpret_cast<const u4*>(vl + kc0 * 16) : u4{0u, 0u, 0u, 0u};
+      for (int kc = kc0; kc <= kc1; ++kc) {
+        const u4 bh = nbh, bl = nbl;
+        if (kc < kc1 && vok) {
+          nbh = *reinterpret_cast<const u4*>(vh + (kc + 1) * 16);
+          nbl = *reinterpret_cast<const u4*>(vl + (kc + 1) * 16);
+        }
+        u4 rh, rl;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          rh[m] = rot_pos(bh[m]);
+          rl[m] = rot_pos(bl[m]);
+        }
+        const int ob = kg[kc * 4 + q];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int item = kc * mte + mt;
+          if (mt < mte && item >= it0 && item < it1) {
+            const int o = ob + oe[mt];
+            const int sft = o & 3;
+            const u4 ah = *reinterpret_cast<const u4*>(cb + sft * CS + (o - sft));
+            const u4 al = *reinterpret_cast<const u4*>(cb + (4 + sft) * CS + (o - sft));
+            re[mt] = mma3(ah, al, bh, bl, re[mt]);
+            im[mt] = mma3(ah, al, rh, rl, im[mt]);
+          }
+        }
+      }
+    }
+    // ---- partial sums of this wave: rows mt*16 + 4q + r, column l16
+    float2* Pw = Pp + w * (MT * 256);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      if (mt < mte) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Pw[(mt * 16 + 4 * q + r) * 16 + l16] = make_float2(re[mt][r], im[mt][r]);
+      }
+    }
+    __syncthreads();
+    // ---- fixed-order reduction over the four waves into slice 0
+    for (int e = tid; e < mte * 256; e += kBlock) {
+      const float2 a0 = Pp[e], a1 = Pp[MT * 256 + e], a2 = Pp[2 * MT * 256 + e], a3 = Pp[3 * MT * 256 + e];
+      Pp[e] = make_float2(((a0.x + a1.x) + a2.x) + a3.x, ((a0.y + a1.y) + a2.y) + a3.y);
+    }
+    __syncthreads();
+    // ---- x transform into the owned rho entries
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
-      const int G = gq4 + 64 * i;
-      if (G < ng) {
-        const int t = gt[G];
-        const float4* sp = reinterpret_cast<const float4*>(S2p + ((t & 31) * 16 + ((t >> 5) & 31)) * 16 + 4 * vq);
+      if (gi[i] >= 0) {
+        const int row = (gi[i] >> 16) & 0xff;
+        const float4* sp = reinterpret_cast<const float4*>(Pp + row * 16 + 4 * w);
         const float4 s01 = sp[0], s23 = sp[1];
-        const float2 w = twx[(t >> 10) * Nx + x];
-        acc[i][0].x = fmaf(s01.x, w.x, fmaf(-s01.y, w.y, acc[i][0].x));
-        acc[i][0].y = fmaf(s01.x, w.y, fmaf(s01.y, w.x, acc[i][0].y));
-        acc[i][1].x = fmaf(s01.z, w.x, fmaf(-s01.w, w.y, acc[i][1].x));
-        acc[i][1].y = fmaf(s01.z, w.y, fmaf(s01.w, w.x, acc[i][1].y));
-        acc[i][2].x = fmaf(s23.x, w.x, fmaf(-s23.y, w.y, acc[i][2].x));
-        acc[i][2].y = fmaf(s23.x, w.y, fmaf(s23.y, w.x, acc[i][2].y));
-        acc[i][3].x = fmaf(s23.z, w.x, fmaf(-s23.w, w.y, acc[i][3].x));
-        acc[i][3].y = fmaf(s23.z, w.y, fmaf(s23.w, w.x, acc[i][3].y));
+        const float2 t = twp[(x & 1) * NxP + ((unsigned)gi[i] >> 24)];
+        acc[i][0].x = fmaf(s01.x, t.x, fmaf(-s01.y, t.y, acc[i][0].x));
+        acc[i][0].y = fmaf(s01.x, t.y, fmaf(s01.y, t.x, acc[i][0].y));
+        acc[i][1].x = fmaf(s01.z, t.x, fmaf(-s01.w, t.y, acc[i][1].x));
+        acc[i][1].y = fmaf(s01.z, t.y, fmaf(s01.w, t.x, acc[i][1].y));
+        acc[i][2].x = fmaf(s23.x, t.x, fmaf(-s23.y, t.y, acc[i][2].x));
+        acc[i][2].y = fmaf(s23.x, t.y, fmaf(s23.y, t.x, acc[i][2].y));
+        acc[i][3].x = fmaf(s23.z, t.x, fmaf(-s23.w, t.y, acc[i][3].x));
+        acc[i][3].y = fmaf(s23.z, t.y, fmaf(s23.w, t.x, acc[i][3].y));
       }
     }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int v = vt * 16 + 4 * vq + u;
-    if (v < P.nv) {
-      float2* out = P.rho + ((size_t)v * P.nc + c) * ng;
+    const int vv = vt * 16 + 4 * w + u;
+    if (vv < P.nv) {
+      float2* out = P.rho + ((size_t)vv * P.nc + c) * ng;
 #pragma unroll
-      for (int i = 0; i < GPT; ++i) {
-        const int G = gq4 + 64 * i;
-        if (G < ng) out[G] = make_float2(acc[i][u].x * scale, acc[i][u].y * scale);
-      }
+      for (int i = 0; i < GPT; ++i)
+        if (gi[i] >= 0) out[gi[i] & 0xffff] = make_float2(acc[i][u].x * scale, acc[i][u].y * scale);
     }
   }
 }
+
 struct PoleDesc {
   const double* ec;
   const double* ev;
@@ -330,278 +315,307 @@ __global__ void pole_energies_b(const PoleDesc* __restrict__ pd) {
 }
 
 // ------------------------------------------------------------------ host --
-static uint16_t host_bf16(float x) {
-  uint32_t u;
-  std::memcpy(&u, &x, 4);
-  const uint32_t r = 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)((u + r) >> 16);
-}
-static float host_from_bf16(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-static void host_split(float x, uint16_t& hi, uint16_t& lo) {
-  hi = host_bf16(x);
-  lo = host_bf16(x - host_from_bf16(hi));
-}
-
-struct Geo {
-  int nz = 0, ezmin = 0;
-  std::vector<uint32_t> F;
-  std::vector<int> gtab;
-  bool ok = true;
+// Box of a plane-wave sphere: dense (m_y, m_z) columns, m_x along the column.
+struct SphereBox {
+  int xlo, ylo, zlo, nbx, nby, nbz;
+  std::vector<int> boxidx;  // per plane wave: (by * nbz + bz) * nbx + bx
 };
 
-// Slot structure of the shifted G-set e = m_G - G0 and the stage-2 DFT operands.
-static Geo make_geo(const xo_rho_args* a, int Nx, int Ny, int Nyp) {
-  Geo g;
-  int ezmin = 1 << 30, ezmax = -(1 << 30);
-  for (int i = 0; i < a->ng; ++i) {
-    const int ez = a->mill_g[3 * i + 2] - a->g0[2];
-    ezmin = std::min(ezmin, ez);
-    ezmax = std::max(ezmax, ez);
+static SphereBox sphere_box(const int32_t* m, int npw, const Extent& ex) {
+  SphereBox b;
+  b.xlo = ex.lo[0];
+  b.ylo = ex.lo[1];
+  b.zlo = ex.lo[2];
+  b.nbx = ex.hi[0] - ex.lo[0] + 1;
+  b.nby = ex.hi[1] - ex.lo[1] + 1;
+  b.nbz = ex.hi[2] - ex.lo[2] + 1;
+  b.boxidx.resize(npw);
+  for (int i = 0; i < npw; ++i)
+    b.boxidx[i] = ((m[3 * i + 1] - b.ylo) * b.nbz + (m[3 * i + 2] - b.zlo)) * b.nbx + (m[3 * i] - b.xlo);
+  return b;
+}
+
+struct PairGeo {
+  std::vector<int> tab;
+  std::vector<int> outc, outv;  // output columns of the two orbital transforms
+  int cpos = 0, kg = 0, oe = 0, gl = 0;
+  int ncb = 0, Kp = 0, CS = 0, nE = 0, MT = 0;
+  int mte[kMaxGroups] = {0};
+};
+
+// Geometry of one pair: valence K-groups, extended conduction box, e-groups.
+// Returns false when the pair does not fit the kernel's limits.
+static bool pair_geo(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe,
+                     const SphereBox& bc, const SphereBox& bv, int GPT, PairGeo* g) {
+  const int Nx = a->n[0];
+  // valence K-groups: per m_y row of the sphere, m_z in runs of four
+  std::vector<int> zl(bv.nby, 1 << 30), zh(bv.nby, -(1 << 30));
+  for (int i = 0; i < a->npw_v; ++i) {
+    const int by = a->mill_v[3 * i + 1] - bv.ylo, z = a->mill_v[3 * i + 2];
+    zl[by] = std::min(zl[by], z);
+    zh[by] = std::max(zh[by], z);
   }
-  g.ezmin = ezmin;
-  g.nz = ezmax - ezmin + 1;
-  if (g.nz > 16) {
-    g.ok = false;
-    return g;
-  }
-  std::vector<std::vector<int>> slots(g.nz);  // e_y mod Ny per slot
-  g.gtab.resize(a->ng);
-  for (int i = 0; i < a->ng; ++i) {
-    const int ex = pmod(a->mill_g[3 * i] - a->g0[0], Nx);
-    const int ey = pmod(a->mill_g[3 * i + 1] - a->g0[1], Ny);
-    const int iz = a->mill_g[3 * i + 2] - a->g0[2] - ezmin;
-    auto& sl = slots[iz];
-    int r = (int)(std::find(sl.begin(), sl.end(), ey) - sl.begin());
-    if (r == (int)sl.size()) sl.push_back(ey);
-    if (r >= 16) {
-      g.ok = false;
-      return g;
+  std::vector<std::pair<int, int>> grp;  // (m_y, first m_z)
+  int zmaxg = xv.lo[2];
+  for (int by = 0; by < bv.nby; ++by)
+    for (int z0 = zl[by]; z0 <= zh[by]; z0 += 4) {
+      grp.push_back({bv.ylo + by, z0});
+      zmaxg = std::max(zmaxg, z0 + 3);
     }
-    g.gtab[i] = iz | (r << 5) | (ex << 10);
+  while (grp.size() % 4) grp.push_back({INT32_MIN, 0});
+  g->Kp = (int)grp.size() * 4;
+  g->outv.assign(g->Kp, -1);
+  for (size_t k = 0; k < grp.size(); ++k) {
+    if (grp[k].first == INT32_MIN) continue;
+    for (int j = 0; j < 4; ++j) {
+      const int by = grp[k].first - bv.ylo, bz = grp[k].second + j - bv.zlo;
+      if (bz < bv.nbz) g->outv[4 * k + j] = by * bv.nbz + bz;
+    }
   }
-  const size_t VS = (size_t)16 * 16 * Nyp;
-  g.F.assign(4 * VS, 0u);
-  for (int iz = 0; iz < g.nz; ++iz)
-    for (int r = 0; r < (int)slots[iz].size(); ++r)
-      for (int y = 0; y < Ny; ++y) {
-        const double th = 2.0 * M_PI * (double)((slots[iz][r] * y) % Ny) / Ny;
-        const float fr = (float)std::cos(th), fi = (float)std::sin(th);
-        uint16_t h0, l0, h1, l1;
-        const size_t o = ((size_t)iz * 16 + r) * Nyp + y;
-        host_split(fr, h0, l0);
-        host_split(-fi, h1, l1);
-        g.F[o] = h0 | ((uint32_t)h1 << 16);
-        g.F[VS + o] = l0 | ((uint32_t)l1 << 16);
-        host_split(fi, h0, l0);
-        host_split(fr, h1, l1);
-        g.F[2 * VS + o] = h0 | ((uint32_t)h1 << 16);
-        g.F[3 * VS + o] = l0 | ((uint32_t)l1 << 16);
-      }
-  return g;
+  // extended conduction box: every U_c(b + e) the gather can touch
+  const int Y0 = xv.lo[1] + xe.lo[1], Y1 = xv.hi[1] + xe.hi[1];
+  const int Z0 = xv.lo[2] + xe.lo[2], Z1 = zmaxg + xe.hi[2];
+  const int EY = Y1 - Y0 + 1, EZ = Z1 - Z0 + 1;
+  g->CS = (EY * EZ + 4 + 3) & ~3;
+  g->ncb = bc.nby * bc.nbz;
+  g->outc.resize(g->ncb);
+  for (int j = 0; j < g->ncb; ++j) g->outc[j] = j;
+  std::vector<int> cpos(g->ncb, -1);
+  for (int by = 0; by < bc.nby; ++by)
+    for (int bz = 0; bz < bc.nbz; ++bz) {
+      const int y = bc.ylo + by, z = bc.zlo + bz;
+      if (y >= Y0 && y <= Y1 && z >= Z0 && z <= Z1) cpos[by * bc.nbz + bz] = (y - Y0) * EZ + (z - Z0);
+    }
+  std::vector<int> kgv(grp.size(), 0);
+  for (size_t k = 0; k < grp.size(); ++k)
+    if (grp[k].first != INT32_MIN) kgv[k] = (grp[k].first - xv.lo[1]) * EZ + (grp[k].second - xv.lo[2]);
+  // e-columns (distinct (e_y, e_z)), sorted; G lists per column
+  std::map<std::pair<int, int>, std::vector<int>> cols;
+  for (int i = 0; i < a->ng; ++i)
+    cols[{a->mill_g[3 * i + 1] - a->g0[1], a->mill_g[3 * i + 2] - a->g0[2]}].push_back(i);
+  // e-groups: consecutive columns, at most 128 columns and GPT*64 G each
+  std::vector<std::vector<std::pair<int, int>>> groups(1);
+  std::vector<int> gcount(1, 0);
+  for (auto& kv : cols) {
+    const int n = (int)kv.second.size();
+    if (n > GPT * 64) return false;
+    if (groups.back().size() == 128 || gcount.back() + n > GPT * 64) {
+      groups.emplace_back();
+      gcount.push_back(0);
+    }
+    groups.back().push_back(kv.first);
+    gcount.back() += n;
+  }
+  g->nE = (int)groups.size();
+  if (g->nE > kMaxGroups) return false;
+  g->MT = 0;
+  for (int e = 0; e < g->nE; ++e) {
+    g->mte[e] = ((int)groups[e].size() + 15) / 16;
+    g->MT = std::max(g->MT, g->mte[e]);
+  }
+  const int MT = g->MT;
+  std::vector<int> oe((size_t)g->nE * MT * 16, 0), gl((size_t)g->nE * GPT * 64, -1);
+  for (int e = 0; e < g->nE; ++e) {
+    std::vector<int> gs;
+    for (size_t r = 0; r < groups[e].size(); ++r) {
+      const auto& key = groups[e][r];
+      oe[(size_t)e * MT * 16 + r] = (key.first - xe.lo[1]) * EZ + (key.second - xe.lo[2]);
+      for (int gidx : cols[key]) gs.push_back(gidx | (int)(r << 16));
+    }
+    std::sort(gs.begin(), gs.end(), [](int u, int v) { return (u & 0xffff) < (v & 0xffff); });
+    for (size_t j = 0; j < gs.size(); ++j) {
+      const int gidx = gs[j] & 0xffff;
+      const int ex = pmod(a->mill_g[3 * gidx] - a->g0[0], Nx);
+      gl[(size_t)e * GPT * 64 + j] = gs[j] | (ex << 24);
+    }
+  }
+  g->tab.clear();
+  g->cpos = 0;
+  g->tab.insert(g->tab.end(), cpos.begin(), cpos.end());
+  g->kg = (int)g->tab.size();
+  g->tab.insert(g->tab.end(), kgv.begin(), kgv.end());
+  g->oe = (int)g->tab.size();
+  g->tab.insert(g->tab.end(), oe.begin(), oe.end());
+  g->gl = (int)g->tab.size();
+  g->tab.insert(g->tab.end(), gl.begin(), gl.end());
+  (void)xc;
+  return true;
 }
 
-// Device geometry per (grid, G-set, G0), built once per process and device.
-struct DevGeo {
-  const void* F = nullptr;
-  const void* gtab = nullptr;
-  int nz = 0;
-};
-
-static int dev_geo(const xo_rho_args* a, int Nx, int Ny, int Nyp, hipStream_t s, const DevGeo** out) {
-  static std::mutex mu;
-  static std::map<std::vector<int>, DevGeo> cache;
-  int dev = 0;
-  XO_TRY_HIP(hipGetDevice(&dev));
-  std::vector<int> key = {dev, Nx, Ny, a->g0[0], a->g0[1], a->g0[2]};
-  key.insert(key.end(), a->mill_g, a->mill_g + 3 * a->ng);
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(key);
-  if (it != cache.end()) {
-    *out = it->second.nz ? &it->second : nullptr;
-    return XO_OK;
-  }
-  Geo g = make_geo(a, Nx, Ny, Nyp);
-  DevGeo d;
-  if (g.ok) {
-    XO_RET(device_table(g.F.data(), g.F.size() * sizeof(uint32_t), s, &d.F));
-    XO_RET(device_table(g.gtab.data(), g.gtab.size() * sizeof(int), s, &d.gtab));
-    d.nz = g.nz;
-  }
-  auto& slot = cache[key];
-  slot = d;
-  *out = d.nz ? &slot : nullptr;
-  return XO_OK;
-}
-
-template <int NK, int GPT>
-static int launch_rho(const void* dpairs, int npairs, int nwg, int Nx, int Ny, int Nyp, int ng, const void* dtw,
-                      hipStream_t s, size_t lds) {
+template <int MT, int GPT>
+static int launch_rho(const void* dpairs, int npairs, int nwg, int Nx, int ng, const void* dtw, hipStream_t s,
+                      size_t lds) {
   if (lds > 64 * 1024)
-    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_mfma<NK, GPT>),
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_yz<MT, GPT>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
-    KernelTimer kt_("rho_mfma", s);
-    hipLaunchKernelGGL((rho_mfma<NK, GPT>), dim3(8 * ((nwg + 7) / 8)), dim3(kBlock), lds, s,
-                       static_cast<const PairDesc*>(dpairs), npairs, nwg, Nx, Ny, Nyp, ng,
-                       static_cast<const float2*>(dtw), (float)(1.0 / ((double)Nx * Ny)));
+    KernelTimer kt_("rho_yz", s);
+    hipLaunchKernelGGL((rho_yz<MT, GPT>), dim3(8 * ((nwg + 7) / 8)), dim3(kBlock), lds, s,
+                       static_cast<const PairDesc*>(dpairs), npairs, nwg, Nx, ng, static_cast<const float2*>(dtw),
+                       (float)(1.0 / (double)Nx));
   }
   XO_CHECK_LAUNCH();
   return XO_OK;
 }
 
-template <int NK>
-static int launch_rho_g(const void* dpairs, int npairs, int nwg, int Nx, int Ny, int Nyp, int ng, const void* dtw,
-                        hipStream_t s, size_t lds) {
-  if (ng <= 64 * 2) return launch_rho<NK, 2>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  if (ng <= 64 * 4) return launch_rho<NK, 4>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  if (ng <= 64 * 8) return launch_rho<NK, 8>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
-  return launch_rho<NK, 16>(dpairs, npairs, nwg, Nx, Ny, Nyp, ng, dtw, s, lds);
+template <int GPT>
+static int launch_rho_mt(int MT, const void* dpairs, int npairs, int nwg, int Nx, int ng, const void* dtw,
+                         hipStream_t s, size_t lds) {
+  switch (MT) {
+    case 1: return launch_rho<1, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 2: return launch_rho<2, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 3: return launch_rho<3, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 4: return launch_rho<4, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 5: return launch_rho<5, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 6: return launch_rho<6, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    case 7: return launch_rho<7, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+    default: return launch_rho<8, GPT>(dpairs, npairs, nwg, Nx, ng, dtw, s, lds);
+  }
 }
 
 // Whether a batch can take the MFMA path (else each pair runs the VALU path in FP32).
-static bool mfma_eligible(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe) {
+static bool mfma_eligible(const xo_rho_args* p, int n) {
   const xo_rho_args& a0 = p[0];
-  if (a0.ng > 1024 || a0.n[0] > 72 || a0.n[1] > 128) return false;
+  if (a0.ng > 65535) return false;
   for (int i = 0; i < n; ++i) {
     if (p[i].q0 || p[i].prec != XO_BF16X3) return false;
-    if (p[i].n[0] != a0.n[0] || p[i].n[1] != a0.n[1] || p[i].ng != a0.ng) return false;
+    if (p[i].n[0] != a0.n[0] || p[i].ng != a0.ng) return false;
     if (std::memcmp(p[i].mill_g, a0.mill_g, sizeof(int32_t) * 3 * a0.ng) != 0) return false;
-    const int no = std::max(xc[i].hi[2] - xc[i].lo[2] + 1, xv[i].hi[2] - xv[i].lo[2] + 1);
-    if (no > 32) return false;
-    const int d0 = xc[i].lo[2] - xv[i].lo[2] - xe[i].lo[2];
-    if (d0 <= -18 || d0 > kLP) return false;
   }
   return true;
 }
 
 static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                           hipStream_t s) {
-  const int Nx = p[0].n[0], Ny = p[0].n[1], ng = p[0].ng;
-  const int Nyp = (Ny + 15) / 16 * 16;
-  int NO = 16;
-  for (int i = 0; i < n; ++i)
-    NO = std::max(NO, std::max(xc[i].hi[2] - xc[i].lo[2] + 1, xv[i].hi[2] - xv[i].lo[2] + 1) > 16 ? 32 : 16);
-
-  // per-G0 geometry (stage-2 operands and G selectors), cached by content
-  std::map<std::tuple<int, int, int>, std::pair<const void*, const void*>> geos;
-  std::map<std::tuple<int, int, int>, int> nzs;
+  const int Nx = p[0].n[0], ng = p[0].ng;
+  const int GPT = ng <= 128 ? 2 : 8;
+  std::vector<SphereBox> bc(n), bv(n);
+  std::vector<PairGeo> geo(n);
+  int MT = 1;
   for (int i = 0; i < n; ++i) {
-    auto key = std::make_tuple(p[i].g0[0], p[i].g0[1], p[i].g0[2]);
-    if (geos.count(key)) continue;
-    const DevGeo* dg = nullptr;
-    XO_RET(dev_geo(&p[i], Nx, Ny, Nyp, s, &dg));
-    if (!dg) return XO_ERR_UNSUPPORTED;
-    geos[key] = {dg->F, dg->gtab};
-    nzs[key] = dg->nz;
+    bc[i] = sphere_box(p[i].mill_c, p[i].npw_c, xc[i]);
+    bv[i] = sphere_box(p[i].mill_v, p[i].npw_v, xv[i]);
+    if (!pair_geo(&p[i], xc[i], xv[i], xe[i], bc[i], bv[i], GPT, &geo[i])) return XO_ERR_UNSUPPORTED;
+    if (geo[i].ncb > kBlock * kMaxPF) return XO_ERR_UNSUPPORTED;
+    MT = std::max(MT, geo[i].MT);
   }
-  std::vector<float2> tw((size_t)Nx * Nx);
-  for (int e = 0; e < Nx; ++e)
-    for (int x = 0; x < Nx; ++x) {
-      const double th = 2.0 * M_PI * (double)((e * x) % Nx) / Nx;
-      tw[(size_t)e * Nx + x] = make_float2((float)std::cos(th), (float)std::sin(th));
-    }
+  if (MT > 8) return XO_ERR_UNSUPPORTED;
+  // the oe tables were laid out with each pair's own MT; re-lay with the batch MT
+  for (int i = 0; i < n; ++i) {
+    if (geo[i].MT == MT) continue;
+    PairGeo& g = geo[i];
+    std::vector<int> oe((size_t)g.nE * MT * 16, 0);
+    for (int e = 0; e < g.nE; ++e)
+      for (int r = 0; r < g.MT * 16; ++r) oe[(size_t)e * MT * 16 + r] = g.tab[g.oe + e * g.MT * 16 + r];
+    std::vector<int> gl(g.tab.begin() + g.gl, g.tab.end());
+    g.tab.resize(g.oe);
+    g.tab.insert(g.tab.end(), oe.begin(), oe.end());
+    g.gl = (int)g.tab.size();
+    g.tab.insert(g.tab.end(), gl.begin(), gl.end());
+    g.MT = MT;
+  }
+  std::vector<float2> tw(Nx);
+  for (int k = 0; k < Nx; ++k) {
+    const double th = 2.0 * M_PI * k / Nx;
+    tw[k] = make_float2((float)std::cos(th), (float)std::sin(th));
+  }
   const void* dtw = nullptr;
   XO_RET(device_table(tw.data(), tw.size() * sizeof(float2), s, &dtw));
-  std::vector<float2> twxy(Nx + Ny);
-  for (int k = 0; k < Nx + Ny; ++k) {
-    const int nn = k < Nx ? Nx : Ny, kk = k < Nx ? k : k - Nx;
-    const double th = 2.0 * M_PI * kk / nn;
-    twxy[k] = make_float2((float)std::cos(th), (float)std::sin(th));
+
+  // workspace: transformed orbitals of every pair (conduction box, valence K rows)
+  std::vector<size_t> offc(n), offv(n);
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    offc[i] = tot;
+    tot += align_up((size_t)p[i].nc * Nx * geo[i].ncb, 64);
+    offv[i] = tot;
+    tot += align_up((size_t)p[i].nv * Nx * geo[i].Kp, 64);
   }
-  const void* dtwxy = nullptr;
-  XO_RET(device_table(twxy.data(), twxy.size() * sizeof(float2), s, &dtwxy));
-
-  // workspace: split orbitals of every pair
-  const size_t plane = (size_t)Nx * Ny * NO;
-  std::vector<size_t> off(n + 1, 0);
-  for (int i = 0; i < n; ++i) off[i + 1] = off[i] + align_up(plane * (p[i].nc + p[i].nv) * 4, 256);
   void* ws = nullptr;
-  XO_RET(workspace(s, 3, 2 * off[n], &ws));
+  XO_RET(workspace(s, 3, 2 * tot * sizeof(uint32_t), &ws));
   uint32_t* Uhi0 = static_cast<uint32_t*>(ws);
-  uint32_t* Ulo0 = Uhi0 + off[n] / 4;
+  uint32_t* Ulo0 = Uhi0 + tot;
 
-  std::vector<SphereTable> tabs(2 * n);
-  std::vector<OrbSide> sides(2 * n);
+  std::vector<OrbX> sides(2 * n);
   int maxnb = 0;
   size_t orb_lds = 0;
   for (int i = 0; i < n; ++i) {
     for (int side = 0; side < 2; ++side) {
-      const Extent& ex = side ? xv[i] : xc[i];
-      SphereTable& t = tabs[2 * i + side];
-      t = sphere_table(side ? p[i].mill_v : p[i].mill_c, side ? p[i].npw_v : p[i].npw_c, ex);
-      const void* dent = nullptr;
-      const void* dzoff = nullptr;
-      XO_RET(device_table(t.ent.data(), t.ent.size() * sizeof(SphereEntry), s, &dent));
-      XO_RET(device_table(t.zoff.data(), t.zoff.size() * sizeof(int), s, &dzoff));
-      OrbSide& o = sides[2 * i + side];
+      const SphereBox& b = side ? bv[i] : bc[i];
+      const std::vector<int>& outcol = side ? geo[i].outv : geo[i].outc;
+      const void* dbox = nullptr;
+      const void* dout = nullptr;
+      XO_RET(device_table(b.boxidx.data(), b.boxidx.size() * sizeof(int), s, &dbox));
+      XO_RET(device_table(outcol.data(), outcol.size() * sizeof(int), s, &dout));
+      OrbX& o = sides[2 * i + side];
       o.coef = static_cast<const float2*>(side ? p[i].coef_v : p[i].coef_c);
-      o.ent = static_cast<const SphereEntry*>(dent);
-      o.zoff = static_cast<const int*>(dzoff);
-      const size_t ubase = off[i] / 4 + (side ? plane * p[i].nc : 0);
-      o.Uhi = Uhi0 + ubase;
-      o.Ulo = Ulo0 + ubase;
+      o.boxidx = static_cast<const int*>(dbox);
+      o.outcol = static_cast<const int*>(dout);
+      o.Uhi = Uhi0 + (side ? offv[i] : offc[i]);
+      o.Ulo = Ulo0 + (side ? offv[i] : offc[i]);
       o.npw = side ? p[i].npw_v : p[i].npw_c;
       o.nb = side ? p[i].nv : p[i].nc;
-      o.nslot = t.nslot;
-      o.xlo = ex.lo[0];
-      o.nbx = ex.hi[0] - ex.lo[0] + 1;
-      o.ylo = ex.lo[1];
-      o.nby = ex.hi[1] - ex.lo[1] + 1;
+      o.nout = (int)outcol.size();
+      o.nbx = b.nbx;
+      o.ncol = b.nby * b.nbz;
+      o.xlo = b.xlo;
       maxnb = std::max(maxnb, o.nb);
-      orb_lds = std::max(orb_lds, (size_t)(Nx + Ny + kSC * (o.nby * o.nbx + o.nby * Nx)) * sizeof(float2));
+      orb_lds = std::max(orb_lds, (size_t)(Nx + o.ncol * o.nbx) * sizeof(float2));
     }
   }
-  const void* dsides = nullptr;
-  XO_RET(device_table(sides.data(), sides.size() * sizeof(OrbSide), s, &dsides));
   if (orb_lds > 160 * 1024) return XO_ERR_UNSUPPORTED;
+  const void* dsides = nullptr;
+  XO_RET(device_table(sides.data(), sides.size() * sizeof(OrbX), s, &dsides));
+  if (orb_lds > 64 * 1024)
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&orb_x), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)orb_lds));
   {
-    auto kfn = NO == 16 ? reinterpret_cast<const void*>(&orb_split<16>) : reinterpret_cast<const void*>(&orb_split<32>);
-    if (orb_lds > 64 * 1024)
-      XO_TRY_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)orb_lds));
-    KernelTimer kt_("orb_split", s);
-    if (NO == 16)
-      hipLaunchKernelGGL(orb_split<16>, dim3(maxnb, 2 * n), dim3(kBlock), orb_lds, s,
-                         static_cast<const OrbSide*>(dsides), Nx, Ny, static_cast<const float2*>(dtwxy));
-    else
-      hipLaunchKernelGGL(orb_split<32>, dim3(maxnb, 2 * n), dim3(kBlock), orb_lds, s,
-                         static_cast<const OrbSide*>(dsides), Nx, Ny, static_cast<const float2*>(dtwxy));
+    KernelTimer kt_("orb_x", s);
+    hipLaunchKernelGGL(orb_x, dim3(maxnb, 2 * n), dim3(kBlock), orb_lds, s, static_cast<const OrbX*>(dsides), Nx,
+                       static_cast<const float2*>(dtw));
   }
   XO_CHECK_LAUNCH();
 
   std::vector<PairDesc> pd(n);
   int nwg = 0;
+  size_t lds = 0;
   for (int i = 0; i < n; ++i) {
-    auto key = std::make_tuple(p[i].g0[0], p[i].g0[1], p[i].g0[2]);
+    const PairGeo& g = geo[i];
+    const void* dtab = nullptr;
+    XO_RET(device_table(g.tab.data(), g.tab.size() * sizeof(int), s, &dtab));
     PairDesc& d = pd[i];
-    d.Uc_hi = sides[2 * i].Uhi;
-    d.Uc_lo = sides[2 * i].Ulo;
-    d.Uv_hi = sides[2 * i + 1].Uhi;
-    d.Uv_lo = sides[2 * i + 1].Ulo;
+    d.Uc_hi = Uhi0 + offc[i];
+    d.Uc_lo = Ulo0 + offc[i];
+    d.Uv_hi = Uhi0 + offv[i];
+    d.Uv_lo = Ulo0 + offv[i];
     d.rho = static_cast<float2*>(p[i].rho);
-    d.F = static_cast<const uint32_t*>(geos[key].first);
-    d.gtab = static_cast<const int*>(geos[key].second);
+    d.tab = static_cast<const int*>(dtab);
+    d.cpos = g.cpos;
+    d.kg = g.kg;
+    d.oe = g.oe;
+    d.gl = g.gl;
     d.nc = p[i].nc;
     d.nv = p[i].nv;
     d.nvt = (p[i].nv + 15) / 16;
-    d.d0 = xc[i].lo[2] - xv[i].lo[2] - xe[i].lo[2];
-    d.nz = nzs[key];
+    d.nE = g.nE;
+    d.ncb = g.ncb;
+    d.Kp = g.Kp;
+    d.CS = g.CS;
+    for (int e = 0; e < kMaxGroups; ++e) d.mte[e] = e < g.nE ? g.mte[e] : 0;
     d.wg0 = nwg;
-    nwg += d.nc * d.nvt;
+    nwg += d.nc * d.nvt * d.nE;
+    const size_t need = (size_t)3 * ((Nx + 1) & ~1) * sizeof(float2) + (size_t)((g.Kp / 4 + 3) & ~3) * 4 +
+                        (size_t)8 * g.CS * 4 +
+                        (size_t)4 * MT * 256 * sizeof(float2);
+    lds = std::max(lds, need);
   }
+  if (lds > 160 * 1024) return XO_ERR_UNSUPPORTED;
   const void* dpairs = nullptr;
   XO_RET(device_table(pd.data(), pd.size() * sizeof(PairDesc), s, &dpairs));
-  const int LW = NO + 2 * kLP;
-  const size_t lds = (size_t)(2 * Ny * LW + 8192) * 4 + (size_t)Nx * Nx * sizeof(float2) + (size_t)ng * 4;
-  if (lds > 160 * 1024) return XO_ERR_UNSUPPORTED;
-  if (NO == 16)
-    XO_RET(launch_rho_g<1>(dpairs, n, nwg, Nx, Ny, Nyp, ng, dtw, s, lds));
+  if (GPT == 2)
+    XO_RET(launch_rho_mt<2>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
   else
-    XO_RET(launch_rho_g<2>(dpairs, n, nwg, Nx, Ny, Nyp, ng, dtw, s, lds));
+    XO_RET(launch_rho_mt<8>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
 
   std::vector<PoleDesc> poles;
   int maxm = 0;
@@ -628,7 +642,7 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
 int rho_batch(const xo_rho_args* p, int n, hipStream_t s) {
   std::vector<Extent> xc(n), xv(n), xe(n);
   for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
-  if (mfma_eligible(p, n, xc.data(), xv.data(), xe.data())) {
+  if (mfma_eligible(p, n)) {
     int r = rho_batch_mfma(p, n, xc.data(), xv.data(), xe.data(), s);
     if (r != XO_ERR_UNSUPPORTED) return r;
   }

@@ -60,6 +60,24 @@ def test_rho_parity(name, prec, tol):
     assert np.array_equal(dE.cpu().numpy(), dEr)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 3e-6), ("bf16x3", 5e-5)])
+def test_rho_parity_large_gset(prec, tol):
+    """NG = 700 on a 28^3 grid: more G-vectors than one workgroup of the MFMA path
+    owns, so the G-set is split into several (e_y, e_z)-column groups."""
+    cr = crystal_for("c2_small", ng=700, grid=28)
+    say(f"rho parity NG=700 {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    K = ntrans(cr)
+    M = torch.empty((K, 700), dtype=torch.complex64, device=DEV)
+    dE = torch.empty(K, dtype=torch.float64, device=DEV)
+    rho_all(dc, M, dE)
+    torch.cuda.synchronize()
+    Mr, _ = rho_all_pairs(cr, "fft")
+    err = np.abs(M.cpu().numpy().astype(np.complex128) - Mr).max() / np.abs(Mr).max()
+    say(f"  max rel err {err:.3e}")
+    assert err < tol
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_rho_batch_equals_per_pair(prec):
     cr = crystal_for("c2_small")
