@@ -164,16 +164,21 @@ int xo_chi0(const xo_chi0_args* a, void* stream);
 
 /* Many chi0 problems (q-points with their own G-set size, transitions and
  * output) sharing precision and frequencies, in one persistent launch: the
- * problems are cut into units (problem, 16-row x 16*nt_tiles-column block of the
- * upper triangle, group of <= 8 frequencies, transition slice of kper), queued
- * longest-first, and taken by num_CUs * wg_per_cu workgroups from an atomic
- * counter until the queue is empty; partials are reduced per block in a fixed
- * order, so the result does not depend on the schedule and equals xo_chi0 on
- * each item up to the order of the FP64 partial sums. items: [host] array. */
+ * problems are cut into units (problem, block of the upper triangle, group of
+ * frequencies, transition slice of kper), queued longest-first, and taken by
+ * num_CUs * wg_per_cu workgroups from an atomic counter until the queue is
+ * empty; partials are reduced per block in a fixed order, so the result does
+ * not depend on the schedule and equals xo_chi0 on each item up to the order
+ * of the FP64 partial sums. Blocks: nt_tiles 1 or 2 gives 16-row x 16*nt_tiles-
+ * column blocks with up to 8 frequencies per unit, one wave per transition
+ * quarter; nt_tiles 4 (XO_BF16X3 only) gives 64 x 64 blocks with 4 frequencies
+ * per unit and the right operand split once per workgroup in LDS. With
+ * nt_tiles 0 XO_BF16X3 takes the 64 x 64 form when there are at least four
+ * frequencies, every other case 16 x 16. items: [host] array. */
 typedef struct {
-  int nt_tiles;   /* column tiles per wave: 1, or 2 (XO_BF16X3 only); 0 = 1      */
+  int nt_tiles;   /* 0 (default), 1, 2, or 4 (XO_BF16X3 only)                     */
   int kper;       /* transitions per unit; 0 = chosen to fill the chip            */
-  int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 4                */
+  int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 2 (64 x 64), 4   */
 } xo_tune;
 
 int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream);

@@ -282,6 +282,174 @@ __global__ void chi0_reduce(const Item* __restrict__ items, const int2* __restri
   }
 }
 
+// Block form of the split-bf16 update. A workgroup owns a 64 x 64 output block
+// and four frequencies per unit; wave r owns rows 16 r .. 16 r + 15 and all four
+// 16-column tiles. Each step of 16 transitions stages the raw left rows, the
+// frequency factors and the right operand (split once, in fragment order) in LDS,
+// double buffered with one barrier per step: the next step's values are loaded
+// into registers before the current step's products and stored after them.
+constexpr int kBlk = 64;
+constexpr int kBW = 4;  // frequencies per unit in the block form
+constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
+            const int* __restrict__ queue, int nunits, int* __restrict__ counter, float* __restrict__ part) {
+  __shared__ u4 Bs[2][4][4][4][16];        // [buffer][hi, lo, rotated hi, rotated lo][column tile][q][column]
+  __shared__ float4 As[2][kBlk][9];        // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
+  __shared__ float4 Ws[2][kBW][4];         // [buffer][frequency][transition quad]
+  __shared__ int su;
+  const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int fn = tid >> 6, fq = (tid >> 4) & 3, fj = tid & 15;  // right-operand slot filled by this thread
+  const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition quad
+  for (;;) {
+    if (tid == 0) su = atomicAdd(counter, 1);
+    __syncthreads();
+    const int qpos = su;
+    __syncthreads();
+    if (qpos >= nunits) break;
+    const int uid = queue[qpos];
+    const Unit U = units[uid];
+    const Item I = items[U.item];
+    const int2 bij = tiles[I.tile0 + U.tile];
+    const f2v* rho = static_cast<const f2v*>(I.rho);
+    const float* W = static_cast<const float*>(I.W) + U.w0;
+    const int Ga = bij.x * kBlk + ar;
+    const int Gb = bij.y * kBlk + 16 * fn + fj;
+    const bool ga_ok = Ga < I.ng, gb_ok = Gb < I.ng;
+    const int nsteps = (U.k1 - U.k0 + 15) / 16;
+
+    f2v ra[4], rb[4];
+    float wv = 0.f;
+    // ---- load step s into registers
+#define CHI0_BLK_LOAD(s_)                                                                          \
+    {                                                                                              \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                              \
+        const int ta = (s_) + 4 * aq + u, tb = (s_) + 4 * fq + u;                                  \
+        ra[u] = (ta < U.k1 && ga_ok) ? gld<f2v>(rho + (size_t)ta * I.ng + Ga) : f2v{0.f, 0.f};      \
+        rb[u] = (tb < U.k1 && gb_ok) ? gld<f2v>(rho + (size_t)tb * I.ng + Gb) : f2v{0.f, 0.f};      \
+      }                                                                                            \
+      const int tw_ = (s_) + (tid & 15);                                                           \
+      wv = (tid < 64 && tw_ < U.k1) ? gld<float>(W + (size_t)tw_ * I.nwpad + (tid >> 4)) : 0.f;    \
+    }
+    // ---- store the loaded step into buffer b
+#define CHI0_BLK_STORE(b_)                                                                         \
+    {                                                                                              \
+      uint32_t h_[4], l_[4];                                                                       \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);        \
+      Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                      \
+      Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                                      \
+      Bs[b_][2][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])};  \
+      Bs[b_][3][fn][fq][fj] = u4{rot_neg(l_[0]), rot_neg(l_[1]), rot_neg(l_[2]), rot_neg(l_[3])};  \
+      As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                         \
+      As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                     \
+      if (tid < 64) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[tid & 15] = wv;                  \
+    }
+    CHI0_BLK_LOAD(U.k0);
+    CHI0_BLK_STORE(0);
+    __syncthreads();
+    f4 acc[kBW][2][4];
+#pragma unroll
+    for (int w = 0; w < kBW; ++w)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[w][r][n] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nsteps; ++k) {
+      const int buf = k & 1;
+      if (k + 1 < nsteps) CHI0_BLK_LOAD(U.k0 + 16 * (k + 1));
+      const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
+      // Im part through the rotated right operand (-im, re): the weighted left
+      // operand is split once per frequency and feeds both parts
+#pragma unroll
+      for (int w = 0; w < kBW; ++w) {
+        const float4 wq = Ws[buf][w][q];
+        uint32_t h[4], l[4];
+        split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
+        split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
+        split2(wq.z * a23.x, wq.z * a23.y, h[2], l[2]);
+        split2(wq.w * a23.z, wq.w * a23.w, h[3], l[3]);
+        const u4 ah = u4{h[0], h[1], h[2], h[3]}, al = u4{l[0], l[1], l[2], l[3]};
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          acc[w][0][n] = mma3(ah, al, Bs[buf][0][n][q][i], Bs[buf][1][n][q][i], acc[w][0][n]);
+          acc[w][1][n] = mma3(ah, al, Bs[buf][2][n][q][i], Bs[buf][3][n][q][i], acc[w][1][n]);
+        }
+      }
+      if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1);
+      __syncthreads();
+    }
+#undef CHI0_BLK_LOAD
+#undef CHI0_BLK_STORE
+    // partials of this thread, contiguous: [frequency][re, im][column tile] x 4 rows
+    f4* out = reinterpret_cast<f4*>(part + ((size_t)uid * 256 + tid) * (kBW * 2 * 4 * 4));
+#pragma unroll
+    for (int w = 0; w < kBW; ++w)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) out[(w * 2 + r) * 4 + n] = acc[w][r][n];
+  }
+}
+
+// Fixed-order sum of the block partials of one output block and frequency. Thread
+// t reads what thread t of the block kernel wrote: rows 16 (t / 64) + 4 q + e,
+// columns 16 n + i, with i = t % 16, q = (t % 64) / 16.
+__global__ void __launch_bounds__(256) chi0_reduce_blocks(const Item* __restrict__ items,
+                                                          const int2* __restrict__ tiles, const Red* __restrict__ reds,
+                                                          const float* __restrict__ part) {
+  const Red R = reds[blockIdx.x];
+  const int w = blockIdx.y;
+  const Item I = items[R.item];
+  if (R.w0 + w >= I.nw) return;
+  const int2 bij = tiles[I.tile0 + R.tile];
+  const int t = threadIdx.x, i = t & 15, q = (t >> 4) & 3, wave = t >> 6;
+  double re[4][4], im[4][4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) re[n][e] = im[n][e] = 0.0;
+  for (int u = 0; u < R.nu; ++u) {
+    const f4* p = reinterpret_cast<const f4*>(part + ((size_t)(R.u0 + u) * 256 + t) * (kBW * 2 * 4 * 4)) + w * 8;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const f4 a = p[n], b = p[4 + n];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        re[n][e] += (double)a[e];
+        im[n][e] += (double)b[e];
+      }
+    }
+  }
+  double* m = I.chi0 + (size_t)(R.w0 + w) * I.ng * I.ng * 2;
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int G = bij.x * kBlk + 16 * wave + 4 * q + e, Gp = bij.y * kBlk + 16 * n + i;
+      if (G >= I.ng || Gp >= I.ng || G > Gp) continue;
+      const double vr = -I.pref * re[n][e];
+      const double vi = G == Gp ? 0.0 : -I.pref * im[n][e];
+      const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
+      if (I.accumulate) {
+        m[up] += vr;
+        m[up + 1] += vi;
+        if (G != Gp) {
+          m[lo] += vr;
+          m[lo + 1] -= vi;
+        }
+      } else {
+        m[up] = vr;
+        m[up + 1] = vi;
+        if (G != Gp) {
+          m[lo] = vr;
+          m[lo + 1] = -vi;
+        }
+      }
+    }
+}
+
 // --------------------------------------------------------------- host side --
 
 int num_cus() {
@@ -370,13 +538,16 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : MODE_BF16X3);
   const size_t tsz = mode == MODE_F64 ? sizeof(double) : sizeof(float);
   const int nw = a[0].nw;
-  const int nwg = nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1));
+  // split-bf16 default: the 64 x 64 block form once there are four frequencies to share it
+  const bool blk = mode == MODE_BF16X3 && ((tune && tune->nt_tiles) ? tune->nt_tiles == 4 : nw >= kBW);
+  const int nwg = blk ? kBW : (nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1)));
   const int ngroups = (nw + nwg - 1) / nwg;
   const int nwpad = ngroups * nwg;
   const int NT = (tune && mode == MODE_BF16X3 && tune->nt_tiles == 2) ? 2 : 1;
-  const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : 4;
+  const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4);
+  const int brow = blk ? kBlk : kTile, bcol = blk ? kBlk : kTile * NT;
 
-  // block pairs: 16-row block i, (16 NT)-column block j, keeping those with a column >= a row
+  // block pairs: brow-row block i, bcol-column block j, keeping those with a column >= a row
   std::vector<int2> tiles;
   std::vector<Item> items(n);
   std::vector<int> ntl(n);
@@ -384,11 +555,11 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   size_t wbytes = 0;
   for (int it = 0; it < n; ++it) {
     const int ng = a[it].ng;
-    const int nbr = (ng + kTile - 1) / kTile, nbc = (ng + kTile * NT - 1) / (kTile * NT);
+    const int nbr = (ng + brow - 1) / brow, nbc = (ng + bcol - 1) / bcol;
     items[it].tile0 = (int)tiles.size();
     for (int i = 0; i < nbr; ++i)
       for (int j = 0; j < nbc; ++j)
-        if (j * kTile * NT + kTile * NT - 1 >= i * kTile) tiles.push_back(make_int2(i, j));
+        if (j * bcol + bcol - 1 >= i * brow) tiles.push_back(make_int2(i, j));
     ntl[it] = (int)tiles.size() - items[it].tile0;
     woff[it] = wbytes;
     wbytes += align_up((size_t)a[it].nt * nwpad * tsz, 256);
@@ -421,14 +592,17 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
         reds.push_back(r);
       }
   }
-  // queue: longest units first (stable: equal units keep their item / block order)
+  // queue: longest units first; among equal lengths, transition slice first, so the
+  // units in flight together read the same slice of every item's rho (cache reuse)
   std::vector<int> queue(units.size());
   for (size_t u = 0; u < units.size(); ++u) queue[u] = (int)u;
   std::stable_sort(queue.begin(), queue.end(), [&](int x, int y) {
-    return (units[x].k1 - units[x].k0) > (units[y].k1 - units[y].k0);
+    const int lx = units[x].k1 - units[x].k0, ly = units[y].k1 - units[y].k0;
+    if (lx != ly) return lx > ly;
+    return units[x].k0 < units[y].k0;
   });
   const int nunits = (int)units.size();
-  const size_t per = (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
+  const size_t per = blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
   const size_t pbytes = per * nunits;
   void* ws = nullptr;
   XO_RET(workspace(s, 1, wbytes + pbytes + 256, &ws));
@@ -487,6 +661,25 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   XO_RET(device_table(reds.data(), reds.size() * sizeof(Red), s, &dreds));
   const int grid = std::min(nunits, num_cus() * grid_per_cu);
   const int nreds = (int)reds.size();
+  if (blk) {
+    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 1);
+    XO_CHECK_LAUNCH();
+    {
+      KernelTimer kt_("chi0_blocks_bf16x3", s);
+      hipLaunchKernelGGL(chi0_blocks, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
+                         static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
+                         static_cast<const int*>(dqueue), nunits, counter, static_cast<float*>(part));
+    }
+    XO_CHECK_LAUNCH();
+    {
+      KernelTimer kt_("chi0_reduce", s);
+      hipLaunchKernelGGL(chi0_reduce_blocks, dim3(nreds, kBW), dim3(256), 0, s, static_cast<const Item*>(ditems),
+                         static_cast<const int2*>(dtiles), static_cast<const Red*>(dreds),
+                         static_cast<const float*>(part));
+    }
+    XO_CHECK_LAUNCH();
+    return XO_OK;
+  }
   if (mode == MODE_F64)
     return launch_nwg<MODE_F64>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
                                 s);
@@ -510,7 +703,9 @@ extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tu
   xo::clear_error();
   XO_ARG(items && n > 0, "xo_chi0_batch: need a non-empty array of items");
   if (tune) {
-    XO_ARG(tune->nt_tiles >= 0 && tune->nt_tiles <= 2, "xo_chi0_batch: nt_tiles must be 0, 1 or 2");
+    XO_ARG(tune->nt_tiles == 0 || tune->nt_tiles == 1 || tune->nt_tiles == 2 || tune->nt_tiles == 4,
+           "xo_chi0_batch: nt_tiles must be 0, 1, 2 or 4");
+    XO_ARG(tune->nt_tiles != 4 || items[0].prec == XO_BF16X3, "xo_chi0_batch: nt_tiles 4 is the XO_BF16X3 block form");
     XO_ARG(tune->kper >= 0 && tune->wg_per_cu >= 0 && tune->wg_per_cu <= 16, "xo_chi0_batch: bad tune values");
   }
   return xo::chi0_batch_run(items, n, tune, static_cast<hipStream_t>(stream));
@@ -521,13 +716,15 @@ extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best,
   XO_ARG(items && n > 0 && best, "xo_chi0_autotune: bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<xo_tune> cands;
-  const int nts = items[0].prec == XO_BF16X3 ? 2 : 1;
+  std::vector<int> nts = {1};
+  if (items[0].prec == XO_BF16X3) nts = {1, 2, 4};
   int ntmax = 0;
   for (int i = 0; i < n; ++i) ntmax = std::max(ntmax, items[i].nt);
-  for (int nt = 1; nt <= nts; ++nt)
+  for (int nt : nts)
     for (int kper : {0, 2048, 8192, 32768})
-      for (int wpc : {2, 4, 8}) {
+      for (int wpc : {1, 2, 4, 8}) {
         if (kper > 0 && kper / 2 > ntmax) continue;
+        if ((wpc == 1) != (nt == 4) && wpc < 2) continue;  // one workgroup per CU only for the block form
         cands.push_back({nt, kper, wpc});
       }
   hipEvent_t e0, e1;

@@ -112,6 +112,7 @@ struct PairDesc {
 };
 
 constexpr int kMaxGroups = 8;
+constexpr int kPS = 18;  // row stride (float2) of the partial sums: 16 bands + 2 padding, spreads LDS banks
 constexpr int kMaxPF = 2;  // conduction box entries per thread per plane
 
 template <int MT, int GPT>
@@ -136,7 +137,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   const int rem = local - c * (nvt * nE);
   const int vt = rem / nE, eg = rem - (rem / nE) * nE;
   const int mte = P.mte[eg];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, l16 = l & 15, q = l >> 4;
+  const int tid = threadIdx.x, l = tid & 63, l16 = l & 15, q = l >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
   const int* tab = P.tab;
 
   const int NxP = (Nx + 1) & ~1;
@@ -144,22 +146,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   float2* twp = tw + NxP;                                       // [2][Nx] this plane's exp(2 pi i e_x x / Nx)
   int* kg = reinterpret_cast<int*>(twp + 2 * NxP);              // [Kp/4], padded to a multiple of 4
   uint32_t* cb = reinterpret_cast<uint32_t*>(kg + ((Kp / 4 + 3) & ~3));  // [2][4][CS]: hi copies, lo copies
-  float2* Pp = reinterpret_cast<float2*>(cb + 8 * CS);          // [4][MT*16][16]
+  float2* Pp = reinterpret_cast<float2*>(cb + 8 * CS);          // [4][MT*16][kPS]
 
   for (int k = tid; k < Nx; k += kBlock) tw[k] = twt[k];
-  for (int k = tid; k < Kp / 4; k += kBlock) kg[k] = tab[P.kg + k];
+  for (int k = tid; k < Kp / 4; k += kBlock) kg[k] = gld<int>(tab + P.kg + k);
   for (int k = tid; k < 8 * CS; k += kBlock) cb[k] = 0u;
 
   // A-operand row offsets of this lane (row l16 of every M-tile)
   int oe[MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) oe[mt] = tab[P.oe + (eg * MT + mt) * 16 + l16];
+  for (int mt = 0; mt < MT; ++mt) oe[mt] = gld<int>(tab + P.oe + (eg * MT + mt) * 16 + l16);
   // owned outputs: G entries l + 64 i, valence bands 4w .. 4w+3 of the tile
   int gi[GPT];
   float2 acc[GPT][4];
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
-    gi[i] = tab[P.gl + eg * GPT * 64 + l + 64 * i];
+    gi[i] = gld<int>(tab + P.gl + eg * GPT * 64 + l + 64 * i);
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[i][u] = make_float2(0.f, 0.f);
   }
@@ -170,9 +172,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
   for (int f = 0; f < kMaxPF; ++f) {
     const int j = tid + kBlock * f;
-    cp[f] = j < ncb ? tab[P.cpos + j] : -1;
-    ph[f] = cp[f] >= 0 ? P.Uc_hi[cbase + j] : 0u;
-    pl[f] = cp[f] >= 0 ? P.Uc_lo[cbase + j] : 0u;
+    cp[f] = j < ncb ? gld<int>(tab + P.cpos + j) : -1;
+    ph[f] = cp[f] >= 0 ? gld<uint32_t>(P.Uc_hi + cbase + j) : 0u;
+    pl[f] = cp[f] >= 0 ? gld<uint32_t>(P.Uc_lo + cbase + j) : 0u;
   }
   __syncthreads();  // boxes zeroed and twiddles loaded before the first plane
   // work items (K-chunk, M-tile), K-chunk major; wave w takes a contiguous share
@@ -205,8 +207,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
       for (int f = 0; f < kMaxPF; ++f) {
         if (cp[f] >= 0) {
-          ph[f] = P.Uc_hi[o + tid + kBlock * f];
-          pl[f] = P.Uc_lo[o + tid + kBlock * f];
+          ph[f] = gld<uint32_t>(P.Uc_hi + o + tid + kBlock * f);
+          pl[f] = gld<uint32_t>(P.Uc_lo + o + tid + kBlock * f);
         }
       }
     }
@@ -222,13 +224,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       const int kc0 = it0 / mte, kc1 = (it1 - 1) / mte;
       const uint32_t* vh = P.Uv_hi + (vrow + x) * Kp + 4 * q;
       const uint32_t* vl = P.Uv_lo + (vrow + x) * Kp + 4 * q;
-      u4 nbh = vok ? *reinterpret_cast<const u4*>(vh + kc0 * 16) : u4{0u, 0u, 0u, 0u};
-      u4 nbl = vok ? *reinterpret_cast<const u4*>(vl + kc0 * 16) : u4{0u, 0u, 0u, 0u};
+      u4 nbh = vok ? gld<u4>(vh + kc0 * 16) : u4{0u, 0u, 0u, 0u};
+      u4 nbl = vok ? gld<u4>(vl + kc0 * 16) : u4{0u, 0u, 0u, 0u};
       for (int kc = kc0; kc <= kc1; ++kc) {
         const u4 bh = nbh, bl = nbl;
         if (kc < kc1 && vok) {
-          nbh = *reinterpret_cast<const u4*>(vh + (kc + 1) * 16);
-          nbl = *reinterpret_cast<const u4*>(vl + (kc + 1) * 16);
+          nbh = gld<u4>(vh + (kc + 1) * 16);
+          nbl = gld<u4>(vl + (kc + 1) * 16);
         }
         u4 rh, rl;
 #pragma unroll
@@ -242,9 +244,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
           const int item = kc * mte + mt;
           if (mt < mte && item >= it0 && item < it1) {
             const int o = ob + oe[mt];
-            const int sft = o & 3;
-            const u4 ah = *reinterpret_cast<const u4*>(cb + sft * CS + (o - sft));
-            const u4 al = *reinterpret_cast<const u4*>(cb + (4 + sft) * CS + (o - sft));
+            const int a = o + (int)__umul24((unsigned)(o & 3), (unsigned)(CS - 1));  // copy (o & 3), aligned
+            const u4 ah = *reinterpret_cast<const u4*>(cb + a);
+            const u4 al = *reinterpret_cast<const u4*>(cb + 4 * CS + a);
             re[mt] = mma3(ah, al, bh, bl, re[mt]);
             im[mt] = mma3(ah, al, rh, rl, im[mt]);
           }
@@ -252,19 +254,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       }
     }
     // ---- partial sums of this wave: rows mt*16 + 4q + r, column l16
-    float2* Pw = Pp + w * (MT * 256);
+    float2* Pw = Pp + w * (MT * 16 * kPS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       if (mt < mte) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Pw[(mt * 16 + 4 * q + r) * 16 + l16] = make_float2(re[mt][r], im[mt][r]);
+        for (int r = 0; r < 4; ++r) Pw[(mt * 16 + 4 * q + r) * kPS + l16] = make_float2(re[mt][r], im[mt][r]);
       }
     }
     __syncthreads();
     // ---- fixed-order reduction over the four waves into slice 0
     for (int e = tid; e < mte * 256; e += kBlock) {
-      const float2 a0 = Pp[e], a1 = Pp[MT * 256 + e], a2 = Pp[2 * MT * 256 + e], a3 = Pp[3 * MT * 256 + e];
-      Pp[e] = make_float2(((a0.x + a1.x) + a2.x) + a3.x, ((a0.y + a1.y) + a2.y) + a3.y);
+      const int o = (e >> 4) * kPS + (e & 15);
+      const float2 a0 = Pp[o], a1 = Pp[MT * 16 * kPS + o], a2 = Pp[2 * MT * 16 * kPS + o],
+                   a3 = Pp[3 * MT * 16 * kPS + o];
+      Pp[o] = make_float2(((a0.x + a1.x) + a2.x) + a3.x, ((a0.y + a1.y) + a2.y) + a3.y);
     }
     __syncthreads();
     // ---- x transform into the owned rho entries
@@ -272,7 +276,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     for (int i = 0; i < GPT; ++i) {
       if (gi[i] >= 0) {
         const int row = (gi[i] >> 16) & 0xff;
-        const float4* sp = reinterpret_cast<const float4*>(Pp + row * 16 + 4 * w);
+        const float4* sp = reinterpret_cast<const float4*>(Pp + row * kPS + 4 * w);
         const float4 s01 = sp[0], s23 = sp[1];
         const float2 t = twp[(x & 1) * NxP + ((unsigned)gi[i] >> 24)];
         acc[i][0].x = fmaf(s01.x, t.x, fmaf(-s01.y, t.y, acc[i][0].x));
@@ -293,7 +297,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       float2* out = P.rho + ((size_t)vv * P.nc + c) * ng;
 #pragma unroll
       for (int i = 0; i < GPT; ++i)
-        if (gi[i] >= 0) out[gi[i] & 0xffff] = make_float2(acc[i][u].x * scale, acc[i][u].y * scale);
+        if (gi[i] >= 0) gst<f2v>(out + (gi[i] & 0xffff), f2v{acc[i][u].x * scale, acc[i][u].y * scale});
     }
   }
 }
@@ -422,7 +426,8 @@ static bool pair_geo(const xo_rho_args* a, const Extent& xc, const Extent& xv, c
       oe[(size_t)e * MT * 16 + r] = (key.first - xe.lo[1]) * EZ + (key.second - xe.lo[2]);
       for (int gidx : cols[key]) gs.push_back(gidx | (int)(r << 16));
     }
-    std::sort(gs.begin(), gs.end(), [](int u, int v) { return (u & 0xffff) < (v & 0xffff); });
+    // by row, then G: neighbouring lanes read the same or adjacent rows of the partial sums
+    std::sort(gs.begin(), gs.end());
     for (size_t j = 0; j < gs.size(); ++j) {
       const int gidx = gs[j] & 0xffff;
       const int ex = pmod(a->mill_g[3 * gidx] - a->g0[0], Nx);
@@ -606,7 +611,7 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     nwg += d.nc * d.nvt * d.nE;
     const size_t need = (size_t)3 * ((Nx + 1) & ~1) * sizeof(float2) + (size_t)((g.Kp / 4 + 3) & ~3) * 4 +
                         (size_t)8 * g.CS * 4 +
-                        (size_t)4 * MT * 256 * sizeof(float2);
+                        (size_t)4 * MT * 16 * kPS * sizeof(float2);
     lds = std::max(lds, need);
   }
   if (lds > 160 * 1024) return XO_ERR_UNSUPPORTED;

@@ -109,6 +109,19 @@ __device__ __forceinline__ void cfma_conj(cplx<T>& acc, cplx<T> a, cplx<T> b) {
   acc.y = fma(-a.y, b.x, acc.y);
 }
 
+// Loads and stores through the global address space. Pointers that reach a
+// kernel inside descriptor tables are otherwise generic (flat) accesses, which
+// also count against the LDS wait counter and serialise with LDS reads.
+// T must be a scalar or a clang vector type.
+template <typename T>
+__device__ __forceinline__ T gld(const void* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(void* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 __host__ __device__ inline int pmod(int a, int n) {
   int r = a % n;
   return r < 0 ? r + n : r;

@@ -130,9 +130,9 @@ def test_chi0_fp64_random(nt, ng, nw):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16x3", 2e-4)])
-def test_chi0_reduced_precision_random(prec, tol):
-    nt, ng, nw = 5000, 45, 4
-    say(f"chi0 {prec} random")
+@pytest.mark.parametrize("nt,ng,nw", [(5000, 45, 4), (3001, 150, 8), (517, 64, 5)])
+def test_chi0_reduced_precision_random(prec, tol, nt, ng, nw):
+    say(f"chi0 {prec} random nt={nt} ng={ng} nw={nw}")
     M = random_complex(7, (nt, ng))
     dE = random_positive(8, nt, 0.05, 3.0)
     w = np.linspace(0.0, 2.0, nw)
@@ -143,6 +143,11 @@ def test_chi0_reduced_precision_random(prec, tol):
     err = rel_fro(got, ref)
     say(f"  rel Frobenius err {err:.3e}")
     assert err < tol
+    for j in range(nw):
+        assert np.array_equal(got[j], got[j].conj().T)
+    again = torch.empty_like(out)
+    xo.chi0(_to(M, torch.complex64), _to(dE, torch.float64), w, 1.0, out=again, prec=prec)
+    assert torch.equal(out, again)   # fixed-order reduction: bitwise repeatable
 
 
 def test_chi0_accumulate_and_determinism():
@@ -268,11 +273,11 @@ def test_alloc_failure_is_reported_and_recovers():
 # ------------------------------------------------------------- batched persistent
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("bf16x3", 2e-4)])
-@pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8)])
+@pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8), (4, 256, 1), (4, 0, 0)])
 def test_chi0_batch_uneven_items(prec, tol, tune):
     """Items with different G-set sizes and transition counts in one persistent launch."""
-    if prec == "fp64" and tune is not None and tune[0] == 2:
-        pytest.skip("two column tiles per wave exist for bf16x3 only (fp64 runs one)")
+    if prec == "fp64" and tune is not None and tune[0] in (2, 4):
+        pytest.skip("two column tiles per wave and the 64 x 64 block form exist for bf16x3 only")
     say(f"chi0 batch {prec} tune={tune}")
     shapes = [(700, 17), (1300, 33), (96, 50), (2000, 41)]
     w = [0.0, 0.3, 1.0]
