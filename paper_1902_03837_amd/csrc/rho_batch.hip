@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "bf16x3.h"
@@ -108,6 +109,7 @@ struct PairDesc {
   const int* tab;
   int cpos, kg, oe, gl;   // offsets into tab
   int nc, nv, nvt, nE, ncb, Kp, CS, wg0;
+  int mts;                // M-tile stride of the oe table (the pair's own largest group)
   int mte[8];             // M-tiles used by each e-group (at most 8 groups)
 };
 
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   // A-operand row offsets of this lane (row l16 of every M-tile)
   int oe[MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) oe[mt] = gld<int>(tab + P.oe + (eg * MT + mt) * 16 + l16);
+  for (int mt = 0; mt < MT; ++mt) oe[mt] = mt < mte ? gld<int>(tab + P.oe + (eg * P.mts + mt) * 16 + l16) : 0;
   // owned outputs: G entries l + 64 i, valence bands 4w .. 4w+3 of the tile
   int gi[GPT];
   float2 acc[GPT][4];
@@ -490,34 +492,63 @@ static bool mfma_eligible(const xo_rho_args* p, int n) {
   return true;
 }
 
+// Geometry of one pair and its device tables, cached by content (Miller lists,
+// G0, grid, G entries per workgroup) for the life of the device tables.
+struct GeoEntry {
+  SphereBox bc, bv;
+  PairGeo g;
+  const void* dbox[2];
+  const void* dout[2];
+  const void* dtab;
+  unsigned gen;
+};
+
+static int pair_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, int GPT,
+                      hipStream_t s, const GeoEntry** out) {
+  static std::mutex mu;
+  static std::map<std::vector<int32_t>, GeoEntry> cache;
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  std::vector<int32_t> key = {dev, a->n[0], GPT, a->g0[0], a->g0[1], a->g0[2], a->npw_c, a->npw_v, a->ng};
+  key.insert(key.end(), a->mill_c, a->mill_c + 3 * a->npw_c);
+  key.insert(key.end(), a->mill_v, a->mill_v + 3 * a->npw_v);
+  key.insert(key.end(), a->mill_g, a->mill_g + 3 * a->ng);
+  const unsigned gen = table_generation();
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end() && it->second.gen == gen) {
+    *out = it->second.g.nE ? &it->second : nullptr;
+    return XO_OK;
+  }
+  GeoEntry e;
+  e.gen = gen;
+  e.bc = sphere_box(a->mill_c, a->npw_c, xc);
+  e.bv = sphere_box(a->mill_v, a->npw_v, xv);
+  if (!pair_geo(a, xc, xv, xe, e.bc, e.bv, GPT, &e.g) || e.g.ncb > kBlock * kMaxPF || e.g.MT > 8) {
+    e.g.nE = 0;  // remembered as unsupported
+  } else {
+    XO_RET(device_table(e.bc.boxidx.data(), e.bc.boxidx.size() * sizeof(int), s, &e.dbox[0]));
+    XO_RET(device_table(e.bv.boxidx.data(), e.bv.boxidx.size() * sizeof(int), s, &e.dbox[1]));
+    XO_RET(device_table(e.g.outc.data(), e.g.outc.size() * sizeof(int), s, &e.dout[0]));
+    XO_RET(device_table(e.g.outv.data(), e.g.outv.size() * sizeof(int), s, &e.dout[1]));
+    XO_RET(device_table(e.g.tab.data(), e.g.tab.size() * sizeof(int), s, &e.dtab));
+  }
+  GeoEntry& slot = cache[key];
+  slot = std::move(e);
+  *out = slot.g.nE ? &slot : nullptr;
+  return XO_OK;
+}
+
 static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                           hipStream_t s) {
   const int Nx = p[0].n[0], ng = p[0].ng;
   const int GPT = ng <= 128 ? 2 : 8;
-  std::vector<SphereBox> bc(n), bv(n);
-  std::vector<PairGeo> geo(n);
+  std::vector<const GeoEntry*> ge(n);
   int MT = 1;
   for (int i = 0; i < n; ++i) {
-    bc[i] = sphere_box(p[i].mill_c, p[i].npw_c, xc[i]);
-    bv[i] = sphere_box(p[i].mill_v, p[i].npw_v, xv[i]);
-    if (!pair_geo(&p[i], xc[i], xv[i], xe[i], bc[i], bv[i], GPT, &geo[i])) return XO_ERR_UNSUPPORTED;
-    if (geo[i].ncb > kBlock * kMaxPF) return XO_ERR_UNSUPPORTED;
-    MT = std::max(MT, geo[i].MT);
-  }
-  if (MT > 8) return XO_ERR_UNSUPPORTED;
-  // the oe tables were laid out with each pair's own MT; re-lay with the batch MT
-  for (int i = 0; i < n; ++i) {
-    if (geo[i].MT == MT) continue;
-    PairGeo& g = geo[i];
-    std::vector<int> oe((size_t)g.nE * MT * 16, 0);
-    for (int e = 0; e < g.nE; ++e)
-      for (int r = 0; r < g.MT * 16; ++r) oe[(size_t)e * MT * 16 + r] = g.tab[g.oe + e * g.MT * 16 + r];
-    std::vector<int> gl(g.tab.begin() + g.gl, g.tab.end());
-    g.tab.resize(g.oe);
-    g.tab.insert(g.tab.end(), oe.begin(), oe.end());
-    g.gl = (int)g.tab.size();
-    g.tab.insert(g.tab.end(), gl.begin(), gl.end());
-    g.MT = MT;
+    XO_RET(pair_entry(&p[i], xc[i], xv[i], xe[i], GPT, s, &ge[i]));
+    if (!ge[i]) return XO_ERR_UNSUPPORTED;
+    MT = std::max(MT, ge[i]->g.MT);
   }
   std::vector<float2> tw(Nx);
   for (int k = 0; k < Nx; ++k) {
@@ -532,9 +563,9 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   size_t tot = 0;
   for (int i = 0; i < n; ++i) {
     offc[i] = tot;
-    tot += align_up((size_t)p[i].nc * Nx * geo[i].ncb, 64);
+    tot += align_up((size_t)p[i].nc * Nx * ge[i]->g.ncb, 64);
     offv[i] = tot;
-    tot += align_up((size_t)p[i].nv * Nx * geo[i].Kp, 64);
+    tot += align_up((size_t)p[i].nv * Nx * ge[i]->g.Kp, 64);
   }
   void* ws = nullptr;
   XO_RET(workspace(s, 3, 2 * tot * sizeof(uint32_t), &ws));
@@ -546,21 +577,17 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   size_t orb_lds = 0;
   for (int i = 0; i < n; ++i) {
     for (int side = 0; side < 2; ++side) {
-      const SphereBox& b = side ? bv[i] : bc[i];
-      const std::vector<int>& outcol = side ? geo[i].outv : geo[i].outc;
-      const void* dbox = nullptr;
-      const void* dout = nullptr;
-      XO_RET(device_table(b.boxidx.data(), b.boxidx.size() * sizeof(int), s, &dbox));
-      XO_RET(device_table(outcol.data(), outcol.size() * sizeof(int), s, &dout));
+      const GeoEntry& e = *ge[i];
+      const SphereBox& b = side ? e.bv : e.bc;
       OrbX& o = sides[2 * i + side];
       o.coef = static_cast<const float2*>(side ? p[i].coef_v : p[i].coef_c);
-      o.boxidx = static_cast<const int*>(dbox);
-      o.outcol = static_cast<const int*>(dout);
+      o.boxidx = static_cast<const int*>(e.dbox[side]);
+      o.outcol = static_cast<const int*>(e.dout[side]);
       o.Uhi = Uhi0 + (side ? offv[i] : offc[i]);
       o.Ulo = Ulo0 + (side ? offv[i] : offc[i]);
       o.npw = side ? p[i].npw_v : p[i].npw_c;
       o.nb = side ? p[i].nv : p[i].nc;
-      o.nout = (int)outcol.size();
+      o.nout = side ? e.g.Kp : e.g.ncb;
       o.nbx = b.nbx;
       o.ncol = b.nby * b.nbz;
       o.xlo = b.xlo;
@@ -585,16 +612,14 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   int nwg = 0;
   size_t lds = 0;
   for (int i = 0; i < n; ++i) {
-    const PairGeo& g = geo[i];
-    const void* dtab = nullptr;
-    XO_RET(device_table(g.tab.data(), g.tab.size() * sizeof(int), s, &dtab));
+    const PairGeo& g = ge[i]->g;
     PairDesc& d = pd[i];
     d.Uc_hi = Uhi0 + offc[i];
     d.Uc_lo = Ulo0 + offc[i];
     d.Uv_hi = Uhi0 + offv[i];
     d.Uv_lo = Ulo0 + offv[i];
     d.rho = static_cast<float2*>(p[i].rho);
-    d.tab = static_cast<const int*>(dtab);
+    d.tab = static_cast<const int*>(ge[i]->dtab);
     d.cpos = g.cpos;
     d.kg = g.kg;
     d.oe = g.oe;
@@ -606,12 +631,12 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     d.ncb = g.ncb;
     d.Kp = g.Kp;
     d.CS = g.CS;
+    d.mts = g.MT;
     for (int e = 0; e < kMaxGroups; ++e) d.mte[e] = e < g.nE ? g.mte[e] : 0;
     d.wg0 = nwg;
     nwg += d.nc * d.nvt * d.nE;
     const size_t need = (size_t)3 * ((Nx + 1) & ~1) * sizeof(float2) + (size_t)((g.Kp / 4 + 3) & ~3) * 4 +
-                        (size_t)8 * g.CS * 4 +
-                        (size_t)4 * MT * 16 * kPS * sizeof(float2);
+                        (size_t)8 * g.CS * 4 + (size_t)4 * MT * 16 * kPS * sizeof(float2);
     lds = std::max(lds, need);
   }
   if (lds > 160 * 1024) return XO_ERR_UNSUPPORTED;

@@ -38,6 +38,12 @@ struct Table {
   void* dev = nullptr;
 };
 static std::map<std::tuple<int, uint64_t, size_t>, std::vector<Table>> g_tables;
+static unsigned g_table_gen = 0;
+
+unsigned table_generation() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_table_gen;
+}
 
 static bool fault_alloc() {
   const char* f = getenv("XO_FAULT");
@@ -227,6 +233,7 @@ const char* xo_version(void) { return "xo 0.1.0 (gfx950)"; }
 
 int xo_release_workspace(void) {
   std::lock_guard<std::mutex> lk(xo::g_mu);
+  ++xo::g_table_gen;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     xo::set_error("hipDeviceSynchronize failed: %s", hipGetErrorString(e));

@@ -65,6 +65,9 @@ int host_flags(hipStream_t s, size_t bytes, void** out);
 // Cached device copy of an immutable host table (geometry, index lists),
 // keyed by content. Returned pointer stays valid until xo_release_workspace.
 int device_table(const void* host, size_t bytes, hipStream_t s, const void** out);
+// Counter bumped by xo_release_workspace: pointers from device_table obtained
+// under an older value are gone.
+unsigned table_generation();
 
 // Event bracket around one kernel launch when timing is enabled (no-op otherwise).
 struct KernelTimer {
