@@ -4,11 +4,12 @@
 //
 // eps~ is Hermitian positive definite at imaginary frequencies. It is inverted
 // in place by blocked Gauss-Jordan elimination without pivoting, all frequencies
-// in the same launches. Per block column K (width b):
-//   P    = A_KK^-1                  (one workgroup per frequency, LDS)
-//   A_K* = P A_K*                   (row block, columns outside K)
-//   A_ij -= A_iK A_Kj               (i, j outside K; rank-b update)
-//   A_iK = -A_iK P,   A_KK = P
+// in the same launches. Per block column K (width b = 64), three launches:
+//   P = A_KK^-1                      diag_inverse: one workgroup per frequency,
+//                                    the block in registers, one barrier per pivot
+//   A_Kj = P A_Kj  (j outside K)     row_col: row tiles of the panel, and
+//   S_iK = A_iK,  A_iK = -A_iK P     column tiles (old column saved in S)
+//   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update
 // The pivots met inside the diagonal blocks are the diagonal of eps~ = L D L^H,
 // so a pivot with non-positive real part proves eps~ is not positive definite.
 
@@ -21,7 +22,7 @@
 namespace xo {
 namespace {
 
-constexpr int kB = 32;  // block width
+constexpr int kB = 64;  // block width
 
 typedef cplx<double> z;
 
@@ -39,132 +40,196 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
   o[1] = -f * c[1];
 }
 
-// In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix.
+// In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
+// (kb <= 64). Thread t holds row t / 4, columns 16 (t % 4) .. 16 (t % 4) + 15 in
+// registers (identity outside kb). Per pivot k the owners publish column k and
+// row k (values before the step) in LDS, double buffered, and every thread
+// updates its own sixteen entries after one barrier.
 __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
                                                    int check_sign, int* __restrict__ flag) {
-  __shared__ z D[kB][kB + 1];
-  __shared__ z rowk[kB];
-  __shared__ z colk[kB];
+  __shared__ z pcol[2][kB];
+  __shared__ z prow[2][kB];
   const int w = blockIdx.x;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-    const int i = e / kb, j = e % kb;
-    D[i][j] = A[(size_t)(o + i) * n + o + j];
+  const int t = threadIdx.x, r = t >> 2, cq = t & 3, c0 = 16 * cq;
+  z a[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int c = c0 + j;
+    a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
   }
-  __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const z piv = D[k][k];
-    // pivot test (uniform across the block: every thread reads the same value)
-    const bool badp = check_sign ? !(piv.x > 0.0) : (piv.x == 0.0 && piv.y == 0.0);
-    if (badp && threadIdx.x == 0 && flag[w] == 0) flag[w] = o + k + 1;
-    const double den = piv.x * piv.x + piv.y * piv.y;
-    const z ip = den > 0.0 ? z{piv.x / den, -piv.y / den} : z{0.0, 0.0};
-    if (threadIdx.x < kb) {
-      const int j = threadIdx.x;
-      rowk[j] = (j == k) ? ip : cmul(D[k][j], ip);
-      colk[j] = D[j][k];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-      const int i = e / kb, j = e % kb;
-      if (i == k) {
-        D[i][j] = rowk[j];
-      } else if (j == k) {
-        const z f = colk[i];
-        D[i][j] = z{-(f.x * ip.x - f.y * ip.y), -(f.x * ip.y + f.y * ip.x)};
+  for (int kq = 0; kq < 4; ++kq) {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * kq + kk;
+      if (k >= kb) break;
+      const int b = k & 1;
+      if (cq == kq) pcol[b][r] = a[kk];
+      if (r == k) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) prow[b][c0 + j] = a[j];
+      }
+      __syncthreads();
+      const z piv = pcol[b][k];
+      if (t == 0) {
+        const bool bad = check_sign ? !(piv.x > 0.0) : (piv.x == 0.0 && piv.y == 0.0);
+        if (bad) atomicCAS(flag + w, 0, o + k + 1);  // first bad pivot of this frequency
+      }
+      const double den = piv.x * piv.x + piv.y * piv.y;
+      const double rd = den > 0.0 ? 1.0 / den : 0.0;
+      const z ip = z{piv.x * rd, -piv.y * rd};
+      if (r == k) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a[j] = (c0 + j == k) ? ip : cmul(prow[b][c0 + j], ip);
       } else {
-        const z f = colk[i], r = rowk[j];
-        D[i][j] = z{D[i][j].x - (f.x * r.x - f.y * r.y), D[i][j].y - (f.x * r.y + f.y * r.x)};
+        const z g = cmul(pcol[b][r], ip);  // A_rk / A_kk
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const z pr = prow[b][c0 + j];
+          if (c0 + j == k) {
+            a[j] = z{-g.x, -g.y};
+          } else {
+            a[j].x -= g.x * pr.x - g.y * pr.y;
+            a[j].y -= g.x * pr.y + g.y * pr.x;
+          }
+        }
       }
     }
-    __syncthreads();
   }
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-    const int i = e / kb, j = e % kb;
-    A[(size_t)(o + i) * n + o + j] = D[i][j];
-  }
-}
-
-// Row block: A_Kj <- P A_Kj for 64 columns j outside K per workgroup.
-__global__ void __launch_bounds__(256) row_block(double* __restrict__ Aall, int n, int K, int kb) {
-  __shared__ z P[kB][kB + 1];
-  __shared__ z T[kB][65];
-  const int w = blockIdx.y;
-  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
-  const int o = K * kB;
-  const int j0 = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) P[e / kb][e % kb] = A[(size_t)(o + e / kb) * n + o + e % kb];
-  for (int e = threadIdx.x; e < kb * 64; e += blockDim.x) {
-    const int r = e / 64, c = e % 64, j = j0 + c;
-    T[r][c] = (j < n && !(j >= o && j < o + kb)) ? A[(size_t)(o + r) * n + j] : z{0.0, 0.0};
-  }
-  __syncthreads();
-  const int c = threadIdx.x & 63, j = j0 + c;
-  if (j >= n || (j >= o && j < o + kb)) return;
-  for (int r = threadIdx.x >> 6; r < kb; r += 4) {
-    z acc = {0.0, 0.0};
-    for (int m = 0; m < kb; ++m) cfma(acc, P[r][m], T[m][c]);
-    A[(size_t)(o + r) * n + j] = acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int c = c0 + j;
+    if (r < kb && c < kb) A[(size_t)(o + r) * n + o + c] = a[j];
   }
 }
 
-// Rank-kb update of every element outside row block K and column block K:
-//   A_ij -= A_iK A_Kj   (A_iK old column, A_Kj new row).
-__global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, int n, int K, int kb) {
-  __shared__ z L[32][kB + 1];
-  __shared__ z R[kB][33];
-  const int w = blockIdx.z;
-  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
-  const int o = K * kB;
-  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-  if (i0 == o || j0 == o) return;  // tiles are aligned with the 32-wide blocks
-  for (int e = threadIdx.x; e < 32 * kb; e += blockDim.x) {
-    const int r = e / kb, m = e % kb;
-    L[r][m] = (i0 + r < n) ? A[(size_t)(i0 + r) * n + o + m] : z{0.0, 0.0};
-    const int m2 = e / 32, c = e % 32;
-    R[m2][c] = (j0 + c < n) ? A[(size_t)(o + m2) * n + j0 + c] : z{0.0, 0.0};
-  }
-  __syncthreads();
-  const int c = threadIdx.x & 31;
-  const int j = j0 + c;
-  if (j >= n) return;
-  for (int r = threadIdx.x >> 5; r < 32; r += 8) {
-    const int i = i0 + r;
-    if (i >= n) break;
-    z acc = A[(size_t)i * n + j];
-    for (int m = 0; m < kb; ++m) {
-      const z a = L[r][m], b = R[m][c];
-      acc.x -= a.x * b.x - a.y * b.y;
-      acc.y -= a.x * b.y + a.y * b.x;
+// One 64 x 64 tile product L R (L: 64 x kb, R: kb x 64, in LDS). Thread t owns
+// rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 4): a wave reads four rows
+// of L (broadcast) and 16 consecutive entries of each row of R per step.
+__device__ __forceinline__ void tile_product(const z (*L)[kB + 1], const z (*R)[kB + 1], int kb, z acc[4][4]) {
+  const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = z{0.0, 0.0};
+  for (int m = 0; m < kb; ++m) {
+    z l[4], rr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      l[u] = L[rr0 + 16 * u][m];
+      rr[u] = R[m][cc0 + 16 * u];
     }
-    A[(size_t)i * n + j] = acc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cfma(acc[u][v], l[u], rr[v]);
   }
 }
 
-// Column block: A_iK <- -A_iK P for 64 rows i outside K per workgroup.
-__global__ void __launch_bounds__(256) col_block(double* __restrict__ Aall, int n, int K, int kb) {
-  __shared__ z P[kB][kB + 1];
-  __shared__ z T[64][kB + 1];
+// Row tiles (blockIdx.x < nt): A_Kj <- P A_Kj for the 64 columns of tile j != K.
+// Column tiles (blockIdx.x >= nt): S_iK <- A_iK, A_iK <- -A_iK P for the 64 rows
+// of tile i != K. S: [nw][n][kB].
+__global__ void __launch_bounds__(256) row_col(double* __restrict__ Aall, int n, int K, int kb, int nt,
+                                              double* __restrict__ Sall) {
+  extern __shared__ unsigned char smem[];
+  z (*P)[kB + 1] = reinterpret_cast<z (*)[kB + 1]>(smem);
+  z (*T)[kB + 1] = P + kB;
   const int w = blockIdx.y;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
-  const int o = K * kB;
-  const int i0 = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) P[e / kb][e % kb] = A[(size_t)(o + e / kb) * n + o + e % kb];
-  for (int e = threadIdx.x; e < 64 * kb; e += blockDim.x) {
-    const int r = e / kb, m = e % kb, i = i0 + r;
-    T[r][m] = (i < n) ? A[(size_t)i * n + o + m] : z{0.0, 0.0};
+  z* S = reinterpret_cast<z*>(Sall) + (size_t)w * n * kB;
+  const bool rowt = (int)blockIdx.x < nt;
+  const int tile = rowt ? (int)blockIdx.x : (int)blockIdx.x - nt;
+  if (tile == K) return;
+  const int o = K * kB, x0 = tile * kB;
+  {
+    // all sixteen loads of each operand in flight before the LDS stores
+    z vp[16], vt[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
+      vp[f] = (i < kb && j < kb) ? A[(size_t)(o + i) * n + o + j] : z{0.0, 0.0};
+      if (rowt)  // T[m][c] = A[o + m][x0 + c]
+        vt[f] = (i < kb && x0 + j < n) ? A[(size_t)(o + i) * n + x0 + j] : z{0.0, 0.0};
+      else       // T[r][m] = A[x0 + r][o + m]
+        vt[f] = (x0 + i < n && j < kb) ? A[(size_t)(x0 + i) * n + o + j] : z{0.0, 0.0};
+    }
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
+      P[i][j] = vp[f];
+      T[i][j] = vt[f];
+    }
   }
   __syncthreads();
-  const int m = threadIdx.x & 31;
-  if (m >= kb) return;
-  for (int r = threadIdx.x >> 5; r < 64; r += 8) {
-    const int i = i0 + r;
-    if (i >= n || (i >= o && i < o + kb)) continue;
-    z acc = {0.0, 0.0};
-    for (int p = 0; p < kb; ++p) cfma(acc, T[r][p], P[p][m]);
-    A[(size_t)i * n + o + m] = z{-acc.x, -acc.y};
+  const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
+  z acc[4][4];
+  if (rowt) {
+    tile_product(P, T, kb, acc);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rr0 + 16 * u, c = x0 + cc0 + 16 * v;
+        if (r < kb && c < n) A[(size_t)(o + r) * n + c] = acc[u][v];
+      }
+  } else {
+    tile_product(T, P, kb, acc);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rr0 + 16 * u, m = cc0 + 16 * v;
+        if (x0 + r < n && m < kb) {
+          const size_t i = x0 + r;
+          S[i * kB + m] = T[r][m];
+          A[i * n + o + m] = z{-acc[u][v].x, -acc[u][v].y};
+        }
+      }
   }
+}
+
+// Rank-kb update of every 64 x 64 tile outside row block K and column block K:
+//   A_ij -= S_iK A_Kj   (S old column, A_Kj new row).
+__global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, int n, int K, int kb,
+                                                  const double* __restrict__ Sall) {
+  extern __shared__ unsigned char smem[];
+  z (*L)[kB + 1] = reinterpret_cast<z (*)[kB + 1]>(smem);
+  z (*R)[kB + 1] = L + kB;
+  const int w = blockIdx.z;
+  if ((int)blockIdx.x == K || (int)blockIdx.y == K) return;
+  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
+  const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
+  const int o = K * kB, i0 = blockIdx.y * kB, j0 = blockIdx.x * kB;
+  {
+    z vl[16], vr[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
+      vl[f] = (i0 + i < n && j < kb) ? S[(size_t)(i0 + i) * kB + j] : z{0.0, 0.0};
+      vr[f] = (i < kb && j0 + j < n) ? A[(size_t)(o + i) * n + j0 + j] : z{0.0, 0.0};
+    }
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
+      L[i][j] = vl[f];
+      R[i][j] = vr[f];
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
+  z acc[4][4];
+  tile_product(L, R, kb, acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + rr0 + 16 * u, j = j0 + cc0 + 16 * v;
+      if (i < n && j < n) {
+        z& x = A[(size_t)i * n + j];
+        x = z{x.x - acc[u][v].x, x.y - acc[u][v].y};
+      }
+    }
 }
 
 __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ s, int n) {
@@ -203,9 +268,13 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* ds = nullptr;
   XO_RET(device_table(s.data(), sizeof(double) * n, st, &ds));
+  const int nblk = (n + kB - 1) / kB;
   void* ws = nullptr;
-  XO_RET(workspace(st, 2, sizeof(int) * a->nw, &ws));
+  const size_t fbytes = align_up(sizeof(int) * a->nw, 256);
+  const size_t sbytes = nblk > 1 ? (size_t)a->nw * n * kB * sizeof(z) : 0;
+  XO_RET(workspace(st, 2, fbytes + sbytes, &ws));
   int* flag = static_cast<int*>(ws);
+  double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + fbytes);
   XO_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int) * a->nw, st));
   const size_t nn = (size_t)n * n;
   {
@@ -214,8 +283,16 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
                        static_cast<const double*>(ds), n, a->out);
   }
   XO_CHECK_LAUNCH();
-  const int nblk = (n + kB - 1) / kB;
   const int check_sign = (a->flags & XO_EPS_LU_FALLBACK) ? 0 : 1;
+  const size_t lds2 = (size_t)2 * kB * (kB + 1) * sizeof(z);
+  static bool attr = false;
+  if (!attr) {
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_col),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rank_update),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    attr = true;
+  }
   for (int K = 0; K < nblk; ++K) {
     const int kb = std::min(kB, n - K * kB);
     {
@@ -225,19 +302,14 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
       {
-        KernelTimer kt_("eps_row_block", st);
-        hipLaunchKernelGGL(row_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+        KernelTimer kt_("eps_row_col", st);
+        hipLaunchKernelGGL(row_col, dim3(2 * nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb, nblk, S);
       }
       XO_CHECK_LAUNCH();
       {
         KernelTimer kt_("eps_rank_update", st);
-        hipLaunchKernelGGL(rank_update, dim3((n + 31) / 32, (n + 31) / 32, a->nw), dim3(256), 0, st, a->out, n,
-                           K, kb);
-      }
-      XO_CHECK_LAUNCH();
-      {
-        KernelTimer kt_("eps_col_block", st);
-        hipLaunchKernelGGL(col_block, dim3((n + 63) / 64, a->nw), dim3(256), 0, st, a->out, n, K, kb);
+        hipLaunchKernelGGL(rank_update, dim3(nblk, nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb,
+                           static_cast<const double*>(S));
       }
       XO_CHECK_LAUNCH();
     }

@@ -196,7 +196,7 @@ def test_epsinv_parity(name):
     assert rel_fro(out.cpu().numpy(), refn) < 1e-12
 
 
-@pytest.mark.parametrize("ng", [1, 31, 32, 33, 97])
+@pytest.mark.parametrize("ng", [1, 31, 32, 33, 63, 64, 65, 97, 128, 200])
 def test_epsinv_sizes_random_hpd(ng):
     say(f"epsinv random HPD ng={ng}")
     X = random_complex(ng, (3 * ng + 2, ng))
