@@ -171,8 +171,9 @@ def roofline(cr, form, K, nw, ng):
     k = kern[name]
     t = k["avg_launch_ms"] * 1e-3
     prec = form["prec"]
-    if name.startswith("chi0_tiles"):
-        fl = chi0_flops(K, ng, min(nw, 8))          # one launch covers one group of <= 8 frequencies
+    if name.startswith("chi0_tiles") or name.startswith("chi0_blocks"):
+        # one launch of the 16x16 form covers one group of <= 8 frequencies, the block form all of them
+        fl = chi0_flops(K, ng, nw if name.startswith("chi0_blocks") else min(nw, 8))
         peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                     frac=fl / t / peak, traffic=measured_traffic(name),
@@ -273,7 +274,7 @@ def run_c3(args):
                    chi0_GFLOPs=fl / (ms * 1e-3) / 1e9, chi0_kernel_TFLOPs=None,
                    transitions_per_s_per_qw=sum(Ks) * nw / (ms * 1e-3), tune=tn,
                    kernels={k: dict(launches=v[0] // nsteps, ms_per_step=v[1] / nsteps) for k, v in kern.items()})
-        ck = [k for k in kern if k.startswith("chi0_tiles")]
+        ck = [k for k in kern if k.startswith("chi0_tiles") or k.startswith("chi0_blocks")]
         if ck:
             res["chi0_kernel_TFLOPs"] = fl / (kern[ck[0]][1] / nsteps * 1e-3) / 1e12
         Eall[prec] = [b["E"].cpu().numpy() for b in bufs]

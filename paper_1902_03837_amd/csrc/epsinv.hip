@@ -79,22 +79,19 @@ __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, i
       const double den = piv.x * piv.x + piv.y * piv.y;
       const double rd = den > 0.0 ? 1.0 / den : 0.0;
       const z ip = z{piv.x * rd, -piv.y * rd};
-      if (r == k) {
+      // one instruction stream for every row: the pivot row is 0 - (-1/p) A_kj,
+      // the others A_rj - (A_rk / p) A_kj; column k is set afterwards
+      const bool prow_k = r == k;
+      const z gr = cmul(pcol[b][r], ip);
+      const z g = prow_k ? z{-ip.x, -ip.y} : gr;
+      const double keep = prow_k ? 0.0 : 1.0;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) a[j] = (c0 + j == k) ? ip : cmul(prow[b][c0 + j], ip);
-      } else {
-        const z g = cmul(pcol[b][r], ip);  // A_rk / A_kk
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const z pr = prow[b][c0 + j];
-          if (c0 + j == k) {
-            a[j] = z{-g.x, -g.y};
-          } else {
-            a[j].x -= g.x * pr.x - g.y * pr.y;
-            a[j].y -= g.x * pr.y + g.y * pr.x;
-          }
-        }
+      for (int j = 0; j < 16; ++j) {
+        const z pr = prow[b][c0 + j];
+        a[j].x = fma(-g.x, pr.x, fma(g.y, pr.y, keep * a[j].x));
+        a[j].y = fma(-g.x, pr.y, fma(-g.y, pr.x, keep * a[j].y));
       }
+      if (cq == kq) a[kk] = prow_k ? ip : z{-gr.x, -gr.y};
     }
   }
 #pragma unroll
@@ -189,41 +186,54 @@ __global__ void __launch_bounds__(256) row_col(double* __restrict__ Aall, int n,
   }
 }
 
-// Rank-kb update of every 64 x 64 tile outside row block K and column block K:
+// Rank-kb update of every 32 x 32 tile outside row block K and column block K:
 //   A_ij -= S_iK A_Kj   (S old column, A_Kj new row).
+// Thread t owns rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 2).
+constexpr int kT = 32;
 __global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, int n, int K, int kb,
                                                   const double* __restrict__ Sall) {
-  extern __shared__ unsigned char smem[];
-  z (*L)[kB + 1] = reinterpret_cast<z (*)[kB + 1]>(smem);
-  z (*R)[kB + 1] = L + kB;
+  __shared__ z L[kT][kB + 1];
+  __shared__ z R[kB][kT + 1];
   const int w = blockIdx.z;
-  if ((int)blockIdx.x == K || (int)blockIdx.y == K) return;
+  const int o = K * kB, i0 = blockIdx.y * kT, j0 = blockIdx.x * kT;
+  if ((i0 >= o && i0 < o + kB) || (j0 >= o && j0 < o + kB)) return;  // 32-tiles sit inside 64-blocks
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
-  const int o = K * kB, i0 = blockIdx.y * kB, j0 = blockIdx.x * kB;
   {
-    z vl[16], vr[16];
+    z vl[8], vr[8];
 #pragma unroll
-    for (int f = 0; f < 16; ++f) {
-      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
-      vl[f] = (i0 + i < n && j < kb) ? S[(size_t)(i0 + i) * kB + j] : z{0.0, 0.0};
-      vr[f] = (i < kb && j0 + j < n) ? A[(size_t)(o + i) * n + j0 + j] : z{0.0, 0.0};
+    for (int f = 0; f < 8; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      const int li = e >> 6, lj = e & 63;   // L: 32 rows x 64
+      const int ri = e >> 5, rj = e & 31;   // R: 64 rows x 32
+      vl[f] = (i0 + li < n && lj < kb) ? S[(size_t)(i0 + li) * kB + lj] : z{0.0, 0.0};
+      vr[f] = (ri < kb && j0 + rj < n) ? A[(size_t)(o + ri) * n + j0 + rj] : z{0.0, 0.0};
     }
 #pragma unroll
-    for (int f = 0; f < 16; ++f) {
-      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
-      L[i][j] = vl[f];
-      R[i][j] = vr[f];
+    for (int f = 0; f < 8; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      L[e >> 6][e & 63] = vl[f];
+      R[e >> 5][e & 31] = vr[f];
     }
   }
   __syncthreads();
   const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
-  z acc[4][4];
-  tile_product(L, R, kb, acc);
+  z acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < 2; ++v) acc[u][v] = z{0.0, 0.0};
+  for (int m = 0; m < kb; ++m) {
+    const z l0 = L[rr0][m], l1 = L[rr0 + 16][m], r0 = R[m][cc0], r1 = R[m][cc0 + 16];
+    cfma(acc[0][0], l0, r0);
+    cfma(acc[0][1], l0, r1);
+    cfma(acc[1][0], l1, r0);
+    cfma(acc[1][1], l1, r1);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
       const int i = i0 + rr0 + 16 * u, j = j0 + cc0 + 16 * v;
       if (i < n && j < n) {
         z& x = A[(size_t)i * n + j];
@@ -289,8 +299,6 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   if (!attr) {
     XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_col),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rank_update),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
     attr = true;
   }
   for (int K = 0; K < nblk; ++K) {
@@ -308,7 +316,8 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
       XO_CHECK_LAUNCH();
       {
         KernelTimer kt_("eps_rank_update", st);
-        hipLaunchKernelGGL(rank_update, dim3(nblk, nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb,
+        const unsigned nt32 = (n + kT - 1) / kT;
+        hipLaunchKernelGGL(rank_update, dim3(nt32, nt32, a->nw), dim3(256), 0, st, a->out, n, K, kb,
                            static_cast<const double*>(S));
       }
       XO_CHECK_LAUNCH();

@@ -241,6 +241,34 @@ __global__ void rho_head_q0(const cplx<T>* __restrict__ cc, const cplx<T>* __res
 
 // ------------------------------------------------------------------ host side
 
+template <typename T>
+static int launch_head_q0(const xo_rho_args* a, hipStream_t s) {
+  int g0idx = -1;
+  for (int g = 0; g < a->ng; ++g)
+    if (a->mill_g[3 * g] == 0 && a->mill_g[3 * g + 1] == 0 && a->mill_g[3 * g + 2] == 0) g0idx = g;
+  double qn = std::sqrt(a->qhat[0] * a->qhat[0] + a->qhat[1] * a->qhat[1] + a->qhat[2] * a->qhat[2]);
+  std::vector<double> proj(a->npw_c);
+  for (int p = 0; p < a->npw_c; ++p) {
+    double kg[3];
+    for (int i = 0; i < 3; ++i)
+      kg[i] = a->kcart[i] + a->mill_c[3 * p] * a->bvec[0 + i] + a->mill_c[3 * p + 1] * a->bvec[3 + i] +
+              a->mill_c[3 * p + 2] * a->bvec[6 + i];
+    proj[p] = (kg[0] * a->qhat[0] + kg[1] * a->qhat[1] + kg[2] * a->qhat[2]) / qn;
+  }
+  const void* dproj = nullptr;
+  XO_RET(device_table(proj.data(), proj.size() * sizeof(double), s, &dproj));
+  const int n = a->nc * a->nv;
+  {
+    KernelTimer kt_("rho_head_q0", s);
+    hipLaunchKernelGGL((rho_head_q0<T>), dim3((n + 255) / 256), dim3(256), 0, s,
+                       static_cast<const cplx<T>*>(a->coef_c), static_cast<const cplx<T>*>(a->coef_v),
+                       a->npw_c, static_cast<const double*>(dproj), a->e_c, a->e_v, a->nc, a->nv, a->ng,
+                       g0idx, static_cast<cplx<T>*>(a->rho));
+  }
+  XO_CHECK_LAUNCH();
+  return XO_OK;
+}
+
 template <typename T, int NO>
 static int launch_orb(const void* coef, int npw, int nb, const SphereTable& st, const Extent& ex,
                       hipStream_t s, int Nx, int Ny, void* U) {
@@ -358,31 +386,7 @@ static int rho_run(const xo_rho_args* a, hipStream_t s, const Extent& xc, const 
     XO_CHECK_LAUNCH();
   }
 
-  if (a->q0) {
-    int g0idx = -1;
-    for (int g = 0; g < a->ng; ++g)
-      if (a->mill_g[3 * g] == 0 && a->mill_g[3 * g + 1] == 0 && a->mill_g[3 * g + 2] == 0) g0idx = g;
-    double qn = std::sqrt(a->qhat[0] * a->qhat[0] + a->qhat[1] * a->qhat[1] + a->qhat[2] * a->qhat[2]);
-    std::vector<double> proj(a->npw_c);
-    for (int p = 0; p < a->npw_c; ++p) {
-      double kg[3];
-      for (int i = 0; i < 3; ++i)
-        kg[i] = a->kcart[i] + a->mill_c[3 * p] * a->bvec[0 + i] + a->mill_c[3 * p + 1] * a->bvec[3 + i] +
-                a->mill_c[3 * p + 2] * a->bvec[6 + i];
-      proj[p] = (kg[0] * a->qhat[0] + kg[1] * a->qhat[1] + kg[2] * a->qhat[2]) / qn;
-    }
-    const void* dproj = nullptr;
-    XO_RET(device_table(proj.data(), proj.size() * sizeof(double), s, &dproj));
-    const int n = a->nc * a->nv;
-    {
-      KernelTimer kt_("rho_head_q0", s);
-      hipLaunchKernelGGL((rho_head_q0<T>), dim3((n + 255) / 256), dim3(256), 0, s,
-                         static_cast<const cplx<T>*>(a->coef_c), static_cast<const cplx<T>*>(a->coef_v),
-                         a->npw_c, static_cast<const double*>(dproj), a->e_c, a->e_v, a->nc, a->nv, a->ng,
-                         g0idx, static_cast<cplx<T>*>(a->rho));
-    }
-    XO_CHECK_LAUNCH();
-  }
+  if (a->q0) XO_RET(launch_head_q0<T>(a, s));
   if (a->dE) {
     const int n = a->nc * a->nv;
     {
@@ -457,6 +461,10 @@ int validate_rho(const xo_rho_args* a, Extent* pxc, Extent* pxv, Extent* pxe) {
   *pxe = xe;
   return XO_OK;
 }
+
+// q -> 0 head of a pair whose other columns came from the batched MFMA path
+// (complex64 output).
+int rho_head_f32(const xo_rho_args* a, hipStream_t s) { return launch_head_q0<float>(a, s); }
 
 // VALU path for one pair (FP64 and FP32).
 int rho_valu(const xo_rho_args* a, hipStream_t s) {

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -39,6 +40,7 @@
 namespace xo {
 
 int rho_valu(const xo_rho_args* a, hipStream_t s);
+int rho_head_f32(const xo_rho_args* a, hipStream_t s);
 
 namespace {
 
@@ -485,7 +487,7 @@ static bool mfma_eligible(const xo_rho_args* p, int n) {
   const xo_rho_args& a0 = p[0];
   if (a0.ng > 65535) return false;
   for (int i = 0; i < n; ++i) {
-    if (p[i].q0 || p[i].prec != XO_BF16X3) return false;
+    if (p[i].prec != XO_BF16X3) return false;
     if (p[i].n[0] != a0.n[0] || p[i].ng != a0.ng) return false;
     if (std::memcmp(p[i].mill_g, a0.mill_g, sizeof(int32_t) * 3 * a0.ng) != 0) return false;
   }
@@ -505,19 +507,31 @@ struct GeoEntry {
 
 static int pair_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, int GPT,
                       hipStream_t s, const GeoEntry** out) {
+  // Lookup by the caller's Miller-list pointers and scalars, then a full
+  // comparison of the lists' contents against the copy kept with the entry
+  // (a reused buffer with new contents is a miss).
+  struct Key {
+    std::vector<int32_t> scal, mc, mv, mg;
+  };
   static std::mutex mu;
-  static std::map<std::vector<int32_t>, GeoEntry> cache;
+  static std::map<std::vector<intptr_t>, std::vector<std::pair<Key, std::unique_ptr<GeoEntry>>>> cache;
   int dev = 0;
   XO_TRY_HIP(hipGetDevice(&dev));
-  std::vector<int32_t> key = {dev, a->n[0], GPT, a->g0[0], a->g0[1], a->g0[2], a->npw_c, a->npw_v, a->ng};
-  key.insert(key.end(), a->mill_c, a->mill_c + 3 * a->npw_c);
-  key.insert(key.end(), a->mill_v, a->mill_v + 3 * a->npw_v);
-  key.insert(key.end(), a->mill_g, a->mill_g + 3 * a->ng);
+  const std::vector<intptr_t> pk = {dev, a->n[0], GPT, a->g0[0], a->g0[1], a->g0[2], a->npw_c, a->npw_v, a->ng,
+                                    (intptr_t)a->mill_c, (intptr_t)a->mill_v, (intptr_t)a->mill_g};
+  auto same = [&](const Key& k) {
+    return std::memcmp(k.mc.data(), a->mill_c, 12 * (size_t)a->npw_c) == 0 &&
+           std::memcmp(k.mv.data(), a->mill_v, 12 * (size_t)a->npw_v) == 0 &&
+           std::memcmp(k.mg.data(), a->mill_g, 12 * (size_t)a->ng) == 0;
+  };
   const unsigned gen = table_generation();
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(key);
-  if (it != cache.end() && it->second.gen == gen) {
-    *out = it->second.g.nE ? &it->second : nullptr;
+  auto& bucket = cache[pk];
+  std::unique_ptr<GeoEntry>* slotp = nullptr;
+  for (auto& kv : bucket)
+    if (same(kv.first)) slotp = &kv.second;
+  if (slotp && (*slotp)->gen == gen) {
+    *out = (*slotp)->g.nE ? slotp->get() : nullptr;
     return XO_OK;
   }
   GeoEntry e;
@@ -533,9 +547,19 @@ static int pair_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, 
     XO_RET(device_table(e.g.outv.data(), e.g.outv.size() * sizeof(int), s, &e.dout[1]));
     XO_RET(device_table(e.g.tab.data(), e.g.tab.size() * sizeof(int), s, &e.dtab));
   }
-  GeoEntry& slot = cache[key];
-  slot = std::move(e);
-  *out = slot.g.nE ? &slot : nullptr;
+  if (!slotp) {
+    Key k;
+    k.mc.assign(a->mill_c, a->mill_c + 3 * a->npw_c);
+    k.mv.assign(a->mill_v, a->mill_v + 3 * a->npw_v);
+    k.mg.assign(a->mill_g, a->mill_g + 3 * a->ng);
+    bucket.emplace_back(std::move(k), nullptr);
+    slotp = &bucket.back().second;
+  }
+  // a stale entry (tables released) is replaced, not freed: callers on other
+  // threads may still hold it
+  slotp->release();
+  *slotp = std::make_unique<GeoEntry>(std::move(e));
+  *out = (*slotp)->g.nE ? slotp->get() : nullptr;
   return XO_OK;
 }
 
@@ -646,6 +670,9 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     XO_RET(launch_rho_mt<2>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
   else
     XO_RET(launch_rho_mt<8>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
+  // q -> 0: the G = 0 column of such pairs is the velocity head, written over the transform's value
+  for (int i = 0; i < n; ++i)
+    if (p[i].q0) XO_RET(rho_head_f32(&p[i], s));
 
   std::vector<PoleDesc> poles;
   int maxm = 0;

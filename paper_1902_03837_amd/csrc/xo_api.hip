@@ -107,7 +107,7 @@ int host_flags(hipStream_t s, size_t bytes, void** out) {
 
 // Content hash for the table cache: 64-bit multiply-xorshift over 8-byte words
 // (a mismatch only costs a memcmp, equality is always checked in full).
-static uint64_t content_hash(const void* p, size_t n) {
+uint64_t content_hash(const void* p, size_t n) {
   const unsigned char* c = static_cast<const unsigned char*>(p);
   uint64_t h = 0x9e3779b97f4a7c15ull ^ n;
   size_t i = 0;

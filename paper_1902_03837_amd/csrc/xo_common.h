@@ -65,6 +65,8 @@ int host_flags(hipStream_t s, size_t bytes, void** out);
 // Cached device copy of an immutable host table (geometry, index lists),
 // keyed by content. Returned pointer stays valid until xo_release_workspace.
 int device_table(const void* host, size_t bytes, hipStream_t s, const void** out);
+// 64-bit hash of a byte range (cache keys; equality is always checked in full).
+uint64_t content_hash(const void* p, size_t n);
 // Counter bumped by xo_release_workspace: pointers from device_table obtained
 // under an older value are gone.
 unsigned table_generation();
