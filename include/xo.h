@@ -276,6 +276,43 @@ int xo_tail_apply(const double* chi_t, const float* Y1, const float* Y2, const d
 int xo_tail_guard(const float* X, long n, int F, const float* lo, const float* hi, const float* Y1,
                   const float* Y2, int ny, double* stats, void* stream);
 
+/* ------------------------------------------------------------------------- */
+/* Bruneval-Gonze extrapolar correction of chi0 (the X-terminator; Eq. X_term_def,
+ * Appendix B Eq. X-term) for one k-pair at imaginary frequencies, added to out:
+ *   out[w][G][G'] += -pref sum_v W(w, ebar - e_v) [ <v| e^{i(G-G').r} |v>
+ *                                                   - sum_{n < nn} rho_nv(G) conj(rho_nv(G')) ],
+ *   W(w, D) = 2 D / (w^2 + D^2).
+ * The empty states above the nn explicit bands at k get the single energy ebar
+ * (the paper's default: the highest explicit band energy + 1.5 Ha), so their sum
+ * closes over all states at k: the density element of each occupied v at k'
+ * minus the explicit bands, occupied ones included. rho holds rho_nv(G) of the
+ * nn explicit bands at k against the nv occupied bands at k', as written by
+ * xo_rho with the conduction side set to bands 0 .. nn-1 (rows t = v nn + n).
+ * Passing the truncated chi0 as out yields the corrected chi0. FP64 only;
+ * q = 0 (head and wings) is not treated. Errors: XO_ERR_ARG for bad sizes or an
+ * ebar not above every e_v (checked on the device; the call then synchronises).
+ *   mill_v [host] [npw_v][3]; coef_v [device] [nv][npw_v] complex128;
+ *   e_v [device] [nv]; mill_g [host] [ng][3]; w [host] [nw];
+ *   rho [device] [nv*nn][ng] complex128; out [device] [nw][ng][ng] complex128. */
+typedef struct {
+  int npw_v;
+  const int32_t* mill_v;
+  int nv;
+  const void* coef_v;
+  const double* e_v;
+  double ebar;
+  int ng;
+  const int32_t* mill_g;
+  int nw;
+  const double* w;
+  double pref;
+  int nn;
+  const void* rho;
+  double* out;
+} xo_xterm_args;
+
+int xo_xterm(const xo_xterm_args* a, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

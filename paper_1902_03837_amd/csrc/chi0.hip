@@ -26,6 +26,7 @@
 // bf16 variant (v_mfma_f32_16x16x32_bf16): lane = i + 16 q holds k = 8 q .. 8 q + 7.
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -463,7 +464,7 @@ int num_cus() {
   return n;
 }
 
-static int validate(const xo_chi0_args* a) {
+static int validate(const xo_chi0_args* a, bool signed_pref) {
   XO_ARG(a, "xo_chi0: null argument block");
   XO_ARG(a->nt > 0 && a->ng > 0 && a->nw > 0, "xo_chi0: sizes must be positive (nt=%d ng=%d nw=%d)", a->nt,
          a->ng, a->nw);
@@ -472,7 +473,7 @@ static int validate(const xo_chi0_args* a) {
   XO_ARG(a->prec == XO_FP64 || a->prec == XO_FP32 || a->prec == XO_BF16X3, "xo_chi0: bad precision %d",
          a->prec);
   for (int j = 0; j < a->nw; ++j) XO_ARG(a->w[j] >= 0.0, "xo_chi0: frequency %d is negative", j);
-  XO_ARG(a->pref > 0.0, "xo_chi0: pref must be positive");
+  XO_ARG(signed_pref ? (a->pref != 0.0 && std::isfinite(a->pref)) : a->pref > 0.0, "xo_chi0: pref must be positive");
   return XO_OK;
 }
 
@@ -527,8 +528,9 @@ static int launch_nwg(int nwg, int nt_tiles, const void* ditems, const void* dti
 }
 
 // Every item of a batch shares the precision and the frequencies.
-static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hipStream_t s) {
-  for (int i = 0; i < n; ++i) XO_RET(validate(&a[i]));
+static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hipStream_t s,
+                          bool signed_pref = false) {
+  for (int i = 0; i < n; ++i) XO_RET(validate(&a[i], signed_pref));
   const int prec = a[0].prec;
   for (int i = 1; i < n; ++i) {
     XO_ARG(a[i].prec == prec && a[i].nw == a[0].nw, "xo_chi0_batch: items must share precision and frequencies");
@@ -691,6 +693,11 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
 }
 
 }  // namespace
+
+// The same update with a prefactor of either sign (the terminator subtracts an
+// explicit-band sum through it).
+int chi0_run_signed(const xo_chi0_args* a, hipStream_t s) { return chi0_batch_run(a, 1, nullptr, s, true); }
+
 }  // namespace xo
 
 extern "C" int xo_chi0(const xo_chi0_args* a, void* stream) {

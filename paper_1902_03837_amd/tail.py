@@ -83,6 +83,27 @@ def chi0_blocks(dc: DeviceCrystal, cuts: List[int], prec: str = "fp64", stream=N
     return out
 
 
+def xterm_chi0(dc: DeviceCrystal, nempty: int, chi_trunc, shift: float = 1.5, stream=None):
+    """chi0 with the Bruneval-Gonze terminator (App. B): chi_trunc, summed over the
+    nempty lowest empty bands, plus the correction of every k-pair (xo_rho over the
+    explicit bands at k, occupied included, then xo_xterm). FP64 crystal only;
+    ebar = highest explicit band energy at k + shift."""
+    cr = dc.cr
+    assert dc.prec == "fp64" and not cr.q0
+    ng = cr.gmill.shape[0]
+    out = chi_trunc.clone()
+    for ik, ikp, g0, _, _, nv in band_ranges(cr):
+        nb = cr.nocc_at(ik) + nempty
+        M = torch.empty((nv * nb, ng), dtype=torch.complex128, device=out.device)
+        xo.rho(dc.coef[ik][:nb], cr.mill[ik], dc.eps[ik][:nb], dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv],
+               cr.gmill, g0, cr.grid, out=M.view(nv, nb, ng), prec="fp64", kcart=cr.kcart(ik), bvec=cr.lat.bvec,
+               stream=stream)
+        ebar = float(cr.eps[ik][nb - 1]) + shift
+        xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], ebar, cr.gmill, cr.omegas, cr.pref, M, nb, out,
+                 stream=stream)
+    return out
+
+
 class MLP:
     """Device-resident MLP parameters with Adam state."""
 
@@ -132,24 +153,36 @@ class TailModel:
     hi: np.ndarray
     tau: float = 0.25
     dims: List[int] = field(default_factory=lambda: list(DIMS))
+    base: str = "trunc"             # what the network corrects: the truncated sum, or it plus the terminator
     info: dict = field(default_factory=dict)
 
     def save(self, path):
         np.savez(path, members=np.stack(self.members), mu=self.mu, isd=self.isd, tsc=self.tsc, lo=self.lo,
-                 hi=self.hi, tau=self.tau, dims=np.array(self.dims))
+                 hi=self.hi, tau=self.tau, dims=np.array(self.dims), base=np.array(self.base))
 
     @classmethod
     def load(cls, path):
         z = np.load(path, allow_pickle=False)
+        base = str(z["base"]) if "base" in z.files else "trunc"
         return cls(list(z["members"]), z["mu"], z["isd"], float(z["tsc"]), z["lo"], z["hi"], float(z["tau"]),
-                   [int(x) for x in z["dims"]])
+                   [int(x) for x in z["dims"]], base)
 
 
-def crystal_tensors(cr, ntrunc, nhalf, with_full=True, prec="fp64"):
+def crystal_tensors(cr, ntrunc, nhalf, with_full=True, prec="fp64", base="trunc"):
+    """[reference, base, (full)] chi0 of one crystal on the device.
+
+    base "trunc": [sum over nhalf, sum over ntrunc, full sum] (the network corrects
+    the truncated sum; the slope feature is the last block of bands).
+    base "bg": [sum over ntrunc, that plus the Bruneval-Gonze terminator, full sum]
+    (the network corrects the terminator; the slope feature is the terminator's
+    own correction)."""
     dc = DeviceCrystal.upload(cr, prec)
-    cuts = [nhalf, ntrunc] + ([cr.coef[0].shape[0] - cr.nocc] if with_full else [])
-    chis = chi0_blocks(dc, cuts, prec)
-    return chis, dc
+    full = [cr.coef[0].shape[0] - cr.nocc] if with_full else []
+    if base == "trunc":
+        return chi0_blocks(dc, [nhalf, ntrunc] + full, prec), dc
+    assert base == "bg"
+    chis = chi0_blocks(dc, [ntrunc] + full, prec)
+    return [chis[0], xterm_chi0(dc, ntrunc, chis[0])] + chis[1:], dc
 
 
 def build_features(cr, chis, mu, isd, tsc, dev="cuda"):

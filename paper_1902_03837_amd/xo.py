@@ -62,6 +62,15 @@ class TailArgs(C.Structure):
     ]
 
 
+class XtermArgs(C.Structure):
+    _fields_ = [
+        ("npw_v", C.c_int), ("mill_v", C.POINTER(C.c_int32)), ("nv", C.c_int), ("coef_v", C.c_void_p),
+        ("e_v", C.c_void_p), ("ebar", C.c_double), ("ng", C.c_int), ("mill_g", C.POINTER(C.c_int32)),
+        ("nw", C.c_int), ("w", _f64p), ("pref", C.c_double), ("nn", C.c_int), ("rho", C.c_void_p),
+        ("out", C.c_void_p),
+    ]
+
+
 class Tune(C.Structure):
     _fields_ = [("nt_tiles", C.c_int), ("kper", C.c_int), ("wg_per_cu", C.c_int)]
 
@@ -76,7 +85,8 @@ _LIB = None
 
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
-           "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard")
+           "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
+           "xo_xterm")
 
 
 def lib():
@@ -88,7 +98,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.xo_last_error.restype = C.c_char_p
         L.xo_version.restype = C.c_char_p
-        for name, argt in (("xo_rho", RhoArgs), ("xo_chi0", Chi0Args), ("xo_epsinv", EpsArgs)):
+        for name, argt in (("xo_rho", RhoArgs), ("xo_chi0", Chi0Args), ("xo_epsinv", EpsArgs),
+                           ("xo_xterm", XtermArgs)):
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
@@ -383,3 +394,25 @@ def col_stats(X, out, stream=None):
     n, F = X.shape
     assert out.numel() >= 4 * F
     _check(lib().xo_col_stats(_ptr(X), n, F, _ptr(out), _stream(stream)))
+
+
+def xterm(coef_v, mill_v, e_v, ebar, gmill, omegas, pref, rho_m, nn, out, stream=None):
+    """xo_xterm: out[nw][ng][ng] (complex128) += Bruneval-Gonze correction of one k-pair.
+
+    coef_v [nv][npw_v] complex128 and e_v [nv] float64 on the device; rho_m
+    [nv*nn][ng] complex128 from xo_rho over the nn explicit bands at k."""
+    import torch
+    assert coef_v.dtype == torch.complex128 and e_v.dtype == torch.float64 and rho_m.dtype == torch.complex128
+    nv, npw = coef_v.shape
+    mv = _host_i32(mill_v)
+    mg = _host_i32(gmill)
+    w = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    assert mv.shape == (npw, 3) and e_v.numel() == nv and tuple(rho_m.shape) == (nv * nn, mg.shape[0])
+    assert tuple(out.shape) == (w.shape[0], mg.shape[0], mg.shape[0]) and out.dtype == torch.complex128
+    a = XtermArgs()
+    a.npw_v, a.mill_v, a.nv = npw, mv.ctypes.data_as(C.POINTER(C.c_int32)), nv
+    a.coef_v, a.e_v, a.ebar = _ptr(coef_v), _ptr(e_v), float(ebar)
+    a.ng, a.mill_g, a.nw, a.w = mg.shape[0], mg.ctypes.data_as(C.POINTER(C.c_int32)), w.shape[0], w.ctypes.data_as(_f64p)
+    a.pref, a.nn, a.rho, a.out = float(pref), int(nn), _ptr(rho_m), _ptr(out)
+    _check(lib().xo_xterm(C.byref(a), _stream(stream)))
+    return out

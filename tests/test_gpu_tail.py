@@ -201,6 +201,35 @@ def test_training_reduces_loss_on_small_family():
     assert hist[-1] < 0.5 * hist[0]
 
 
+def test_xterm_matches_oracle(small):
+    """Bruneval-Gonze terminator on the GPU vs the FP64 oracle (App. B), c4_small with 20
+    explicit empty bands."""
+    cr, chis, dchis = small
+    from oracle.terminator import xterm_bg
+    ref = chis[1] + xterm_bg(cr, 20)
+    dc = T.DeviceCrystal.upload(cr, "fp64")
+    got = T.xterm_chi0(dc, 20, dchis[1]).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"xterm vs oracle max rel err {err:.3e}")
+    assert err < 1e-12
+    for j in range(got.shape[0]):
+        assert np.allclose(got[j], got[j].conj().T, rtol=0, atol=1e-14 * np.abs(got).max())
+    # the correction moves the truncated sum towards the full sum here
+    assert np.linalg.norm(got - chis[2]) < np.linalg.norm(chis[1] - chis[2])
+
+
+def test_xterm_rejects_extrapolar_energy_below_occupied(small):
+    cr, chis, dchis = small
+    dc = T.DeviceCrystal.upload(cr, "fp64")
+    ik, ikp, g0 = cr.pairs[0]
+    nv, nb, ng = cr.nocc_at(ikp), cr.nocc_at(ik) + 2, cr.gmill.shape[0]
+    M = torch.zeros((nv * nb, ng), dtype=torch.complex128, device=DEV)
+    out = dchis[1].clone()
+    with pytest.raises(xo.XoError):
+        xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], float(cr.eps[ikp][0]) - 1.0, cr.gmill,
+                 cr.omegas, cr.pref, M, nb, out)
+
+
 def test_fallback_returns_the_full_sum(small):
     """Guard rejection (a model whose range excludes the data) hands back None; the caller
     then uses the full band sum, which is the plain path's result bit for bit."""
@@ -218,23 +247,28 @@ def test_fallback_returns_the_full_sum(small):
 
 
 @pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained tail model in the tree")
-def test_trained_tail_beats_truncation_on_held_out():
-    """The committed model (trained on seeds 1000..1063 by train_tail) on two held-out crystals."""
+def test_trained_tail_beats_its_base_on_held_out():
+    """The committed model (trained on seeds 1000..1063 by train_tail) on three held-out crystals:
+    it must cut the error of the method it corrects (the truncated sum plus the
+    Bruneval-Gonze terminator for a model with base "bg") by 25 % on each and 40 % on average."""
     model = T.TailModel.load(MODEL)
-    for s in (2001, 2002):   # 2000 is out of the training range: the guard sends it to the full sum
+    ratios = []
+    for s in (2002, 2003, 2004):   # the first held-out seeds the guard lets through (2000, 2001 fall back)
         say(f"held-out crystal seed {s}")
         cr = crystal_for("c4", seed=s)
-        chis, _ = T.crystal_tensors(cr, 100, 50)
+        chis, _ = T.crystal_tensors(cr, 100, 50, base=model.base)
         out, info = T.predict(model, cr, chis[:2])
         assert out is not None, info
         qpg = cr.qpg()
         E = {}
-        for k, c in (("t", chis[1]), ("l", out), ("f", chis[2])):
+        for k, c in (("t", chis[1]), ("l", out), ("f", chis[2])):   # t: the base the network corrects
             E[k] = torch.empty_like(c)
             xo.epsinv(c, qpg, out=E[k])
         et = max(float(torch.linalg.norm(E["t"][j] - E["f"][j]) / torch.linalg.norm(E["f"][j]))
                  for j in range(len(cr.omegas)))
         el = max(float(torch.linalg.norm(E["l"][j] - E["f"][j]) / torch.linalg.norm(E["f"][j]))
                  for j in range(len(cr.omegas)))
-        say(f"  e_F truncated {et:.3e} learned {el:.3e}")
-        assert el < 0.5 * et
+        say(f"  e_F base {et:.3e} learned {el:.3e}")
+        assert el < 0.75 * et
+        ratios.append(el / et)
+    assert np.mean(ratios) < 0.6
