@@ -274,8 +274,17 @@ def find_pairs(kf: np.ndarray, qf: np.ndarray) -> List[Tuple[int, int, np.ndarra
 
 def hamiltonian(lat: Lattice, kf: np.ndarray, mill: np.ndarray, pot) -> np.ndarray:
     kg = (np.asarray(kf, float)[None, :] + mill) @ lat.bvec
-    dm = mill[:, None, :].astype(np.int64) - mill[None, :, :]
-    H = pot(dm)
+    # V(G - G') depends only on the Miller difference: evaluate it once per distinct
+    # difference (a dense box of them) and gather
+    lo = mill.min(0).astype(np.int64)
+    span = mill.max(0).astype(np.int64) - lo
+    size = 2 * span + 1
+    box = np.stack(np.meshgrid(*[np.arange(-s, s + 1) for s in span], indexing="ij"), axis=-1).reshape(-1, 3)
+    vbox = pot(box)
+    m = mill.astype(np.int64)
+    flat = ((m[:, 0] * size[1] + m[:, 1]) * size[2] + m[:, 2])
+    base = (span[0] * size[1] + span[1]) * size[2] + span[2]
+    H = vbox[flat[:, None] - flat[None, :] + base]
     H[np.diag_indices_from(H)] += 0.5 * np.einsum("ij,ij->i", kg, kg)
     return H
 
