@@ -8,7 +8,8 @@ c3  batched: 3x3x3 k, all 27 q, 32 occ + 400 empty, 48^3, NG per q from the clos
 c4  learned tail: c1 family on a 20^3 grid (N_pw ~ 1100), 8 occ + 1000 empty (full) / 100 (truncated),
     NG = 59, 8 freqs; train seeds 1000..1063, held-out 2000..2015.
 c5  large cell: 32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occ + 2000 empty,
-    72^3, NG = 3000, 16 freqs.
+    72^3, NG = 3000, 16 freqs (c5_small: the same cell, G-set and grid with k = {Gamma, b1/2},
+    N_pw ~ 1500, 200 empty bands, 4 freqs).
 """
 
 from __future__ import annotations
@@ -40,6 +41,9 @@ CONFIGS["c1_small"] = dict(CONFIGS["c1"], npw=200, nempty=12)
 CONFIGS["c2_small"] = dict(CONFIGS["c2"], kset=2, q=(.5, 0., 0.), nocc=4, nempty=28,
                            grid=20, npw=180, ng=89, nw=3)
 CONFIGS["c4_small"] = dict(CONFIGS["c4"], grid=16, npw=300, nempty=120, ntrunc=20, nw=4)
+# large cell at its real G-set (NG = 3000) and grid, one k-pair and its partner
+# (Gamma and b1/2), a smaller plane-wave sphere and 200 empty bands
+CONFIGS["c5_small"] = dict(CONFIGS["c5"], kset=((0., 0., 0.), (.5, 0., 0.)), npw=1500, nempty=200, nw=4)
 
 
 def closed_shell_counts(lo: int, hi: int):
@@ -56,6 +60,8 @@ def _kset(spec):
     ks = spec["kset"]
     if isinstance(ks, str) and ks == "fcc4":
         return FCC4.copy()
+    if isinstance(ks, (list, tuple)):
+        return np.array(ks, float).reshape(-1, 3)
     return kgrid_gamma(int(ks))
 
 

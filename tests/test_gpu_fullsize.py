@@ -63,3 +63,50 @@ def test_c2_full_size_sampled(c2, prec, rtol_rho, rtol_chi):
         assert np.abs(E_h[j] - E_h[j].conj().T).max() < 1e-10
         ev = np.linalg.eigvalsh(0.5 * (E_h[j] + E_h[j].conj().T))
         assert ev.min() > 0 and ev.max() <= 1 + 1e-10
+
+
+# ------------------------------------------------------------------ large cell
+C5S = [0, 1, 17, 500, 1999, 2999]
+
+
+@pytest.fixture(scope="module")
+def c5s():
+    """The large cell at its real G-set (NG = 3000) and 72^3 grid, k = {Gamma, b1/2},
+    128 occupied + 200 empty bands, 4 frequencies: K = 51 200."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+    cr = crystal_for("c5_small")
+    Ms, dEs = [], []
+    for ik, ikp, g0 in cr.pairs:
+        cc, cv = cr.coef[ik][cr.nocc:], cr.coef[ikp][:cr.nocc]
+        Ms.append(rho_direct(cc, cr.mill[ik], cv, cr.mill[ikp], cr.gmill[C5S], g0).reshape(-1, len(C5S)))
+        dEs.append((cr.eps[ik][cr.nocc:][None, :] - cr.eps[ikp][:cr.nocc][:, None]).reshape(-1))
+    Mref, dEref = np.concatenate(Ms), np.concatenate(dEs)
+    return cr, Mref, chi0_from_rho(Mref, dEref, cr.omegas, cr.pref), {}
+
+
+@pytest.mark.parametrize("prec,rtol_rho,rtol_chi", [("fp64", 1e-12, 1e-12), ("bf16x3", 5e-5, 5e-5)])
+def test_c5_small_real_gset(c5s, prec, rtol_rho, rtol_chi):
+    cr, Mref, chiref, keep = c5s
+    say(f"large cell, NG = 3000, {prec}")
+    dc = DeviceCrystal.upload(cr, prec)
+    M, dE, chi, E = run_crystal(dc, check_dE=False)
+    torch.cuda.synchronize()
+    Mg = M[:, C5S].cpu().numpy().astype(np.complex128)
+    erho = np.abs(Mg - Mref).max() / np.abs(Mref).max()
+    chig = chi[:, C5S][:, :, C5S].cpu().numpy()
+    echi = np.abs(chig - chiref).max() / np.abs(chiref).max()
+    say(f"  sampled rho err {erho:.2e}, sampled chi0 err {echi:.2e}")
+    assert erho < rtol_rho and echi < rtol_chi
+    keep[prec] = (chi.cpu().numpy(), E.cpu().numpy())
+    if len(keep) == 2:
+        # split precision against the plain FP64 path on the whole eps~^-1
+        (c64, E64), (_, E3) = keep["fp64"], keep["bf16x3"]
+        e_f = max(np.linalg.norm(E3[j] - E64[j]) / np.linalg.norm(E64[j]) for j in range(len(cr.omegas)))
+        say(f"  eps~^-1 bf16x3 vs fp64: {e_f:.2e}")
+        assert e_f < 1e-4
+        # FP64 eps~^-1 of one frequency against the oracle's inverse of the same chi0
+        from oracle.epsinv import epsinv_sym
+        ref = epsinv_sym(c64[1:2], cr.qpg())
+        assert np.abs(E64[1] - ref[0]).max() < 1e-10 * np.abs(ref[0]).max()
