@@ -39,6 +39,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 16;
+constexpr int kFp32Slice = 65536;  // longest transition slice accumulated in FP32 by default
 constexpr int kWaves = 4;
 constexpr int MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2;
 
@@ -581,6 +582,10 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
       kper = (int)((a[it].nt + slices - 1) / slices);
     }
     kper = std::max(64, (kper + 63) / 64 * 64);
+    // FP32 accumulators (FP32 and split-bf16 forms): at most kFp32Slice transitions per
+    // unit, so the rounding of the running sums stays bounded and the FP64 reduction
+    // adds many short partial sums
+    if (mode != MODE_F64 && !(tune && tune->kper > 0)) kper = std::min(kper, kFp32Slice);
     for (int t = 0; t < ntl[it]; ++t)
       for (int g = 0; g < ngroups; ++g) {
         Red r;

@@ -66,7 +66,7 @@ def _kset(spec):
 
 
 def crystal_for(name: str, seed: int = None, q=None, potential_zero: bool = False,
-                nb_all: bool = False, **over):
+                nb_all: bool = False, progress=None, **over):
     """Build the crystal for a named workload (deterministic in the seed)."""
     spec = dict(CONFIGS[name], **over)
     seed = spec["seed"] if seed is None else seed
@@ -86,7 +86,7 @@ def crystal_for(name: str, seed: int = None, q=None, potential_zero: bool = Fals
         ng = int(choices[np.random.default_rng(seed).integers(len(choices))])
     nb = None if nb_all else spec["nocc"] + spec["nempty"]
     cr = make_crystal(lat, pot, kf, qf, grid, ecut, spec["nocc"], nb, ng, spec["nw"], seed,
-                      scissor_min=None if nb_all else 0.05)
+                      scissor_min=None if nb_all else 0.05, progress=progress)
     cr.meta = dict(name=name, spec=spec)
     return cr
 

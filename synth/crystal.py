@@ -312,7 +312,7 @@ def alias_extents(grid, mill_c: np.ndarray, mill_v: np.ndarray, gmill: np.ndarra
 def make_crystal(lat: Lattice, pot, kf: np.ndarray, qf: np.ndarray, grid, ecut: float,
                  nocc: int, nb: Optional[int], ng: int, nw: int, seed: int,
                  scissor_min: Optional[float] = 0.05, phases: bool = True,
-                 check_alias: bool = True, nocc_k: Optional[Sequence[int]] = None) -> Crystal:
+                 check_alias: bool = True, nocc_k: Optional[Sequence[int]] = None, progress=None) -> Crystal:
     kf = np.asarray(kf, float).reshape(-1, 3)
     qf = np.asarray(qf, float).reshape(3)
     pairs = find_pairs(kf, qf)
@@ -331,6 +331,8 @@ def make_crystal(lat: Lattice, pot, kf: np.ndarray, qf: np.ndarray, grid, ecut: 
         mills.append(m)
         coefs.append(c)
         epss.append(w.astype(np.float64))
+        if progress:
+            progress(f"k-point {ik + 1}/{len(kf)}: {m.shape[0]} plane waves, {nbk} bands")
     shift = 0.0
     occ = [nocc] * len(kf) if nocc_k is None else list(nocc_k)
     if scissor_min is not None:
