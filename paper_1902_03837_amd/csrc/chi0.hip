@@ -297,7 +297,7 @@ constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
             const int* __restrict__ queue, int nunits, int* __restrict__ counter, float* __restrict__ part) {
-  __shared__ u4 Bs[2][4][4][4][16];        // [buffer][hi, lo, rotated hi, rotated lo][column tile][q][column]
+  __shared__ u4 Bs[2][2][4][4][16];        // [buffer][hi, lo][column tile][q][column]
   __shared__ float4 As[2][kBlk][9];        // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
   __shared__ float4 Ws[2][kBW][4];         // [buffer][frequency][transition quad]
   __shared__ int su;
@@ -342,8 +342,6 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);        \
       Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                      \
       Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                                      \
-      Bs[b_][2][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])};  \
-      Bs[b_][3][fn][fq][fj] = u4{rot_neg(l_[0]), rot_neg(l_[1]), rot_neg(l_[2]), rot_neg(l_[3])};  \
       As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                         \
       As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                     \
       if (tid < 64) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[tid & 15] = wv;                  \
@@ -362,8 +360,20 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       const int buf = k & 1;
       if (k + 1 < nsteps) CHI0_BLK_LOAD(U.k0 + 16 * (k + 1));
       const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
-      // Im part through the rotated right operand (-im, re): the weighted left
-      // operand is split once per frequency and feeds both parts
+      // Im part through the rotated right operand (-im, re), rotated in registers
+      // (LDS holds hi and lo only: the reads of all waves stay within the LDS bandwidth);
+      // the weighted left operand is split once per frequency and feeds both parts
+      u4 bh[4], bl[4], rh[4], rl[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        bh[n] = Bs[buf][0][n][q][i];
+        bl[n] = Bs[buf][1][n][q][i];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          rh[n][m] = rot_neg(bh[n][m]);
+          rl[n][m] = rot_neg(bl[n][m]);
+        }
+      }
 #pragma unroll
       for (int w = 0; w < kBW; ++w) {
         const float4 wq = Ws[buf][w][q];
@@ -375,8 +385,8 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         const u4 ah = u4{h[0], h[1], h[2], h[3]}, al = u4{l[0], l[1], l[2], l[3]};
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          acc[w][0][n] = mma3(ah, al, Bs[buf][0][n][q][i], Bs[buf][1][n][q][i], acc[w][0][n]);
-          acc[w][1][n] = mma3(ah, al, Bs[buf][2][n][q][i], Bs[buf][3][n][q][i], acc[w][1][n]);
+          acc[w][0][n] = mma3(ah, al, bh[n], bl[n], acc[w][0][n]);
+          acc[w][1][n] = mma3(ah, al, rh[n], rl[n], acc[w][1][n]);
         }
       }
       if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1);
