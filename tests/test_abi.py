@@ -113,3 +113,59 @@ def test_epsinv_argument_errors():
     a.flags = 64
     rc, msg = _rc(L.xo_epsinv, a)
     assert rc == xo.XO_ERR_ARG and "flags" in msg
+
+
+def test_xterm_argument_errors():
+    L = xo.lib()
+    a = xo.XtermArgs()
+    rc, msg = _rc(L.xo_xterm, a)
+    assert rc == xo.XO_ERR_ARG and "positive" in msg
+    mv = np.zeros((2, 3), dtype=np.int32)
+    mv[1, 0] = 1
+    mg = np.zeros((1, 3), dtype=np.int32)
+    w = np.array([0.0, -0.5])
+    a.npw_v, a.nv, a.ng, a.nw, a.nn = 2, 1, 1, 2, 1
+    a.mill_v = mv.ctypes.data_as(C.POINTER(C.c_int32))
+    a.mill_g = mg.ctypes.data_as(C.POINTER(C.c_int32))
+    a.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    rc, msg = _rc(L.xo_xterm, a)
+    assert rc == xo.XO_ERR_ARG and "null device pointer" in msg
+    a.coef_v = a.e_v = a.rho = a.out = 8   # never dereferenced: validation fails first
+    a.pref, a.ebar = 1.0, 2.0
+    rc, msg = _rc(L.xo_xterm, a)
+    assert rc == xo.XO_ERR_ARG and "negative" in msg
+    w[1] = 0.5
+    mv[1, 0] = 0   # a repeated Miller vector
+    rc, msg = _rc(L.xo_xterm, a)
+    assert rc == xo.XO_ERR_ARG and "repeats" in msg
+
+
+def test_empty_and_degenerate_inputs_are_rejected():
+    """Zero bands, zero G vectors, empty batches and zero-row MLP batches fail validation
+    with XO_ERR_ARG before any device work."""
+    L = xo.lib()
+    sphere = np.array([[i, j, k] for i in range(-1, 2) for j in range(-1, 2) for k in range(-1, 2)])
+    gs = np.array([[0, 0, 0], [1, 0, 0]])
+    for field in ("nc", "nv"):
+        a, keep = _rho_args(sphere, sphere, gs, [8, 8, 8])
+        setattr(a, field, 0)
+        rc, msg = _rc(L.xo_rho, a)
+        assert rc == xo.XO_ERR_ARG and "positive" in msg, (field, msg)
+    a, keep = _rho_args(sphere, sphere, gs[:0], [8, 8, 8])
+    rc, msg = _rc(L.xo_rho, a)
+    assert rc == xo.XO_ERR_ARG
+    assert L.xo_rho_batch(None, 0, None) == xo.XO_ERR_ARG
+    assert L.xo_chi0_batch(None, 0, None, None) == xo.XO_ERR_ARG
+    best, ms = xo.Tune(), C.c_double()
+    assert L.xo_chi0_autotune(None, 0, C.byref(best), C.byref(ms), None) == xo.XO_ERR_ARG
+    e = xo.EpsArgs()
+    rc, msg = _rc(L.xo_epsinv, e)
+    assert rc == xo.XO_ERR_ARG and "positive" in msg
+    q = np.ones(2)
+    e.ng, e.nw, e.qpg, e.chi0, e.out = 2, 1, q.ctypes.data_as(C.POINTER(C.c_double)), 8, 8
+    rc, msg = _rc(L.xo_epsinv, e)
+    assert rc == xo.XO_ERR_ARG and "alias" in msg
+    dims = (C.c_int * 2)(4, 4)
+    assert L.xo_mlp_forward(1, dims, 8, 8, 0, 8, 8, None) == xo.XO_ERR_ARG
+    assert L.xo_mse(8, 8, 0, 8, 8, 8, None) == xo.XO_ERR_ARG
+    assert L.xo_gather_rows(8, 8, 0, 4, 8, None) == xo.XO_ERR_ARG
