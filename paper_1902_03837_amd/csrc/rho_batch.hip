@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -41,6 +42,9 @@ namespace xo {
 
 int rho_valu(const xo_rho_args* a, hipStream_t s);
 int rho_head_f32(const xo_rho_args* a, hipStream_t s);
+int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                   hipStream_t s);
+int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s);
 
 namespace {
 
@@ -670,6 +674,13 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     XO_RET(launch_rho_mt<2>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
   else
     XO_RET(launch_rho_mt<8>(MT, dpairs, n, nwg, Nx, ng, dtw, s, lds));
+  return rho_batch_finish(p, n, s);
+}
+
+}  // namespace
+
+// After the batched MFMA kernels: q -> 0 heads and pole energies of the batch.
+int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s) {
   // q -> 0: the G = 0 column of such pairs is the velocity head, written over the transform's value
   for (int i = 0; i < n; ++i)
     if (p[i].q0) XO_RET(rho_head_f32(&p[i], s));
@@ -694,14 +705,31 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
   return XO_OK;
 }
 
-}  // namespace
+// Which split-bf16 kernel a batch may take: the gathered product when its
+// tables fit in LDS, else the axis-factorised transform. XO_RHO_KERNEL=gemm or
+// =yz restricts the choice to one of them (the other paths still apply when it
+// cannot run).
+static int rho_kernel_choice() {
+  const char* e = std::getenv("XO_RHO_KERNEL");
+  if (!e) return 0;
+  if (!std::strcmp(e, "gemm")) return 1;
+  if (!std::strcmp(e, "yz")) return 2;
+  return 0;
+}
 
 int rho_batch(const xo_rho_args* p, int n, hipStream_t s) {
   std::vector<Extent> xc(n), xv(n), xe(n);
   for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
   if (mfma_eligible(p, n)) {
-    int r = rho_batch_mfma(p, n, xc.data(), xv.data(), xe.data(), s);
-    if (r != XO_ERR_UNSUPPORTED) return r;
+    const int choice = rho_kernel_choice();
+    if (choice != 2) {
+      int r = rho_batch_gemm(p, n, xc.data(), xv.data(), xe.data(), s);
+      if (r != XO_ERR_UNSUPPORTED) return r;
+    }
+    if (choice != 1) {
+      int r = rho_batch_mfma(p, n, xc.data(), xv.data(), xe.data(), s);
+      if (r != XO_ERR_UNSUPPORTED) return r;
+    }
   }
   for (int i = 0; i < n; ++i) XO_RET(rho_valu(&p[i], s));
   return XO_OK;

@@ -1,0 +1,447 @@
+// Oscillator strengths as a gathered matrix product on MFMA (split bf16, FP32
+// accumulation), many k-pairs per launch.
+//
+// With both orbitals expanded in plane waves, the cell-averaged transform of
+// the product conj(psi_c) psi_v (Eq. rhotw, the umklapp vector G0 from
+// k - q = k' + G0) is a finite sum over the conduction sphere:
+//
+//   rho_cv(G) = sum_a conj(c_c(a)) c_v(a - e),    e = m_G - G0,
+//
+// terms with a - e outside the valence sphere being zero. This is exactly what
+// the FFT of the real-space product gives on any alias-free grid; at the sizes
+// of these workloads it costs fewer multiply-adds per transition than the
+// transform, and it is a dense contraction. For one k-pair it is a complex
+// matrix product:
+//
+//   rows     (v, G), flattened r = v ng + G            left operand: c_v(a - e), gathered
+//   columns  conduction band c                         right operand: c_c(a)
+//   K        conduction plane wave a (interleaved re, im)
+//
+// The gather goes through one table per pair: the box of every difference
+// a - e is laid out linearly, so that the offset of a - e splits as
+// Oa[a] + Oe[G], and T[offset] is the valence plane-wave index (or the index of
+// a zero entry). T and the valence bands of a workgroup's rows sit in LDS; the
+// conduction tile is double buffered through LDS.
+//
+// Complex operands: the right operand holds (re, im) of c_c; the left operand
+// of Re rho holds (re, im) of c_v and that of Im rho (im, -re), so that
+// sum (vr cr + vi ci) = Re(conj(c) v) and sum (vi cr - vr ci) = Im(conj(c) v).
+// Every FP32 value x enters as hi = bf16(x), lo = bf16(x - hi); a product is
+// hi*hi + hi*lo + lo*hi, accumulated in FP32.
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "bf16x3.h"
+#include "rho_geom.h"
+
+namespace xo {
+
+int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s);
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCT = 8;               // column tiles (16 conduction bands each) per workgroup, at most
+constexpr int kRT = 2;               // row tiles (16 (v, G) rows each) per wave
+constexpr int kRows = 4 * 16 * kRT;  // rows per workgroup
+constexpr size_t kBsBytes = (size_t)2 * 2 * kCT * 4 * 16 * sizeof(u4);  // [buffer][hi, lo][tile][q][column]
+constexpr size_t kLdsMax = 160 * 1024;
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+// Split coefficients of one band set: [nb][npwp] (hi, lo) pairs, zero for j >= npw.
+struct SplitDesc {
+  const float2* src;  // [nb][npw]
+  uint2* dst;
+  int nb, npw, npwp;
+};
+
+__global__ void __launch_bounds__(kThreads) orb_split(const SplitDesc* __restrict__ d) {
+  const SplitDesc D = d[blockIdx.y];
+  const int n = D.nb * D.npwp;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+    const int b = i / D.npwp, j = i - b * D.npwp;
+    const float2 v = j < D.npw ? D.src[(size_t)b * D.npw + j] : make_float2(0.f, 0.f);
+    uint32_t h, l;
+    split2(v.x, v.y, h, l);
+    D.dst[i] = make_uint2(h, l);
+  }
+}
+
+struct GemmPair {
+  const uint2* Sc;  // conduction split coefficients [nc][npwc]
+  const uint2* Sv;  // valence [nv][npwv]; entry npw_v of each row is zero
+  float2* rho;      // [nv][nc][ng]
+  const int* Oa;    // [nK * 16] box offset of each conduction plane wave (a valid offset for padding)
+  const int* Oe;    // [ng] box offset of -e = G0 - m_G
+  const u4* T;      // [ncell / 8] uint16 valence index of each box cell, npw_v outside the sphere
+  int npwc, npwv;   // row strides of Sc and Sv (multiples of 16)
+  int nK;           // K steps of 16 conduction plane waves
+  int ncell;        // box cells, a multiple of 8
+  int nc, nv;
+  int nct, ncg;     // column tiles and column groups
+  int nrb;          // row blocks of kRows rows
+  int wg0;          // first logical workgroup of the pair
+};
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous
+  // logical range, so a pair's tables and coefficients stay in that XCD's L2.
+  const int per = (nwg + 7) >> 3;
+  const int L = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (L >= nwg) return;
+  int plo = 0, phi = npairs - 1;
+  while (plo < phi) {
+    const int mid = (plo + phi + 1) >> 1;
+    if (pairs[mid].wg0 <= L) plo = mid; else phi = mid - 1;
+  }
+  const GemmPair& P = pairs[plo];
+  const int local = L - P.wg0;
+  const int cg = local / P.nrb, rb = local - cg * P.nrb;
+  const int ct0 = cg * P.nct / P.ncg, nt = (cg + 1) * P.nct / P.ncg - ct0;
+  const int nrows = P.nv * ng;
+  const int r0 = rb * kRows;
+  const int vlo = r0 / ng, vhi = min(P.nv - 1, (r0 + kRows - 1) / ng);
+  const int npwv = P.npwv, npwc = P.npwc, nK = P.nK;
+
+  u4* Bs = reinterpret_cast<u4*>(smem);                                // [2][2][kCT][4][16]
+  uint2* Vs = reinterpret_cast<uint2*>(smem + kBsBytes);                // [vhi - vlo + 1][npwv]
+  const int nvs = (vhi - vlo + 1) * npwv;                              // a multiple of 16
+  uint16_t* Ts = reinterpret_cast<uint16_t*>(Vs + nvs);                 // [ncell]
+
+  const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  // ---- box table and the valence bands of this workgroup's rows into LDS
+  for (int k = tid; k < P.ncell / 8; k += kThreads) reinterpret_cast<u4*>(Ts)[k] = gld<u4>(P.T + k);
+  {
+    const u4* src = reinterpret_cast<const u4*>(P.Sv + (size_t)vlo * npwv);
+    for (int k = tid; k < nvs / 2; k += kThreads) reinterpret_cast<u4*>(Vs)[k] = gld<u4>(src + k);
+  }
+
+  // ---- rows of this lane: row tile rt holds rows r0 + 32 w + 16 rt + (0..15); lane i gathers row i
+  int vb[kRT], oe[kRT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+    const int r = r0 + 32 * w + 16 * rt + i;
+    const int v = r < nrows ? r / ng : vlo;
+    const int g = r < nrows ? r - v * ng : 0;
+    vb[rt] = (v - vlo) * npwv;
+    oe[rt] = gld<int>(P.Oe + g);
+  }
+
+  // ---- right operand staging: slot s = tid + 256 f is (tile s / 64, quad (s / 16) % 4, column s % 16)
+  u4 raw[2][2];
+  bool sok[2];
+  const uint2* sp[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const int s = tid + kThreads * f;
+    const int ct = s >> 6, sq = (s >> 4) & 3, c = (ct0 + ct) * 16 + (s & 15);
+    sok[f] = ct < nt && c < P.nc;
+    sp[f] = P.Sc + (size_t)(sok[f] ? c : 0) * npwc + 4 * sq;
+  }
+#define RHO_GEMM_LOAD(k_)                                                         \
+  _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
+    if (sok[f]) {                                                                 \
+      raw[f][0] = gld<u4>(sp[f] + 16 * (k_));                                     \
+      raw[f][1] = gld<u4>(sp[f] + 16 * (k_) + 2);                                 \
+    } else {                                                                      \
+      raw[f][0] = raw[f][1] = u4{0u, 0u, 0u, 0u};                                 \
+    }                                                                             \
+  }
+#define RHO_GEMM_STORE(b_)                                                        \
+  _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
+    const int s_ = tid + kThreads * f;                                            \
+    Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = u4{raw[f][0].x, raw[f][0].z, raw[f][1].x, raw[f][1].z}; \
+    Bs[((b_) * 2 + 1) * (kCT * 64) + s_] = u4{raw[f][0].y, raw[f][0].w, raw[f][1].y, raw[f][1].w}; \
+  }
+
+  RHO_GEMM_LOAD(0);
+  RHO_GEMM_STORE(0);
+  i4 oa = gld<i4>(P.Oa + 4 * q);
+  __syncthreads();
+
+  f4 re[kRT][kCT], im[kRT][kCT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct) re[rt][ct] = im[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k = 0; k < nK; ++k) {
+    const int buf = k & 1;
+    i4 oan = oa;
+    if (k + 1 < nK) {
+      RHO_GEMM_LOAD(k + 1);
+      oan = gld<i4>(P.Oa + 16 * (k + 1) + 4 * q);
+    }
+    // ---- gathered left operand of this lane's rows: c_v(a - e) for a = 16 k + 4 q + (0..3)
+    u4 ah[kRT], al[kRT], bh[kRT], bl[kRT];
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      const int o[4] = {oa.x, oa.y, oa.z, oa.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint2 x = Vs[vb[rt] + Ts[o[u] + oe[rt]]];
+        ah[rt][u] = x.x;
+        al[rt][u] = x.y;
+        bh[rt][u] = rot_pos(x.x);
+        bl[rt][u] = rot_pos(x.y);
+      }
+    }
+    const u4* Bh = Bs + (buf * 2 + 0) * (kCT * 64) + lane;
+    const u4* Bl = Bs + (buf * 2 + 1) * (kCT * 64) + lane;
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct) {
+      if (ct < nt) {
+        const u4 ch = Bh[ct * 64], cl = Bl[ct * 64];
+#pragma unroll
+        for (int rt = 0; rt < kRT; ++rt) {
+          re[rt][ct] = mma3(ah[rt], al[rt], ch, cl, re[rt][ct]);
+          im[rt][ct] = mma3(bh[rt], bl[rt], ch, cl, im[rt][ct]);
+        }
+      }
+    }
+    if (k + 1 < nK) RHO_GEMM_STORE(buf ^ 1);
+    oa = oan;
+    __syncthreads();
+  }
+#undef RHO_GEMM_LOAD
+#undef RHO_GEMM_STORE
+
+  // ---- results: lane holds rows 4 q + (0..3) of each row tile, column i of each column tile
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+    const int rb4 = r0 + 32 * w + 16 * rt + 4 * q;
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct) {
+      const int c = (ct0 + ct) * 16 + i;
+      if (ct >= nt || c >= P.nc) continue;
+      const int v4 = rb4 < nrows ? rb4 / ng : 0, g4 = rb4 - v4 * ng;
+      float2* o4 = P.rho + ((size_t)v4 * P.nc + c) * ng + g4;
+      if (rb4 + 3 < nrows && g4 + 3 < ng && ((uintptr_t)o4 & 15) == 0) {
+        // four consecutive G of one band: two 16-byte stores
+        f4* out = reinterpret_cast<f4*>(o4);
+        gst<f4>(out, f4{re[rt][ct][0], im[rt][ct][0], re[rt][ct][1], im[rt][ct][1]});
+        gst<f4>(out + 1, f4{re[rt][ct][2], im[rt][ct][2], re[rt][ct][3], im[rt][ct][3]});
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = rb4 + e;
+          if (r >= nrows) break;
+          const int v = r / ng, g = r - v * ng;
+          gst<f2v>(P.rho + ((size_t)v * P.nc + c) * ng + g, f2v{re[rt][ct][e], im[rt][ct][e]});
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host --
+struct GemmGeo {
+  std::vector<int> Oa, Oe;
+  std::vector<uint16_t> T;
+  int nK = 0;
+  const void* dOa = nullptr;
+  const void* dOe = nullptr;
+  const void* dT = nullptr;
+  unsigned gen = 0;
+  bool ok = false;
+};
+
+// Gather tables of one pair. The box spans every a - e (a over the conduction
+// sphere, e = m_G - G0 over the G-set): lo = min a - max e, hi = max a - min e.
+static void gemm_geo(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, GemmGeo* g) {
+  int lo[3], w[3];
+  size_t ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = xc.lo[d] - xe.hi[d];
+    w[d] = (xc.hi[d] - xe.lo[d]) - lo[d] + 1;
+    ncell *= (size_t)w[d];
+  }
+  g->ok = a->npw_v < 65535 && ncell * 2 <= kLdsMax;
+  if (!g->ok) return;
+  const long SX = w[0], SY = (long)w[0] * w[1];
+  g->nK = (a->npw_c + 15) / 16;
+  g->Oa.resize((size_t)g->nK * 16);
+  for (int p = 0; p < a->npw_c; ++p)
+    g->Oa[p] = (int)((a->mill_c[3 * p] - lo[0]) + SX * (a->mill_c[3 * p + 1] - lo[1]) +
+                     SY * (a->mill_c[3 * p + 2] - lo[2]));
+  for (size_t p = a->npw_c; p < g->Oa.size(); ++p) g->Oa[p] = g->Oa[0];
+  g->Oe.resize(a->ng);
+  for (int j = 0; j < a->ng; ++j) {
+    const long ex = a->mill_g[3 * j] - a->g0[0], ey = a->mill_g[3 * j + 1] - a->g0[1],
+               ez = a->mill_g[3 * j + 2] - a->g0[2];
+    g->Oe[j] = (int)(-ex - SX * ey - SY * ez);
+  }
+  g->T.assign((ncell + 7) / 8 * 8, (uint16_t)a->npw_v);
+  for (int p = 0; p < a->npw_v; ++p) {
+    const int x = a->mill_v[3 * p] - lo[0], y = a->mill_v[3 * p + 1] - lo[1], z = a->mill_v[3 * p + 2] - lo[2];
+    // valence plane waves outside the box are never reached by any a - e
+    if (x < 0 || y < 0 || z < 0 || x >= w[0] || y >= w[1] || z >= w[2]) continue;
+    g->T[x + SX * y + SY * z] = (uint16_t)p;
+  }
+  (void)xv;
+}
+
+// Tables cached by the caller's Miller-list pointers and scalars, confirmed by
+// a full comparison of the lists' contents (a reused buffer with new contents
+// is a miss), for the life of the device tables.
+static int gemm_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, hipStream_t s,
+                      const GemmGeo** out) {
+  struct Key {
+    std::vector<int32_t> mc, mv, mg;
+  };
+  static std::mutex mu;
+  static std::map<std::vector<intptr_t>, std::vector<std::pair<Key, std::unique_ptr<GemmGeo>>>> cache;
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  const std::vector<intptr_t> pk = {dev, a->g0[0], a->g0[1], a->g0[2], a->npw_c, a->npw_v, a->ng,
+                                    (intptr_t)a->mill_c, (intptr_t)a->mill_v, (intptr_t)a->mill_g};
+  auto same = [&](const Key& k) {
+    return std::memcmp(k.mc.data(), a->mill_c, 12 * (size_t)a->npw_c) == 0 &&
+           std::memcmp(k.mv.data(), a->mill_v, 12 * (size_t)a->npw_v) == 0 &&
+           std::memcmp(k.mg.data(), a->mill_g, 12 * (size_t)a->ng) == 0;
+  };
+  const unsigned gen = table_generation();
+  std::lock_guard<std::mutex> lk(mu);
+  auto& bucket = cache[pk];
+  std::unique_ptr<GemmGeo>* slotp = nullptr;
+  for (auto& kv : bucket)
+    if (same(kv.first)) slotp = &kv.second;
+  if (slotp && (*slotp)->gen == gen) {
+    *out = (*slotp)->ok ? slotp->get() : nullptr;
+    return XO_OK;
+  }
+  GemmGeo e;
+  e.gen = gen;
+  gemm_geo(a, xc, xv, xe, &e);
+  if (e.ok) {
+    XO_RET(device_table(e.Oa.data(), e.Oa.size() * sizeof(int), s, &e.dOa));
+    XO_RET(device_table(e.Oe.data(), e.Oe.size() * sizeof(int), s, &e.dOe));
+    XO_RET(device_table(e.T.data(), e.T.size() * sizeof(uint16_t), s, &e.dT));
+  }
+  if (!slotp) {
+    Key k;
+    k.mc.assign(a->mill_c, a->mill_c + 3 * a->npw_c);
+    k.mv.assign(a->mill_v, a->mill_v + 3 * a->npw_v);
+    k.mg.assign(a->mill_g, a->mill_g + 3 * a->ng);
+    bucket.emplace_back(std::move(k), nullptr);
+    slotp = &bucket.back().second;
+  }
+  // a stale entry (tables released) is replaced, not freed: callers on other
+  // threads may still hold it
+  slotp->release();
+  *slotp = std::make_unique<GemmGeo>(std::move(e));
+  *out = (*slotp)->ok ? slotp->get() : nullptr;
+  return XO_OK;
+}
+
+inline int padded_row(int npw) { return (npw + 1 + 15) / 16 * 16; }
+
+}  // namespace
+
+// The batch on the gathered-product kernel, or XO_ERR_UNSUPPORTED (nothing
+// enqueued) when a pair's tables do not fit in LDS. All pairs share ng and the G-set.
+int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                   hipStream_t s) {
+  const int ng = p[0].ng;
+  std::vector<const GemmGeo*> ge(n);
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    XO_RET(gemm_entry(&p[i], xc[i], xv[i], xe[i], s, &ge[i]));
+    if (!ge[i]) return XO_ERR_UNSUPPORTED;
+    // band slots: the rows [r0, r0 + kRows) of a workgroup span at most this many bands
+    int nbs = 1;
+    const int nrows = p[i].nv * ng;
+    for (int r0 = 0; r0 < nrows; r0 += kRows)
+      nbs = std::max(nbs, std::min(p[i].nv - 1, (r0 + kRows - 1) / ng) - r0 / ng + 1);
+    const size_t need = kBsBytes + (size_t)nbs * padded_row(p[i].npw_v) * sizeof(uint2) + ge[i]->T.size() * 2;
+    lds = std::max(lds, need);
+  }
+  if (lds > kLdsMax) return XO_ERR_UNSUPPORTED;
+
+  // split coefficients, once per distinct band set of the batch
+  std::map<std::tuple<const void*, int, int>, size_t> sets;
+  std::vector<SplitDesc> sd;
+  size_t tot = 0;
+  auto add = [&](const void* c, int nb, int npw) {
+    auto key = std::make_tuple(c, nb, npw);
+    if (sets.count(key)) return;
+    sets[key] = tot;
+    SplitDesc d;
+    d.src = static_cast<const float2*>(c);
+    d.dst = nullptr;
+    d.nb = nb;
+    d.npw = npw;
+    d.npwp = padded_row(npw);
+    sd.push_back(d);
+    tot += (size_t)nb * d.npwp;
+  };
+  for (int i = 0; i < n; ++i) {
+    add(p[i].coef_c, p[i].nc, p[i].npw_c);
+    add(p[i].coef_v, p[i].nv, p[i].npw_v);
+  }
+  void* ws = nullptr;
+  XO_RET(workspace(s, 3, tot * sizeof(uint2), &ws));
+  uint2* S0 = static_cast<uint2*>(ws);
+  int maxn = 0;
+  for (auto& d : sd) {
+    d.dst = S0 + sets[std::make_tuple(static_cast<const void*>(d.src), d.nb, d.npw)];
+    maxn = std::max(maxn, d.nb * d.npwp);
+  }
+  const void* dsd = nullptr;
+  XO_RET(device_table(sd.data(), sd.size() * sizeof(SplitDesc), s, &dsd));
+  {
+    KernelTimer kt_("orb_split", s);
+    hipLaunchKernelGGL(orb_split, dim3(std::min(256, (maxn + kThreads - 1) / kThreads), (unsigned)sd.size()),
+                       dim3(kThreads), 0, s, static_cast<const SplitDesc*>(dsd));
+  }
+  XO_CHECK_LAUNCH();
+
+  std::vector<GemmPair> gp(n);
+  int nwg = 0;
+  for (int i = 0; i < n; ++i) {
+    const GemmGeo& g = *ge[i];
+    GemmPair& d = gp[i];
+    d.Sc = S0 + sets[std::make_tuple(p[i].coef_c, p[i].nc, p[i].npw_c)];
+    d.Sv = S0 + sets[std::make_tuple(p[i].coef_v, p[i].nv, p[i].npw_v)];
+    d.rho = static_cast<float2*>(p[i].rho);
+    d.Oa = static_cast<const int*>(g.dOa);
+    d.Oe = static_cast<const int*>(g.dOe);
+    d.T = static_cast<const u4*>(g.dT);
+    d.npwc = padded_row(p[i].npw_c);
+    d.npwv = padded_row(p[i].npw_v);
+    d.nK = g.nK;
+    d.ncell = (int)g.T.size();
+    d.nc = p[i].nc;
+    d.nv = p[i].nv;
+    d.nct = (p[i].nc + 15) / 16;
+    d.ncg = (d.nct + kCT - 1) / kCT;
+    d.nrb = (p[i].nv * ng + kRows - 1) / kRows;
+    d.wg0 = nwg;
+    nwg += d.ncg * d.nrb;
+  }
+  const void* dgp = nullptr;
+  XO_RET(device_table(gp.data(), gp.size() * sizeof(GemmPair), s, &dgp));
+  if (lds > 64 * 1024)
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  {
+    KernelTimer kt_("rho_gemm", s);
+    hipLaunchKernelGGL(rho_gemm, dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
+                       static_cast<const GemmPair*>(dgp), n, nwg, ng);
+  }
+  XO_CHECK_LAUNCH();
+  return rho_batch_finish(p, n, s);
+}
+
+}  // namespace xo

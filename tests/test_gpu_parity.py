@@ -40,17 +40,50 @@ def _to(a, dt=torch.complex128):
 
 # ----------------------------------------------------------------------------- rho
 
+# split-bf16 rho has two kernels: the gathered product (default where its tables
+# fit in LDS) and the axis-factorised transform; XO_RHO_KERNEL pins one of them
+RHO_FORMS = [("fp64", None, 1e-13), ("fp32", None, 3e-6), ("bf16x3", "gemm", 5e-5), ("bf16x3", "yz", 5e-5)]
+
+
+class rho_kernel:
+    """Pin the split-bf16 rho kernel for the calls inside the block and check that it ran."""
+
+    def __init__(self, name):
+        self.name = name
+
+    def __enter__(self):
+        self.old = os.environ.get("XO_RHO_KERNEL")
+        if self.name:
+            os.environ["XO_RHO_KERNEL"] = self.name
+            xo.timing_enable(True)
+        return self
+
+    def __exit__(self, *exc):
+        if self.name:
+            torch.cuda.synchronize()
+            ran = xo.timing_report()
+            xo.timing_enable(False)
+            if exc[0] is None:
+                assert ("rho_gemm" if self.name == "gemm" else "rho_yz") in ran, ran.keys()
+        if self.old is None:
+            os.environ.pop("XO_RHO_KERNEL", None)
+        else:
+            os.environ["XO_RHO_KERNEL"] = self.old
+        return False
+
+
 @pytest.mark.parametrize("name", ["c1", "c2_small"])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6), ("bf16x3", 5e-5)])
-def test_rho_parity(name, prec, tol):
+@pytest.mark.parametrize("prec,kern,tol", RHO_FORMS)
+def test_rho_parity(name, prec, kern, tol):
     cr = crystal_for(name)
-    say(f"rho parity {name} {prec}")
+    say(f"rho parity {name} {prec} {kern}")
     dc = DeviceCrystal.upload(cr, prec)
     K = ntrans(cr)
     ng = cr.gmill.shape[0]
     M = torch.empty((K, ng), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    rho_all(dc, M, dE)
+    with rho_kernel(kern):
+        rho_all(dc, M, dE)
     torch.cuda.synchronize()
     Mr, dEr = rho_all_pairs(cr, "fft")
     Mg = M.cpu().numpy().astype(np.complex128)
@@ -60,17 +93,19 @@ def test_rho_parity(name, prec, tol):
     assert np.array_equal(dE.cpu().numpy(), dEr)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 3e-6), ("bf16x3", 5e-5)])
-def test_rho_parity_large_gset(prec, tol):
-    """NG = 700 on a 28^3 grid: more G-vectors than one workgroup of the MFMA path
-    owns, so the G-set is split into several (e_y, e_z)-column groups."""
+@pytest.mark.parametrize("prec,kern,tol", RHO_FORMS[1:])
+def test_rho_parity_large_gset(prec, kern, tol):
+    """NG = 700 on a 28^3 grid: more G-vectors than one workgroup of the axis-factorised
+    kernel owns (the G-set is split into several (e_y, e_z)-column groups); for the
+    gathered product, row blocks that straddle two valence bands."""
     cr = crystal_for("c2_small", ng=700, grid=28)
-    say(f"rho parity NG=700 {prec}")
+    say(f"rho parity NG=700 {prec} {kern}")
     dc = DeviceCrystal.upload(cr, prec)
     K = ntrans(cr)
     M = torch.empty((K, 700), dtype=torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    rho_all(dc, M, dE)
+    with rho_kernel(kern):
+        rho_all(dc, M, dE)
     torch.cuda.synchronize()
     Mr, _ = rho_all_pairs(cr, "fft")
     err = np.abs(M.cpu().numpy().astype(np.complex128) - Mr).max() / np.abs(Mr).max()
@@ -95,20 +130,22 @@ def test_rho_batch_equals_per_pair(prec):
     assert torch.equal(M1, M2) and torch.equal(d1, d2)
 
 
-@pytest.mark.parametrize("prec,tol_head,tol", [("fp64", 1e-12, 1e-12), ("bf16x3", 1e-6, 5e-5)])
-def test_rho_q0_head_parity(prec, tol_head, tol):
+@pytest.mark.parametrize("prec,kern,tol_head,tol", [("fp64", None, 1e-12, 1e-12), ("bf16x3", "gemm", 1e-6, 5e-5),
+                                                    ("bf16x3", "yz", 1e-6, 5e-5)])
+def test_rho_q0_head_parity(prec, kern, tol_head, tol):
     """q -> 0: the G = 0 column is the velocity head (accumulated in FP64 in every
     form, rounded to the output precision); the other columns come from the transform."""
     lat = fcc_lattice(A_FCC)
     cr = make_crystal(lat, shell_potential(lat, 31), kgrid_gamma(2), np.zeros(3), (16,) * 3,
                       ecut_for_npw(lat, 160), 4, 12, 27, 2, 31)
-    say(f"rho q0 head parity {prec}")
+    say(f"rho q0 head parity {prec} {kern}")
     assert cr.q0
     dc = DeviceCrystal.upload(cr, prec)
     K = ntrans(cr)
     M = torch.empty((K, 27), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    rho_all(dc, M, dE)
+    with rho_kernel(kern):
+        rho_all(dc, M, dE)
     Mr, _ = rho_all_pairs(cr, "fft")
     Mg = M.cpu().numpy().astype(np.complex128)
     assert np.abs(Mg[:, 0] - Mr[:, 0]).max() < tol_head * np.abs(Mr[:, 0]).max()
