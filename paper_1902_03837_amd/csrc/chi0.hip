@@ -308,45 +308,69 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
   for (;;) {
     if (tid == 0) su = atomicAdd(counter, 1);
     __syncthreads();
-    const int qpos = su;
+    const int qpos = __builtin_amdgcn_readfirstlane(su);
     __syncthreads();
     if (qpos >= nunits) break;
     const int uid = queue[qpos];
     const Unit U = units[uid];
     const Item I = items[U.item];
     const int2 bij = tiles[I.tile0 + U.tile];
-    const f2v* rho = static_cast<const f2v*>(I.rho);
-    const float* W = static_cast<const float*>(I.W) + U.w0;
-    const int Ga = bij.x * kBlk + ar;
-    const int Gb = bij.y * kBlk + 16 * fn + fj;
-    const bool ga_ok = Ga < I.ng, gb_ok = Gb < I.ng;
-    const int nsteps = (U.k1 - U.k0 + 15) / 16;
+    const int ng = I.ng, len = U.k1 - U.k0;
+    const int nsteps = (len + 15) / 16;
+    // 16 x 16 tiles this wave computes: its row tile and the column tiles inside
+    // the G-set, and in a diagonal block only those on or above the diagonal
+    int nmask = 0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      if (bij.x * kBlk + 16 * wave < ng && bij.y * kBlk + 16 * n < ng && (bij.x != bij.y || n >= wave))
+        nmask |= 1 << n;
+    // Loads address the unit's transition slice by 32-bit byte offsets (the host
+    // keeps len * ng * 8 below 2^31). Rows past the slice and G past the G-set are
+    // clamped to valid entries: the former carry a zero weight, the latter land
+    // in outputs the reduction drops.
+    const char* rbase = static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v);
+    const char* wbase = static_cast<const char*>(I.W) + ((size_t)U.k0 * I.nwpad + U.w0) * sizeof(float);
+    const unsigned rstep = 16u * ng * sizeof(f2v), wstep = 16u * I.nwpad * sizeof(float);
+    const unsigned Ga = min(bij.x * kBlk + ar, ng - 1), Gb = min(bij.y * kBlk + 16 * fn + fj, ng - 1);
+    const unsigned amax = ((unsigned)(len - 1) * ng + Ga) * sizeof(f2v);
+    const unsigned bmax = ((unsigned)(len - 1) * ng + Gb) * sizeof(f2v);
+    unsigned oa[4], ob[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      oa[u] = ((unsigned)(4 * aq + u) * ng + Ga) * sizeof(f2v);
+      ob[u] = ((unsigned)(4 * fq + u) * ng + Gb) * sizeof(f2v);
+    }
+    const int wt = tid & 15;
+    const unsigned ow = ((unsigned)wt * I.nwpad + (tid >> 4)) * sizeof(float);
 
     f2v ra[4], rb[4];
     float wv = 0.f;
     // ---- load step s into registers
-#define CHI0_BLK_LOAD(s_)                                                                          \
-    {                                                                                              \
-      _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                              \
-        const int ta = (s_) + 4 * aq + u, tb = (s_) + 4 * fq + u;                                  \
-        ra[u] = (ta < U.k1 && ga_ok) ? gld<f2v>(rho + (size_t)ta * I.ng + Ga) : f2v{0.f, 0.f};      \
-        rb[u] = (tb < U.k1 && gb_ok) ? gld<f2v>(rho + (size_t)tb * I.ng + Gb) : f2v{0.f, 0.f};      \
-      }                                                                                            \
-      const int tw_ = (s_) + (tid & 15);                                                           \
-      wv = (tid < 64 && tw_ < U.k1) ? gld<float>(W + (size_t)tw_ * I.nwpad + (tid >> 4)) : 0.f;    \
+#define CHI0_BLK_LOAD(s_)                                                                     \
+    {                                                                                         \
+      const unsigned d_ = (unsigned)(s_) * rstep;                                             \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                         \
+        ra[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                      \
+        rb[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                      \
+      }                                                                                       \
+      if (wave == 0) {                                                                        \
+        const bool in_ = 16 * (s_) + wt < len;                                                \
+        const float x_ = gld<float>(wbase + (in_ ? ow + (unsigned)(s_) * wstep : 0u));         \
+        wv = in_ ? x_ : 0.f;                                                                  \
+      }                                                                                       \
     }
     // ---- store the loaded step into buffer b
-#define CHI0_BLK_STORE(b_)                                                                         \
-    {                                                                                              \
-      uint32_t h_[4], l_[4];                                                                       \
-      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);        \
-      Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                      \
-      Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                                      \
-      As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                         \
-      As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                     \
-      if (tid < 64) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[tid & 15] = wv;                  \
+#define CHI0_BLK_STORE(b_)                                                                    \
+    {                                                                                         \
+      uint32_t h_[4], l_[4];                                                                  \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);   \
+      Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                 \
+      Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                                 \
+      As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                    \
+      As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                \
+      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[tid & 15] = wv;           \
     }
-    CHI0_BLK_LOAD(U.k0);
+    CHI0_BLK_LOAD(0);
     CHI0_BLK_STORE(0);
     __syncthreads();
     f4 acc[kBW][2][4];
@@ -358,35 +382,47 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         for (int n = 0; n < 4; ++n) acc[w][r][n] = f4{0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < nsteps; ++k) {
       const int buf = k & 1;
-      if (k + 1 < nsteps) CHI0_BLK_LOAD(U.k0 + 16 * (k + 1));
-      const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
-      // Im part through the rotated right operand (-im, re), rotated in registers
-      // (LDS holds hi and lo only: the reads of all waves stay within the LDS bandwidth);
-      // the weighted left operand is split once per frequency and feeds both parts
-      u4 bh[4], bl[4], rh[4], rl[4];
+      if (k + 1 < nsteps) CHI0_BLK_LOAD(k + 1);
+      if (nmask) {
+        // weighted left operand of every frequency, split once and shared by the column tiles
+        const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
+        u4 ah[kBW], al[kBW];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        bh[n] = Bs[buf][0][n][q][i];
-        bl[n] = Bs[buf][1][n][q][i];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          rh[n][m] = rot_neg(bh[n][m]);
-          rl[n][m] = rot_neg(bl[n][m]);
+        for (int w = 0; w < kBW; ++w) {
+          const float4 wq = Ws[buf][w][q];
+          uint32_t h[4], l[4];
+          split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
+          split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
+          split2(wq.z * a23.x, wq.z * a23.y, h[2], l[2]);
+          split2(wq.w * a23.z, wq.w * a23.w, h[3], l[3]);
+          ah[w] = u4{h[0], h[1], h[2], h[3]};
+          al[w] = u4{l[0], l[1], l[2], l[3]};
         }
-      }
-#pragma unroll
-      for (int w = 0; w < kBW; ++w) {
-        const float4 wq = Ws[buf][w][q];
-        uint32_t h[4], l[4];
-        split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
-        split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
-        split2(wq.z * a23.x, wq.z * a23.y, h[2], l[2]);
-        split2(wq.w * a23.z, wq.w * a23.w, h[3], l[3]);
-        const u4 ah = u4{h[0], h[1], h[2], h[3]}, al = u4{l[0], l[1], l[2], l[3]};
+        // column tiles: Re through the right operand, Im through its rotation (-im, re),
+        // rotated in registers; the next tile's operand is read ahead of the products
+        u4 bh = Bs[buf][0][0][q][i], bl = Bs[buf][1][0][q][i];
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          acc[w][0][n] = mma3(ah, al, bh[n], bl[n], acc[w][0][n]);
-          acc[w][1][n] = mma3(ah, al, rh[n], rl[n], acc[w][1][n]);
+          u4 nbh = bh, nbl = bl;
+          if (n < 3) {
+            nbh = Bs[buf][0][n + 1][q][i];
+            nbl = Bs[buf][1][n + 1][q][i];
+          }
+          if (nmask & (1 << n)) {
+            u4 rh, rl;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              rh[m] = rot_neg(bh[m]);
+              rl[m] = rot_neg(bl[m]);
+            }
+#pragma unroll
+            for (int w = 0; w < kBW; ++w) {
+              acc[w][0][n] = mma3(ah[w], al[w], bh, bl, acc[w][0][n]);
+              acc[w][1][n] = mma3(ah[w], al[w], rh, rl, acc[w][1][n]);
+            }
+          }
+          bh = nbh;
+          bl = nbl;
         }
       }
       if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1);
@@ -596,6 +632,8 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     // unit, so the rounding of the running sums stays bounded and the FP64 reduction
     // adds many short partial sums
     if (mode != MODE_F64 && !(tune && tune->kper > 0)) kper = std::min(kper, kFp32Slice);
+    // the block form addresses a slice by 32-bit byte offsets
+    if (blk) kper = std::min(kper, std::max(64, (int)(((1u << 31) / (8u * a[it].ng) - 16) / 64 * 64)));
     for (int t = 0; t < ntl[it]; ++t)
       for (int g = 0; g < ngroups; ++g) {
         Red r;
@@ -609,13 +647,25 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
         reds.push_back(r);
       }
   }
-  // queue: longest units first; among equal lengths, transition slice first, so the
-  // units in flight together read the same slice of every item's rho (cache reuse)
+  // queue: costliest units first (transitions times the 16 x 16 tiles the block form
+  // computes); among equal costs, transition slice first, so the units in flight
+  // together read the same slice of every item's rho (cache reuse)
+  auto tile_work = [&](const Unit& u) {
+    if (!blk) return 16;
+    const int2 b = tiles[items[u.item].tile0 + u.tile];
+    const int ng = a[u.item].ng;
+    int c = 0;
+    for (int r = 0; r < 4; ++r)
+      for (int m = 0; m < 4; ++m)
+        c += b.x * kBlk + 16 * r < ng && b.y * kBlk + 16 * m < ng && (b.x != b.y || m >= r);
+    return c;
+  };
+  std::vector<long> cost(units.size());
+  for (size_t u = 0; u < units.size(); ++u) cost[u] = (long)(units[u].k1 - units[u].k0) * tile_work(units[u]);
   std::vector<int> queue(units.size());
   for (size_t u = 0; u < units.size(); ++u) queue[u] = (int)u;
   std::stable_sort(queue.begin(), queue.end(), [&](int x, int y) {
-    const int lx = units[x].k1 - units[x].k0, ly = units[y].k1 - units[y].k0;
-    if (lx != ly) return lx > ly;
+    if (cost[x] != cost[y]) return cost[x] > cost[y];
     return units[x].k0 < units[y].k0;
   });
   const int nunits = (int)units.size();

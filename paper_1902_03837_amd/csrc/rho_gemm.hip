@@ -138,25 +138,21 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
     oe[rt] = gld<int>(P.Oe + g);
   }
 
-  // ---- right operand staging: slot s = tid + 256 f is (tile s / 64, quad (s / 16) % 4, column s % 16)
+  // ---- right operand staging: slot s = tid + 256 f is (tile s / 64, quad (s / 16) % 4, column s % 16).
+  // Columns past the group or the band count read a valid row (clamped); their
+  // products land in outputs that are never stored.
   u4 raw[2][2];
-  bool sok[2];
   const uint2* sp[2];
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     const int s = tid + kThreads * f;
-    const int ct = s >> 6, sq = (s >> 4) & 3, c = (ct0 + ct) * 16 + (s & 15);
-    sok[f] = ct < nt && c < P.nc;
-    sp[f] = P.Sc + (size_t)(sok[f] ? c : 0) * npwc + 4 * sq;
+    const int sq = (s >> 4) & 3, c = min((ct0 + (s >> 6)) * 16 + (s & 15), P.nc - 1);
+    sp[f] = P.Sc + (size_t)c * npwc + 4 * sq;
   }
 #define RHO_GEMM_LOAD(k_)                                                         \
   _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
-    if (sok[f]) {                                                                 \
-      raw[f][0] = gld<u4>(sp[f] + 16 * (k_));                                     \
-      raw[f][1] = gld<u4>(sp[f] + 16 * (k_) + 2);                                 \
-    } else {                                                                      \
-      raw[f][0] = raw[f][1] = u4{0u, 0u, 0u, 0u};                                 \
-    }                                                                             \
+    raw[f][0] = gld<u4>(sp[f] + 16 * (k_));                                       \
+    raw[f][1] = gld<u4>(sp[f] + 16 * (k_) + 2);                                   \
   }
 #define RHO_GEMM_STORE(b_)                                                        \
   _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
@@ -184,17 +180,22 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
       oan = gld<i4>(P.Oa + 16 * (k + 1) + 4 * q);
     }
     // ---- gathered left operand of this lane's rows: c_v(a - e) for a = 16 k + 4 q + (0..3)
+    // (hi and lo are read as two words, straight into the operand registers)
     u4 ah[kRT], al[kRT], bh[kRT], bl[kRT];
+    const uint32_t* Vw = reinterpret_cast<const uint32_t*>(Vs);
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       const int o[4] = {oa.x, oa.y, oa.z, oa.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const uint2 x = Vs[vb[rt] + Ts[o[u] + oe[rt]]];
-        ah[rt][u] = x.x;
-        al[rt][u] = x.y;
-        bh[rt][u] = rot_pos(x.x);
-        bl[rt][u] = rot_pos(x.y);
+        const int j = 2 * (vb[rt] + Ts[o[u] + oe[rt]]);
+        ah[rt][u] = Vw[j];
+        al[rt][u] = Vw[j + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bh[rt][u] = rot_pos(ah[rt][u]);
+        bl[rt][u] = rot_pos(al[rt][u]);
       }
     }
     const u4* Bh = Bs + (buf * 2 + 0) * (kCT * 64) + lane;
