@@ -40,6 +40,26 @@ def chi0_flops(K, ng, nw):
     return 4.0 * ng * ng * K * nw
 
 
+def rho_direct_terms(cr):
+    """Nonzero terms of the direct plane-wave sum, summed over the k-pairs: for each pair
+    the (a, G) with a in the conduction sphere and a - (m_G - G0) in the valence sphere,
+    times nc * nv. Each term is one complex multiply-add (8 flops)."""
+    tot = 0
+    G = cr.gmill.astype(np.int64)
+    for ik, ikp, g0 in cr.pairs:
+        mc, mv = cr.mill[ik].astype(np.int64), cr.mill[ikp].astype(np.int64)
+        lo = mv.min(0)
+        box = np.zeros(tuple(mv.max(0) - lo + 1), dtype=bool)
+        box[tuple((mv - lo).T)] = True
+        d = mc[:, None, :] - (G - np.asarray(g0))[None, :, :] - lo
+        ok = np.all((d >= 0) & (d < np.array(box.shape)), axis=-1)
+        hit = np.zeros(ok.shape, dtype=bool)
+        hit[ok] = box[tuple(d[ok].T)]
+        nc = cr.coef[ik].shape[0] - cr.nocc_at(ik)
+        tot += int(hit.sum()) * nc * cr.nocc_at(ikp)
+    return tot
+
+
 def rho_zy_flops(cr, pairs_meta):
     """Useful flops of the rho_zy kernel per transition (stages 1 and 2, no padding).
 
@@ -165,9 +185,11 @@ def measured_traffic(kernel):
     return tr[kernel] if cur == h else None
 
 
-def roofline(cr, form, K, nw, ng):
+def roofline(cr, form, K, nw, ng, name=None):
+    """Roofline entry of one kernel (default: the one with the largest time per step)."""
     kern = form["kernels"]
-    name = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    if name is None:
+        name = max(kern, key=lambda k: kern[k]["ms_per_step"])
     k = kern[name]
     t = k["avg_launch_ms"] * 1e-3
     prec = form["prec"]
@@ -185,6 +207,13 @@ def roofline(cr, form, K, nw, ng):
         return dict(kernel=name, bound="alu", achieved=fl / t / 1e12, peak=PEAK["valu"] / 1e12,
                     unit="TFLOP/s", frac=fl / t / PEAK["valu"], traffic=None,
                     note="useful complex MACs of the z-correlation and pruned y-DFT, 8 flops each")
+    if name == "rho_gemm":
+        fl = 8.0 * rho_direct_terms(cr) / k["launches"]   # per launch (all pairs of the step in one)
+        return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=PEAK["bf16_mfma"] / 1e12,
+                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name),
+                    note="algorithmic flops: the nonzero terms of the direct plane-wave sum (8 per complex "
+                         "multiply-add) over the bf16 dense peak; the kernel executes three split-bf16 products "
+                         "per term and the zero terms of its dense tiles")
     if name == "rho_yz":
         # algorithmic count: an FFT of the product grid per transition, 5 N_r log2 N_r
         nr = float(np.prod(cr.grid))
@@ -413,6 +442,10 @@ def main():
         "roofline": roofline(cr, fb, K, nw, ng),
         "fixture_s": t_fix,
     }
+    # the oscillator-strength kernel of the same step, for reference
+    rk = [k for k in ("rho_gemm", "rho_yz", "rho_zy") if k in fb["kernels"]]
+    if rk and rk[0] != res["roofline"]["kernel"]:
+        res["roofline_rho"] = roofline(cr, fb, K, nw, ng, name=rk[0])
     if not args.no_cpu:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(cr, args.cpu_pairs)
