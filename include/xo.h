@@ -120,13 +120,19 @@ int xo_rho(const xo_rho_args* a, void* stream);
 
 /* Several k-pairs in one call, with the same semantics as calling xo_rho on each
  * pair in order (each pair's output slice is written exactly as xo_rho writes
- * it). pairs: [host] array of npairs argument blocks. With prec XO_BF16X3 and
- * no q0 pair, pairs that share the grid and the G-set run in one MFMA launch:
- * orbitals become split bf16 (hi + lo) in real space along x and y, and the
- * z-correlation and pruned y-transform are bf16 x 3 matrix products with FP32
- * accumulation; the x-transform accumulates in FP32 (G-sets up to 1024 vectors,
- * x axis up to 72 points, sphere z-extent up to 32). Other batches, and
- * XO_BF16X3 batches outside those limits, run the FP32 path pair by pair. */
+ * it). pairs: [host] array of npairs argument blocks. With prec XO_BF16X3, pairs
+ * that share the grid's x axis and the G-set run in one MFMA launch, in one of
+ * two split-bf16 (hi + lo, three products, FP32 accumulation) kernels:
+ *   - the direct plane-wave sum rho_cv(G) = sum_a conj(c_c(a)) c_v(a - G + G0)
+ *     as a gathered matrix product (equal to the transform on the alias-free
+ *     grids that validation requires), when every pair's gather box and the
+ *     valence bands of a workgroup fit in LDS;
+ *   - otherwise the axis-factorised transform (orbitals real-space along x,
+ *     y-z correlation of Miller spectra on MFMA, x-DFT in FP32).
+ * The environment variable XO_RHO_KERNEL=gemm or =yz, read on each call,
+ * restricts the choice to one of the two. q0 pairs take the same kernels; their
+ * G = 0 column is then written from the FP64 velocity sum. Other batches, and
+ * batches that neither kernel can take, run the FP32 path pair by pair. */
 int xo_rho_batch(const xo_rho_args* pairs, int npairs, void* stream);
 
 /* ------------------------------------------------------------------------- */
