@@ -207,13 +207,15 @@ def roofline(cr, form, K, nw, ng, name=None):
         return dict(kernel=name, bound="alu", achieved=fl / t / 1e12, peak=PEAK["valu"] / 1e12,
                     unit="TFLOP/s", frac=fl / t / PEAK["valu"], traffic=None,
                     note="useful complex MACs of the z-correlation and pruned y-DFT, 8 flops each")
-    if name == "rho_gemm":
+    if name.startswith("rho_gemm"):
         fl = 8.0 * rho_direct_terms(cr) / k["launches"]   # per launch (all pairs of the step in one)
-        return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=PEAK["bf16_mfma"] / 1e12,
-                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name),
+        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[prec]
+        return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12,
+                    unit="TFLOP/s", frac=fl / t / peak, traffic=measured_traffic(name),
                     note="algorithmic flops: the nonzero terms of the direct plane-wave sum (8 per complex "
-                         "multiply-add) over the bf16 dense peak; the kernel executes three split-bf16 products "
-                         "per term and the zero terms of its dense tiles")
+                         "multiply-add) over the dense MFMA peak of the precision; the kernel also executes "
+                         "the zero terms of its dense tiles" + (" and three split-bf16 products per term"
+                                                                 if prec == "bf16x3" else ""))
     if name == "rho_yz":
         # algorithmic count: an FFT of the product grid per transition, 5 N_r log2 N_r
         nr = float(np.prod(cr.grid))
@@ -443,7 +445,7 @@ def main():
         "fixture_s": t_fix,
     }
     # the oscillator-strength kernel of the same step, for reference
-    rk = [k for k in ("rho_gemm", "rho_yz", "rho_zy") if k in fb["kernels"]]
+    rk = [k for k in fb["kernels"] if k.startswith("rho_gemm") or k in ("rho_yz", "rho_zy")]
     if rk and rk[0] != res["roofline"]["kernel"]:
         res["roofline_rho"] = roofline(cr, fb, K, nw, ng, name=rk[0])
     if not args.no_cpu:

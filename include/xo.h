@@ -120,19 +120,19 @@ int xo_rho(const xo_rho_args* a, void* stream);
 
 /* Several k-pairs in one call, with the same semantics as calling xo_rho on each
  * pair in order (each pair's output slice is written exactly as xo_rho writes
- * it). pairs: [host] array of npairs argument blocks. With prec XO_BF16X3, pairs
- * that share the grid's x axis and the G-set run in one MFMA launch, in one of
- * two split-bf16 (hi + lo, three products, FP32 accumulation) kernels:
- *   - the direct plane-wave sum rho_cv(G) = sum_a conj(c_c(a)) c_v(a - G + G0)
- *     as a gathered matrix product (equal to the transform on the alias-free
- *     grids that validation requires), when every pair's gather box and the
- *     valence bands of a workgroup fit in LDS;
- *   - otherwise the axis-factorised transform (orbitals real-space along x,
- *     y-z correlation of Miller spectra on MFMA, x-DFT in FP32).
- * The environment variable XO_RHO_KERNEL=gemm or =yz, read on each call,
- * restricts the choice to one of the two. q0 pairs take the same kernels; their
- * G = 0 column is then written from the FP64 velocity sum. Other batches, and
- * batches that neither kernel can take, run the FP32 path pair by pair. */
+ * it). pairs: [host] array of npairs argument blocks. Pairs of one precision
+ * that share the grid's x axis and the G-set run in one MFMA launch of the
+ * direct plane-wave sum rho_cv(G) = sum_a conj(c_c(a)) c_v(a - G + G0) as a
+ * gathered matrix product (equal to the transform on the alias-free grids that
+ * validation requires), when every pair's gather box and the valence bands of a
+ * workgroup fit in LDS: FP64 and FP32 on the 16x16x4 MFMAs of their precision,
+ * XO_BF16X3 as split bf16 (hi + lo, three products, FP32 accumulation).
+ * Otherwise XO_BF16X3 batches take the axis-factorised transform on MFMA
+ * (orbitals real-space along x, y-z correlation of Miller spectra, x-DFT in
+ * FP32) and FP64 / FP32 pairs the VALU transform, pair by pair. The environment
+ * variable XO_RHO_KERNEL=gemm or =transform, read on each call, restricts the
+ * choice to one of the two. q0 pairs take the same kernels; their G = 0 column
+ * is then written from the velocity sum (accumulated in FP64). */
 int xo_rho_batch(const xo_rho_args* pairs, int npairs, void* stream);
 
 /* ------------------------------------------------------------------------- */
@@ -277,7 +277,9 @@ int xo_tail_features(const xo_tail_args* a, void* stream);
 int xo_tail_apply(const double* chi_t, const float* Y1, const float* Y2, const double* qpg, int ng, int nw,
                   double tsc, double* out, void* stream);
 /* Fallback test inputs: stats[0] = number of features outside the training range
- * widened by 10 % of its span; stats[1] = sum |Y1 - Y2|^2 and stats[2] =
+ * widened by 10 % of its span (at least 1e-6: a feature that is zero up to
+ * rounding in training, as Im chi0 of a centrosymmetric crystal, does not reject
+ * data for its rounding); stats[1] = sum |Y1 - Y2|^2 and stats[2] =
  * sum |(Y1 + Y2)/2|^2 for two ensemble members. lo, hi [host] [F]; stats [device] [3]. */
 int xo_tail_guard(const float* X, long n, int F, const float* lo, const float* hi, const float* Y1,
                   const float* Y2, int ny, double* stats, void* stream);

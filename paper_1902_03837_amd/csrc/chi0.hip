@@ -180,20 +180,51 @@ __device__ __forceinline__ void unit_wave(const Item& I, int2 bij, int w0, int k
       acc[w][0] = V4{0, 0, 0, 0};
       acc[w][1] = V4{0, 0, 0, 0};
     }
-    for (int s = kb; s < ke; s += 2) {
+    // The next step's operands and weights are requested before this step's
+    // products (software pipelining: the loads are in flight during the MFMAs).
+    // Rows past the slice read the slice's last row with the left operand zeroed;
+    // columns past the G-set read column 0 and land in outputs that are dropped.
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const int Gic = gi_ok ? Gi : 0, Gjc = gj_ok ? Gj : 0;
+    T2 ra, rb;
+    T2 wt[NWG / 2 > 0 ? NWG / 2 : 1];
+    T wt1 = T(0);
+    bool tv = false;
+    auto load = [&](int s) {
       const int t = s + tsub;
-      const bool tv = t < ke;
-      cplx<T> ra = {T(0), T(0)}, rb = {T(0), T(0)};
-      if (tv && gi_ok) ra = rho[(size_t)t * I.ng + Gi];
-      if (tv && gj_ok) rb = rho[(size_t)t * I.ng + Gj];
-      const T bval = a ? rb.y : rb.x;
-      const T are = a ? ra.y : ra.x;
-      const T aim = a ? -ra.x : ra.y;
+      tv = t < ke;
+      const size_t row = (size_t)min(t, ke - 1);
+      ra = gld<T2>(rho + row * I.ng + Gic);
+      rb = gld<T2>(rho + row * I.ng + Gjc);
+      if constexpr (NWG >= 2) {
+#pragma unroll
+        for (int w = 0; w < NWG / 2; ++w) wt[w] = gld<T2>(W + row * I.nwpad + 2 * w);
+      } else {
+        wt1 = gld<T>(W + row * I.nwpad);
+      }
+    };
+    if (kb < ke) load(kb);
+#pragma unroll 1
+    for (int s = kb; s < ke; s += 2) {
+      const T2 ca = tv ? ra : T2{T(0), T(0)}, cb = rb;
+      T cw[NWG];
+      if constexpr (NWG >= 2) {
+#pragma unroll
+        for (int w = 0; w < NWG / 2; ++w) {
+          cw[2 * w] = wt[w].x;
+          cw[2 * w + 1] = wt[w].y;
+        }
+      } else {
+        cw[0] = wt1;
+      }
+      load(s + 2);  // clamped: the last step re-reads valid rows
+      const T bval = a ? cb.y : cb.x;
+      const T are = a ? ca.y : ca.x;
+      const T aim = a ? -ca.x : ca.y;
 #pragma unroll
       for (int w = 0; w < NWG; ++w) {
-        const T wt = tv ? W[(size_t)t * I.nwpad + w] : T(0);
-        acc[w][0] = mfma4(wt * are, bval, acc[w][0]);
-        acc[w][1] = mfma4(wt * aim, bval, acc[w][1]);
+        acc[w][0] = mfma4(cw[w] * are, bval, acc[w][0]);
+        acc[w][1] = mfma4(cw[w] * aim, bval, acc[w][1]);
       }
     }
     T* out = MODE == MODE_F64 ? reinterpret_cast<T*>(outd) : reinterpret_cast<T*>(outf);
@@ -212,12 +243,12 @@ __global__ void __launch_bounds__(256) chi0_units(const Item* __restrict__ items
                                                   const Unit* __restrict__ units, const int* __restrict__ queue,
                                                   int nunits, int* __restrict__ counter, void* __restrict__ part) {
   __shared__ int su;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int PER = NWG * 2 * NT * 256;  // values per wave partial
   for (;;) {
     if (threadIdx.x == 0) su = atomicAdd(counter, 1);
     __syncthreads();
-    const int qpos = su;
+    const int qpos = __builtin_amdgcn_readfirstlane(su);
     __syncthreads();
     if (qpos >= nunits) break;
     const int uid = queue[qpos];

@@ -246,15 +246,19 @@ __global__ void tail_apply(const double* __restrict__ chi_t, const float* __rest
   }
 }
 
-// stats[0] += features outside [lo - 10% span, hi + 10% span]; stats[1] += |Y1 - Y2|^2; stats[2] += |Y1 + Y2|^2 / 4
+// stats[0] += features outside [lo - m, hi + m], m = max(10% span, kGuardFloor); stats[1] += |Y1 - Y2|^2;
+// stats[2] += |Y1 + Y2|^2 / 4. The floor (features are normalised to order one) keeps a feature
+// that is zero up to rounding in every training crystal (Im chi0 of a crystal with inversion
+// and time reversal) from rejecting data whose rounding differs.
+constexpr float kGuardFloor = 1e-6f;
 __global__ void tail_guard(const float* __restrict__ X, long n, int F, const float* __restrict__ lo,
                            const float* __restrict__ hi, const float* __restrict__ Y1, const float* __restrict__ Y2,
                            int ny, double* __restrict__ stats) {
   double out = 0.0, dd = 0.0, mm = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     for (int k = 0; k < F; ++k) {
-      const float x = X[e * F + k], span = hi[k] - lo[k];
-      if (x < lo[k] - 0.1f * span || x > hi[k] + 0.1f * span) out += 1.0;
+      const float x = X[e * F + k], m = fmaxf(0.1f * (hi[k] - lo[k]), kGuardFloor);
+      if (x < lo[k] - m || x > hi[k] + m) out += 1.0;
     }
     for (int k = 0; k < ny; ++k) {
       const double a = Y1[e * ny + k], b = Y2[e * ny + k];

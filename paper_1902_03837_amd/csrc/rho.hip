@@ -465,6 +465,7 @@ int validate_rho(const xo_rho_args* a, Extent* pxc, Extent* pxv, Extent* pxe) {
 // q -> 0 head of a pair whose other columns came from the batched MFMA path
 // (complex64 output).
 int rho_head_f32(const xo_rho_args* a, hipStream_t s) { return launch_head_q0<float>(a, s); }
+int rho_head_f64(const xo_rho_args* a, hipStream_t s) { return launch_head_q0<double>(a, s); }
 
 // VALU path for one pair (FP64 and FP32).
 int rho_valu(const xo_rho_args* a, hipStream_t s) {

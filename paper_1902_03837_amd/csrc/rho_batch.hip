@@ -42,9 +42,12 @@ namespace xo {
 
 int rho_valu(const xo_rho_args* a, hipStream_t s);
 int rho_head_f32(const xo_rho_args* a, hipStream_t s);
+int rho_head_f64(const xo_rho_args* a, hipStream_t s);
 int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                    hipStream_t s);
 int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s);
+int rho_batch_gemm_fp(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                      hipStream_t s);
 
 namespace {
 
@@ -486,12 +489,13 @@ static int launch_rho_mt(int MT, const void* dpairs, int npairs, int nwg, int Nx
   }
 }
 
-// Whether a batch can take the MFMA path (else each pair runs the VALU path in FP32).
+// Whether a batch can take one batched MFMA launch (same precision, grid x axis
+// and G-set); else each pair runs on its own.
 static bool mfma_eligible(const xo_rho_args* p, int n) {
   const xo_rho_args& a0 = p[0];
   if (a0.ng > 65535) return false;
   for (int i = 0; i < n; ++i) {
-    if (p[i].prec != XO_BF16X3) return false;
+    if (p[i].prec != a0.prec) return false;
     if (p[i].n[0] != a0.n[0] || p[i].ng != a0.ng) return false;
     if (std::memcmp(p[i].mill_g, a0.mill_g, sizeof(int32_t) * 3 * a0.ng) != 0) return false;
   }
@@ -683,7 +687,7 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
 int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s) {
   // q -> 0: the G = 0 column of such pairs is the velocity head, written over the transform's value
   for (int i = 0; i < n; ++i)
-    if (p[i].q0) XO_RET(rho_head_f32(&p[i], s));
+    if (p[i].q0) XO_RET(p[i].prec == XO_FP64 ? rho_head_f64(&p[i], s) : rho_head_f32(&p[i], s));
 
   std::vector<PoleDesc> poles;
   int maxm = 0;
@@ -705,15 +709,15 @@ int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s) {
   return XO_OK;
 }
 
-// Which split-bf16 kernel a batch may take: the gathered product when its
-// tables fit in LDS, else the axis-factorised transform. XO_RHO_KERNEL=gemm or
-// =yz restricts the choice to one of them (the other paths still apply when it
-// cannot run).
+// Which kernel a batch may take: the gathered product when its tables fit in
+// LDS, else the transform (axis-factorised on MFMA for split bf16, on VALU pair
+// by pair for FP32 / FP64). XO_RHO_KERNEL=gemm or =transform restricts the choice
+// to one of them (the other paths still apply when it cannot run).
 static int rho_kernel_choice() {
   const char* e = std::getenv("XO_RHO_KERNEL");
   if (!e) return 0;
   if (!std::strcmp(e, "gemm")) return 1;
-  if (!std::strcmp(e, "yz")) return 2;
+  if (!std::strcmp(e, "transform")) return 2;
   return 0;
 }
 
@@ -722,12 +726,17 @@ int rho_batch(const xo_rho_args* p, int n, hipStream_t s) {
   for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
   if (mfma_eligible(p, n)) {
     const int choice = rho_kernel_choice();
-    if (choice != 2) {
-      int r = rho_batch_gemm(p, n, xc.data(), xv.data(), xe.data(), s);
-      if (r != XO_ERR_UNSUPPORTED) return r;
-    }
-    if (choice != 1) {
-      int r = rho_batch_mfma(p, n, xc.data(), xv.data(), xe.data(), s);
+    if (p[0].prec == XO_BF16X3) {
+      if (choice != 2) {
+        int r = rho_batch_gemm(p, n, xc.data(), xv.data(), xe.data(), s);
+        if (r != XO_ERR_UNSUPPORTED) return r;
+      }
+      if (choice != 1) {
+        int r = rho_batch_mfma(p, n, xc.data(), xv.data(), xe.data(), s);
+        if (r != XO_ERR_UNSUPPORTED) return r;
+      }
+    } else if (choice != 2) {
+      int r = rho_batch_gemm_fp(p, n, xc.data(), xv.data(), xe.data(), s);
       if (r != XO_ERR_UNSUPPORTED) return r;
     }
   }

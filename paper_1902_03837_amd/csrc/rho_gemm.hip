@@ -163,8 +163,31 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
 
   RHO_GEMM_LOAD(0);
   RHO_GEMM_STORE(0);
-  i4 oa = gld<i4>(P.Oa + 4 * q);
+  // Box offsets of this lane's conduction plane waves, two steps ahead.
+  i4 oa1 = gld<i4>(P.Oa + 4 * q);
+  i4 oa2 = gld<i4>(P.Oa + 16 * min(1, nK - 1) + 4 * q);
   __syncthreads();
+
+  // Gathered left operand of this lane's rows, c_v(a - e) for a = 16 k + 4 q + (0..3)
+  // (hi and lo read as two words, straight into the operand registers). The box
+  // table and valence bands do not change during the loop, so the next step's
+  // gather is issued while this step's products run.
+  const uint32_t* Vw = reinterpret_cast<const uint32_t*>(Vs);
+  auto gather = [&](i4 oa, u4* gh, u4* gl) {
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      const int o[4] = {oa.x, oa.y, oa.z, oa.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = 2 * (vb[rt] + Ts[o[u] + oe[rt]]);
+        gh[rt][u] = Vw[j];
+        gl[rt][u] = Vw[j + 1];
+      }
+    }
+  };
+  u4 ah[kRT], al[kRT];
+  gather(oa1, ah, al);
+  oa1 = oa2;
 
   f4 re[kRT][kCT], im[kRT][kCT];
 #pragma unroll
@@ -174,30 +197,22 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
 
   for (int k = 0; k < nK; ++k) {
     const int buf = k & 1;
-    i4 oan = oa;
     if (k + 1 < nK) {
       RHO_GEMM_LOAD(k + 1);
-      oan = gld<i4>(P.Oa + 16 * (k + 1) + 4 * q);
+      oa2 = gld<i4>(P.Oa + 16 * min(k + 2, nK - 1) + 4 * q);
     }
-    // ---- gathered left operand of this lane's rows: c_v(a - e) for a = 16 k + 4 q + (0..3)
-    // (hi and lo are read as two words, straight into the operand registers)
-    u4 ah[kRT], al[kRT], bh[kRT], bl[kRT];
-    const uint32_t* Vw = reinterpret_cast<const uint32_t*>(Vs);
+    // next step's gather (the last step re-gathers valid offsets, unused)
+    u4 nah[kRT], nal[kRT];
+    gather(oa1, nah, nal);
+    // Im operand: (im, -re) of the gathered values
+    u4 bh[kRT], bl[kRT];
 #pragma unroll
-    for (int rt = 0; rt < kRT; ++rt) {
-      const int o[4] = {oa.x, oa.y, oa.z, oa.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = 2 * (vb[rt] + Ts[o[u] + oe[rt]]);
-        ah[rt][u] = Vw[j];
-        al[rt][u] = Vw[j + 1];
-      }
+    for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         bh[rt][u] = rot_pos(ah[rt][u]);
         bl[rt][u] = rot_pos(al[rt][u]);
       }
-    }
     const u4* Bh = Bs + (buf * 2 + 0) * (kCT * 64) + lane;
     const u4* Bl = Bs + (buf * 2 + 1) * (kCT * 64) + lane;
 #pragma unroll
@@ -212,7 +227,12 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
       }
     }
     if (k + 1 < nK) RHO_GEMM_STORE(buf ^ 1);
-    oa = oan;
+#pragma unroll
+    for (int rt = 0; rt < kRT; ++rt) {
+      ah[rt] = nah[rt];
+      al[rt] = nal[rt];
+    }
+    oa1 = oa2;
     __syncthreads();
   }
 #undef RHO_GEMM_LOAD
@@ -246,11 +266,206 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   }
 }
 
+// ------------------------------------------------- FP64 / FP32 products --
+// The same gathered product in the working precision on v_mfma_f64_16x16x4f64 /
+// v_mfma_f32_16x16x4f32: K = 4 real columns per instruction, i.e. two plane
+// waves (re, im). Lane l = i + 16 kk holds row i (left) or column i (right) at
+// K index kk: plane wave 16 k + 2 s + kk / 2, component kk % 2. The left
+// operand of Re rho is that component of c_v(a - e), the one of Im rho the
+// component of (im, -re); the right operand is the component of c_c(a).
+// Coefficients are read straight from the caller's arrays (no split).
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int kBsTile = 16 * 17;  // staged right-operand tile: 16 plane waves x (16 columns + 1 pad)
+
+template <typename T>
+struct FpMma;
+template <>
+struct FpMma<double> {
+  typedef d4v V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kk, int r) { return kk + 4 * r; }  // result register r
+};
+template <>
+struct FpMma<float> {
+  typedef f4 V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kk, int r) { return 4 * kk + r; }
+};
+
+struct GemmPairFp {
+  const void* Cc;  // conduction coefficients [nc][npw_c] complex (caller's)
+  const void* Cv;  // valence [nv][npw_v] complex (caller's)
+  void* rho;       // [nv][nc][ng] complex
+  const int* OaP;  // [nK][2][8] box offsets by step and parity
+  const int* Oe;   // [ng]
+  const u4* T;     // [ncell / 8] uint16 valence index of each box cell, npw_v outside the sphere
+  int npw_c, npw_v, vstride;  // vstride: LDS row of a valence band (npw_v + 1, even)
+  int nK, ncell, nc, nv, nct, ncg, nrb, wg0;
+};
+
+// complex load through the global address space
+template <typename T>
+__device__ __forceinline__ cplx<T> gld_c(const cplx<T>* p) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  const T2 x = gld<T2>(p);
+  return cplx<T>{x.x, x.y};
+}
+
+template <typename T, int CT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+rho_gemm_fp(const GemmPairFp* __restrict__ pairs, int npairs, int nwg, int ng) {
+  typedef cplx<T> C;
+  typedef typename FpMma<T>::V V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int per = (nwg + 7) >> 3;
+  const int L = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (L >= nwg) return;
+  int plo = 0, phi = npairs - 1;
+  while (plo < phi) {
+    const int mid = (plo + phi + 1) >> 1;
+    if (pairs[mid].wg0 <= L) plo = mid; else phi = mid - 1;
+  }
+  const GemmPairFp& P = pairs[plo];
+  const int local = L - P.wg0;
+  const int cg = local / P.nrb, rb = local - cg * P.nrb;
+  const int ct0 = cg * P.nct / P.ncg, nt = (cg + 1) * P.nct / P.ncg - ct0;
+  const int nrows = P.nv * ng;
+  const int r0 = rb * kRows;
+  const int vlo = r0 / ng, vhi = min(P.nv - 1, (r0 + kRows - 1) / ng);
+  const int nK = P.nK, npw_c = P.npw_c, vstride = P.vstride;
+
+  C* Bs = reinterpret_cast<C*>(smem);                                    // [2][CT][16 a][17]: 16 columns + pad
+  uint16_t* Ts = reinterpret_cast<uint16_t*>(smem + 2 * CT * kBsTile * sizeof(C));  // [ncell]
+  C* Vs = reinterpret_cast<C*>(Ts + P.ncell);                            // [vhi - vlo + 1][vstride]
+  const int nvs = (vhi - vlo + 1) * vstride;
+
+  const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, kk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  // ---- box table and the valence bands of this workgroup's rows (zero past each band)
+  for (int k = tid; k < P.ncell / 8; k += kThreads) reinterpret_cast<u4*>(Ts)[k] = gld<u4>(P.T + k);
+  {
+    const C* src = static_cast<const C*>(P.Cv) + (size_t)vlo * P.npw_v;
+    for (int k = tid; k < nvs; k += kThreads) {
+      const int sl = k / vstride, j = k - sl * vstride;
+      const C x = gld_c(src + (size_t)sl * P.npw_v + min(j, P.npw_v - 1));
+      Vs[k] = j < P.npw_v ? x : C{T(0), T(0)};
+    }
+  }
+  int vb[kRT], oe[kRT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt) {
+    const int r = r0 + 32 * w + 16 * rt + i;
+    const int v = r < nrows ? r / ng : vlo;
+    const int g = r < nrows ? r - v * ng : 0;
+    vb[rt] = (v - vlo) * vstride;
+    oe[rt] = gld<int>(P.Oe + g);
+  }
+  // ---- right operand staging: element e = tid + 256 f is (tile e / 256, column (e / 16) % 16,
+  // plane wave e % 16); invalid columns and plane waves past the sphere stage zeros
+  const C* Cc = static_cast<const C*>(P.Cc);
+  int cidx[CT];
+  bool cok[CT];
+#pragma unroll
+  for (int f = 0; f < CT; ++f) {
+    const int e = tid + kThreads * f;
+    const int c = (ct0 + (e >> 8)) * 16 + ((e >> 4) & 15);
+    cok[f] = (e >> 8) < nt && c < P.nc;
+    cidx[f] = min(c, P.nc - 1) * npw_c;
+  }
+  const int al = tid & 15;
+  C raw[CT];
+  auto load = [&](int k) {
+    const int a = 16 * k + al;
+#pragma unroll
+    for (int f = 0; f < CT; ++f) {
+      const C x = gld_c(Cc + cidx[f] + min(a, npw_c - 1));
+      raw[f] = (cok[f] && a < npw_c) ? x : C{T(0), T(0)};
+    }
+  };
+  // element e = tid + 256 f goes to [tile e / 256][plane wave e % 16][column (e / 16) % 16]
+  auto store = [&](int b) {
+#pragma unroll
+    for (int f = 0; f < CT; ++f) {
+      const int e = tid + kThreads * f;
+      Bs[((size_t)b * CT + (e >> 8)) * kBsTile + (e & 15) * 17 + ((e >> 4) & 15)] = raw[f];
+    }
+  };
+  load(0);
+  store(0);
+  i4 oa0 = gld<i4>(P.OaP + 8 * (kk >> 1)), oa1 = gld<i4>(P.OaP + 8 * (kk >> 1) + 4);
+  __syncthreads();
+
+  V re[kRT][CT], im[kRT][CT];
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) re[rt][ct] = im[rt][ct] = V{T(0), T(0), T(0), T(0)};
+  const T* Bw = reinterpret_cast<const T*>(Bs);
+  for (int k = 0; k < nK; ++k) {
+    const int buf = k & 1;
+    i4 na0 = oa0, na1 = oa1;
+    if (k + 1 < nK) {
+      load(k + 1);
+      na0 = gld<i4>(P.OaP + 16 * (k + 1) + 8 * (kk >> 1));
+      na1 = gld<i4>(P.OaP + 16 * (k + 1) + 8 * (kk >> 1) + 4);
+    }
+    const int o[8] = {oa0.x, oa0.y, oa0.z, oa0.w, oa1.x, oa1.y, oa1.z, oa1.w};
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      T xr[kRT], xi[kRT];
+#pragma unroll
+      for (int rt = 0; rt < kRT; ++rt) {
+        const C v = Vs[vb[rt] + Ts[o[st] + oe[rt]]];
+        xr[rt] = (kk & 1) ? v.y : v.x;
+        xi[rt] = (kk & 1) ? -v.x : v.y;
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        if (ct < nt) {
+          const T bv = Bw[(((size_t)buf * CT + ct) * kBsTile + (2 * st + (kk >> 1)) * 17 + i) * 2 + (kk & 1)];
+#pragma unroll
+          for (int rt = 0; rt < kRT; ++rt) {
+            re[rt][ct] = FpMma<T>::mma(xr[rt], bv, re[rt][ct]);
+            im[rt][ct] = FpMma<T>::mma(xi[rt], bv, im[rt][ct]);
+          }
+        }
+      }
+    }
+    if (k + 1 < nK) store(buf ^ 1);
+    oa0 = na0;
+    oa1 = na1;
+    __syncthreads();
+  }
+  // ---- results: lane holds rows FpMma::row(kk, r) of each row tile, column i of each column tile
+  C* rho = static_cast<C*>(P.rho);
+#pragma unroll
+  for (int rt = 0; rt < kRT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c = (ct0 + ct) * 16 + i;
+      if (ct >= nt || c >= P.nc) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 32 * w + 16 * rt + FpMma<T>::row(kk, r);
+        if (row >= nrows) continue;
+        const int v = row / ng, g = row - v * ng;
+        rho[((size_t)v * P.nc + c) * ng + g] = C{re[rt][ct][r], im[rt][ct][r]};
+      }
+    }
+}
+
 // ------------------------------------------------------------------ host --
 struct GemmGeo {
   std::vector<int> Oa, Oe;
+  std::vector<int> OaP;  // Oa by step and parity, [nK][2][8]: OaP[16 k + 8 p + s] = Oa[16 k + 2 s + p]
   std::vector<uint16_t> T;
   int nK = 0;
+  const void* dOaP = nullptr;
   const void* dOa = nullptr;
   const void* dOe = nullptr;
   const void* dT = nullptr;
@@ -277,6 +492,10 @@ static void gemm_geo(const xo_rho_args* a, const Extent& xc, const Extent& xv, c
     g->Oa[p] = (int)((a->mill_c[3 * p] - lo[0]) + SX * (a->mill_c[3 * p + 1] - lo[1]) +
                      SY * (a->mill_c[3 * p + 2] - lo[2]));
   for (size_t p = a->npw_c; p < g->Oa.size(); ++p) g->Oa[p] = g->Oa[0];
+  g->OaP.resize(g->Oa.size());
+  for (int k = 0; k < g->nK; ++k)
+    for (int pp = 0; pp < 2; ++pp)
+      for (int st = 0; st < 8; ++st) g->OaP[16 * k + 8 * pp + st] = g->Oa[16 * k + 2 * st + pp];
   g->Oe.resize(a->ng);
   for (int j = 0; j < a->ng; ++j) {
     const long ex = a->mill_g[3 * j] - a->g0[0], ey = a->mill_g[3 * j + 1] - a->g0[1],
@@ -327,6 +546,7 @@ static int gemm_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, 
   gemm_geo(a, xc, xv, xe, &e);
   if (e.ok) {
     XO_RET(device_table(e.Oa.data(), e.Oa.size() * sizeof(int), s, &e.dOa));
+    XO_RET(device_table(e.OaP.data(), e.OaP.size() * sizeof(int), s, &e.dOaP));
     XO_RET(device_table(e.Oe.data(), e.Oe.size() * sizeof(int), s, &e.dOe));
     XO_RET(device_table(e.T.data(), e.T.size() * sizeof(uint16_t), s, &e.dT));
   }
@@ -443,6 +663,72 @@ int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* 
   }
   XO_CHECK_LAUNCH();
   return rho_batch_finish(p, n, s);
+}
+
+
+// FP64 / FP32 batch on the gathered product, or XO_ERR_UNSUPPORTED (nothing
+// enqueued) when a pair's tables do not fit in LDS.
+template <typename T, int CT>
+static int rho_batch_gemm_fp_t(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                               hipStream_t s) {
+  typedef cplx<T> C;
+  const int ng = p[0].ng;
+  std::vector<const GemmGeo*> ge(n);
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    XO_RET(gemm_entry(&p[i], xc[i], xv[i], xe[i], s, &ge[i]));
+    if (!ge[i]) return XO_ERR_UNSUPPORTED;
+    int nbs = 1;
+    const int nrows = p[i].nv * ng;
+    for (int r0 = 0; r0 < nrows; r0 += kRows)
+      nbs = std::max(nbs, std::min(p[i].nv - 1, (r0 + kRows - 1) / ng) - r0 / ng + 1);
+    const size_t vstride = (size_t)(p[i].npw_v + 2) & ~(size_t)1;
+    const size_t need = (size_t)2 * CT * kBsTile * sizeof(C) + ge[i]->T.size() * 2 + nbs * vstride * sizeof(C);
+    lds = std::max(lds, need);
+  }
+  if (lds > kLdsMax) return XO_ERR_UNSUPPORTED;
+  std::vector<GemmPairFp> gp(n);
+  int nwg = 0;
+  for (int i = 0; i < n; ++i) {
+    const GemmGeo& g = *ge[i];
+    GemmPairFp& d = gp[i];
+    d.Cc = p[i].coef_c;
+    d.Cv = p[i].coef_v;
+    d.rho = p[i].rho;
+    d.OaP = static_cast<const int*>(g.dOaP);
+    d.Oe = static_cast<const int*>(g.dOe);
+    d.T = static_cast<const u4*>(g.dT);
+    d.npw_c = p[i].npw_c;
+    d.npw_v = p[i].npw_v;
+    d.vstride = (p[i].npw_v + 2) & ~1;
+    d.nK = g.nK;
+    d.ncell = (int)g.T.size();
+    d.nc = p[i].nc;
+    d.nv = p[i].nv;
+    d.nct = (p[i].nc + 15) / 16;
+    d.ncg = (d.nct + CT - 1) / CT;
+    d.nrb = (p[i].nv * ng + kRows - 1) / kRows;
+    d.wg0 = nwg;
+    nwg += d.ncg * d.nrb;
+  }
+  const void* dgp = nullptr;
+  XO_RET(device_table(gp.data(), gp.size() * sizeof(GemmPairFp), s, &dgp));
+  if (lds > 64 * 1024)
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm_fp<T, CT>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  {
+    KernelTimer kt_(sizeof(T) == 8 ? "rho_gemm_f64" : "rho_gemm_f32", s);
+    hipLaunchKernelGGL((rho_gemm_fp<T, CT>), dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
+                       static_cast<const GemmPairFp*>(dgp), n, nwg, ng);
+  }
+  XO_CHECK_LAUNCH();
+  return rho_batch_finish(p, n, s);
+}
+
+int rho_batch_gemm_fp(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                      hipStream_t s) {
+  if (p[0].prec == XO_FP64) return rho_batch_gemm_fp_t<double, 4>(p, n, xc, xv, xe, s);
+  return rho_batch_gemm_fp_t<float, 8>(p, n, xc, xv, xe, s);
 }
 
 }  // namespace xo

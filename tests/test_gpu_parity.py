@@ -40,16 +40,18 @@ def _to(a, dt=torch.complex128):
 
 # ----------------------------------------------------------------------------- rho
 
-# split-bf16 rho has two kernels: the gathered product (default where its tables
-# fit in LDS) and the axis-factorised transform; XO_RHO_KERNEL pins one of them
-RHO_FORMS = [("fp64", None, 1e-13), ("fp32", None, 3e-6), ("bf16x3", "gemm", 5e-5), ("bf16x3", "yz", 5e-5)]
+# rho has two kernels in every precision: the gathered product (default where its
+# tables fit in LDS) and the transform (axis-factorised on MFMA for split bf16, on
+# VALU for FP32 / FP64); XO_RHO_KERNEL pins one of them
+RHO_FORMS = [("fp64", "gemm", 1e-13), ("fp64", "transform", 1e-13), ("fp32", "gemm", 3e-6),
+             ("fp32", "transform", 3e-6), ("bf16x3", "gemm", 5e-5), ("bf16x3", "transform", 5e-5)]
 
 
 class rho_kernel:
-    """Pin the split-bf16 rho kernel for the calls inside the block and check that it ran."""
+    """Pin the rho kernel for the calls inside the block and check that it ran."""
 
-    def __init__(self, name):
-        self.name = name
+    def __init__(self, name, prec="bf16x3"):
+        self.name, self.prec = name, prec
 
     def __enter__(self):
         self.old = os.environ.get("XO_RHO_KERNEL")
@@ -64,7 +66,8 @@ class rho_kernel:
             ran = xo.timing_report()
             xo.timing_enable(False)
             if exc[0] is None:
-                assert ("rho_gemm" if self.name == "gemm" else "rho_yz") in ran, ran.keys()
+                want = "rho_gemm" if self.name == "gemm" else ("rho_yz" if self.prec == "bf16x3" else "rho_zy")
+                assert any(k.startswith(want) for k in ran), ran.keys()
         if self.old is None:
             os.environ.pop("XO_RHO_KERNEL", None)
         else:
@@ -82,7 +85,7 @@ def test_rho_parity(name, prec, kern, tol):
     ng = cr.gmill.shape[0]
     M = torch.empty((K, ng), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    with rho_kernel(kern):
+    with rho_kernel(kern, prec):
         rho_all(dc, M, dE)
     torch.cuda.synchronize()
     Mr, dEr = rho_all_pairs(cr, "fft")
@@ -93,7 +96,7 @@ def test_rho_parity(name, prec, kern, tol):
     assert np.array_equal(dE.cpu().numpy(), dEr)
 
 
-@pytest.mark.parametrize("prec,kern,tol", RHO_FORMS[1:])
+@pytest.mark.parametrize("prec,kern,tol", RHO_FORMS)
 def test_rho_parity_large_gset(prec, kern, tol):
     """NG = 700 on a 28^3 grid: more G-vectors than one workgroup of the axis-factorised
     kernel owns (the G-set is split into several (e_y, e_z)-column groups); for the
@@ -102,9 +105,9 @@ def test_rho_parity_large_gset(prec, kern, tol):
     say(f"rho parity NG=700 {prec} {kern}")
     dc = DeviceCrystal.upload(cr, prec)
     K = ntrans(cr)
-    M = torch.empty((K, 700), dtype=torch.complex64, device=DEV)
+    M = torch.empty((K, 700), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    with rho_kernel(kern):
+    with rho_kernel(kern, prec):
         rho_all(dc, M, dE)
     torch.cuda.synchronize()
     Mr, _ = rho_all_pairs(cr, "fft")
@@ -130,8 +133,8 @@ def test_rho_batch_equals_per_pair(prec):
     assert torch.equal(M1, M2) and torch.equal(d1, d2)
 
 
-@pytest.mark.parametrize("prec,kern,tol_head,tol", [("fp64", None, 1e-12, 1e-12), ("bf16x3", "gemm", 1e-6, 5e-5),
-                                                    ("bf16x3", "yz", 1e-6, 5e-5)])
+@pytest.mark.parametrize("prec,kern,tol_head,tol", [("fp64", "gemm", 1e-12, 1e-12), ("fp64", "transform", 1e-12, 1e-12),
+                                                    ("bf16x3", "gemm", 1e-6, 5e-5), ("bf16x3", "transform", 1e-6, 5e-5)])
 def test_rho_q0_head_parity(prec, kern, tol_head, tol):
     """q -> 0: the G = 0 column is the velocity head (accumulated in FP64 in every
     form, rounded to the output precision); the other columns come from the transform."""
@@ -144,7 +147,7 @@ def test_rho_q0_head_parity(prec, kern, tol_head, tol):
     K = ntrans(cr)
     M = torch.empty((K, 27), dtype=torch.complex128 if prec == "fp64" else torch.complex64, device=DEV)
     dE = torch.empty(K, dtype=torch.float64, device=DEV)
-    with rho_kernel(kern):
+    with rho_kernel(kern, prec):
         rho_all(dc, M, dE)
     Mr, _ = rho_all_pairs(cr, "fft")
     Mg = M.cpu().numpy().astype(np.complex128)

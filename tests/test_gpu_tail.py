@@ -175,6 +175,12 @@ def test_guard_flags_out_of_range_and_disagreement():
     xo.tail_guard(X, lo, hi, Y, Y * 2, stats)
     s = stats.cpu().numpy()
     assert s[0] == 1 and s[1] == pytest.approx(n * 2)
+    # a feature that was zero up to rounding in training: rounding noise passes, a real value does not
+    lo[5] = hi[5] = 0.0
+    X[7, 3] = 0.0
+    X[3, 5], X[4, 5] = 1e-9, 1e-5
+    xo.tail_guard(X, lo, hi, Y, Y, stats)
+    assert stats.cpu().numpy()[0] == 1
 
 
 def test_training_reduces_loss_on_small_family():
