@@ -448,6 +448,11 @@ def main():
     rk = [k for k in fb["kernels"] if k.startswith("rho_gemm") or k in ("rho_yz", "rho_zy")]
     if rk and rk[0] != res["roofline"]["kernel"]:
         res["roofline_rho"] = roofline(cr, fb, K, nw, ng, name=rk[0])
+    # the chi0 kernel of every form timed, against the MFMA peak of its own precision
+    res["roofline_chi0_by_form"] = {
+        p: roofline(cr, f, K, nw, ng, name=next(k for k in f["kernels"] if k.startswith("chi0_tiles")
+                                                or k.startswith("chi0_blocks")))
+        for p, f in forms.items()}
     if not args.no_cpu:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(cr, args.cpu_pairs)
