@@ -48,7 +48,7 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
 __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
                                                    int check_sign, int* __restrict__ flag) {
   __shared__ z pcol[2][kB];
-  __shared__ z prow[2][kB];
+  __shared__ z prow[2][kB + kB / 16];  // column c at c + c / 16: the four column quarters on distinct banks
   const int w = blockIdx.x;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, i
       if (cq == kq) pcol[b][r] = a[kk];
       if (r == k) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) prow[b][c0 + j] = a[j];
+        for (int j = 0; j < 16; ++j) prow[b][c0 + cq + j] = a[j];
       }
       __syncthreads();
       const z piv = pcol[b][k];
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, i
       const double keep = prow_k ? 0.0 : 1.0;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const z pr = prow[b][c0 + j];
+        const z pr = prow[b][c0 + cq + j];
         a[j].x = fma(-g.x, pr.x, fma(g.y, pr.y, keep * a[j].x));
         a[j].y = fma(-g.x, pr.y, fma(-g.y, pr.x, keep * a[j].y));
       }
