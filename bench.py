@@ -8,10 +8,11 @@ inputs already resident in HBM: oscillator strengths for all 64 k-pairs
 (xo_rho), chi0 for all frequencies (xo_chi0) and the FP64 Dyson inversion
 (xo_epsinv).
 
-Every form is timed: plain FP64, FP32 (FP32 rho, FP32-MFMA chi0) and BF16x3
-(FP32 rho, split-bf16 MFMA chi0); eps^-1 is FP64 in all. The reported form is
-the fastest whose eps~^-1 stays within 1e-4 (relative Frobenius, worst
-frequency) of the plain FP64 path. Output: one JSON line.
+Every form is timed: plain FP64, FP32 (FP32-MFMA rho and chi0), BF16x3 (split
+bf16 on MFMA: three products, FP32 accumulation) and BF16 (operands rounded to
+bf16, one product, FP32 accumulation); eps^-1 is FP64 in all. The reported form
+is the fastest whose eps~^-1 stays within 1e-4 (relative Frobenius, worst
+frequency) of the plain FP64 path timed in the same run. Output: one JSON line.
 """
 
 from __future__ import annotations
@@ -33,6 +34,10 @@ PEAK = {  # MI355X published peaks
     "valu": 78.6e12,   # fp64 vector; fp32 vector without packed-FP32 instructions
 }
 GATE = 1e-4
+MFMA_PEAK = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"],
+             "bf16": PEAK["bf16_mfma"]}
+DTYPE = {"fp64": "f64", "fp32": "f32 (eps^-1 f64)", "bf16x3": "bf16x3+f32 (eps^-1 f64)",
+         "bf16": "bf16+f32 (eps^-1 f64)"}
 
 
 def chi0_flops(K, ng, nw):
@@ -196,7 +201,7 @@ def roofline(cr, form, K, nw, ng, name=None):
     if name.startswith("chi0_tiles") or name.startswith("chi0_blocks"):
         # one launch of the 16x16 form covers one group of <= 8 frequencies, the block form all of them
         fl = chi0_flops(K, ng, nw if name.startswith("chi0_blocks") else min(nw, 8))
-        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[prec]
+        peak = MFMA_PEAK[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                     frac=fl / t / peak, traffic=measured_traffic(name),
                     note="algorithmic flops 4 NG^2 K per frequency (Hermitian half)")
@@ -209,7 +214,7 @@ def roofline(cr, form, K, nw, ng, name=None):
                     note="useful complex MACs of the z-correlation and pruned y-DFT, 8 flops each")
     if name.startswith("rho_gemm"):
         fl = 8.0 * rho_direct_terms(cr) / k["launches"]   # per launch (all pairs of the step in one)
-        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[prec]
+        peak = MFMA_PEAK[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12,
                     unit="TFLOP/s", frac=fl / t / peak, traffic=measured_traffic(name),
                     note="algorithmic flops: the nonzero terms of the direct plane-wave sum (8 per complex "
@@ -237,26 +242,30 @@ def run_c5(args):
     t_fix = time.perf_counter() - t0
     ng, nw = cr.gmill.shape[0], len(cr.omegas)
     print(f"[bench] c5 fixture built in {t_fix:.1f} s", file=sys.stderr, flush=True)
-    out = {}
-    r3, E3 = run_form(cr, "bf16x3", args.steps, args.warmup)
-    print(f"[bench] c5 bf16x3: {r3['ms_per_step']:.1f} ms/step (rho {r3['t_rho_ms']:.1f}, chi0 {r3['t_chi0_ms']:.1f}, "
-          f"eps {r3['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
-    out["bf16x3"] = r3
-    if "fp64" in args.c5_forms:
-        r64, E64 = run_form(cr, "fp64", 1, 0)
-        print(f"[bench] c5 fp64: {r64['ms_per_step']:.1f} ms/step (rho {r64['t_rho_ms']:.1f}, "
-              f"chi0 {r64['t_chi0_ms']:.1f}, eps {r64['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
-        out["fp64"] = r64
-        r3["e_F_vs_fp64"] = max(float(np.linalg.norm(E3[j] - E64[j]) / np.linalg.norm(E64[j])) for j in range(nw))
-        r3["speedup_vs_fp64"] = r64["ms_per_step"] / r3["ms_per_step"]
-    K = r3["K"]
+    out, Es = {}, {}
+    forms = args.c5_forms.split(",")
+    for prec in [p for p in forms if p != "fp64"] + (["fp64"] if "fp64" in forms else []):
+        steps, warm = (args.steps, args.warmup) if prec != "fp64" else (1, 0)
+        r, Es[prec] = run_form(cr, prec, steps, warm)
+        print(f"[bench] c5 {prec}: {r['ms_per_step']:.1f} ms/step (rho {r['t_rho_ms']:.1f}, chi0 "
+              f"{r['t_chi0_ms']:.1f}, eps {r['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
+        out[prec] = r
+    if "fp64" in out:
+        E64 = Es["fp64"]
+        for prec, r in out.items():
+            if prec != "fp64":
+                r["e_F_vs_fp64"] = max(float(np.linalg.norm(Es[prec][j] - E64[j]) / np.linalg.norm(E64[j]))
+                                       for j in range(nw))
+                r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / r["ms_per_step"]
+                print(f"[bench] c5 {prec}: e_F vs fp64 {r['e_F_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+    K = next(iter(out.values()))["K"]
     fl = chi0_flops(K, ng, nw)
     for prec, r in out.items():
         r["chi0_GFLOPs_over_step"] = fl / (r["ms_per_step"] * 1e-3) / 1e9
         ck = [k for k in r["kernels"] if k.startswith("chi0_tiles") or k.startswith("chi0_blocks")]
         if ck:
             t = sum(r["kernels"][k]["ms_per_step"] for k in ck) * 1e-3
-            peak = PEAK["bf16_mfma"] if prec == "bf16x3" else PEAK["fp64_mfma"]
+            peak = MFMA_PEAK[prec]
             r["chi0_kernel_TFLOPs"] = fl / t / 1e12
             r["chi0_kernel_frac_of_peak"] = fl / t / peak
     res = {"metric": "chi0 GFLOP/s + transitions/s per q,w; speedup vs FP64 at eps^-1 rel err<=1e-4",
@@ -264,7 +273,8 @@ def run_c5(args):
                        f"bands, FFT 72^3, NG={ng}, {nw} imaginary frequencies, K={K} transitions",
            "forms": out, "fixture_s": t_fix,
            "note": "chi0_kernel_frac_of_peak is algorithmic (4 NG^2 K per frequency, Hermitian half) over the "
-                   "dense peak of the executed precision; the split-bf16 form executes three products"}
+                   "dense peak of the executed precision; the split-bf16 form executes three products, "
+                   "the plain-bf16 form one"}
     if args.detail:
         with open(args.detail, "w") as fh:
             json.dump(res, fh, indent=1)
@@ -273,8 +283,8 @@ def run_c5(args):
 
 def run_c3(args):
     """Batched persistent workload: 3x3x3 k-grid, all 27 q-points, uneven G-sets (169..893),
-    32 occupied + 400 empty bands, 48^3 grid, 16 frequencies; bf16x3 rho and chi0 with one
-    persistent chi0 launch over all q (tiles autotuned), FP64 eps^-1 per q."""
+    32 occupied + 400 empty bands, 48^3 grid, 16 frequencies; bf16 (plain and split) rho and
+    chi0 with one persistent chi0 launch over all q (tiles autotuned), FP64 eps^-1 per q."""
     import torch
     from synth.configs import crystal_q_set
     from paper_1902_03837_amd import xo, tune
@@ -381,14 +391,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--forms", default="fp64,fp32,bf16x3")
+    ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16")
     ap.add_argument("--cpu-pairs", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--detail", default=None, help="write the per-form detail JSON here")
     ap.add_argument("--nq", type=int, default=27, help="c3: number of q-points")
-    ap.add_argument("--c3-forms", default="bf16x3,fp64", help="c3: forms to time (fp64 is the reference)")
+    ap.add_argument("--c3-forms", default="bf16,bf16x3,fp64", help="c3: forms to time (fp64 is the reference)")
     ap.add_argument("--tune-cache", default=None, help="c3: JSON file for autotuned launch shapes")
-    ap.add_argument("--c5-forms", default="bf16x3,fp64", help="c5: forms (fp64 gives the error reference)")
+    ap.add_argument("--c5-forms", default="bf16,bf16x3,fp64", help="c5: forms (fp64 gives the error reference)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -431,7 +441,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": fb["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32 (eps^-1 f64)", "bf16x3": "bf16x3+f32 (eps^-1 f64)"}[best],
+        "dtype": DTYPE[best],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: fcc 4x4x4 k, 16 occ + 200 empty bands, FFT 36^3, "
                                f"NG={ng}, {nw} imaginary frequencies, K={K} transitions",

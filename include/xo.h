@@ -18,8 +18,8 @@
  *   as void*; NULL means the default stream) unless its comment says it
  *   synchronises.
  * - Complex numbers are interleaved (re, im). Precision XO_FP64 uses complex128
- *   (two doubles); XO_FP32 and XO_BF16X3 use complex64 (two floats) for rho and
- *   orbital coefficients. chi0 and eps^-1 are always complex128.
+ *   (two doubles); XO_FP32, XO_BF16X3 and XO_BF16 use complex64 (two floats) for
+ *   rho and orbital coefficients. chi0 and eps^-1 are always complex128.
  * - Miller triples are int32 [n][3]; the reciprocal vector is m . (b1,b2,b3).
  *   The FFT index of m on an N1 x N2 x N3 grid is m mod N.
  * - Return values: XO_OK or an error code; xo_last_error() then holds a
@@ -48,7 +48,16 @@ enum {
   XO_ERR_UNSUPPORTED = 5   /* size or option outside what the kernels handle   */
 };
 
-enum { XO_FP64 = 0, XO_FP32 = 1, XO_BF16X3 = 2 };
+/* Arithmetic of rho and chi0 (eps^-1 is FP64 in every form):
+ *   XO_FP64   FP64 throughout (complex128 rho and orbitals);
+ *   XO_FP32   FP32 MFMA / VALU (complex64);
+ *   XO_BF16X3 complex64 data, each MFMA operand split into bf16 hi + lo and
+ *             three products hi*hi + hi*lo + lo*hi, FP32 accumulation;
+ *   XO_BF16   complex64 data, each MFMA operand rounded to bf16 (2^-9 relative)
+ *             and one product, FP32 accumulation. Its eps^-1 error depends on
+ *             the number of transitions averaging the operand rounding; callers
+ *             check it against an FP64 run of their workload. */
+enum { XO_FP64 = 0, XO_FP32 = 1, XO_BF16X3 = 2, XO_BF16 = 3 };
 
 /* Thread-local message describing the last error of this thread ("" if none). */
 const char* xo_last_error(void);
@@ -91,7 +100,7 @@ int xo_timing_report(char* buf, int len);
 typedef struct {
   int n[3];                 /* FFT grid                                        */
   double bvec[9];           /* [host] rows b1,b2,b3 in 1/bohr (q0 velocities)  */
-  int prec;                 /* XO_FP64 / XO_FP32 / XO_BF16X3 (see xo_rho_batch) */
+  int prec;                 /* XO_FP64 / XO_FP32 / XO_BF16X3 / XO_BF16 (see xo_rho_batch) */
   /* bra: conduction bands at k */
   int npw_c;
   const int32_t* mill_c;    /* [host] [npw_c][3]                               */
@@ -126,10 +135,11 @@ int xo_rho(const xo_rho_args* a, void* stream);
  * gathered matrix product (equal to the transform on the alias-free grids that
  * validation requires), when every pair's gather box and the valence bands of a
  * workgroup fit in LDS: FP64 and FP32 on the 16x16x4 MFMAs of their precision,
- * XO_BF16X3 as split bf16 (hi + lo, three products, FP32 accumulation).
- * Otherwise XO_BF16X3 batches take the axis-factorised transform on MFMA
- * (orbitals real-space along x, y-z correlation of Miller spectra, x-DFT in
- * FP32) and FP64 / FP32 pairs the VALU transform, pair by pair. The environment
+ * XO_BF16X3 as split bf16 (hi + lo, three products, FP32 accumulation), XO_BF16
+ * as plain bf16 (one product, FP32 accumulation).
+ * Otherwise XO_BF16X3 and XO_BF16 batches take the axis-factorised split-bf16
+ * transform on MFMA (orbitals real-space along x, y-z correlation of Miller
+ * spectra, x-DFT in FP32) and FP64 / FP32 pairs the VALU transform, pair by pair. The environment
  * variable XO_RHO_KERNEL=gemm or =transform, read on each call, restricts the
  * choice to one of the two. q0 pairs take the same kernels; their G = 0 column
  * is then written from the velocity sum (accumulated in FP64). */
@@ -152,7 +162,9 @@ int xo_rho_batch(const xo_rho_args* pairs, int npairs, void* stream);
  * prec: XO_FP64 (FP64 MFMA), XO_FP32 (FP32 MFMA, FP32 accumulation within a
  *      transition chunk, FP64 across chunks), XO_BF16X3 (each operand split
  *      into bf16 hi + lo, three bf16 MFMA products hi*hi + hi*lo + lo*hi,
- *      FP32 accumulation within a chunk, FP64 across chunks).
+ *      FP32 accumulation within a chunk, FP64 across chunks), XO_BF16 (each
+ *      operand rounded to bf16, one product, FP32 accumulation within a chunk,
+ *      FP64 across chunks).
  */
 typedef struct {
   int nt, ng, nw;
@@ -177,12 +189,12 @@ int xo_chi0(const xo_chi0_args* a, void* stream);
  * not depend on the schedule and equals xo_chi0 on each item up to the order
  * of the FP64 partial sums. Blocks: nt_tiles 1 or 2 gives 16-row x 16*nt_tiles-
  * column blocks with up to 8 frequencies per unit, one wave per transition
- * quarter; nt_tiles 4 (XO_BF16X3 only) gives 64 x 64 blocks with 4 frequencies
- * per unit and the right operand split once per workgroup in LDS. With
- * nt_tiles 0 XO_BF16X3 takes the 64 x 64 form when there are at least four
- * frequencies, every other case 16 x 16. items: [host] array. */
+ * quarter; nt_tiles 4 (XO_BF16X3 and XO_BF16 only) gives 64 x 64 blocks with 4
+ * frequencies per unit and the right operand converted once per workgroup in
+ * LDS. With nt_tiles 0 the bf16 forms take the 64 x 64 form when there are at
+ * least four frequencies, every other case 16 x 16. items: [host] array. */
 typedef struct {
-  int nt_tiles;   /* 0 (default), 1, 2, or 4 (XO_BF16X3 only)                     */
+  int nt_tiles;   /* 0 (default), 1, 2, or 4 (XO_BF16X3 / XO_BF16 only)           */
   int kper;       /* transitions per unit; 0 = chosen to fill the chip            */
   int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 2 (64 x 64), 4   */
 } xo_tune;

@@ -1,9 +1,10 @@
-// Split-bf16 ("bf16 x 3") helpers shared by the MFMA kernels.
+// Split-bf16 ("bf16 x 3") and plain-bf16 helpers shared by the MFMA kernels.
 //
 // A float x is carried as hi = bf16(x) and lo = bf16(x - hi) (round to nearest
 // even); a product is formed as hi*hi + hi*lo + lo*hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation, dropping the lo*lo term
-// (about 2^-16 relative). Complex numbers are packed as (re, im) bf16 pairs in
+// (about 2^-16 relative). The plain form keeps hi only and forms hi*hi (operand
+// rounding 2^-9 relative). Complex numbers are packed as (re, im) bf16 pairs in
 // one 32-bit word, element 0 in the low half.
 #pragma once
 
@@ -39,6 +40,16 @@ __device__ __forceinline__ f4 mma3(u4 ah, u4 al, u4 bh, u4 bl, f4 c) {
   c = mma(ah, bl, c);
   c = mma(al, bh, c);
   return c;
+}
+
+// NP products per operand pair: 3 (split) or 1 (plain, the lo words unused)
+template <int NP>
+__device__ __forceinline__ f4 mma_np(u4 ah, u4 al, u4 bh, u4 bl, f4 c) {
+  static_assert(NP == 1 || NP == 3, "one or three products");
+  if constexpr (NP == 3)
+    return mma3(ah, al, bh, bl, c);
+  else
+    return mma(ah, bh, c);
 }
 
 }  // namespace xo

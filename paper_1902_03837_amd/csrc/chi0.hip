@@ -41,7 +41,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kTile = 16;
 constexpr int kFp32Slice = 65536;  // longest transition slice accumulated in FP32 by default
 constexpr int kWaves = 4;
-constexpr int MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2;
+constexpr int MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2, MODE_BF16 = 3;
+// bf16 forms: products per operand pair (3 split, 1 plain)
+constexpr bool is_bf(int mode) { return mode == MODE_BF16X3 || mode == MODE_BF16; }
+constexpr int nprod(int mode) { return mode == MODE_BF16X3 ? 3 : 1; }
 
 __device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -105,7 +108,8 @@ __device__ __forceinline__ void unit_wave(const Item& I, int2 bij, int w0, int k
   const int i = lane & 15;
   const int Gi = bij.x * kTile + i;
   const bool gi_ok = Gi < I.ng;
-  if constexpr (MODE == MODE_BF16X3) {
+  if constexpr (is_bf(MODE)) {
+    constexpr int NP = nprod(MODE);
     const int q = lane >> 4;  // lane holds k = 8q .. 8q+7 -> transitions 4q .. 4q+3, (re, im)
     const cplx<float>* rho = static_cast<const cplx<float>*>(I.rho);
     const float* W = static_cast<const float*>(I.W) + w0;
@@ -150,8 +154,8 @@ __device__ __forceinline__ void unit_wave(const Item& I, int2 bij, int w0, int k
         const u4 iml = u4{rot_pos(l[0]), rot_pos(l[1]), rot_pos(l[2]), rot_pos(l[3])};
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          acc[w][0][n] = mma3(reh, rel, bh[n], bl[n], acc[w][0][n]);
-          acc[w][1][n] = mma3(imh, iml, bh[n], bl[n], acc[w][1][n]);
+          acc[w][0][n] = mma_np<NP>(reh, rel, bh[n], bl[n], acc[w][0][n]);
+          acc[w][1][n] = mma_np<NP>(imh, iml, bh[n], bl[n], acc[w][1][n]);
         }
       }
     }
@@ -315,7 +319,7 @@ __global__ void chi0_reduce(const Item* __restrict__ items, const int2* __restri
   }
 }
 
-// Block form of the split-bf16 update. A workgroup owns a 64 x 64 output block
+// Block form of the bf16 update (NP = 3 split, 1 plain). A workgroup owns a 64 x 64 output block
 // and four frequencies per unit; wave r owns rows 16 r .. 16 r + 15 and all four
 // 16-column tiles. Each step of 16 transitions stages the raw left rows, the
 // frequency factors and the right operand (split once, in fragment order) in LDS,
@@ -325,6 +329,7 @@ constexpr int kBlk = 64;
 constexpr int kBW = 4;  // frequencies per unit in the block form
 constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 
+template <int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
             const int* __restrict__ queue, int nunits, int* __restrict__ counter, float* __restrict__ part) {
@@ -371,8 +376,12 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       oa[u] = ((unsigned)(4 * aq + u) * ng + Ga) * sizeof(f2v);
       ob[u] = ((unsigned)(4 * fq + u) * ng + Gb) * sizeof(f2v);
     }
+    // frequency factors (wave 0): transition wt of the step, frequency tid / 16; rows past
+    // the slice read its last row and are zeroed when stored, so that no wait for the
+    // load sits between its issue and the products
     const int wt = tid & 15;
     const unsigned ow = ((unsigned)wt * I.nwpad + (tid >> 4)) * sizeof(float);
+    const unsigned wmax = ((unsigned)(len - 1) * I.nwpad + (tid >> 4)) * sizeof(float);
 
     f2v ra[4], rb[4];
     float wv = 0.f;
@@ -384,25 +393,21 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         ra[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                      \
         rb[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                      \
       }                                                                                       \
-      if (wave == 0) {                                                                        \
-        const bool in_ = 16 * (s_) + wt < len;                                                \
-        const float x_ = gld<float>(wbase + (in_ ? ow + (unsigned)(s_) * wstep : 0u));         \
-        wv = in_ ? x_ : 0.f;                                                                  \
-      }                                                                                       \
+      if (wave == 0) wv = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));        \
     }
-    // ---- store the loaded step into buffer b
-#define CHI0_BLK_STORE(b_)                                                                    \
+    // ---- store the loaded step s into buffer b
+#define CHI0_BLK_STORE(b_, s_)                                                                \
     {                                                                                         \
       uint32_t h_[4], l_[4];                                                                  \
       _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);   \
       Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                 \
-      Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                                 \
+      if constexpr (NP == 3) Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};          \
       As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                    \
       As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                \
-      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[tid & 15] = wv;           \
+      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[wt] = 16 * (s_) + wt < len ? wv : 0.f; \
     }
     CHI0_BLK_LOAD(0);
-    CHI0_BLK_STORE(0);
+    CHI0_BLK_STORE(0, 0);
     __syncthreads();
     f4 acc[kBW][2][4];
 #pragma unroll
@@ -415,7 +420,7 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       const int buf = k & 1;
       if (k + 1 < nsteps) CHI0_BLK_LOAD(k + 1);
       if (nmask) {
-        // weighted left operand of every frequency, split once and shared by the column tiles
+        // weighted left operand of every frequency, converted once and shared by the column tiles
         const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
         u4 ah[kBW], al[kBW];
 #pragma unroll
@@ -431,13 +436,14 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         }
         // column tiles: Re through the right operand, Im through its rotation (-im, re),
         // rotated in registers; the next tile's operand is read ahead of the products
-        u4 bh = Bs[buf][0][0][q][i], bl = Bs[buf][1][0][q][i];
+        u4 bh = Bs[buf][0][0][q][i], bl = bh;
+        if constexpr (NP == 3) bl = Bs[buf][1][0][q][i];
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
           u4 nbh = bh, nbl = bl;
           if (n < 3) {
             nbh = Bs[buf][0][n + 1][q][i];
-            nbl = Bs[buf][1][n + 1][q][i];
+            if constexpr (NP == 3) nbl = Bs[buf][1][n + 1][q][i];
           }
           if (nmask & (1 << n)) {
             u4 rh, rl;
@@ -448,15 +454,15 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
             }
 #pragma unroll
             for (int w = 0; w < kBW; ++w) {
-              acc[w][0][n] = mma3(ah[w], al[w], bh, bl, acc[w][0][n]);
-              acc[w][1][n] = mma3(ah[w], al[w], rh, rl, acc[w][1][n]);
+              acc[w][0][n] = mma_np<NP>(ah[w], al[w], bh, bl, acc[w][0][n]);
+              acc[w][1][n] = mma_np<NP>(ah[w], al[w], rh, rl, acc[w][1][n]);
             }
           }
           bh = nbh;
           bl = nbl;
         }
       }
-      if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1);
+      if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1, k + 1);
       __syncthreads();
     }
 #undef CHI0_BLK_LOAD
@@ -548,8 +554,8 @@ static int validate(const xo_chi0_args* a, bool signed_pref) {
          a->ng, a->nw);
   XO_ARG(a->nw <= 64, "xo_chi0: at most 64 frequencies per call (got %d)", a->nw);
   XO_ARG(a->rho && a->dE && a->w && a->chi0, "xo_chi0: null pointer");
-  XO_ARG(a->prec == XO_FP64 || a->prec == XO_FP32 || a->prec == XO_BF16X3, "xo_chi0: bad precision %d",
-         a->prec);
+  XO_ARG(a->prec == XO_FP64 || a->prec == XO_FP32 || a->prec == XO_BF16X3 || a->prec == XO_BF16,
+         "xo_chi0: bad precision %d", a->prec);
   for (int j = 0; j < a->nw; ++j) XO_ARG(a->w[j] >= 0.0, "xo_chi0: frequency %d is negative", j);
   XO_ARG(signed_pref ? (a->pref != 0.0 && std::isfinite(a->pref)) : a->pref > 0.0, "xo_chi0: pref must be positive");
   return XO_OK;
@@ -562,7 +568,8 @@ static int launch_units(const void* ditems, const void* dtiles, const void* duni
   hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 1);
   XO_CHECK_LAUNCH();
   {
-    KernelTimer kt_(MODE == MODE_BF16X3 ? "chi0_tiles_bf16x3" : "chi0_tiles", s);
+    KernelTimer kt_(MODE == MODE_BF16X3 ? "chi0_tiles_bf16x3" : (MODE == MODE_BF16 ? "chi0_tiles_bf16" : "chi0_tiles"),
+                    s);
     hipLaunchKernelGGL((chi0_units<MODE, NWG, NT>), dim3(grid), dim3(256), 0, s,
                        static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
                        static_cast<const Unit*>(dunits), static_cast<const int*>(dqueue), nunits, counter, part);
@@ -581,7 +588,7 @@ static int launch_units(const void* ditems, const void* dtiles, const void* duni
 template <int MODE, int NWG>
 static int launch_nt(int nt_tiles, const void* ditems, const void* dtiles, const void* dunits, const void* dqueue,
                      int nunits, int* counter, void* part, const void* dreds, int nreds, int grid, hipStream_t s) {
-  if constexpr (MODE == MODE_BF16X3) {
+  if constexpr (is_bf(MODE)) {
     if (nt_tiles == 2)
       return launch_units<MODE, NWG, 2>(ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
                                         s);
@@ -615,15 +622,15 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     for (int j = 0; j < a[0].nw; ++j)
       XO_ARG(a[i].w[j] == a[0].w[j], "xo_chi0_batch: items must share the frequency list");
   }
-  const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : MODE_BF16X3);
+  const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : (prec == XO_BF16 ? MODE_BF16 : MODE_BF16X3));
   const size_t tsz = mode == MODE_F64 ? sizeof(double) : sizeof(float);
   const int nw = a[0].nw;
-  // split-bf16 default: the 64 x 64 block form once there are four frequencies to share it
-  const bool blk = mode == MODE_BF16X3 && ((tune && tune->nt_tiles) ? tune->nt_tiles == 4 : nw >= kBW);
+  // bf16 default: the 64 x 64 block form once there are four frequencies to share it
+  const bool blk = is_bf(mode) && ((tune && tune->nt_tiles) ? tune->nt_tiles == 4 : nw >= kBW);
   const int nwg = blk ? kBW : (nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1)));
   const int ngroups = (nw + nwg - 1) / nwg;
   const int nwpad = ngroups * nwg;
-  const int NT = (tune && mode == MODE_BF16X3 && tune->nt_tiles == 2) ? 2 : 1;
+  const int NT = (tune && is_bf(mode) && tune->nt_tiles == 2) ? 2 : 1;
   const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4);
   const int brow = blk ? kBlk : kTile, bcol = blk ? kBlk : kTile * NT;
 
@@ -659,7 +666,7 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
       kper = (int)((a[it].nt + slices - 1) / slices);
     }
     kper = std::max(64, (kper + 63) / 64 * 64);
-    // FP32 accumulators (FP32 and split-bf16 forms): at most kFp32Slice transitions per
+    // FP32 accumulators (FP32 and bf16 forms): at most kFp32Slice transitions per
     // unit, so the rounding of the running sums stays bounded and the FP64 reduction
     // adds many short partial sums
     if (mode != MODE_F64 && !(tune && tune->kper > 0)) kper = std::min(kper, kFp32Slice);
@@ -762,9 +769,14 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   if (blk) {
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 1);
     XO_CHECK_LAUNCH();
-    {
+    if (mode == MODE_BF16) {
+      KernelTimer kt_("chi0_blocks_bf16", s);
+      hipLaunchKernelGGL(chi0_blocks<1>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
+                         static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
+                         static_cast<const int*>(dqueue), nunits, counter, static_cast<float*>(part));
+    } else {
       KernelTimer kt_("chi0_blocks_bf16x3", s);
-      hipLaunchKernelGGL(chi0_blocks, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
+      hipLaunchKernelGGL(chi0_blocks<3>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
                          static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
                          static_cast<const int*>(dqueue), nunits, counter, static_cast<float*>(part));
     }
@@ -784,6 +796,9 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   if (mode == MODE_F32)
     return launch_nwg<MODE_F32>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
                                 s);
+  if (mode == MODE_BF16)
+    return launch_nwg<MODE_BF16>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
+                                 s);
   return launch_nwg<MODE_BF16X3>(nwg, NT, ditems, dtiles, dunits, dqueue, nunits, counter, part, dreds, nreds, grid,
                                  s);
 }
@@ -808,7 +823,8 @@ extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tu
   if (tune) {
     XO_ARG(tune->nt_tiles == 0 || tune->nt_tiles == 1 || tune->nt_tiles == 2 || tune->nt_tiles == 4,
            "xo_chi0_batch: nt_tiles must be 0, 1, 2 or 4");
-    XO_ARG(tune->nt_tiles != 4 || items[0].prec == XO_BF16X3, "xo_chi0_batch: nt_tiles 4 is the XO_BF16X3 block form");
+    XO_ARG(tune->nt_tiles != 4 || items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16,
+           "xo_chi0_batch: nt_tiles 4 is the bf16 block form (XO_BF16X3, XO_BF16)");
     XO_ARG(tune->kper >= 0 && tune->wg_per_cu >= 0 && tune->wg_per_cu <= 16, "xo_chi0_batch: bad tune values");
   }
   return xo::chi0_batch_run(items, n, tune, static_cast<hipStream_t>(stream));
@@ -820,7 +836,7 @@ extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best,
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<xo_tune> cands;
   std::vector<int> nts = {1};
-  if (items[0].prec == XO_BF16X3) nts = {1, 2, 4};
+  if (items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16) nts = {1, 2, 4};
   int ntmax = 0;
   for (int i = 0; i < n; ++i) ntmax = std::max(ntmax, items[i].nt);
   for (int nt : nts)

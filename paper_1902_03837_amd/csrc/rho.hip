@@ -429,8 +429,8 @@ int validate_rho(const xo_rho_args* a, Extent* pxc, Extent* pxv, Extent* pxe) {
          a->nv, a->ng);
   XO_ARG(a->mill_c && a->mill_v && a->mill_g, "xo_rho: Miller lists must be host arrays");
   XO_ARG(a->coef_c && a->coef_v && a->rho, "xo_rho: null device pointer");
-  XO_ARG(a->prec == XO_FP64 || a->prec == XO_FP32 || a->prec == XO_BF16X3, "xo_rho: bad precision %d",
-         a->prec);
+  XO_ARG(a->prec == XO_FP64 || a->prec == XO_FP32 || a->prec == XO_BF16X3 || a->prec == XO_BF16,
+         "xo_rho: bad precision %d", a->prec);
   XO_ARG(!a->dE || (a->e_c && a->e_v), "xo_rho: dE requested without band energies");
   Extent xc = extent_of(a->mill_c, a->npw_c, nullptr);
   Extent xv = extent_of(a->mill_v, a->npw_v, nullptr);

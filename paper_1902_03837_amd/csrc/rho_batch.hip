@@ -726,7 +726,7 @@ int rho_batch(const xo_rho_args* p, int n, hipStream_t s) {
   for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
   if (mfma_eligible(p, n)) {
     const int choice = rho_kernel_choice();
-    if (p[0].prec == XO_BF16X3) {
+    if (p[0].prec == XO_BF16X3 || p[0].prec == XO_BF16) {
       if (choice != 2) {
         int r = rho_batch_gemm(p, n, xc.data(), xv.data(), xe.data(), s);
         if (r != XO_ERR_UNSUPPORTED) return r;

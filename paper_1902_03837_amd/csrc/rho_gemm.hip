@@ -1,5 +1,5 @@
-// Oscillator strengths as a gathered matrix product on MFMA (split bf16, FP32
-// accumulation), many k-pairs per launch.
+// Oscillator strengths as a gathered matrix product on MFMA (split or plain bf16,
+// FP32 accumulation; FP64 / FP32 further down), many k-pairs per launch.
 //
 // With both orbitals expanded in plane waves, the cell-averaged transform of
 // the product conj(psi_c) psi_v (Eq. rhotw, the umklapp vector G0 from
@@ -26,8 +26,9 @@
 // Complex operands: the right operand holds (re, im) of c_c; the left operand
 // of Re rho holds (re, im) of c_v and that of Im rho (im, -re), so that
 // sum (vr cr + vi ci) = Re(conj(c) v) and sum (vi cr - vr ci) = Im(conj(c) v).
-// Every FP32 value x enters as hi = bf16(x), lo = bf16(x - hi); a product is
-// hi*hi + hi*lo + lo*hi, accumulated in FP32.
+// Split form (NP = 3): every FP32 value x enters as hi = bf16(x), lo = bf16(x - hi);
+// a product is hi*hi + hi*lo + lo*hi, accumulated in FP32. Plain form (NP = 1):
+// hi only, one product; coefficients then take one 32-bit word instead of two.
 
 #include <algorithm>
 #include <cstring>
@@ -55,13 +56,15 @@ constexpr size_t kLdsMax = 160 * 1024;
 
 typedef int i4 __attribute__((ext_vector_type(4)));
 
-// Split coefficients of one band set: [nb][npwp] (hi, lo) pairs, zero for j >= npw.
+// Converted coefficients of one band set: [nb][npwp] entries, zero for j >= npw;
+// an entry is the (hi, lo) word pair (NP = 3) or the hi word (NP = 1).
 struct SplitDesc {
   const float2* src;  // [nb][npw]
-  uint2* dst;
+  uint32_t* dst;
   int nb, npw, npwp;
 };
 
+template <int NP>
 __global__ void __launch_bounds__(kThreads) orb_split(const SplitDesc* __restrict__ d) {
   const SplitDesc D = d[blockIdx.y];
   const int n = D.nb * D.npwp;
@@ -70,13 +73,16 @@ __global__ void __launch_bounds__(kThreads) orb_split(const SplitDesc* __restric
     const float2 v = j < D.npw ? D.src[(size_t)b * D.npw + j] : make_float2(0.f, 0.f);
     uint32_t h, l;
     split2(v.x, v.y, h, l);
-    D.dst[i] = make_uint2(h, l);
+    if constexpr (NP == 3)
+      reinterpret_cast<uint2*>(D.dst)[i] = make_uint2(h, l);
+    else
+      D.dst[i] = h;
   }
 }
 
 struct GemmPair {
-  const uint2* Sc;  // conduction split coefficients [nc][npwc]
-  const uint2* Sv;  // valence [nv][npwv]; entry npw_v of each row is zero
+  const uint32_t* Sc;  // conduction converted coefficients [nc][npwc] entries
+  const uint32_t* Sv;  // valence [nv][npwv] entries; entry npw_v of each row is zero
   float2* rho;      // [nv][nc][ng]
   const int* Oa;    // [nK * 16] box offset of each conduction plane wave (a valid offset for padding)
   const int* Oe;    // [ng] box offset of -e = G0 - m_G
@@ -90,8 +96,10 @@ struct GemmPair {
   int wg0;          // first logical workgroup of the pair
 };
 
+template <int NP>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
+  constexpr int kW = NP == 3 ? 2 : 1;  // 32-bit words per coefficient
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous
   // logical range, so a pair's tables and coefficients stay in that XCD's L2.
@@ -113,8 +121,8 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   const int npwv = P.npwv, npwc = P.npwc, nK = P.nK;
 
   u4* Bs = reinterpret_cast<u4*>(smem);                                // [2][2][kCT][4][16]
-  uint2* Vs = reinterpret_cast<uint2*>(smem + kBsBytes);                // [vhi - vlo + 1][npwv]
-  const int nvs = (vhi - vlo + 1) * npwv;                              // a multiple of 16
+  uint32_t* Vs = reinterpret_cast<uint32_t*>(smem + kBsBytes);          // [vhi - vlo + 1][npwv] entries
+  const int nvs = (vhi - vlo + 1) * npwv * kW;                         // words, a multiple of 16
   uint16_t* Ts = reinterpret_cast<uint16_t*>(Vs + nvs);                 // [ncell]
 
   const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
@@ -123,8 +131,8 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   // ---- box table and the valence bands of this workgroup's rows into LDS
   for (int k = tid; k < P.ncell / 8; k += kThreads) reinterpret_cast<u4*>(Ts)[k] = gld<u4>(P.T + k);
   {
-    const u4* src = reinterpret_cast<const u4*>(P.Sv + (size_t)vlo * npwv);
-    for (int k = tid; k < nvs / 2; k += kThreads) reinterpret_cast<u4*>(Vs)[k] = gld<u4>(src + k);
+    const u4* src = reinterpret_cast<const u4*>(P.Sv + (size_t)vlo * npwv * kW);
+    for (int k = tid; k < nvs / 4; k += kThreads) reinterpret_cast<u4*>(Vs)[k] = gld<u4>(src + k);
   }
 
   // ---- rows of this lane: row tile rt holds rows r0 + 32 w + 16 rt + (0..15); lane i gathers row i
@@ -141,24 +149,29 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   // ---- right operand staging: slot s = tid + 256 f is (tile s / 64, quad (s / 16) % 4, column s % 16).
   // Columns past the group or the band count read a valid row (clamped); their
   // products land in outputs that are never stored.
+  // (split: two 16-byte loads of (hi, lo) pairs per slot; plain: one of hi words)
   u4 raw[2][2];
-  const uint2* sp[2];
+  const uint32_t* sp[2];
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     const int s = tid + kThreads * f;
     const int sq = (s >> 4) & 3, c = min((ct0 + (s >> 6)) * 16 + (s & 15), P.nc - 1);
-    sp[f] = P.Sc + (size_t)c * npwc + 4 * sq;
+    sp[f] = P.Sc + ((size_t)c * npwc + 4 * sq) * kW;
   }
 #define RHO_GEMM_LOAD(k_)                                                         \
   _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
-    raw[f][0] = gld<u4>(sp[f] + 16 * (k_));                                       \
-    raw[f][1] = gld<u4>(sp[f] + 16 * (k_) + 2);                                   \
+    raw[f][0] = gld<u4>(sp[f] + 16 * kW * (k_));                                  \
+    if constexpr (NP == 3) raw[f][1] = gld<u4>(sp[f] + 16 * kW * (k_) + 4);       \
   }
 #define RHO_GEMM_STORE(b_)                                                        \
   _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
     const int s_ = tid + kThreads * f;                                            \
-    Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = u4{raw[f][0].x, raw[f][0].z, raw[f][1].x, raw[f][1].z}; \
-    Bs[((b_) * 2 + 1) * (kCT * 64) + s_] = u4{raw[f][0].y, raw[f][0].w, raw[f][1].y, raw[f][1].w}; \
+    if constexpr (NP == 3) {                                                      \
+      Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = u4{raw[f][0].x, raw[f][0].z, raw[f][1].x, raw[f][1].z}; \
+      Bs[((b_) * 2 + 1) * (kCT * 64) + s_] = u4{raw[f][0].y, raw[f][0].w, raw[f][1].y, raw[f][1].w}; \
+    } else {                                                                      \
+      Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = raw[f][0];                           \
+    }                                                                             \
   }
 
   RHO_GEMM_LOAD(0);
@@ -169,23 +182,23 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   __syncthreads();
 
   // Gathered left operand of this lane's rows, c_v(a - e) for a = 16 k + 4 q + (0..3)
-  // (hi and lo read as two words, straight into the operand registers). The box
+  // (hi and lo read as words, straight into the operand registers). The box
   // table and valence bands do not change during the loop, so the next step's
   // gather is issued while this step's products run.
-  const uint32_t* Vw = reinterpret_cast<const uint32_t*>(Vs);
+  const uint32_t* Vw = Vs;
   auto gather = [&](i4 oa, u4* gh, u4* gl) {
 #pragma unroll
     for (int rt = 0; rt < kRT; ++rt) {
       const int o[4] = {oa.x, oa.y, oa.z, oa.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int j = 2 * (vb[rt] + Ts[o[u] + oe[rt]]);
+        const int j = kW * (vb[rt] + Ts[o[u] + oe[rt]]);
         gh[rt][u] = Vw[j];
-        gl[rt][u] = Vw[j + 1];
+        if constexpr (NP == 3) gl[rt][u] = Vw[j + 1];
       }
     }
   };
-  u4 ah[kRT], al[kRT];
+  u4 ah[kRT], al[kRT] = {};
   gather(oa1, ah, al);
   oa1 = oa2;
 
@@ -202,7 +215,7 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
       oa2 = gld<i4>(P.Oa + 16 * min(k + 2, nK - 1) + 4 * q);
     }
     // next step's gather (the last step re-gathers valid offsets, unused)
-    u4 nah[kRT], nal[kRT];
+    u4 nah[kRT], nal[kRT] = {};
     gather(oa1, nah, nal);
     // Im operand: (im, -re) of the gathered values
     u4 bh[kRT], bl[kRT];
@@ -218,11 +231,13 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
 #pragma unroll
     for (int ct = 0; ct < kCT; ++ct) {
       if (ct < nt) {
-        const u4 ch = Bh[ct * 64], cl = Bl[ct * 64];
+        const u4 ch = Bh[ct * 64];
+        u4 cl = ch;
+        if constexpr (NP == 3) cl = Bl[ct * 64];
 #pragma unroll
         for (int rt = 0; rt < kRT; ++rt) {
-          re[rt][ct] = mma3(ah[rt], al[rt], ch, cl, re[rt][ct]);
-          im[rt][ct] = mma3(bh[rt], bl[rt], ch, cl, im[rt][ct]);
+          re[rt][ct] = mma_np<NP>(ah[rt], al[rt], ch, cl, re[rt][ct]);
+          im[rt][ct] = mma_np<NP>(bh[rt], bl[rt], ch, cl, im[rt][ct]);
         }
       }
     }
@@ -570,10 +585,13 @@ inline int padded_row(int npw) { return (npw + 1 + 15) / 16 * 16; }
 
 }  // namespace
 
-// The batch on the gathered-product kernel, or XO_ERR_UNSUPPORTED (nothing
-// enqueued) when a pair's tables do not fit in LDS. All pairs share ng and the G-set.
-int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
-                   hipStream_t s) {
+// The batch on the gathered-product kernel (NP = 3 split, 1 plain bf16), or
+// XO_ERR_UNSUPPORTED (nothing enqueued) when a pair's tables do not fit in LDS.
+// All pairs share ng and the G-set.
+template <int NP>
+static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                            hipStream_t s) {
+  constexpr int kW = NP == 3 ? 2 : 1;
   const int ng = p[0].ng;
   std::vector<const GemmGeo*> ge(n);
   size_t lds = 0;
@@ -585,7 +603,7 @@ int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* 
     const int nrows = p[i].nv * ng;
     for (int r0 = 0; r0 < nrows; r0 += kRows)
       nbs = std::max(nbs, std::min(p[i].nv - 1, (r0 + kRows - 1) / ng) - r0 / ng + 1);
-    const size_t need = kBsBytes + (size_t)nbs * padded_row(p[i].npw_v) * sizeof(uint2) + ge[i]->T.size() * 2;
+    const size_t need = kBsBytes + (size_t)nbs * padded_row(p[i].npw_v) * kW * 4 + ge[i]->T.size() * 2;
     lds = std::max(lds, need);
   }
   if (lds > kLdsMax) return XO_ERR_UNSUPPORTED;
@@ -612,18 +630,18 @@ int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* 
     add(p[i].coef_v, p[i].nv, p[i].npw_v);
   }
   void* ws = nullptr;
-  XO_RET(workspace(s, 3, tot * sizeof(uint2), &ws));
-  uint2* S0 = static_cast<uint2*>(ws);
+  XO_RET(workspace(s, 3, tot * kW * 4, &ws));
+  uint32_t* S0 = static_cast<uint32_t*>(ws);
   int maxn = 0;
   for (auto& d : sd) {
-    d.dst = S0 + sets[std::make_tuple(static_cast<const void*>(d.src), d.nb, d.npw)];
+    d.dst = S0 + sets[std::make_tuple(static_cast<const void*>(d.src), d.nb, d.npw)] * kW;
     maxn = std::max(maxn, d.nb * d.npwp);
   }
   const void* dsd = nullptr;
   XO_RET(device_table(sd.data(), sd.size() * sizeof(SplitDesc), s, &dsd));
   {
     KernelTimer kt_("orb_split", s);
-    hipLaunchKernelGGL(orb_split, dim3(std::min(256, (maxn + kThreads - 1) / kThreads), (unsigned)sd.size()),
+    hipLaunchKernelGGL(orb_split<NP>, dim3(std::min(256, (maxn + kThreads - 1) / kThreads), (unsigned)sd.size()),
                        dim3(kThreads), 0, s, static_cast<const SplitDesc*>(dsd));
   }
   XO_CHECK_LAUNCH();
@@ -633,8 +651,8 @@ int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* 
   for (int i = 0; i < n; ++i) {
     const GemmGeo& g = *ge[i];
     GemmPair& d = gp[i];
-    d.Sc = S0 + sets[std::make_tuple(p[i].coef_c, p[i].nc, p[i].npw_c)];
-    d.Sv = S0 + sets[std::make_tuple(p[i].coef_v, p[i].nv, p[i].npw_v)];
+    d.Sc = S0 + sets[std::make_tuple(p[i].coef_c, p[i].nc, p[i].npw_c)] * kW;
+    d.Sv = S0 + sets[std::make_tuple(p[i].coef_v, p[i].nv, p[i].npw_v)] * kW;
     d.rho = static_cast<float2*>(p[i].rho);
     d.Oa = static_cast<const int*>(g.dOa);
     d.Oe = static_cast<const int*>(g.dOe);
@@ -654,15 +672,21 @@ int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* 
   const void* dgp = nullptr;
   XO_RET(device_table(gp.data(), gp.size() * sizeof(GemmPair), s, &dgp));
   if (lds > 64 * 1024)
-    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm),
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm<NP>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
-    KernelTimer kt_("rho_gemm", s);
-    hipLaunchKernelGGL(rho_gemm, dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
+    KernelTimer kt_(NP == 3 ? "rho_gemm" : "rho_gemm_bf16", s);
+    hipLaunchKernelGGL(rho_gemm<NP>, dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
                        static_cast<const GemmPair*>(dgp), n, nwg, ng);
   }
   XO_CHECK_LAUNCH();
   return rho_batch_finish(p, n, s);
+}
+
+int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                   hipStream_t s) {
+  if (p[0].prec == XO_BF16) return rho_batch_gemm_t<1>(p, n, xc, xv, xe, s);
+  return rho_batch_gemm_t<3>(p, n, xc, xv, xe, s);
 }
 
 

@@ -14,7 +14,7 @@ import torch
 
 from . import xo
 
-CDTYPE = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16x3": torch.complex64}
+CDTYPE = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16x3": torch.complex64, "bf16": torch.complex64}
 
 
 @dataclass

@@ -17,10 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxo.so")
 
 XO_OK, XO_ERR_ARG, XO_ERR_ALLOC, XO_ERR_HIP, XO_ERR_NOTPD, XO_ERR_UNSUPPORTED = range(6)
-XO_FP64, XO_FP32, XO_BF16X3 = 0, 1, 2
+XO_FP64, XO_FP32, XO_BF16X3, XO_BF16 = 0, 1, 2, 3
 XO_EPS_SYM, XO_EPS_NONSYM, XO_EPS_LU_FALLBACK = 0, 1, 2
 
-PREC = {"fp64": XO_FP64, "fp32": XO_FP32, "bf16x3": XO_BF16X3}
+PREC = {"fp64": XO_FP64, "fp32": XO_FP32, "bf16x3": XO_BF16X3, "bf16": XO_BF16}
 ERRNAME = {1: "XO_ERR_ARG", 2: "XO_ERR_ALLOC", 3: "XO_ERR_HIP", 4: "XO_ERR_NOTPD", 5: "XO_ERR_UNSUPPORTED"}
 
 _i32p = C.POINTER(C.c_int32)
