@@ -6,7 +6,9 @@ q = b1/4, 16 occupied + 200 empty bands, 36^3 FFT grid, 400 G-vectors, 8
 imaginary frequencies; K = 204 800 transitions. One step is the whole path on
 inputs already resident in HBM: oscillator strengths for all 64 k-pairs
 (xo_rho), chi0 for all frequencies (xo_chi0) and the FP64 Dyson inversion
-(xo_epsinv).
+(xo_epsinv). The positive-definiteness flags of the inversion go to a device
+array and are checked once after the timed steps, so the host enqueues the next
+step while the GPU inverts.
 
 Every form is timed: plain FP64, FP32 (FP32-MFMA rho and chi0), BF16x3 (split
 bf16 on MFMA: three products, FP32 accumulation) and BF16 (operands rounded to
@@ -97,6 +99,7 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
     dE = torch.empty(K, dtype=torch.float64, device=dev)
     chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
     E = torch.empty_like(chi)
+    info = torch.zeros(nw, dtype=torch.int32, device=dev)   # pivot flags, read after the timed steps
     qpg = cr.qpg()
     st = torch.cuda.current_stream()
 
@@ -109,7 +112,7 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
         xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=prec, check_dE=False)
         if ev:
             ev[2].record(st)
-        xo.epsinv(chi, qpg, out=E)
+        xo.epsinv(chi, qpg, out=E, info=info)
         if ev:
             ev[3].record(st)
 
@@ -127,6 +130,8 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
     wall = (time.perf_counter() - t0) / steps
     xo.timing_enable(False)
     kern = xo.timing_report()
+    if int(info.abs().sum().item()):
+        raise RuntimeError(f"eps~ not positive definite ({prec}): pivot flags {info.tolist()}")
     stages = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) for j in range(3)] for i in range(steps)])
     step_ms = np.array([evs[i][0].elapsed_time(evs[i][3]) for i in range(steps)])
     out = dict(prec=prec, K=K, ms_per_step=float(np.median(step_ms)), wall_ms_per_step=wall * 1e3,
@@ -306,7 +311,8 @@ def run_c3(args):
             bufs.append(dict(M=torch.empty((K, ng), dtype=CDTYPE[prec], device="cuda"),
                              dE=torch.empty(K, dtype=torch.float64, device="cuda"),
                              chi=torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda"),
-                             E=torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda")))
+                             E=torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda"),
+                             info=torch.zeros(nw, dtype=torch.int32, device="cuda")))
         return dcs, bufs
 
     def step(dcs, bufs, prec, tn, ev=None):
@@ -322,7 +328,7 @@ def run_c3(args):
         if ev:
             ev[2].record(st)
         for dc, b in zip(dcs, bufs):
-            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"])
+            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"], info=b["info"])
         if ev:
             ev[3].record(st)
 
@@ -350,6 +356,8 @@ def run_c3(args):
         torch.cuda.synchronize()
         xo.timing_enable(False)
         kern = xo.timing_report()
+        if any(int(b["info"].abs().sum().item()) for b in bufs):
+            raise RuntimeError(f"eps~ not positive definite at some q ({prec})")
         ms = float(np.median([evs[i][0].elapsed_time(evs[i][3]) for i in range(nsteps)]))
         st = [float(np.median([evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(nsteps)])) for j in range(3)]
         Ks = [b["M"].shape[0] for b in bufs]

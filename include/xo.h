@@ -216,10 +216,15 @@ int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* be
  * the LDL^H diagonal, so a non-positive pivot proves eps~ is not PD: the call
  * then returns XO_ERR_NOTPD naming the first such frequency. With
  * XO_EPS_LU_FALLBACK the sign test is skipped (an exactly zero pivot still
- * fails). The call synchronises the stream to read the pivot flags.
+ * fails). With info NULL the call synchronises the stream to read the pivot
+ * flags; with info set it does not synchronise and leaves them to the caller.
  * qpg: [host] [ng] |q+G| (at q = 0 the G = 0 entry is 1 and chi0's G = 0 row and
  *      column are the q-normalised head and wings).
  * chi0: [device] [nw][ng][ng] complex128 (read only); out: [device] same shape.
+ * info: [device] [nw] int32 or NULL. When set, info[w] receives 0 if frequency w
+ *      passed and 1 + the index of its first failing pivot otherwise, written
+ *      in stream order; the call then returns XO_OK without waiting for the
+ *      kernels, and out is valid only where info[w] == 0.
  */
 enum { XO_EPS_SYM = 0, XO_EPS_NONSYM = 1, XO_EPS_LU_FALLBACK = 2 };
 
@@ -229,6 +234,7 @@ typedef struct {
   const double* chi0;
   int flags;
   double* out;
+  int* info;
 } xo_eps_args;
 
 int xo_epsinv(const xo_eps_args* a, void* stream);

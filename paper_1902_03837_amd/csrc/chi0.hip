@@ -376,39 +376,44 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       oa[u] = ((unsigned)(4 * aq + u) * ng + Ga) * sizeof(f2v);
       ob[u] = ((unsigned)(4 * fq + u) * ng + Gb) * sizeof(f2v);
     }
-    // frequency factors (wave 0): transition wt of the step, frequency tid / 16; rows past
-    // the slice read its last row and are zeroed when stored, so that no wait for the
-    // load sits between its issue and the products
-    const int wt = tid & 15;
-    const unsigned ow = ((unsigned)wt * I.nwpad + (tid >> 4)) * sizeof(float);
-    const unsigned wmax = ((unsigned)(len - 1) * I.nwpad + (tid >> 4)) * sizeof(float);
+    // frequency factors: transition wt of the step, frequency wf (read by every wave, so
+    // that all waves issue the same loads; wave 0 stores them); rows past the slice read
+    // its last row and are zeroed when stored
+    const int wt = tid & 15, wf = (tid >> 4) & 3;
+    const unsigned ow = ((unsigned)wt * I.nwpad + wf) * sizeof(float);
+    const unsigned wmax = ((unsigned)(len - 1) * I.nwpad + wf) * sizeof(float);
 
-    f2v ra[4], rb[4];
-    float wv = 0.f;
-    // ---- load step s into registers
-#define CHI0_BLK_LOAD(s_)                                                                     \
+    // Plain form: two register sets (A, B) of staged loads; step s + 1 is stored to LDS
+    // while step s + 2 is in flight, so each load has two steps of products to arrive.
+    // Loads are unconditional (clamped addresses), so the wait before a store counts
+    // exactly the other set's loads.
+    f2v raA[4], rbA[4], raB[4], rbB[4];
+    float wvA = 0.f, wvB = 0.f;
+    // ---- load step s into register set (ra, rb, wv)
+#define CHI0_BLK_LOAD(s_, ra_, rb_, wv_)                                                      \
     {                                                                                         \
       const unsigned d_ = (unsigned)(s_) * rstep;                                             \
       _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                         \
-        ra[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                      \
-        rb[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                      \
+        ra_[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                     \
+        rb_[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                     \
       }                                                                                       \
-      if (wave == 0) wv = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));        \
+      wv_ = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));                       \
     }
-    // ---- store the loaded step s into buffer b
-#define CHI0_BLK_STORE(b_, s_)                                                                \
+    // ---- store step s from register set (ra, rb, wv) into buffer b. Split form: hi and
+    // lo of the right operand; plain form: hi and its rotation (-im, re)
+#define CHI0_BLK_STORE(b_, s_, ra_, rb_, wv_)                                                 \
     {                                                                                         \
       uint32_t h_[4], l_[4];                                                                  \
-      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb[u].x, rb[u].y, h_[u], l_[u]);   \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
       Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                 \
-      if constexpr (NP == 3) Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};          \
-      As[b_][ar][2 * aq] = make_float4(ra[0].x, ra[0].y, ra[1].x, ra[1].y);                    \
-      As[b_][ar][2 * aq + 1] = make_float4(ra[2].x, ra[2].y, ra[3].x, ra[3].y);                \
-      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][tid >> 4][0])[wt] = 16 * (s_) + wt < len ? wv : 0.f; \
+      if constexpr (NP == 3)                                                                  \
+        Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                               \
+      else                                                                                    \
+        Bs[b_][1][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])}; \
+      As[b_][ar][2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);                \
+      As[b_][ar][2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y);            \
+      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 16 * (s_) + wt < len ? wv_ : 0.f; \
     }
-    CHI0_BLK_LOAD(0);
-    CHI0_BLK_STORE(0, 0);
-    __syncthreads();
     f4 acc[kBW][2][4];
 #pragma unroll
     for (int w = 0; w < kBW; ++w)
@@ -416,54 +421,88 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[w][r][n] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nsteps; ++k) {
-      const int buf = k & 1;
-      if (k + 1 < nsteps) CHI0_BLK_LOAD(k + 1);
-      if (nmask) {
-        // weighted left operand of every frequency, converted once and shared by the column tiles
-        const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
-        u4 ah[kBW], al[kBW];
+    // products of the step held in buffer buf
+    auto products = [&](int buf) {
+      if (!nmask) return;
+      // weighted left operand of every frequency, converted once and shared by the column tiles
+      const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
+      u4 ah[kBW], al[kBW];
 #pragma unroll
-        for (int w = 0; w < kBW; ++w) {
-          const float4 wq = Ws[buf][w][q];
-          uint32_t h[4], l[4];
-          split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
-          split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
-          split2(wq.z * a23.x, wq.z * a23.y, h[2], l[2]);
-          split2(wq.w * a23.z, wq.w * a23.w, h[3], l[3]);
-          ah[w] = u4{h[0], h[1], h[2], h[3]};
-          al[w] = u4{l[0], l[1], l[2], l[3]};
+      for (int w = 0; w < kBW; ++w) {
+        const float4 wq = Ws[buf][w][q];
+        uint32_t h[4], l[4];
+        split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
+        split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
+        split2(wq.z * a23.x, wq.z * a23.y, h[2], l[2]);
+        split2(wq.w * a23.z, wq.w * a23.w, h[3], l[3]);
+        ah[w] = u4{h[0], h[1], h[2], h[3]};
+        al[w] = u4{l[0], l[1], l[2], l[3]};
+      }
+      // column tiles: Re through the right operand, Im through its rotation (-im, re)
+      // (split form: rotated in registers; plain form: read from LDS); the next tile's
+      // operands are read ahead of the products
+      u4 b0 = Bs[buf][0][0][q][i], b1 = Bs[buf][1][0][q][i];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        u4 nb0 = b0, nb1 = b1;
+        if (n < 3) {
+          nb0 = Bs[buf][0][n + 1][q][i];
+          nb1 = Bs[buf][1][n + 1][q][i];
         }
-        // column tiles: Re through the right operand, Im through its rotation (-im, re),
-        // rotated in registers; the next tile's operand is read ahead of the products
-        u4 bh = Bs[buf][0][0][q][i], bl = bh;
-        if constexpr (NP == 3) bl = Bs[buf][1][0][q][i];
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          u4 nbh = bh, nbl = bl;
-          if (n < 3) {
-            nbh = Bs[buf][0][n + 1][q][i];
-            if constexpr (NP == 3) nbl = Bs[buf][1][n + 1][q][i];
-          }
-          if (nmask & (1 << n)) {
+        if (nmask & (1 << n)) {
+          if constexpr (NP == 3) {
             u4 rh, rl;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-              rh[m] = rot_neg(bh[m]);
-              rl[m] = rot_neg(bl[m]);
+              rh[m] = rot_neg(b0[m]);
+              rl[m] = rot_neg(b1[m]);
             }
 #pragma unroll
             for (int w = 0; w < kBW; ++w) {
-              acc[w][0][n] = mma_np<NP>(ah[w], al[w], bh, bl, acc[w][0][n]);
-              acc[w][1][n] = mma_np<NP>(ah[w], al[w], rh, rl, acc[w][1][n]);
+              acc[w][0][n] = mma3(ah[w], al[w], b0, b1, acc[w][0][n]);
+              acc[w][1][n] = mma3(ah[w], al[w], rh, rl, acc[w][1][n]);
+            }
+          } else {
+#pragma unroll
+            for (int w = 0; w < kBW; ++w) {
+              acc[w][0][n] = mma(ah[w], b0, acc[w][0][n]);
+              acc[w][1][n] = mma(ah[w], b1, acc[w][1][n]);
             }
           }
-          bh = nbh;
-          bl = nbl;
         }
+        b0 = nb0;
+        b1 = nb1;
       }
-      if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1, k + 1);
+    };
+    CHI0_BLK_LOAD(0, raA, rbA, wvA);
+    CHI0_BLK_STORE(0, 0, raA, rbA, wvA);
+    if constexpr (NP == 1) {
+      // step k sits in buffer k % 2; entering an even k, step k + 1 is in set B and
+      // step k + 2 in set A
+      CHI0_BLK_LOAD(1, raB, rbB, wvB);
+      CHI0_BLK_LOAD(2, raA, rbA, wvA);
       __syncthreads();
+      for (int k = 0; k < nsteps; k += 2) {
+        products(0);
+        if (k + 1 < nsteps) CHI0_BLK_STORE(1, k + 1, raB, rbB, wvB);
+        __syncthreads();
+        if (k + 1 >= nsteps) break;
+        CHI0_BLK_LOAD(k + 3, raB, rbB, wvB);
+        products(1);
+        if (k + 2 < nsteps) CHI0_BLK_STORE(0, k + 2, raA, rbA, wvA);
+        __syncthreads();
+        CHI0_BLK_LOAD(k + 4, raA, rbA, wvA);
+      }
+    } else {
+      // the split form has no registers for a second set: one step ahead
+      __syncthreads();
+      for (int k = 0; k < nsteps; ++k) {
+        const int buf = k & 1;
+        if (k + 1 < nsteps) CHI0_BLK_LOAD(k + 1, raA, rbA, wvA);
+        products(buf);
+        if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
+        __syncthreads();
+      }
     }
 #undef CHI0_BLK_LOAD
 #undef CHI0_BLK_STORE

@@ -283,7 +283,8 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   const size_t fbytes = align_up(sizeof(int) * a->nw, 256);
   const size_t sbytes = nblk > 1 ? (size_t)a->nw * n * kB * sizeof(z) : 0;
   XO_RET(workspace(st, 2, fbytes + sbytes, &ws));
-  int* flag = static_cast<int*>(ws);
+  // pivot flags: the caller's info array (deferred check) or library workspace
+  int* flag = a->info ? a->info : static_cast<int*>(ws);
   double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + fbytes);
   XO_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int) * a->nw, st));
   const size_t nn = (size_t)n * n;
@@ -331,6 +332,7 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
     }
     XO_CHECK_LAUNCH();
   }
+  if (a->info) return XO_OK;  // the caller reads the flags when it needs them
   int* hf = nullptr;
   XO_RET(host_flags(st, sizeof(int) * a->nw, reinterpret_cast<void**>(&hf)));
   XO_TRY_HIP(hipMemcpyAsync(hf, flag, sizeof(int) * a->nw, hipMemcpyDeviceToHost, st));

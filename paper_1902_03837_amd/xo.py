@@ -50,7 +50,7 @@ class Chi0Args(C.Structure):
 class EpsArgs(C.Structure):
     _fields_ = [
         ("ng", C.c_int), ("nw", C.c_int), ("qpg", _f64p), ("chi0", C.c_void_p),
-        ("flags", C.c_int), ("out", C.c_void_p),
+        ("flags", C.c_int), ("out", C.c_void_p), ("info", C.c_void_p),
     ]
 
 
@@ -305,8 +305,11 @@ def chi0_autotune(items, omegas, *, prec="fp64", stream=None):
     return (t.nt_tiles, t.kper, t.wg_per_cu), ms.value
 
 
-def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, stream=None):
-    """xo_epsinv: out = eps~^-1 (or (I - v chi0)^-1 with XO_EPS_NONSYM), complex128."""
+def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, info=None, stream=None):
+    """xo_epsinv: out = eps~^-1 (or (I - v chi0)^-1 with XO_EPS_NONSYM), complex128.
+
+    info: optional int32 device tensor [nw]; when given the call does not synchronise and
+    the pivot flags land there (0: frequency passed, else 1 + its first failing pivot)."""
     import torch
     q = np.ascontiguousarray(np.asarray(qpg, dtype=np.float64))
     assert chi0_m.ndim == 3 and chi0_m.shape[1] == chi0_m.shape[2] == q.shape[0]
@@ -315,6 +318,9 @@ def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, stream=None):
     a = EpsArgs()
     a.ng, a.nw = chi0_m.shape[-1], chi0_m.shape[0]
     a.qpg, a.chi0, a.flags, a.out = q.ctypes.data_as(_f64p), _ptr(chi0_m), int(flags), _ptr(out)
+    if info is not None:
+        assert info.dtype == torch.int32 and info.numel() == a.nw and info.is_contiguous()
+        a.info = _ptr(info)
     _check(lib().xo_epsinv(C.byref(a), _stream(stream)))
     return out
 

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header_sizes():
     src = open(os.path.join(ROOT, "include", "xo.h")).read()
     assert "xo_rho_args" in src and "xo_chi0_args" in src and "xo_eps_args" in src
     assert C.sizeof(xo.Chi0Args) == 4 * 4 + 3 * 8 + 8 + 4 + 4 + 8
-    assert C.sizeof(xo.EpsArgs) == 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(xo.EpsArgs) == 8 + 8 + 8 + 8 + 8 + 8
 
 
 def _rc(fn, a):

@@ -289,6 +289,11 @@ def test_epsinv_sizes_random_hpd(ng):
     out = torch.empty(chi.shape, dtype=torch.complex128, device=DEV)
     xo.epsinv(_to(chi), qpg, out=out)
     assert rel_fro(out.cpu().numpy(), ref) < 1e-12
+    # the deferred-check call gives the same result and all-zero flags
+    info = torch.full((2,), -1, dtype=torch.int32, device=DEV)
+    out2 = torch.empty_like(out)
+    xo.epsinv(_to(chi), qpg, out=out2, info=info)
+    assert torch.equal(out2, out) and info.tolist() == [0, 0]
 
 
 def test_epsinv_not_positive_definite():
@@ -300,6 +305,10 @@ def test_epsinv_not_positive_definite():
     with pytest.raises(xo.XoError) as e:
         xo.epsinv(_to(chi), qpg, out=out)
     assert e.value.code == xo.XO_ERR_NOTPD
+    # deferred check: no error from the call, the flag lands in info
+    info = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    xo.epsinv(_to(chi), qpg, out=out, info=info)
+    assert info.item() > 0
     xo.epsinv(_to(chi), qpg, out=out, flags=xo.XO_EPS_LU_FALLBACK)
     s = np.sqrt(4 * np.pi) / qpg
     ref = np.linalg.inv(np.eye(ng) - s[:, None] * chi[0] * s[None, :])
