@@ -5,8 +5,9 @@
 // eps~ is Hermitian positive definite at imaginary frequencies. It is inverted
 // in place by blocked Gauss-Jordan elimination without pivoting, all frequencies
 // in the same launches. Per block column K (width b = 64), three launches:
-//   P = A_KK^-1                      diag_inverse: one workgroup per frequency,
-//                                    the block in registers, one barrier per pivot
+//   P = A_KK^-1                      diag_inverse: one 1024-thread workgroup per
+//                                    frequency, the block in registers, one barrier
+//                                    per pivot
 //   A_Kj = P A_Kj  (j outside K)     row_col: row tiles of the panel, and
 //   S_iK = A_iK,  A_iK = -A_iK P     column tiles (old column saved in S)
 //   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update
@@ -41,34 +42,36 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
 }
 
 // In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
-// (kb <= 64). Thread t holds row t / 4, columns 16 (t % 4) .. 16 (t % 4) + 15 in
-// registers (identity outside kb). Per pivot k the owners publish column k and
-// row k (values before the step) in LDS, double buffered, and every thread
-// updates its own sixteen entries after one barrier.
-__global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
-                                                   int check_sign, int* __restrict__ flag) {
+// (kb <= 64). 1024 threads per frequency: thread t holds row t / 16, columns
+// 4 (t % 16) .. 4 (t % 16) + 3 in registers (identity outside kb), so that four
+// waves share each SIMD and hide one another's latency. Per pivot k the owners
+// publish column k and row k (values before the step) in LDS, double buffered,
+// and every thread updates its own four entries after one barrier.
+constexpr int kDiagThreads = 1024;
+__global__ void __launch_bounds__(kDiagThreads) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
+                                                            int check_sign, int* __restrict__ flag) {
   __shared__ z pcol[2][kB];
-  __shared__ z prow[2][kB + kB / 16];  // column c at c + c / 16: the four column quarters on distinct banks
+  __shared__ z prow[2][4][kB / 4];  // [buffer][j][column quad]: entry 4 q + j at [j][q], read without bank conflicts
   const int w = blockIdx.x;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
-  const int t = threadIdx.x, r = t >> 2, cq = t & 3, c0 = 16 * cq;
-  z a[16];
+  const int t = threadIdx.x, r = t >> 4, cq = t & 15, c0 = 4 * cq;
+  z a[4];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < 4; ++j) {
     const int c = c0 + j;
     a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
   }
-  for (int kq = 0; kq < 4; ++kq) {
+  for (int kq = 0; kq < 16; ++kq) {
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * kq + kk;
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = 4 * kq + kk;
       if (k >= kb) break;
       const int b = k & 1;
       if (cq == kq) pcol[b][r] = a[kk];
       if (r == k) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) prow[b][c0 + cq + j] = a[j];
+        for (int j = 0; j < 4; ++j) prow[b][j][cq] = a[j];
       }
       __syncthreads();
       const z piv = pcol[b][k];
@@ -86,8 +89,8 @@ __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, i
       const z g = prow_k ? z{-ip.x, -ip.y} : gr;
       const double keep = prow_k ? 0.0 : 1.0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const z pr = prow[b][c0 + cq + j];
+      for (int j = 0; j < 4; ++j) {
+        const z pr = prow[b][j][cq];
         a[j].x = fma(-g.x, pr.x, fma(g.y, pr.y, keep * a[j].x));
         a[j].y = fma(-g.x, pr.y, fma(-g.y, pr.x, keep * a[j].y));
       }
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(256) diag_inverse(double* __restrict__ Aall, i
     }
   }
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < 4; ++j) {
     const int c = c0 + j;
     if (r < kb && c < kb) A[(size_t)(o + r) * n + o + c] = a[j];
   }
@@ -306,7 +309,8 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
     const int kb = std::min(kB, n - K * kB);
     {
       KernelTimer kt_("eps_diag_inverse", st);
-      hipLaunchKernelGGL(diag_inverse, dim3(a->nw), dim3(256), 0, st, a->out, n, K, kb, check_sign, flag);
+      hipLaunchKernelGGL(diag_inverse, dim3(a->nw), dim3(kDiagThreads), 0, st, a->out, n, K, kb, check_sign,
+                         flag);
     }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
