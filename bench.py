@@ -10,6 +10,11 @@ inputs already resident in HBM: oscillator strengths for all 64 k-pairs
 array and are checked once after the timed steps, so the host enqueues the next
 step while the GPU inverts.
 
+Each form runs its warm-up steps, the timed steps (HIP events at the stage
+boundaries only) and then as many steps again with the library's per-kernel HIP
+event brackets on (xo_timing_enable), which give the kernel durations of the
+roofline entries without weighing on the timed steps.
+
 Every form is timed: plain FP64, FP32 (FP32-MFMA rho and chi0), BF16x3 (split
 bf16 on MFMA: three products, FP32 accumulation) and BF16 (operands rounded to
 bf16, one product, FP32 accumulation); eps^-1 is FP64 in all. The reported form
@@ -119,8 +124,7 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    xo.timing_report()            # drop anything recorded before the timed region
-    xo.timing_enable(True)
+    # timed region: the library's per-kernel event brackets off, stage events only
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -128,6 +132,12 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
         step(evs[i])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
+    # the same steps again with every kernel bracketed by HIP events on its launch stream
+    xo.timing_report()            # drop anything recorded before
+    xo.timing_enable(True)
+    for i in range(steps):
+        step()
+    torch.cuda.synchronize()
     xo.timing_enable(False)
     kern = xo.timing_report()
     if int(info.abs().sum().item()):
@@ -178,7 +188,7 @@ def measured_traffic(kernel):
     counters; otherwise the figures describe an older kernel and are not reported.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", "c2_bf16x3_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     src, tr = {}, {}

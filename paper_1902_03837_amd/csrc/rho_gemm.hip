@@ -616,7 +616,9 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
     auto key = std::make_tuple(c, nb, npw);
     if (sets.count(key)) return;
     sets[key] = tot;
+    // zeroed first: the padding bytes take part in the table cache's content hash
     SplitDesc d;
+    std::memset(&d, 0, sizeof d);
     d.src = static_cast<const float2*>(c);
     d.dst = nullptr;
     d.nb = nb;
