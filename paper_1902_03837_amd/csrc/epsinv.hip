@@ -42,36 +42,38 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
 }
 
 // In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
-// (kb <= 64). 1024 threads per frequency: thread t holds row t / 16, columns
-// 4 (t % 16) .. 4 (t % 16) + 3 in registers (identity outside kb), so that four
-// waves share each SIMD and hide one another's latency. Per pivot k the owners
-// publish column k and row k (values before the step) in LDS, double buffered,
-// and every thread updates its own four entries after one barrier.
-constexpr int kDiagThreads = 1024;
-__global__ void __launch_bounds__(kDiagThreads) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
+// (kb <= 64). 4096 / E threads per frequency: thread t holds row t / (64 / E),
+// columns E (t % (64 / E)) .. + E - 1 in registers (identity outside kb). Per
+// pivot k the owners publish column k and row k (values before the step) in LDS,
+// double buffered, and every thread updates its own E entries after one barrier.
+// The pivot row is stored transposed ([j][column group]) so that a wave reads it
+// without bank conflicts.
+template <int E>
+__global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
                                                             int check_sign, int* __restrict__ flag) {
+  constexpr int CG = kB / E;  // column groups
   __shared__ z pcol[2][kB];
-  __shared__ z prow[2][4][kB / 4];  // [buffer][j][column quad]: entry 4 q + j at [j][q], read without bank conflicts
+  __shared__ z prow[2][E][CG];
   const int w = blockIdx.x;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
-  const int t = threadIdx.x, r = t >> 4, cq = t & 15, c0 = 4 * cq;
-  z a[4];
+  const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq;
+  z a[E];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
     a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
   }
-  for (int kq = 0; kq < 16; ++kq) {
+  for (int kq = 0; kq < CG; ++kq) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kq + kk;
+    for (int kk = 0; kk < E; ++kk) {
+      const int k = E * kq + kk;
       if (k >= kb) break;
       const int b = k & 1;
       if (cq == kq) pcol[b][r] = a[kk];
       if (r == k) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) prow[b][j][cq] = a[j];
+        for (int j = 0; j < E; ++j) prow[b][j][cq] = a[j];
       }
       __syncthreads();
       const z piv = pcol[b][k];
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_inverse(double* __restrict_
       const z g = prow_k ? z{-ip.x, -ip.y} : gr;
       const double keep = prow_k ? 0.0 : 1.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < E; ++j) {
         const z pr = prow[b][j][cq];
         a[j].x = fma(-g.x, pr.x, fma(g.y, pr.y, keep * a[j].x));
         a[j].y = fma(-g.x, pr.y, fma(-g.y, pr.x, keep * a[j].y));
@@ -98,11 +100,12 @@ __global__ void __launch_bounds__(kDiagThreads) diag_inverse(double* __restrict_
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
     if (r < kb && c < kb) A[(size_t)(o + r) * n + o + c] = a[j];
   }
 }
+constexpr int kDiagE = 8;  // entries per thread of diag_inverse (512 threads: two waves per SIMD)
 
 // One 64 x 64 tile product L R (L: 64 x kb, R: kb x 64, in LDS). Thread t owns
 // rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 4): a wave reads four rows
@@ -309,8 +312,8 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
     const int kb = std::min(kB, n - K * kB);
     {
       KernelTimer kt_("eps_diag_inverse", st);
-      hipLaunchKernelGGL(diag_inverse, dim3(a->nw), dim3(kDiagThreads), 0, st, a->out, n, K, kb, check_sign,
-                         flag);
+      hipLaunchKernelGGL(diag_inverse<kDiagE>, dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n, K, kb,
+                         check_sign, flag);
     }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
