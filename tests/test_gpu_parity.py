@@ -232,6 +232,45 @@ def test_chi0_reduced_precision_random(prec, tol, nt, ng, nw):
     assert torch.equal(out, again)   # fixed-order reduction: bitwise repeatable
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("nt,ng,nw,tune", [(1, 1, 1, None), (1, 1, 1, (4, 0, 0)), (33, 17, 1, (4, 0, 0)),
+                                           (700, 65, 3, (4, 256, 1)), (130, 129, 6, None)])
+def test_chi0_bf16_edges(prec, nt, ng, nw, tune):
+    """Degenerate and ragged shapes of the bf16 forms: one transition, one G-vector, one
+    frequency in the 64 x 64 block form (three padded frequency slots), G-sets one past a
+    block edge, transition slices shorter than a step; within the bf16 rounding bound
+    (plain) or 2e-4 (split), exactly Hermitian."""
+    say(f"chi0 {prec} edge nt={nt} ng={ng} nw={nw} tune={tune}")
+    M = random_complex(300 + nt, (nt, ng)).astype(np.complex64).astype(np.complex128)
+    dE = random_positive(400 + nt, nt, 0.05, 3.0)
+    w = list(np.linspace(0.0, 1.5, nw))
+    ref = chi0_from_rho(M, dE, w, 0.8)
+    out = torch.empty((nw, ng, ng), dtype=torch.complex128, device=DEV)
+    xo.chi0_batch([(_to(M, torch.complex64), _to(dE, torch.float64), 0.8, out)], w, prec=prec, tune=tune)
+    got = out.cpu().numpy()
+    if prec == "bf16":
+        assert (np.abs(got - ref) / bf16_chi0_bound(M, dE, w, 0.8)).max() <= 1.0
+    else:
+        assert rel_fro(got, ref) < 2e-4
+    for j in range(nw):
+        assert np.array_equal(got[j], got[j].conj().T)
+
+
+def test_chi0_bf16_accumulate_chunks():
+    """Streaming transitions in chunks (accumulate = 1) adds up to the unsplit result
+    within the plain-bf16 bound."""
+    nt, ng, nw = 2000, 70, 4
+    M = random_complex(21, (nt, ng)).astype(np.complex64).astype(np.complex128)
+    dE = random_positive(22, nt, 0.1, 2.0)
+    w = [0.0, 0.4, 1.0, 2.0]
+    Md, dEd = _to(M, torch.complex64), _to(dE, torch.float64)
+    part = torch.empty((nw, ng, ng), dtype=torch.complex128, device=DEV)
+    xo.chi0(Md[:700], dEd[:700], w, 1.0, out=part, prec="bf16")
+    xo.chi0(Md[700:], dEd[700:], w, 1.0, out=part, prec="bf16", accumulate=True)
+    ref = chi0_from_rho(M, dE, w, 1.0)
+    assert (np.abs(part.cpu().numpy() - ref) / bf16_chi0_bound(M, dE, w, 1.0)).max() <= 1.0
+
+
 def test_chi0_accumulate_and_determinism():
     nt, ng, nw = 3000, 50, 3
     M = random_complex(11, (nt, ng))
