@@ -48,10 +48,19 @@ int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s);
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kCT = 8;               // column tiles (16 conduction bands each) per workgroup, at most
+constexpr int kCT = 8;               // column tiles (16 conduction bands each) per workgroup, at most (split form)
 constexpr int kRT = 2;               // row tiles (16 (v, G) rows each) per wave
 constexpr int kRows = 4 * 16 * kRT;  // rows per workgroup
 constexpr size_t kBsBytes = (size_t)2 * 2 * kCT * 4 * 16 * sizeof(u4);  // [buffer][hi, lo][tile][q][column]
+// Per form: column tiles per workgroup and planes of the staged right operand. The
+// plain form keeps one plane and seven tiles, so that its registers (<= 168) and
+// LDS allow three workgroups per CU (three waves per SIMD) instead of two.
+template <int NP>
+struct GemmShape {
+  static constexpr int CT = NP == 3 ? 8 : 7;
+  static constexpr int PL = NP == 3 ? 2 : 1;
+  static constexpr size_t bs_bytes = (size_t)2 * PL * CT * 64 * sizeof(u4);  // [buffer][plane][tile][q][column]
+};
 constexpr size_t kLdsMax = 160 * 1024;
 
 typedef int i4 __attribute__((ext_vector_type(4)));
@@ -97,9 +106,10 @@ struct GemmPair {
 };
 
 template <int NP>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NP == 3 ? 2 : 3)))
 rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   constexpr int kW = NP == 3 ? 2 : 1;  // 32-bit words per coefficient
+  constexpr int CT = GemmShape<NP>::CT, PL = GemmShape<NP>::PL;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous
   // logical range, so a pair's tables and coefficients stay in that XCD's L2.
@@ -120,8 +130,8 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   const int vlo = r0 / ng, vhi = min(P.nv - 1, (r0 + kRows - 1) / ng);
   const int npwv = P.npwv, npwc = P.npwc, nK = P.nK;
 
-  u4* Bs = reinterpret_cast<u4*>(smem);                                // [2][2][kCT][4][16]
-  uint32_t* Vs = reinterpret_cast<uint32_t*>(smem + kBsBytes);          // [vhi - vlo + 1][npwv] entries
+  u4* Bs = reinterpret_cast<u4*>(smem);                                // [2][PL][CT][4][16]
+  uint32_t* Vs = reinterpret_cast<uint32_t*>(smem + GemmShape<NP>::bs_bytes);  // [vhi - vlo + 1][npwv] entries
   const int nvs = (vhi - vlo + 1) * npwv * kW;                         // words, a multiple of 16
   uint16_t* Ts = reinterpret_cast<uint16_t*>(Vs + nvs);                 // [ncell]
 
@@ -166,11 +176,13 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
 #define RHO_GEMM_STORE(b_)                                                        \
   _Pragma("unroll") for (int f = 0; f < 2; ++f) {                                 \
     const int s_ = tid + kThreads * f;                                            \
-    if constexpr (NP == 3) {                                                      \
-      Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = u4{raw[f][0].x, raw[f][0].z, raw[f][1].x, raw[f][1].z}; \
-      Bs[((b_) * 2 + 1) * (kCT * 64) + s_] = u4{raw[f][0].y, raw[f][0].w, raw[f][1].y, raw[f][1].w}; \
-    } else {                                                                      \
-      Bs[((b_) * 2 + 0) * (kCT * 64) + s_] = raw[f][0];                           \
+    if (s_ < CT * 64) {                                                           \
+      if constexpr (NP == 3) {                                                    \
+        Bs[((b_) * PL + 0) * (CT * 64) + s_] = u4{raw[f][0].x, raw[f][0].z, raw[f][1].x, raw[f][1].z}; \
+        Bs[((b_) * PL + 1) * (CT * 64) + s_] = u4{raw[f][0].y, raw[f][0].w, raw[f][1].y, raw[f][1].w}; \
+      } else {                                                                    \
+        Bs[(b_) * (CT * 64) + s_] = raw[f][0];                                    \
+      }                                                                           \
     }                                                                             \
   }
 
@@ -202,11 +214,11 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   gather(oa1, ah, al);
   oa1 = oa2;
 
-  f4 re[kRT][kCT], im[kRT][kCT];
+  f4 re[kRT][CT], im[kRT][CT];
 #pragma unroll
   for (int rt = 0; rt < kRT; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < kCT; ++ct) re[rt][ct] = im[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < CT; ++ct) re[rt][ct] = im[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
   for (int k = 0; k < nK; ++k) {
     const int buf = k & 1;
@@ -226,10 +238,10 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
         bh[rt][u] = rot_pos(ah[rt][u]);
         bl[rt][u] = rot_pos(al[rt][u]);
       }
-    const u4* Bh = Bs + (buf * 2 + 0) * (kCT * 64) + lane;
-    const u4* Bl = Bs + (buf * 2 + 1) * (kCT * 64) + lane;
+    const u4* Bh = Bs + (buf * PL + 0) * (CT * 64) + lane;
+    const u4* Bl = Bs + (buf * PL + PL - 1) * (CT * 64) + lane;  // the lo plane (split form)
 #pragma unroll
-    for (int ct = 0; ct < kCT; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
       if (ct < nt) {
         const u4 ch = Bh[ct * 64];
         u4 cl = ch;
@@ -258,7 +270,7 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   for (int rt = 0; rt < kRT; ++rt) {
     const int rb4 = r0 + 32 * w + 16 * rt + 4 * q;
 #pragma unroll
-    for (int ct = 0; ct < kCT; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
       const int c = (ct0 + ct) * 16 + i;
       if (ct >= nt || c >= P.nc) continue;
       const int v4 = rb4 < nrows ? rb4 / ng : 0, g4 = rb4 - v4 * ng;
@@ -603,7 +615,7 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
     const int nrows = p[i].nv * ng;
     for (int r0 = 0; r0 < nrows; r0 += kRows)
       nbs = std::max(nbs, std::min(p[i].nv - 1, (r0 + kRows - 1) / ng) - r0 / ng + 1);
-    const size_t need = kBsBytes + (size_t)nbs * padded_row(p[i].npw_v) * kW * 4 + ge[i]->T.size() * 2;
+    const size_t need = GemmShape<NP>::bs_bytes + (size_t)nbs * padded_row(p[i].npw_v) * kW * 4 + ge[i]->T.size() * 2;
     lds = std::max(lds, need);
   }
   if (lds > kLdsMax) return XO_ERR_UNSUPPORTED;
@@ -666,7 +678,7 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
     d.nc = p[i].nc;
     d.nv = p[i].nv;
     d.nct = (p[i].nc + 15) / 16;
-    d.ncg = (d.nct + kCT - 1) / kCT;
+    d.ncg = (d.nct + GemmShape<NP>::CT - 1) / GemmShape<NP>::CT;
     d.nrb = (p[i].nv * ng + kRows - 1) / kRows;
     d.wg0 = nwg;
     nwg += d.ncg * d.nrb;
