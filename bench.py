@@ -410,7 +410,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16")
-    ap.add_argument("--cpu-pairs", type=int, default=2)
+    ap.add_argument("--cpu-pairs", type=int, default=6, help="k-pairs of the oracle's CPU timing (about 13 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--detail", default=None, help="write the per-form detail JSON here")
     ap.add_argument("--nq", type=int, default=27, help="c3: number of q-points")
