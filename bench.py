@@ -325,6 +325,10 @@ def run_c3(args):
                              info=torch.zeros(nw, dtype=torch.int32, device="cuda")))
         return dcs, bufs
 
+    # the q-points' inversions are independent: four streams (default priority) overlap
+    # their latency-bound block chains
+    side = [torch.cuda.Stream() for _ in range(4)]
+
     def step(dcs, bufs, prec, tn, ev=None):
         st = torch.cuda.current_stream()
         if ev:
@@ -337,8 +341,12 @@ def run_c3(args):
                       prec=prec, tune=tn, check_dE=False)
         if ev:
             ev[2].record(st)
-        for dc, b in zip(dcs, bufs):
-            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"], info=b["info"])
+        for sd in side:
+            sd.wait_stream(st)
+        for j, (dc, b) in enumerate(zip(dcs, bufs)):
+            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"], info=b["info"], stream=side[j % len(side)])
+        for sd in side:
+            st.wait_stream(sd)
         if ev:
             ev[3].record(st)
 

@@ -52,12 +52,12 @@ constexpr int kCT = 8;               // column tiles (16 conduction bands each) 
 constexpr int kRT = 2;               // row tiles (16 (v, G) rows each) per wave
 constexpr int kRows = 4 * 16 * kRT;  // rows per workgroup
 constexpr size_t kBsBytes = (size_t)2 * 2 * kCT * 4 * 16 * sizeof(u4);  // [buffer][hi, lo][tile][q][column]
-// Per form: column tiles per workgroup and planes of the staged right operand. The
-// plain form keeps one plane and seven tiles, so that its registers (<= 168) and
-// LDS allow three workgroups per CU (three waves per SIMD) instead of two.
-template <int NP>
+// Column tiles per workgroup (CT) and planes of the staged right operand (PL) of a
+// form. The plain form keeps one plane; with seven tiles its registers (<= 168) and
+// LDS allow three workgroups per CU (three waves per SIMD) instead of two, which it
+// takes when seven-tile groups cover the columns in as many groups as eight-tile ones.
+template <int NP, int CT>
 struct GemmShape {
-  static constexpr int CT = NP == 3 ? 8 : 7;
   static constexpr int PL = NP == 3 ? 2 : 1;
   static constexpr size_t bs_bytes = (size_t)2 * PL * CT * 64 * sizeof(u4);  // [buffer][plane][tile][q][column]
 };
@@ -105,11 +105,11 @@ struct GemmPair {
   int wg0;          // first logical workgroup of the pair
 };
 
-template <int NP>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NP == 3 ? 2 : 3)))
+template <int NP, int CT>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CT <= 7 ? 3 : 2)))
 rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   constexpr int kW = NP == 3 ? 2 : 1;  // 32-bit words per coefficient
-  constexpr int CT = GemmShape<NP>::CT, PL = GemmShape<NP>::PL;
+  constexpr int PL = GemmShape<NP, CT>::PL;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous
   // logical range, so a pair's tables and coefficients stay in that XCD's L2.
@@ -131,7 +131,7 @@ rho_gemm(const GemmPair* __restrict__ pairs, int npairs, int nwg, int ng) {
   const int npwv = P.npwv, npwc = P.npwc, nK = P.nK;
 
   u4* Bs = reinterpret_cast<u4*>(smem);                                // [2][PL][CT][4][16]
-  uint32_t* Vs = reinterpret_cast<uint32_t*>(smem + GemmShape<NP>::bs_bytes);  // [vhi - vlo + 1][npwv] entries
+  uint32_t* Vs = reinterpret_cast<uint32_t*>(smem + GemmShape<NP, CT>::bs_bytes);  // [vhi - vlo + 1][npwv] entries
   const int nvs = (vhi - vlo + 1) * npwv * kW;                         // words, a multiple of 16
   uint16_t* Ts = reinterpret_cast<uint16_t*>(Vs + nvs);                 // [ncell]
 
@@ -600,7 +600,7 @@ inline int padded_row(int npw) { return (npw + 1 + 15) / 16 * 16; }
 // The batch on the gathered-product kernel (NP = 3 split, 1 plain bf16), or
 // XO_ERR_UNSUPPORTED (nothing enqueued) when a pair's tables do not fit in LDS.
 // All pairs share ng and the G-set.
-template <int NP>
+template <int NP, int CT>
 static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                             hipStream_t s) {
   constexpr int kW = NP == 3 ? 2 : 1;
@@ -615,7 +615,7 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
     const int nrows = p[i].nv * ng;
     for (int r0 = 0; r0 < nrows; r0 += kRows)
       nbs = std::max(nbs, std::min(p[i].nv - 1, (r0 + kRows - 1) / ng) - r0 / ng + 1);
-    const size_t need = GemmShape<NP>::bs_bytes + (size_t)nbs * padded_row(p[i].npw_v) * kW * 4 + ge[i]->T.size() * 2;
+    const size_t need = GemmShape<NP, CT>::bs_bytes + (size_t)nbs * padded_row(p[i].npw_v) * kW * 4 + ge[i]->T.size() * 2;
     lds = std::max(lds, need);
   }
   if (lds > kLdsMax) return XO_ERR_UNSUPPORTED;
@@ -678,7 +678,7 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
     d.nc = p[i].nc;
     d.nv = p[i].nv;
     d.nct = (p[i].nc + 15) / 16;
-    d.ncg = (d.nct + GemmShape<NP>::CT - 1) / GemmShape<NP>::CT;
+    d.ncg = (d.nct + CT - 1) / CT;
     d.nrb = (p[i].nv * ng + kRows - 1) / kRows;
     d.wg0 = nwg;
     nwg += d.ncg * d.nrb;
@@ -686,11 +686,11 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
   const void* dgp = nullptr;
   XO_RET(device_table(gp.data(), gp.size() * sizeof(GemmPair), s, &dgp));
   if (lds > 64 * 1024)
-    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm<NP>),
+    XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rho_gemm<NP, CT>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
     KernelTimer kt_(NP == 3 ? "rho_gemm" : "rho_gemm_bf16", s);
-    hipLaunchKernelGGL(rho_gemm<NP>, dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
+    hipLaunchKernelGGL((rho_gemm<NP, CT>), dim3(8 * ((nwg + 7) / 8)), dim3(kThreads), lds, s,
                        static_cast<const GemmPair*>(dgp), n, nwg, ng);
   }
   XO_CHECK_LAUNCH();
@@ -699,8 +699,13 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
 
 int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                    hipStream_t s) {
-  if (p[0].prec == XO_BF16) return rho_batch_gemm_t<1>(p, n, xc, xv, xe, s);
-  return rho_batch_gemm_t<3>(p, n, xc, xv, xe, s);
+  if (p[0].prec == XO_BF16) {
+    int nct = 1;
+    for (int i = 0; i < n; ++i) nct = std::max(nct, (p[i].nc + 15) / 16);
+    if ((nct + 6) / 7 == (nct + 7) / 8) return rho_batch_gemm_t<1, 7>(p, n, xc, xv, xe, s);
+    return rho_batch_gemm_t<1, 8>(p, n, xc, xv, xe, s);
+  }
+  return rho_batch_gemm_t<3, kCT>(p, n, xc, xv, xe, s);
 }
 
 

@@ -145,6 +145,22 @@ def test_rho_parity_large_gset(prec, kern, tol):
     check_rho(M.cpu().numpy().astype(np.complex128), Mr, tol, max(len(m) for m in cr.mill))
 
 
+@pytest.mark.parametrize("nempty", [28, 128])
+def test_rho_plain_bf16_column_groups(nempty):
+    """The plain-bf16 gathered product takes seven column tiles per workgroup when that
+    needs no more groups than eight (28 empty bands: 2 tiles), else eight (128: 8 tiles)."""
+    cr = crystal_for("c2_small", nempty=nempty)
+    say(f"rho plain bf16, {nempty} empty bands")
+    dc = DeviceCrystal.upload(cr, "bf16")
+    K = ntrans(cr)
+    M = torch.empty((K, cr.gmill.shape[0]), dtype=torch.complex64, device=DEV)
+    dE = torch.empty(K, dtype=torch.float64, device=DEV)
+    with rho_kernel("gemm", "bf16"):
+        rho_all(dc, M, dE)
+    Mr, _ = rho_all_pairs(cr, "fft")
+    check_rho(M.cpu().numpy().astype(np.complex128), Mr, None, max(len(m) for m in cr.mill))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16"])
 def test_rho_batch_equals_per_pair(prec):
     cr = crystal_for("c2_small")
