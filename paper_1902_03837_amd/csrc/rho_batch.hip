@@ -710,8 +710,8 @@ int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s) {
 }
 
 // Which kernel a batch may take: the gathered product when its tables fit in
-// LDS, else the transform (axis-factorised on MFMA for split bf16, on VALU pair
-// by pair for FP32 / FP64). XO_RHO_KERNEL=gemm or =transform restricts the choice
+// LDS, else the transform (axis-factorised on MFMA in split bf16 for both bf16
+// forms, on VALU pair by pair for FP32 / FP64). XO_RHO_KERNEL=gemm or =transform restricts the choice
 // to one of them (the other paths still apply when it cannot run).
 static int rho_kernel_choice() {
   const char* e = std::getenv("XO_RHO_KERNEL");
