@@ -16,10 +16,13 @@ Every function is written from the paper's equations (Yambo 2019, arXiv
 * the RPA Dyson equation as a matrix inversion, Eq. (X_rpa_inv), and the
   symmetrised screened interaction of Eq. (W_def);
 * the Bruneval-Gonze X-terminator, Eq. (X_term_def) and Appendix B;
+* the Godby-Needs plasmon-pole model and the GW self-energy matrix elements
+  Sigma_x and Sigma_c, Eq. (sigma_c), Eq. (I_c), Eq. (W_def) (oracle/sigma.py);
 * a small MLP (not in the paper) used by the learned band tail.
 
 Parity status: rho, chi0 and epsilon^-1 are pinned by identities, closed forms
-and brute force in tests/test_oracle_pins.py; the MLP by finite differences.
+and brute force in tests/test_oracle_pins.py; the MLP by finite differences; the plasmon-pole
+fit and the self-energies in tests/test_oracle_sigma.py.
 Absolute values for the synthetic crystals beyond those pins are parity
 unpinned: the oracle is the reference.
 """
