@@ -339,6 +339,70 @@ typedef struct {
 
 int xo_xterm(const xo_xterm_args* a, void* stream);
 
+/* ------------------------------------------------------------------------- */
+/* Godby-Needs plasmon-pole model of the screened interaction (Quasi-particle
+ * corrections section, plasmon-pole paragraph; Eq. W_def). Every element of
+ * X = eps~^-1 - 1 (eps~^-1 as written by xo_epsinv with XO_EPS_SYM) gets one
+ * pole pair X(w) = R [1/(w - Om) - 1/(w + Om)], fixed by X(0) and X(i omega_p):
+ *   Om = omega_p sqrt(Xp / (X0 - Xp))  (principal root),  R = -X0 Om / 2,
+ * where Re(Xp conj(X0 - Xp)) > 0 (evaluated without fused operations); any
+ * other element keeps its static value: Om = omega_p, R = -X0 omega_p / 2.
+ * Output is the residue of the screened part of W, Wr = R vsqrt_G vsqrt_G',
+ * and Om. At q = 0 pass vsqrt[0] = 0 (wings) and the cell average of 4pi/q^2
+ * as head (>= 0), which replaces vsqrt_0^2 for the (0, 0) element; head < 0
+ * means no override. FP64.
+ *   einv0, einvp: [device] [ng][ng] complex128 (eps~^-1 at 0 and i omega_p)
+ *   vsqrt: [host] [ng] sqrt(4 pi)/|q+G| (finite, >= 0)
+ *   wr, om: [device] [ng][ng] complex128, written (may not alias the inputs).
+ * Errors: XO_ERR_ARG for ng <= 0, null pointers, omega_p <= 0, bad vsqrt. */
+typedef struct {
+  int ng;
+  const void* einv0;
+  const void* einvp;
+  double omega_p;
+  const double* vsqrt;
+  double head;
+  void* wr;
+  void* om;
+} xo_ppa_args;
+
+int xo_ppa_fit(const xo_ppa_args* a, void* stream);
+
+/* Diagonal GW self-energy matrix elements of one q (Eq. sigma_c with the
+ * plasmon-pole W, whose frequency integral is done in closed form; Eq. I_c
+ * for the index order):
+ *   sigc[n][j] (+)= pref sum_m sum_{G,G'} rho_nm(G) conj(rho_nm(G')) Wr_GG'
+ *                   [ f_m / (z_nj - e_m + Om_GG' - i eta) + (1 - f_m) / (z_nj - e_m - Om_GG' + i eta) ]
+ *   sigx[n]    (+)= -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G,  v_G = vsqrt_G^2 (head at G = 0 if >= 0)
+ * rho_nm(G) = <n k| e^{i(q+G).r} |m k-q> as written by xo_rho with the states n
+ * on the conduction side (at k) and the bands m on the valence side (at k-q).
+ * pref = 1/(N_k Omega); e_m in Ha on the scale of z; f_m in [0, 1] per spin.
+ * Sum over q by calling once per q with accumulate = 1 after the first.
+ *   rho: [device] [nm][nn][ng] complex128; wr, om: [device] [ng][ng] complex128
+ *   (from xo_ppa_fit); e_m, f_m: [device] [nm]; z: [device] [nn][nz] complex128
+ *   (nz <= 4; z may be complex, e.g. i nu with eta = 0 on the imaginary axis);
+ *   vsqrt: [host] [ng] (needed when sigx is set); sigx: [device] [nn] or NULL;
+ *   sigc: [device] [nn][nz] complex128 (unused when nz = 0).
+ * Errors: XO_ERR_ARG for bad sizes, nz > 4, null pointers, pref <= 0, eta < 0. */
+typedef struct {
+  int nm, nn, ng, nz;
+  const void* rho;
+  const void* wr;
+  const void* om;
+  const double* e_m;
+  const double* f_m;
+  const void* z;
+  double eta;
+  double pref;
+  const double* vsqrt;
+  double head;
+  double* sigx;
+  void* sigc;
+  int accumulate;
+} xo_sigma_args;
+
+int xo_sigma(const xo_sigma_args* a, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,3 +114,48 @@ def sigma_x(rho, f_m, vsqrt, head, pref: float):
         for m in range(nm):
             out[n] -= pref * float(f_m[m]) * np.sum(np.abs(rho[m, n]) ** 2 * v)
     return out
+
+
+def coulomb_head_average(nk: int, omega: float) -> float:
+    """Cell average of 4 pi / q^2 at q = 0, over the sphere whose volume is the
+    Brillouin-zone share of one k-point, (2 pi)^3 / (N_k Omega) (a reading: the paper
+    leaves the q = 0 treatment of Sigma to the Coulomb subsection's options)."""
+    qc = (6.0 * np.pi ** 2 / (nk * omega)) ** (1.0 / 3.0)
+    # int_0^qc 4 pi q^2 (4 pi / q^2) dq / (4/3 pi qc^3)
+    return 16.0 * np.pi ** 2 * qc / (4.0 / 3.0 * np.pi * qc ** 3)
+
+
+def sigma_kpoint(crs, einv_by_q, ik0: int, states, z, eta: float = 0.0, omega_p: float = 1.0):
+    """Sigma_x and Sigma_c of the states n at k-point ik0, summed over the q of `crs`.
+
+    crs: one crystal per q sharing the orbitals; einv_by_q[iq] = eps~^-1 at (0, i omega_p);
+    the bands m at k - q are all the stored bands, occupied ones with f = 1.
+    Returns (sigx [n], sigc [n, j])."""
+    from .rho import rho_fft
+    states = list(states)
+    z = np.asarray(z, np.complex128).reshape(len(states), -1)
+    sx = np.zeros(len(states))
+    sc = np.zeros(z.shape, np.complex128)
+    for cr, E in zip(crs, einv_by_q):
+        ik, ikp, g0 = cr.pairs[ik0]
+        assert ik == ik0
+        nb = cr.coef[ikp].shape[0]
+        rho = rho_fft(cr.coef[ik0][states], cr.mill[ik0], cr.coef[ikp], cr.mill[ikp], cr.gmill, g0, cr.grid)
+        qg = (cr.qf @ cr.lat.bvec)[None, :] + cr.gmill.astype(np.float64) @ cr.lat.bvec
+        nrm = np.sqrt(np.sum(qg * qg, axis=1))
+        head = None
+        assert np.all(cr.gmill[0] == 0)
+        if cr.q0:
+            s = np.zeros_like(nrm)
+            s[1:] = np.sqrt(4.0 * np.pi) / nrm[1:]
+            head = coulomb_head_average(cr.nk, cr.lat.omega)
+        else:
+            s = np.sqrt(4.0 * np.pi) / nrm
+        R, Om = ppa_fit(E[0], E[1], omega_p)
+        Wr = R * coulomb_factor(s, head)
+        f = np.zeros(nb)
+        f[:cr.nocc_at(ikp)] = 1.0
+        pref = 1.0 / (cr.nk * cr.lat.omega)
+        sx += sigma_x(rho, f, s, head, pref)
+        sc += sigma_c_ppa(rho, Wr, Om, cr.eps[ikp], f, z, eta, pref)
+    return sx, sc

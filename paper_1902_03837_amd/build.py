@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libxo.so")
 OBJ = os.path.join(ROOT, "_build")
 
-SOURCES = ["xo_api.hip", "rho.hip", "rho_batch.hip", "rho_gemm.hip", "chi0.hip", "epsinv.hip", "mlp.hip", "xterm.hip"]
+SOURCES = ["xo_api.hip", "rho.hip", "rho_batch.hip", "rho_gemm.hip", "chi0.hip", "epsinv.hip", "mlp.hip", "xterm.hip", "sigma.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

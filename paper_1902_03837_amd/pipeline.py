@@ -101,3 +101,54 @@ def run_crystal(dc: DeviceCrystal, nempty=None, chi_prec=None, M=None, dE=None, 
     xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=chi_prec or dc.prec, check_dE=check_dE, stream=stream)
     xo.epsinv(chi, cr.qpg(), out=E, stream=stream)
     return M, dE, chi, E
+
+
+def q0_coulomb_head(nk: int, omega: float) -> float:
+    """Mean of 4 pi / q^2 over a sphere of volume (2 pi)^3 / (N_k Omega) around q = 0:
+    (3 / qc^3) * 4 pi * qc with qc the sphere's radius."""
+    qc = (6.0 * np.pi ** 2 / (nk * omega)) ** (1.0 / 3.0)
+    return 12.0 * np.pi / (qc * qc)
+
+
+class SigmaPlan:
+    """Device buffers and per-q argument lists for the self-energy of states at one k-point."""
+
+    def __init__(self, dc: DeviceCrystal, crs, ik0: int, states: slice):
+        assert dc.prec == "fp64", "the self-energy path takes FP64 orbitals"
+        self.dc, self.crs, self.ik0, self.states = dc, crs, ik0, states
+        dev = dc.coef[0].device
+        self.nn = states.stop - states.start
+        self.qs = []
+        for cr in crs:
+            ik, ikp, g0 = cr.pairs[ik0]
+            assert ik == ik0 and np.all(cr.gmill[0] == 0)
+            ng, nb = cr.gmill.shape[0], dc.coef[ikp].shape[0]
+            qpg = cr.qpg()
+            s = np.sqrt(4.0 * np.pi) / qpg
+            head = None
+            if cr.q0:
+                s[0] = 0.0
+                head = q0_coulomb_head(cr.nk, cr.lat.omega)
+            f = torch.zeros(nb, dtype=torch.float64, device=dev)
+            f[:cr.nocc_at(ikp)] = 1.0
+            self.qs.append(dict(ikp=ikp, g0=g0, ng=ng, nb=nb, vsqrt=s, head=head, f=f, cr=cr,
+                                rho=torch.empty((nb, self.nn, ng), dtype=torch.complex128, device=dev),
+                                wr=torch.empty((ng, ng), dtype=torch.complex128, device=dev),
+                                om=torch.empty((ng, ng), dtype=torch.complex128, device=dev)))
+
+
+def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0, stream=None):
+    """Sigma_x and Sigma_c of the planned states, summed over q: per q one xo_rho
+    (states at k against every band at k - q, no q -> 0 substitution), one
+    xo_ppa_fit on eps~^-1 at (0, i omega_p) and one xo_sigma."""
+    dc, st = plan.dc, plan.states
+    for iq, Q in enumerate(plan.qs):
+        cr, ikp = Q["cr"], Q["ikp"]
+        xo.rho(dc.coef[plan.ik0][st], cr.mill[plan.ik0], None, dc.coef[ikp], cr.mill[ikp], None,
+               cr.gmill, Q["g0"], cr.grid, out=Q["rho"], prec="fp64", kcart=cr.kcart(plan.ik0),
+               bvec=cr.lat.bvec, stream=stream)
+        E = einv_by_q[iq]
+        xo.ppa_fit(E[0], E[1], omega_p, Q["vsqrt"], Q["head"], wr=Q["wr"], om=Q["om"], stream=stream)
+        xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, 1.0 / (cr.nk * cr.lat.omega),
+                 sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, stream=stream)
+    return sigc, sigx

@@ -71,6 +71,18 @@ class XtermArgs(C.Structure):
     ]
 
 
+class PpaArgs(C.Structure):
+    _fields_ = [("ng", C.c_int), ("einv0", C.c_void_p), ("einvp", C.c_void_p), ("omega_p", C.c_double),
+                ("vsqrt", _f64p), ("head", C.c_double), ("wr", C.c_void_p), ("om", C.c_void_p)]
+
+
+class SigmaArgs(C.Structure):
+    _fields_ = [("nm", C.c_int), ("nn", C.c_int), ("ng", C.c_int), ("nz", C.c_int), ("rho", C.c_void_p),
+                ("wr", C.c_void_p), ("om", C.c_void_p), ("e_m", C.c_void_p), ("f_m", C.c_void_p),
+                ("z", C.c_void_p), ("eta", C.c_double), ("pref", C.c_double), ("vsqrt", _f64p),
+                ("head", C.c_double), ("sigx", C.c_void_p), ("sigc", C.c_void_p), ("accumulate", C.c_int)]
+
+
 class Tune(C.Structure):
     _fields_ = [("nt_tiles", C.c_int), ("kper", C.c_int), ("wg_per_cu", C.c_int)]
 
@@ -86,7 +98,7 @@ _LIB = None
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
-           "xo_xterm")
+           "xo_xterm", "xo_ppa_fit", "xo_sigma")
 
 
 def lib():
@@ -99,7 +111,7 @@ def lib():
         L.xo_last_error.restype = C.c_char_p
         L.xo_version.restype = C.c_char_p
         for name, argt in (("xo_rho", RhoArgs), ("xo_chi0", Chi0Args), ("xo_epsinv", EpsArgs),
-                           ("xo_xterm", XtermArgs)):
+                           ("xo_xterm", XtermArgs), ("xo_ppa_fit", PpaArgs), ("xo_sigma", SigmaArgs)):
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
@@ -422,3 +434,57 @@ def xterm(coef_v, mill_v, e_v, ebar, gmill, omegas, pref, rho_m, nn, out, stream
     a.pref, a.nn, a.rho, a.out = float(pref), int(nn), _ptr(rho_m), _ptr(out)
     _check(lib().xo_xterm(C.byref(a), _stream(stream)))
     return out
+
+
+def _host_f64(a, n):
+    v = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    assert v.shape == (n,), (v.shape, n)
+    return v
+
+
+def ppa_fit(einv0, einvp, omega_p, vsqrt, head=None, *, wr, om, stream=None):
+    """xo_ppa_fit: plasmon-pole residue of W_c (wr) and pole energies (om), [ng][ng] complex128."""
+    import torch
+    ng = einv0.shape[-1]
+    for t in (einv0, einvp, wr, om):
+        assert tuple(t.shape) == (ng, ng) and t.dtype == torch.complex128 and t.is_contiguous()
+    vs = _host_f64(vsqrt, ng)
+    a = PpaArgs()
+    a.ng, a.einv0, a.einvp, a.omega_p = ng, _ptr(einv0), _ptr(einvp), float(omega_p)
+    a.vsqrt, a.head = vs.ctypes.data_as(_f64p), -1.0 if head is None else float(head)
+    a.wr, a.om = _ptr(wr), _ptr(om)
+    _check(lib().xo_ppa_fit(C.byref(a), _stream(stream)))
+    return wr, om
+
+
+def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=None, head=None,
+          accumulate=False, stream=None):
+    """xo_sigma for one q: sigc[nn][nz] (complex128) and sigx[nn] (float64), (+)=.
+
+    rho_m [nm][nn][ng] complex128 (xo_rho with the states n on the conduction side),
+    e_m, f_m [nm] float64 and z [nn][nz] complex128 on the device."""
+    import torch
+    nm, nn, ng = rho_m.shape
+    assert rho_m.dtype == torch.complex128 and rho_m.is_contiguous()
+    assert e_m.dtype == f_m.dtype == torch.float64 and e_m.numel() == nm and f_m.numel() == nm
+    nz = 0 if z is None else z.shape[1]
+    if nz:
+        assert tuple(z.shape) == (nn, nz) and z.dtype == torch.complex128 and z.is_contiguous()
+        assert sigc is not None and tuple(sigc.shape) == (nn, nz) and sigc.dtype == torch.complex128
+        for t in (wr, om):
+            assert tuple(t.shape) == (ng, ng) and t.dtype == torch.complex128 and t.is_contiguous()
+    if sigx is not None:
+        assert tuple(sigx.shape) == (nn,) and sigx.dtype == torch.float64 and vsqrt is not None
+    vs = _host_f64(vsqrt, ng) if vsqrt is not None else None
+    a = SigmaArgs()
+    a.nm, a.nn, a.ng, a.nz = nm, nn, ng, nz
+    a.rho, a.wr, a.om = _ptr(rho_m), _ptr(wr) if nz else None, _ptr(om) if nz else None
+    a.e_m, a.f_m, a.z = _ptr(e_m), _ptr(f_m), _ptr(z) if nz else None
+    a.eta, a.pref = float(eta), float(pref)
+    a.vsqrt = vs.ctypes.data_as(_f64p) if vs is not None else None
+    a.head = -1.0 if head is None else float(head)
+    a.sigx = _ptr(sigx) if sigx is not None else None
+    a.sigc = _ptr(sigc) if nz else None
+    a.accumulate = 1 if accumulate else 0
+    _check(lib().xo_sigma(C.byref(a), _stream(stream)))
+    return sigc, sigx

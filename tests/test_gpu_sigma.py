@@ -1,0 +1,181 @@
+"""GPU parity of the plasmon-pole fit and the GW self-energy against the FP64 oracle.
+
+xo_ppa_fit and xo_sigma through the C ABI on seeded inputs (G-sets spanning
+several 32 x 64 blocks with ragged edges, band counts that split into chunks,
+fractional occupations, the q = 0 head override, one-element cases), then the
+whole chain for the c1 crystal family: eps~^-1 at (0, i 1 Ha) of every q from the
+library, oscillator strengths, fit and self-energies summed over q, against the
+oracle's chain.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from synth import crystal_for  # noqa: E402
+from synth.crystal import find_pairs  # noqa: E402
+from synth.rand import random_complex, rng  # noqa: E402
+from oracle.sigma import ppa_fit, coulomb_factor, sigma_c_ppa, sigma_x, sigma_kpoint  # noqa: E402
+from oracle.pipeline import epsinv_crystal  # noqa: E402
+from paper_1902_03837_amd import xo  # noqa: E402
+from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal, SigmaPlan, sigma_kpoint as sigma_gpu  # noqa: E402
+
+DEV = "cuda"
+TOL = 1e-11
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+
+
+def _to(a, dt=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dt)
+
+
+def _einv_pair(seed, ng):
+    """eps~^-1 - 1 at 0 and i omega_p shaped like a screened response: a Hermitian
+    negative part decaying with frequency plus element noise (so some elements fail
+    the fit condition)."""
+    A = random_complex(seed, (ng, ng), 0.3)
+    X0 = -(A @ A.conj().T) / ng - 0.2 * np.eye(ng)
+    Xp = 0.55 * X0 + random_complex(seed + 1, (ng, ng), 0.02)
+    return X0 + np.eye(ng), Xp + np.eye(ng)
+
+
+@pytest.mark.parametrize("ng,head", [(1, None), (1, 3.0), (130, None), (130, 2.5), (400, None)])
+def test_ppa_fit_matches_oracle(ng, head):
+    say(f"ppa_fit ng={ng} head={head}")
+    e0, ep = _einv_pair(10 + ng, ng)
+    s = rng(ng).uniform(0.2, 3.0, ng)
+    if head is not None:
+        s[0] = 0.0
+    R, Om = ppa_fit(e0, ep, 1.0)
+    Wr_ref = R * coulomb_factor(s, head)
+    wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
+    om = torch.empty_like(wr)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, head, wr=wr, om=om)
+    torch.cuda.synchronize()
+    wr, om = wr.cpu().numpy(), om.cpu().numpy()
+    # same fit decision everywhere (the fallback pole sits exactly at omega_p)
+    assert np.array_equal(om == 1.0, Om == 1.0)
+    assert np.max(np.abs(om - Om)) <= TOL * np.max(np.abs(Om))
+    assert np.max(np.abs(wr - Wr_ref)) <= TOL * max(np.max(np.abs(Wr_ref)), 1e-300)
+    if ng > 1:
+        assert 0 < np.sum(Om != 1.0) < ng * ng
+
+
+SIGMA_CASES = [
+    # nm, nn, ng, nz, fractional occupations
+    (7, 3, 97, 3, False),
+    (1, 1, 1, 1, False),
+    (40, 2, 130, 4, True),
+    (5, 2, 33, 0, False),
+    (300, 1, 65, 2, False),
+]
+
+
+@pytest.mark.parametrize("nm,nn,ng,nz,frac", SIGMA_CASES)
+def test_sigma_matches_oracle(nm, nn, ng, nz, frac):
+    say(f"sigma nm={nm} nn={nn} ng={ng} nz={nz} frac={frac}")
+    seed = nm * 1000 + ng
+    e0, ep = _einv_pair(seed, ng)
+    s = rng(seed + 2).uniform(0.2, 3.0, ng)
+    R, Om = ppa_fit(e0, ep, 1.0)
+    Wr = R * coulomb_factor(s)
+    rho = random_complex(seed + 3, (nm, nn, ng), 0.2)
+    g = rng(seed + 4)
+    e = np.sort(g.uniform(-1.0, 1.5, nm))
+    f = (e < 0.1).astype(float)
+    if frac:
+        f[g.integers(0, nm, 5)] = 0.5
+    z = (g.uniform(-0.5, 0.8, (nn, max(nz, 1))) + 1j * g.uniform(-0.05, 0.05, (nn, max(nz, 1))))[:, :nz]
+    eta, pref = 0.02, 0.013
+    sx_ref = sigma_x(rho, f, s, None, pref)
+    wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
+    om = torch.empty_like(wr)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, None, wr=wr, om=om)
+    sigc = torch.full((nn, nz), 7.0 + 7.0j, dtype=torch.complex128, device=DEV) if nz else None
+    sigx = torch.full((nn,), 7.0, dtype=torch.float64, device=DEV)
+    args = (_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z) if nz else None, eta, pref)
+    xo.sigma(*args, sigc=sigc, sigx=sigx, vsqrt=s)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(sigx.cpu().numpy() - sx_ref)) <= TOL * np.max(np.abs(sx_ref))
+    if nz:
+        sc_ref = sigma_c_ppa(rho, Wr, Om, e, f, z, eta, pref)
+        got = sigc.cpu().numpy()
+        assert np.max(np.abs(got - sc_ref)) <= TOL * np.max(np.abs(sc_ref)), (got, sc_ref)
+    # accumulate: a second call adds the same values
+    xo.sigma(*args, sigc=sigc, sigx=sigx, vsqrt=s, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(sigx.cpu().numpy() - 2 * sx_ref)) <= TOL * np.max(np.abs(sx_ref))
+    if nz:
+        assert np.max(np.abs(sigc.cpu().numpy() - 2 * sc_ref)) <= 2 * TOL * np.max(np.abs(sc_ref))
+
+
+def test_sigma_head_override_at_q0():
+    say("sigma q=0 head override")
+    nm, nn, ng = 6, 2, 40
+    e0, ep = _einv_pair(77, ng)
+    s = rng(78).uniform(0.2, 3.0, ng)
+    s[0] = 0.0
+    head = 4.2
+    R, Om = ppa_fit(e0, ep, 1.0)
+    Wr = R * coulomb_factor(s, head)
+    rho = random_complex(79, (nm, nn, ng), 0.2)
+    e = np.linspace(-0.8, 1.2, nm)
+    f = (e < 0).astype(float)
+    z = np.array([[0.1 + 0.01j, 0.3 + 0.0j], [-0.2 + 0.0j, 0.5 + 0.02j]])
+    wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
+    om = torch.empty_like(wr)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, head, wr=wr, om=om)
+    sigc = torch.empty((nn, 2), dtype=torch.complex128, device=DEV)
+    sigx = torch.empty((nn,), dtype=torch.float64, device=DEV)
+    xo.sigma(_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, 0.5,
+             sigc=sigc, sigx=sigx, vsqrt=s, head=head)
+    torch.cuda.synchronize()
+    sc_ref = sigma_c_ppa(rho, Wr, Om, e, f, z, 0.01, 0.5)
+    sx_ref = sigma_x(rho, f, s, head, 0.5)
+    assert np.max(np.abs(sigc.cpu().numpy() - sc_ref)) <= TOL * np.max(np.abs(sc_ref))
+    assert np.max(np.abs(sigx.cpu().numpy() - sx_ref)) <= TOL * np.max(np.abs(sx_ref))
+
+
+def test_sigma_chain_c1_small_all_q():
+    """Whole chain for the c1 family (fcc, 4 k-points, 8 occupied + 12 empty bands, NG = 59,
+    frequencies 0 and i 1 Ha): Sigma_x and Sigma_c of four bands around the gap at Gamma,
+    summed over all four q, each q's eps~^-1 from the library."""
+    base = crystal_for("c1_small")
+    assert np.allclose(base.omegas, [0.0, 1.0])
+    crs = [dataclasses.replace(base, qf=q.copy(), pairs=find_pairs(base.kf, q)) for q in base.kf]
+    dc = DeviceCrystal.upload(base, "fp64")
+    Es = []
+    for iq, cr in enumerate(crs):
+        say(f"sigma chain: eps~^-1 of q {iq}")
+        dcq = DeviceCrystal(cr, "fp64", dc.coef, dc.eps)
+        Es.append(run_crystal(dcq)[3].clone())
+    ik0, states = 0, slice(base.nocc - 2, base.nocc + 2)
+    nn = states.stop - states.start
+    z = np.stack([base.eps[ik0][states] + d for d in (-0.05, 0.0, 0.05)], axis=1).astype(np.complex128)
+    plan = SigmaPlan(dc, crs, ik0, states)
+    sigc = torch.empty((nn, 3), dtype=torch.complex128, device=DEV)
+    sigx = torch.empty((nn,), dtype=torch.float64, device=DEV)
+    sigma_gpu(plan, Es, _to(z), sigc, sigx, eta=0.01)
+    torch.cuda.synchronize()
+    say("sigma chain: oracle")
+    E_ref = [epsinv_crystal(cr)[0] for cr in crs]
+    sx_ref, sc_ref = sigma_kpoint(crs, E_ref, ik0, range(states.start, states.stop), z, eta=0.01)
+    gx, gc = sigx.cpu().numpy(), sigc.cpu().numpy()
+    say(f"Sigma_x {gx} Sigma_c(e_n) {gc[:, 1]}")
+    assert np.all(sx_ref < 0)
+    assert np.max(np.abs(gx - sx_ref)) <= 1e-9 * np.max(np.abs(sx_ref))
+    assert np.max(np.abs(gc - sc_ref)) <= 1e-9 * np.max(np.abs(sc_ref))
