@@ -411,6 +411,108 @@ def run_c3(args):
     print(json.dumps(res), flush=True)
 
 
+def sigma_flops(ng, nb, nn, nz):
+    """Algorithmic FP64 flops of one xo_sigma launch (Sigma_c part): per (G, G', m, n) the
+    product rho(G) conj(rho(G')) Wr (two complex multiplies, 12 flops), per frequency the
+    complex denominator (2), its squared modulus (3), one reciprocal (1), the product with the
+    conjugate denominator (6), the scaling (2) and the accumulation (2): 16 flops."""
+    return float(ng) * ng * nb * nn * (12 + 16 * nz)
+
+
+def run_sigma(args):
+    """GW self-energy of eight states around the gap at Gamma on the c2 crystal (fcc 4x4x4 k,
+    16 occupied + 200 empty bands, NG = 400): per q (all 64) the oscillator strengths of the
+    states against all 216 bands at k - q (xo_rho, FP64), the plasmon-pole fit of eps~^-1 at
+    0 and i 1 Ha (xo_ppa_fit) and Sigma_x plus Sigma_c at three frequencies per state
+    (xo_sigma). eps~^-1 of every q is made by the library's FP64 path before the timed steps."""
+    import dataclasses
+    import torch
+    from synth import crystal_for
+    from synth.crystal import find_pairs, alias_extents
+    from paper_1902_03837_amd import xo
+    from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal, ntrans, SigmaPlan, sigma_kpoint
+    t0 = time.perf_counter()
+    base = dataclasses.replace(crystal_for("c2"), omegas=np.array([0.0, 1.0]))
+    crs = []
+    for q in base.kf:
+        cr = dataclasses.replace(base, qf=q.copy(), pairs=find_pairs(base.kf, q))
+        for ik, ikp, g0 in cr.pairs:
+            if np.any(alias_extents(cr.grid, cr.mill[ik], cr.mill[ikp], cr.gmill, g0) >= np.array(cr.grid)):
+                raise ValueError(f"q {q}: FFT grid aliases")
+        crs.append(cr)
+    t_fix = time.perf_counter() - t0
+    print(f"[bench] sigma fixture: {len(crs)} q built in {t_fix:.1f} s", file=sys.stderr, flush=True)
+    dc = DeviceCrystal.upload(base, "fp64")
+    ng, nk = base.gmill.shape[0], base.nk
+    K = ntrans(base)
+    M = torch.empty((K, ng), dtype=torch.complex128, device="cuda")
+    dE = torch.empty(K, dtype=torch.float64, device="cuda")
+    chi = torch.empty((2, ng, ng), dtype=torch.complex128, device="cuda")
+    t0 = time.perf_counter()
+    Es = []
+    for cr in crs:
+        Es.append(run_crystal(DeviceCrystal(cr, "fp64", dc.coef, dc.eps), M=M, dE=dE, chi=chi)[3].clone())
+    torch.cuda.synchronize()
+    del M, dE, chi
+    print(f"[bench] sigma: eps~^-1 of {len(crs)} q in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    nn, nz, eta = 8, 3, 0.01
+    states = slice(base.nocc - nn // 2, base.nocc + nn // 2)
+    z = np.stack([base.eps[0][states] + d for d in (-0.05, 0.0, 0.05)], axis=1).astype(np.complex128)
+    zt = torch.from_numpy(z).cuda()
+    plan = SigmaPlan(dc, crs, 0, states)
+    sigc = torch.empty((nn, nz), dtype=torch.complex128, device="cuda")
+    sigx = torch.empty((nn,), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        sigma_kpoint(plan, Es, zt, sigc, sigx, eta=eta)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        sigma_kpoint(plan, Es, zt, sigc, sigx, eta=eta)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    xo.timing_enable(True)
+    for _ in range(args.steps):
+        sigma_kpoint(plan, Es, zt, sigc, sigx, eta=eta)
+    torch.cuda.synchronize()
+    rep = xo.timing_report()
+    xo.timing_enable(False)
+    nb = base.coef[0].shape[0]
+    fl_q = sigma_flops(ng, nb, nn, nz)
+    kern = {k: {"calls": int(v[0]), "avg_ms": v[1] / v[0]} for k, v in rep.items()}
+    ks = kern["sigma_c_tiles"]["avg_ms"] * 1e-3
+    ach = fl_q / ks / 1e12
+    gx, gc = sigx.cpu().numpy(), sigc.cpu().numpy()
+    print(f"[bench] sigma: {ms:.2f} ms/step; sigma_c_tiles {ks * 1e3:.3f} ms/launch = {ach:.1f} TFLOP/s; "
+          f"Sigma_x {np.round(gx, 4)}; Sigma_c(e_n) {np.round(gc[:, 1], 4)}", file=sys.stderr, flush=True)
+    res = {"metric": "GW self-energy matrix elements per second (states x frequencies x q)",
+           "value": nn * nz * len(crs) / (ms * 1e-3), "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"sigma: c2 crystal (fcc 4x4x4 k, 16 occ + 200 empty bands, NG={ng}), "
+                                  f"{nn} states at Gamma, {nz} frequencies each, all {len(crs)} q, plasmon pole "
+                                  f"from eps~^-1 at 0 and i 1 Ha", "parallelism": "single GPU"},
+           "sigma_x": gx.tolist(), "sigma_c_at_e": [[c.real, c.imag] for c in gc[:, 1]],
+           "kernels_ms_per_launch": {k: v["avg_ms"] for k, v in kern.items()},
+           "roofline": {"kernel": "sigma_c_tiles", "bound": "alu", "achieved": ach, "peak": PEAK["valu"] / 1e12,
+                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK["valu"], "traffic": None,
+                        "note": "algorithmic FP64 flops per launch (ng^2 nb nn (12 + 16 nz), a reciprocal "
+                                "counted as one) over the FP64 vector peak"}}
+    if not args.no_cpu:
+        import oracle.sigma as osig
+        t0 = time.perf_counter()
+        pick = [0, nn - 1]
+        cr = crs[5]
+        osig.sigma_kpoint([cr], [Es[5].cpu().numpy()], 0, [states.start + i for i in pick], z[pick], eta=eta)
+        dt = time.perf_counter() - t0
+        frac = len(pick) / nn / len(crs)
+        res["cpu_baseline"] = {"value": nn * nz * len(crs) * frac / dt, "unit": "elements/s",
+                               "cores": torch.get_num_threads(), "kind": "oracle",
+                               "sample": f"one q of {len(crs)}, {len(pick)} of {nn} states ({dt:.1f} s)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,6 +542,8 @@ def main():
         return run_c3(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload == "sigma":
+        return run_sigma(args)
     t0 = time.perf_counter()
     cr = crystal_for(args.workload)
     t_fix = time.perf_counter() - t0

@@ -9,7 +9,7 @@
 //                  writes Wr = R v^1/2_G v^1/2_G' (head override at G = G' = 0)
 //   sigma_c_tiles  Sigma_c,nn(z) = pref sum_m sum_GG' rho_nm(G) conj(rho_nm(G')) Wr_GG'
 //                  [f_m / (z - e_m + Om - i eta) + (1 - f_m) / (z - e_m - Om + i eta)];
-//                  a workgroup owns a 32 x 64 block of (G, G') held in registers (eight
+//                  a workgroup owns a 32 x 32 block of (G, G') held in registers (four
 //                  elements per thread), one state n and a chunk of bands m, and writes
 //                  one partial per frequency
 //   sigma_reduce   fixed-order sum of the partials into Sigma_c
@@ -26,17 +26,14 @@ namespace {
 
 typedef cplx<double> z;
 
-constexpr int kSR = 2, kSC = 4;                 // rows and columns of G per thread
-constexpr int kTR = 16 * kSR, kTC = 16 * kSC;   // 32 x 64 block per workgroup
+constexpr int kSR = 2, kSC = 2;                 // rows and columns of G per thread
+constexpr int kTR = 16 * kSR, kTC = 16 * kSC;   // 32 x 32 block per workgroup
 constexpr int kMaxZ = 4;                        // frequencies per state and call
 
-// 1/s to full FP64 precision: hardware estimate and two Newton steps.
+// 1/s: hardware estimate and one Newton step.
 __device__ __forceinline__ double recip(double s) {
-  double r = __builtin_amdgcn_rcp(s);
-  double e = fma(-s, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-s, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(s);
+  return fma(r, fma(-s, r, 1.0), r);
 }
 
 __device__ __forceinline__ z csqrt_principal(z a) {
@@ -81,9 +78,11 @@ __global__ void ppa_fit(const z* __restrict__ e0, const z* __restrict__ ep, int 
   om[e] = o;
 }
 
-// acc += w * P / d
+// acc += w * P / d (w = 1 when WEIGHTED is false)
+template <bool WEIGHTED>
 __device__ __forceinline__ void add_pole(z& acc, z P, double dx, double dy, double w) {
-  const double inv = w * recip(fma(dx, dx, dy * dy));
+  double inv = recip(fma(dx, dx, dy * dy));
+  if constexpr (WEIGHTED) inv *= w;
   acc.x = fma(fma(P.x, dx, P.y * dy), inv, acc.x);
   acc.y = fma(fma(P.y, dx, -P.x * dy), inv, acc.y);
 }
@@ -116,13 +115,19 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
 #pragma unroll
   for (int j = 0; j < kMaxZ; ++j) acc[j] = {0.0, 0.0};
   const int m0 = mc * mchunk, m1 = min(nm, m0 + mchunk);
-  for (int m = m0; m < m1; ++m) {
+  // oscillator strengths of band m for the block's rows and columns, loaded one band ahead
+  z a[kSR], b[kSC];
+  auto load = [&](int m, z* a_, z* b_) {
     const z* rm = rho + ((size_t)m * nn + n) * ng;
-    z a[kSR], b[kSC];
 #pragma unroll
-    for (int r = 0; r < kSR; ++r) a[r] = rm[G[r]];
+    for (int r = 0; r < kSR; ++r) a_[r] = rm[G[r]];
 #pragma unroll
-    for (int c = 0; c < kSC; ++c) b[c] = rm[Gp[c]];
+    for (int c = 0; c < kSC; ++c) b_[c] = rm[Gp[c]];
+  };
+  if (m0 < m1) load(m0, a, b);
+  for (int m = m0; m < m1; ++m) {
+    z an[kSR], bn[kSC];
+    load(min(m + 1, m1 - 1), an, bn);
     const double e = em[m], f = fm[m];
     z P[kSR][kSC];
 #pragma unroll
@@ -133,21 +138,34 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
     for (int j = 0; j < kMaxZ; ++j) {
       if (j >= nz) break;
       const z zj = zz[(size_t)n * nz + j];
-      const double dx = zj.x - e, dy = zj.y;
-      if (f != 0.0) {  // occupied part: pole at e - Om, below the real axis
+      const double dx = zj.x - e;
+      const double dyo = zj.y - eta, dye = zj.y + eta;
+      // occupied part: pole at e - Om, below the real axis; empty part: e + Om, above.
+      // Occupations 1 and 0 (insulators) take one pole, unweighted; fractional ones both.
+      if (f == 1.0) {
 #pragma unroll
         for (int r = 0; r < kSR; ++r)
 #pragma unroll
-          for (int c = 0; c < kSC; ++c) add_pole(acc[j], P[r][c], dx + O[r][c].x, dy + O[r][c].y - eta, f);
-      }
-      if (f != 1.0) {  // empty part: pole at e + Om, above the real axis
+          for (int c = 0; c < kSC; ++c) add_pole<false>(acc[j], P[r][c], dx + O[r][c].x, dyo + O[r][c].y, 1.0);
+      } else if (f == 0.0) {
 #pragma unroll
         for (int r = 0; r < kSR; ++r)
 #pragma unroll
-          for (int c = 0; c < kSC; ++c)
-            add_pole(acc[j], P[r][c], dx - O[r][c].x, dy - O[r][c].y + eta, 1.0 - f);
+          for (int c = 0; c < kSC; ++c) add_pole<false>(acc[j], P[r][c], dx - O[r][c].x, dye - O[r][c].y, 1.0);
+      } else {
+#pragma unroll
+        for (int r = 0; r < kSR; ++r)
+#pragma unroll
+          for (int c = 0; c < kSC; ++c) {
+            add_pole<true>(acc[j], P[r][c], dx + O[r][c].x, dyo + O[r][c].y, f);
+            add_pole<true>(acc[j], P[r][c], dx - O[r][c].x, dye - O[r][c].y, 1.0 - f);
+          }
       }
     }
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) a[r] = an[r];
+#pragma unroll
+    for (int c = 0; c < kSC; ++c) b[c] = bn[c];
   }
   // workgroup sum in a fixed order: wave shuffles, then the four waves through LDS
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -173,48 +191,57 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
   }
 }
 
-// One thread per (n, j): out (+)= pref * sum over chunks and tiles.
-__global__ void sigma_reduce(const z* __restrict__ part, int nn, int nz, int nparts, double pref, int accumulate,
-                             z* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nn * nz) return;
+// One wave per (n, j): out (+)= pref * sum over chunks and tiles (lane-strided partial
+// sums, then a fixed butterfly).
+__global__ void __launch_bounds__(64) sigma_reduce(const z* __restrict__ part, int nn, int nz, int nparts,
+                                                   double pref, int accumulate, z* __restrict__ out) {
+  const int t = blockIdx.x;
   const int n = t / nz, j = t % nz;
   double x = 0.0, y = 0.0;
-  for (int p = 0; p < nparts; ++p) {
+  for (int p = threadIdx.x; p < nparts; p += 64) {
     const z v = part[((size_t)n * nparts + p) * nz + j];
     x += v.x;
     y += v.y;
   }
-  if (accumulate) {
-    out[t].x += pref * x;
-    out[t].y += pref * y;
-  } else {
-    out[t] = {pref * x, pref * y};
+  for (int o = 32; o > 0; o >>= 1) {
+    x += __shfl_xor(x, o);
+    y += __shfl_xor(y, o);
+  }
+  if (threadIdx.x == 0) {
+    if (accumulate) {
+      out[t].x += pref * x;
+      out[t].y += pref * y;
+    } else {
+      out[t] = {pref * x, pref * y};
+    }
   }
 }
 
-// One workgroup per state n: -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G.
-__global__ void __launch_bounds__(256) sigma_x_sum(const z* __restrict__ rho, const double* __restrict__ fm,
-                                                   const double* __restrict__ vs, double head, int nm, int nn,
-                                                   int ng, double pref, int accumulate, double* __restrict__ out) {
-  __shared__ double red[256];
+// One 1024-thread workgroup per state n over the flattened (m, G) index:
+// -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G, per-thread sums then a fixed LDS tree.
+__global__ void __launch_bounds__(1024) sigma_x_sum(const z* __restrict__ rho, const double* __restrict__ fm,
+                                                    const double* __restrict__ vs, double head, int nm, int nn,
+                                                    int ng, double pref, int accumulate, double* __restrict__ out) {
+  __shared__ double red[1024];
   const int n = blockIdx.x;
   double s = 0.0;
-  for (int m = 0; m < nm; ++m) {
+  // (m, g) of flat index threadIdx.x + 1024 k, stepped without divisions
+  const int dm = 1024 / ng, dg = 1024 % ng;
+  for (int m = threadIdx.x / ng, g = threadIdx.x % ng; m < nm;) {
     const double f = fm[m];
-    if (f == 0.0) continue;
-    const z* rm = rho + ((size_t)m * nn + n) * ng;
-    double t = 0.0;
-    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-      const double v = (g == 0 && head >= 0.0) ? head : vs[g] * vs[g];
-      const z a = rm[g];
-      t = fma(fma(a.x, a.x, a.y * a.y), v, t);
+    const double v = (g == 0 && head >= 0.0) ? head : vs[g] * vs[g];
+    const z a = rho[((size_t)m * nn + n) * ng + g];
+    s = fma(f * v, fma(a.x, a.x, a.y * a.y), s);
+    g += dg;
+    m += dm;
+    if (g >= ng) {
+      g -= ng;
+      ++m;
     }
-    s = fma(f, t, s);
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = 512; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -270,7 +297,7 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
     const void* dvs = nullptr;
     XO_RET(device_table(a->vsqrt, sizeof(double) * a->ng, s, &dvs));
     KernelTimer kt_("sigma_x_sum", s);
-    hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(256), 0, s, static_cast<const z*>(a->rho), a->f_m,
+    hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(1024), 0, s, static_cast<const z*>(a->rho), a->f_m,
                        static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, a->pref, a->accumulate,
                        a->sigx);
     XO_CHECK_LAUNCH();
@@ -295,8 +322,7 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
   XO_CHECK_LAUNCH();
   {
     KernelTimer kt_("sigma_reduce", s);
-    const int nt = a->nn * a->nz;
-    hipLaunchKernelGGL(sigma_reduce, dim3((nt + 255) / 256), dim3(256), 0, s, static_cast<const z*>(ws), a->nn,
+    hipLaunchKernelGGL(sigma_reduce, dim3(a->nn * a->nz), dim3(64), 0, s, static_cast<const z*>(ws), a->nn,
                        a->nz, nparts, a->pref, a->accumulate, static_cast<z*>(a->sigc));
   }
   XO_CHECK_LAUNCH();

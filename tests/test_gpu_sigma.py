@@ -179,3 +179,31 @@ def test_sigma_chain_c1_small_all_q():
     assert np.all(sx_ref < 0)
     assert np.max(np.abs(gx - sx_ref)) <= 1e-9 * np.max(np.abs(sx_ref))
     assert np.max(np.abs(gc - sc_ref)) <= 1e-9 * np.max(np.abs(sc_ref))
+
+
+def test_sigma_full_size_c2_sampled():
+    """c2 orbitals at their real sizes (216 bands at k - q, NG = 400) in the launch the
+    benchmark times (eight states around the gap at Gamma, three frequencies each), for one
+    q with seeded eps~^-1 samples shaped like a screened response; two of the eight states
+    are computed by the oracle."""
+    base = crystal_for("c2")
+    q = base.kf[5].copy()
+    cr = dataclasses.replace(base, qf=q, pairs=find_pairs(base.kf, q))
+    ng = cr.gmill.shape[0]
+    e0, ep = _einv_pair(2024, ng)
+    dc = DeviceCrystal.upload(base, "fp64")
+    lo = base.nocc - 4
+    states = slice(lo, lo + 8)
+    z = np.stack([base.eps[0][states] + d for d in (-0.05, 0.0, 0.05)], axis=1).astype(np.complex128)
+    plan = SigmaPlan(dc, [cr], 0, states)
+    sigc = torch.empty((8, 3), dtype=torch.complex128, device=DEV)
+    sigx = torch.empty((8,), dtype=torch.float64, device=DEV)
+    say(f"sigma full size: nb={dc.coef[cr.pairs[0][1]].shape[0]} ng={ng}")
+    sigma_gpu(plan, [torch.stack([_to(e0), _to(ep)])], _to(z), sigc, sigx, eta=0.01)
+    torch.cuda.synchronize()
+    pick = [1, 6]   # one valence and one conduction state
+    say("sigma full size: oracle on two states")
+    sx_ref, sc_ref = sigma_kpoint([cr], [np.stack([e0, ep])], 0, [lo + i for i in pick], z[pick], eta=0.01)
+    gx, gc = sigx.cpu().numpy()[pick], sigc.cpu().numpy()[pick]
+    assert np.max(np.abs(gx - sx_ref)) <= 1e-10 * np.max(np.abs(sx_ref))
+    assert np.max(np.abs(gc - sc_ref)) <= 1e-10 * np.max(np.abs(sc_ref))
