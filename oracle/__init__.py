@@ -10,7 +10,7 @@ Every function is written from the paper's equations (Yambo 2019, arXiv
 
 * oscillator strengths, Eq. (rhotw) in the Linear Response section;
 * the IP response sum over states, Eq. (X_IP), with the R/F split of
-  Appendix A;
+  Appendix A, at imaginary and at real frequencies (chi0_real_axis);
 * the q -> 0 limit through velocity matrix elements, Eq. (dip) (G-space v);
 * the bare Coulomb potential, Coulomb interaction subsection;
 * the RPA Dyson equation as a matrix inversion, Eq. (X_rpa_inv), and the
@@ -22,13 +22,14 @@ Every function is written from the paper's equations (Yambo 2019, arXiv
 
 Parity status: rho, chi0 and epsilon^-1 are pinned by identities, closed forms
 and brute force in tests/test_oracle_pins.py; the MLP by finite differences; the plasmon-pole
-fit and the self-energies in tests/test_oracle_sigma.py.
+fit and the self-energies in tests/test_oracle_sigma.py; the real-axis response
+in tests/test_oracle_real_axis.py.
 Absolute values for the synthetic crystals beyond those pins are parity
 unpinned: the oracle is the reference.
 """
 
 from .rho import rho_direct, rho_fft, orbitals_real_space, rho_head_q0  # noqa: F401
-from .chi0 import chi0_from_rho, pole_weights  # noqa: F401
+from .chi0 import chi0_from_rho, pole_weights, chi0_real_axis  # noqa: F401
 from .epsinv import epsinv_sym, epsinv_nonsym, eps_tilde  # noqa: F401
 from .pipeline import rho_all_pairs, chi0_crystal, epsinv_crystal  # noqa: F401
 from .metrics import rel_fro, err_table  # noqa: F401

@@ -38,3 +38,26 @@ def chi0_from_rho(M: np.ndarray, dE: np.ndarray, omegas, pref: float) -> np.ndar
         # sum_t wt_t M[t, G] conj(M[t, G'])
         out[j] = -pref * (M.T * wt[None, :]) @ np.conj(M)
     return out
+
+
+def pole_factor_real_axis(dE, omega, eta: float):
+    """F_t(omega) = 1/(omega - Delta_t + i eta) - 1/(omega + Delta_t - i eta) (complex).
+
+    The time-ordered form of the bracket of Eq. (X_IP) with the sign reading above
+    (poles at Delta - i eta and -Delta + i eta). omega may be complex: omega = i w with
+    eta = 0 gives the imaginary-axis factor -2 Delta / (w^2 + Delta^2)."""
+    dE = np.asarray(dE, dtype=np.float64)
+    return 1.0 / (omega - dE + 1j * eta) - 1.0 / (omega + dE - 1j * eta)
+
+
+def chi0_real_axis(M: np.ndarray, dE: np.ndarray, omegas, eta: float, pref: float) -> np.ndarray:
+    """chi0[w, G, G'] = pref sum_t F_t(omega_w) M[t, G] conj(M[t, G']) at real (or complex)
+    frequencies: Eq. (X_IP) with every transition its own pole group (Appendix A with
+    the degeneracy threshold at zero). Not Hermitian: chi0 = A + i B with A and B the
+    Hermitian sums weighted by Re F and Im F."""
+    M = np.asarray(M, dtype=np.complex128)
+    out = np.empty((len(omegas), M.shape[1], M.shape[1]), dtype=np.complex128)
+    for j, w in enumerate(omegas):
+        F = pole_factor_real_axis(dE, w, eta)
+        out[j] = pref * (M.T * F[None, :]) @ np.conj(M)
+    return out
