@@ -180,6 +180,38 @@ typedef struct {
 
 int xo_chi0(const xo_chi0_args* a, void* stream);
 
+/* Independent-particle response at real frequencies, Eq. (X_IP) with the
+ * time-ordered poles (every transition its own pole group: the split of
+ * Appendix A with the degeneracy threshold at zero):
+ *   chi0[w][G][G'] (+)= pref sum_t F_t(w) rho[t][G] conj(rho[t][G']),
+ *   F_t(w) = 1/(w - dE_t + i eta) - 1/(w + dE_t - i eta).
+ * Not Hermitian. It is formed as A + i B, A and B the Hermitian updates with
+ * the real weights Re F and Im F, each run by the kernels of xo_chi0 in the
+ * given precision (so XO_BF16X3 / XO_BF16 / XO_FP32 accumulate in FP32 within a
+ * transition chunk and in FP64 across chunks, as there); frequencies go in
+ * chunks of 32 (64 weight slots). The Dyson step for these matrices is
+ * xo_epsinv with XO_EPS_LU_FALLBACK (eps~ is not Hermitian off the imaginary
+ * axis).
+ * rho: [device] [nt][ng] complex (complex128 for XO_FP64, complex64 otherwise);
+ * dE:  [device] [nt] pole energies > 0 (check_dE as for xo_chi0);
+ * w:   [host] [nw] real frequencies (Ha), finite and >= 0, any count;
+ * eta: broadening (Ha), > 0; chi0: [device] [nw][ng][ng] complex128.
+ * Errors: XO_ERR_ARG for bad sizes, pointers, frequencies, eta or precision. */
+typedef struct {
+  int nt, ng, nw;
+  int prec;
+  const void* rho;
+  const double* dE;
+  const double* w;
+  double eta;
+  double pref;
+  int accumulate;
+  int check_dE;
+  double* chi0;
+} xo_chi0_real_args;
+
+int xo_chi0_real(const xo_chi0_real_args* a, void* stream);
+
 /* Many chi0 problems (q-points with their own G-set size, transitions and
  * output) sharing precision and frequencies, in one persistent launch: the
  * problems are cut into units (problem, block of the upper triangle, group of

@@ -82,6 +82,51 @@ __global__ void pole_factors(const double* __restrict__ dE, int nt, const double
   }
 }
 
+// Real-axis factors of Eq. (X_IP), time-ordered: F = 1/(w - D + i eta) - 1/(w + D - i eta).
+// Frequency w_j takes two slots of the Hermitian update: W[t][2j] = -Re F, W[t][2j+1] = -Im F,
+// so that -pref sum_t W rho rho^H gives A_j = pref sum Re F rho rho^H and B_j likewise,
+// chi0(w_j) = A_j + i B_j.
+template <typename T>
+__global__ void pole_factors_real(const double* __restrict__ dE, int nt, const double* __restrict__ w, int nwc,
+                                  double eta, int nwpad, T* __restrict__ W, int* __restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const double d = dE[t];
+  if (!(d > 0.0) && bad) atomicAdd(bad, 1);
+  const double e2 = eta * eta;
+  for (int j = 0; j < nwpad / 2; ++j) {
+    double re = 0.0, im = 0.0;
+    if (j < nwc) {
+      const double a1 = w[j] - d, a2 = w[j] + d;
+      const double i1 = 1.0 / (a1 * a1 + e2), i2 = 1.0 / (a2 * a2 + e2);
+      re = a1 * i1 - a2 * i2;
+      im = -eta * (i1 + i2);
+    }
+    W[(size_t)t * nwpad + 2 * j] = (T)(-re);
+    W[(size_t)t * nwpad + 2 * j + 1] = (T)(-im);
+  }
+}
+
+// out[j] (+)= A_j + i B_j from the Hermitian pair (A_j, B_j) in slots 2j, 2j + 1.
+__global__ void chi0_combine_real(const double* __restrict__ AB, int ng, int nwc, int accumulate,
+                                  double* __restrict__ out) {
+  const size_t nn = (size_t)ng * ng;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= nn || j >= nwc) return;
+  const double* A = AB + ((size_t)(2 * j) * nn + e) * 2;
+  const double* B = AB + ((size_t)(2 * j + 1) * nn + e) * 2;
+  double* o = out + ((size_t)j * nn + e) * 2;
+  const double re = A[0] - B[1], im = A[1] + B[0];
+  if (accumulate) {
+    o[0] += re;
+    o[1] += im;
+  } else {
+    o[0] = re;
+    o[1] = im;
+  }
+}
+
 __global__ void zero_ints(int* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -652,8 +697,10 @@ static int launch_nwg(int nwg, int nt_tiles, const void* ditems, const void* dti
 }
 
 // Every item of a batch shares the precision and the frequencies.
+// With wreal set (host, nw / 2 real frequencies) the nw slots carry the real-axis factor
+// pairs of pole_factors_real instead of the imaginary-axis factors.
 static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hipStream_t s,
-                          bool signed_pref = false) {
+                          bool signed_pref = false, const double* wreal = nullptr, double eta = 0.0) {
   for (int i = 0; i < n; ++i) XO_RET(validate(&a[i], signed_pref));
   const int prec = a[0].prec;
   for (int i = 1; i < n; ++i) {
@@ -765,18 +812,32 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     XO_CHECK_LAUNCH();
   }
   const void* dw = nullptr;
-  XO_RET(device_table(a[0].w, sizeof(double) * nw, s, &dw));
+  if (wreal)
+    XO_RET(device_table(wreal, sizeof(double) * (nw / 2), s, &dw));
+  else
+    XO_RET(device_table(a[0].w, sizeof(double) * nw, s, &dw));
   for (int it = 0; it < n; ++it) {
     void* W = wbase + woff[it];
-    {
-      KernelTimer kt_("pole_factors", s);
+    const dim3 pg((a[it].nt + 255) / 256);
+    if (wreal) {
+      KernelTimer kt_("pole_factors_real", s);
       if (mode == MODE_F64)
-        hipLaunchKernelGGL((pole_factors<double>), dim3((a[it].nt + 255) / 256), dim3(256), 0, s, a[it].dE,
-                           a[it].nt, static_cast<const double*>(dw), nw, nwpad, static_cast<double*>(W),
+        hipLaunchKernelGGL((pole_factors_real<double>), pg, dim3(256), 0, s, a[it].dE, a[it].nt,
+                           static_cast<const double*>(dw), nw / 2, eta, nwpad, static_cast<double*>(W),
                            a[it].check_dE ? bad : nullptr);
       else
-        hipLaunchKernelGGL((pole_factors<float>), dim3((a[it].nt + 255) / 256), dim3(256), 0, s, a[it].dE,
-                           a[it].nt, static_cast<const double*>(dw), nw, nwpad, static_cast<float*>(W),
+        hipLaunchKernelGGL((pole_factors_real<float>), pg, dim3(256), 0, s, a[it].dE, a[it].nt,
+                           static_cast<const double*>(dw), nw / 2, eta, nwpad, static_cast<float*>(W),
+                           a[it].check_dE ? bad : nullptr);
+    } else {
+      KernelTimer kt_("pole_factors", s);
+      if (mode == MODE_F64)
+        hipLaunchKernelGGL((pole_factors<double>), pg, dim3(256), 0, s, a[it].dE, a[it].nt,
+                           static_cast<const double*>(dw), nw, nwpad, static_cast<double*>(W),
+                           a[it].check_dE ? bad : nullptr);
+      else
+        hipLaunchKernelGGL((pole_factors<float>), pg, dim3(256), 0, s, a[it].dE, a[it].nt,
+                           static_cast<const double*>(dw), nw, nwpad, static_cast<float*>(W),
                            a[it].check_dE ? bad : nullptr);
     }
     XO_CHECK_LAUNCH();
@@ -848,12 +909,59 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
 // explicit-band sum through it).
 int chi0_run_signed(const xo_chi0_args* a, hipStream_t s) { return chi0_batch_run(a, 1, nullptr, s, true); }
 
+// Real-axis chi0 in chunks of kRealChunk frequencies: each chunk is one Hermitian update
+// over 2 kRealChunk factor slots into a scratch pair buffer, then the combination.
+constexpr int kRealChunk = 32;
+
+int chi0_real_run(const xo_chi0_real_args* a, hipStream_t s) {
+  XO_ARG(a, "xo_chi0_real: null argument block");
+  XO_ARG(a->nt > 0 && a->ng > 0 && a->nw > 0, "xo_chi0_real: sizes must be positive (nt=%d ng=%d nw=%d)", a->nt,
+         a->ng, a->nw);
+  XO_ARG(a->rho && a->dE && a->w && a->chi0, "xo_chi0_real: null pointer");
+  XO_ARG(a->eta > 0.0 && std::isfinite(a->eta), "xo_chi0_real: eta must be positive and finite");
+  for (int j = 0; j < a->nw; ++j)
+    XO_ARG(a->w[j] >= 0.0 && std::isfinite(a->w[j]), "xo_chi0_real: frequency %d must be finite and >= 0", j);
+  const size_t nn = (size_t)a->ng * a->ng;
+  const int nwc_max = std::min(kRealChunk, a->nw);
+  void* ws = nullptr;
+  XO_RET(workspace(s, 7, 2 * (size_t)nwc_max * nn * 2 * sizeof(double), &ws));
+  double* AB = static_cast<double*>(ws);
+  for (int j0 = 0; j0 < a->nw; j0 += kRealChunk) {
+    const int nwc = std::min(kRealChunk, a->nw - j0);
+    std::vector<double> slots(2 * nwc);
+    for (int j = 0; j < nwc; ++j) slots[2 * j] = slots[2 * j + 1] = a->w[j0 + j];
+    xo_chi0_args c{};
+    c.nt = a->nt;
+    c.ng = a->ng;
+    c.nw = 2 * nwc;
+    c.prec = a->prec;
+    c.rho = a->rho;
+    c.dE = a->dE;
+    c.w = slots.data();
+    c.pref = a->pref;
+    c.accumulate = 0;
+    c.check_dE = j0 == 0 ? a->check_dE : 0;
+    c.chi0 = AB;
+    XO_RET(chi0_batch_run(&c, 1, nullptr, s, false, a->w + j0, a->eta));
+    KernelTimer kt_("chi0_combine_real", s);
+    hipLaunchKernelGGL(chi0_combine_real, dim3((unsigned)((nn + 255) / 256), nwc), dim3(256), 0, s, AB, a->ng, nwc,
+                       a->accumulate, a->chi0 + (size_t)j0 * nn * 2);
+    XO_CHECK_LAUNCH();
+  }
+  return XO_OK;
+}
+
 }  // namespace xo
 
 extern "C" int xo_chi0(const xo_chi0_args* a, void* stream) {
   xo::clear_error();
   XO_ARG(a, "xo_chi0: null argument block");
   return xo::chi0_batch_run(a, 1, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int xo_chi0_real(const xo_chi0_real_args* a, void* stream) {
+  xo::clear_error();
+  return xo::chi0_real_run(a, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream) {

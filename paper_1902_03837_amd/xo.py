@@ -71,6 +71,12 @@ class XtermArgs(C.Structure):
     ]
 
 
+class Chi0RealArgs(C.Structure):
+    _fields_ = [("nt", C.c_int), ("ng", C.c_int), ("nw", C.c_int), ("prec", C.c_int), ("rho", C.c_void_p),
+                ("dE", C.c_void_p), ("w", _f64p), ("eta", C.c_double), ("pref", C.c_double),
+                ("accumulate", C.c_int), ("check_dE", C.c_int), ("chi0", C.c_void_p)]
+
+
 class PpaArgs(C.Structure):
     _fields_ = [("ng", C.c_int), ("einv0", C.c_void_p), ("einvp", C.c_void_p), ("omega_p", C.c_double),
                 ("vsqrt", _f64p), ("head", C.c_double), ("wr", C.c_void_p), ("om", C.c_void_p)]
@@ -98,7 +104,7 @@ _LIB = None
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
-           "xo_xterm", "xo_ppa_fit", "xo_sigma")
+           "xo_xterm", "xo_ppa_fit", "xo_sigma", "xo_chi0_real")
 
 
 def lib():
@@ -111,7 +117,8 @@ def lib():
         L.xo_last_error.restype = C.c_char_p
         L.xo_version.restype = C.c_char_p
         for name, argt in (("xo_rho", RhoArgs), ("xo_chi0", Chi0Args), ("xo_epsinv", EpsArgs),
-                           ("xo_xterm", XtermArgs), ("xo_ppa_fit", PpaArgs), ("xo_sigma", SigmaArgs)):
+                           ("xo_xterm", XtermArgs), ("xo_ppa_fit", PpaArgs), ("xo_sigma", SigmaArgs),
+                           ("xo_chi0_real", Chi0RealArgs)):
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(argt), C.c_void_p]
             fn.restype = C.c_int
@@ -488,3 +495,21 @@ def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=
     a.accumulate = 1 if accumulate else 0
     _check(lib().xo_sigma(C.byref(a), _stream(stream)))
     return sigc, sigx
+
+
+def chi0_real(rho_m, dE, omegas, eta, pref, *, out, prec="fp64", accumulate=False, check_dE=True, stream=None):
+    """xo_chi0_real: out[nw][ng][ng] complex128 (+)= pref sum_t F_t(w) rho_t rho_t^H at real w."""
+    import torch
+    nt, ng = rho_m.shape
+    assert rho_m.dtype == _cdtype(prec) and rho_m.is_contiguous()
+    assert dE.dtype == torch.float64 and dE.numel() == nt
+    w = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64).reshape(-1))
+    assert tuple(out.shape) == (w.shape[0], ng, ng) and out.dtype == torch.complex128 and out.is_contiguous()
+    a = Chi0RealArgs()
+    a.nt, a.ng, a.nw = nt, ng, w.shape[0]
+    a.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    a.rho, a.dE, a.w = _ptr(rho_m), _ptr(dE), w.ctypes.data_as(_f64p)
+    a.eta, a.pref = float(eta), float(pref)
+    a.accumulate, a.check_dE, a.chi0 = 1 if accumulate else 0, 1 if check_dE else 0, _ptr(out)
+    _check(lib().xo_chi0_real(C.byref(a), _stream(stream)))
+    return out

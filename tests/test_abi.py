@@ -201,3 +201,21 @@ def test_ppa_and_sigma_argument_errors():
     s.eta, s.sigx = 0.0, 8
     rc, msg = _rc(L.xo_sigma, s)
     assert rc == xo.XO_ERR_ARG and "vsqrt" in msg
+
+
+def test_chi0_real_argument_errors():
+    L = xo.lib()
+    assert C.sizeof(xo.Chi0RealArgs) == 4 * 4 + 3 * 8 + 2 * 8 + 4 + 4 + 8
+    a = xo.Chi0RealArgs()
+    rc, msg = _rc(L.xo_chi0_real, a)
+    assert rc == xo.XO_ERR_ARG and "positive" in msg
+    w = np.array([0.5, -1.0])
+    a.nt, a.ng, a.nw, a.prec = 4, 3, 2, 0
+    a.rho, a.dE, a.chi0 = 8, 8, 8   # never dereferenced: validation fails first
+    a.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    a.pref = 1.0
+    rc, msg = _rc(L.xo_chi0_real, a)
+    assert rc == xo.XO_ERR_ARG and "eta" in msg
+    a.eta = 0.01
+    rc, msg = _rc(L.xo_chi0_real, a)
+    assert rc == xo.XO_ERR_ARG and "frequency 1" in msg
