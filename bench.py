@@ -91,13 +91,15 @@ def rho_zy_flops(cr, pairs_meta):
     return 8.0 * Nx * (Ny * s1 + nyz * Ny)
 
 
-def run_form(cr, prec, steps, warmup, ref_E=None):
+def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
+    """One form of the path on crystal cr; real = (frequencies, eta) runs it at real frequencies
+    (xo_chi0_real, Dyson step with the LU fallback) instead of the crystal's imaginary ones."""
     import torch
     from paper_1902_03837_amd import xo
     from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE
 
     dc = DeviceCrystal.upload(cr, prec)
-    ng, nw = cr.gmill.shape[0], len(cr.omegas)
+    ng, nw = cr.gmill.shape[0], len(cr.omegas) if real is None else len(real[0])
     K = ntrans(cr)
     dev = dc.coef[0].device
     M = torch.empty((K, ng), dtype=CDTYPE[prec], device=dev)
@@ -114,10 +116,13 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
         rho_all(dc, M, dE)
         if ev:
             ev[1].record(st)
-        xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=prec, check_dE=False)
+        if real is None:
+            xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=prec, check_dE=False)
+        else:
+            xo.chi0_real(M, dE, real[0], real[1], cr.pref, out=chi, prec=prec, check_dE=False)
         if ev:
             ev[2].record(st)
-        xo.epsinv(chi, qpg, out=E, info=info)
+        xo.epsinv(chi, qpg, out=E, info=info, flags=xo.XO_EPS_SYM if real is None else xo.XO_EPS_LU_FALLBACK)
         if ev:
             ev[3].record(st)
 
@@ -141,7 +146,7 @@ def run_form(cr, prec, steps, warmup, ref_E=None):
     xo.timing_enable(False)
     kern = xo.timing_report()
     if int(info.abs().sum().item()):
-        raise RuntimeError(f"eps~ not positive definite ({prec}): pivot flags {info.tolist()}")
+        raise RuntimeError(f"eps~ inversion failed ({prec}): pivot flags {info.tolist()}")
     stages = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) for j in range(3)] for i in range(steps)])
     step_ms = np.array([evs[i][0].elapsed_time(evs[i][3]) for i in range(steps)])
     out = dict(prec=prec, K=K, ms_per_step=float(np.median(step_ms)), wall_ms_per_step=wall * 1e3,
@@ -513,6 +518,53 @@ def run_sigma(args):
     print(json.dumps(res), flush=True)
 
 
+def run_real(args):
+    """Real-axis workload: the c2 crystal (fcc 4x4x4 k, q = b1/4, 16 occupied + 200 empty bands,
+    36^3, NG = 400, K = 204 800) at 100 real frequencies spread evenly over [0, max dE] with
+    eta = 0.1 eV: rho, xo_chi0_real (two Hermitian weighted updates per frequency) and the
+    Dyson step with the LU fallback; each form against plain FP64 timed in the same run."""
+    from synth import crystal_for
+    cr = crystal_for("c2")
+    ng = cr.gmill.shape[0]
+    dmax = max(float(np.max(cr.eps[ik][cr.nocc_at(ik):]) - np.min(cr.eps[ikp][:cr.nocc_at(ikp)]))
+               for ik, ikp, _ in cr.pairs)
+    ws = list(np.linspace(0.0, dmax, args.real_nw))
+    eta = 0.1 / 27.211386
+    out, Es = {}, {}
+    forms = args.real_forms.split(",")
+    for prec in [p for p in forms if p != "fp64"] + (["fp64"] if "fp64" in forms else []):
+        steps, warm = (args.steps, args.warmup) if prec != "fp64" else (1, 1)
+        r, Es[prec] = run_form(cr, prec, steps, warm, real=(ws, eta))
+        print(f"[bench] real {prec}: {r['ms_per_step']:.1f} ms/step (rho {r['t_rho_ms']:.1f}, chi0 "
+              f"{r['t_chi0_ms']:.1f}, eps {r['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
+        out[prec] = r
+    K = next(iter(out.values()))["K"]
+    nslot = 2 * len(ws)
+    fl = chi0_flops(K, ng, nslot)   # two Hermitian updates per frequency
+    for prec, r in out.items():
+        if "fp64" in out and prec != "fp64":
+            E64 = Es["fp64"]
+            r["e_F_vs_fp64"] = max(float(np.linalg.norm(Es[prec][j] - E64[j]) / np.linalg.norm(E64[j]))
+                                   for j in range(len(ws)))
+            r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / r["ms_per_step"]
+        ck = [k for k in r["kernels"] if k.startswith("chi0_tiles") or k.startswith("chi0_blocks")]
+        t = sum(r["kernels"][k]["ms_per_step"] for k in ck) * 1e-3
+        r["chi0_kernel_TFLOPs"] = fl / t / 1e12
+        r["chi0_kernel_frac_of_peak"] = fl / t / MFMA_PEAK[prec]
+        print(f"[bench] real {prec}: chi0 kernels {t * 1e3:.1f} ms = {fl / t / 1e12:.1f} TFLOP/s; "
+              f"e_F vs fp64 {r.get('e_F_vs_fp64')}", file=sys.stderr, flush=True)
+    res = {"metric": "chi0 GFLOP/s at real frequencies; speedup vs FP64 at eps^-1 rel err<=1e-4",
+           "workload": f"real: c2 crystal, {len(ws)} real frequencies on [0, {dmax:.3f}] Ha, eta = 0.1 eV, "
+                       f"NG={ng}, K={K} transitions",
+           "forms": out,
+           "note": "chi0_kernel_frac_of_peak: algorithmic flops 4 NG^2 K per Hermitian update (two per "
+                   "frequency: weights Re F and Im F) over the dense peak of the executed precision"}
+    if args.detail:
+        with open(args.detail, "w") as fh:
+            json.dump(res, fh, indent=1)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -527,6 +579,8 @@ def main():
     ap.add_argument("--c3-forms", default="bf16,bf16x3,fp64", help="c3: forms to time (fp64 is the reference)")
     ap.add_argument("--tune-cache", default=None, help="c3: JSON file for autotuned launch shapes")
     ap.add_argument("--c5-forms", default="bf16,bf16x3,fp64", help="c5: forms (fp64 gives the error reference)")
+    ap.add_argument("--real-forms", default="bf16,bf16x3,fp64", help="real: forms (fp64 gives the error reference)")
+    ap.add_argument("--real-nw", type=int, default=100, help="real: number of real frequencies")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -544,6 +598,8 @@ def main():
         return run_c5(args)
     if args.workload == "sigma":
         return run_sigma(args)
+    if args.workload == "real":
+        return run_real(args)
     t0 = time.perf_counter()
     cr = crystal_for(args.workload)
     t_fix = time.perf_counter() - t0
