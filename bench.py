@@ -585,7 +585,7 @@ def main():
                     help="end with a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
               "multi-GPU sharding is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
 

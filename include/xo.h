@@ -275,7 +275,7 @@ int xo_epsinv(const xo_eps_args* a, void* stream);
 /* Learned empty-band tail (not in the paper: it takes the place of the
  * extrapolar X-terminator of Eq. (X_term_def) / Appendix B). A small MLP maps
  * features of the truncated band sum to the missing tail of chi0; the full band
- * sum stays available as fallback and as the judge of its error.
+ * sum stays available as fallback and as the reference for its error.
  *
  * MLP layout: nl layers with widths dims[0..nl] ([host]); SiLU after every layer
  * but the last. params [device] FP32: per layer W [dims[l+1]][dims[l]] row-major

@@ -6,7 +6,7 @@ Appendix B). Here an ensemble of two small MLPs predicts the missing tail
 s_G (chi0_full - chi0_trunc) s_G' element by element from features of the
 truncated sum (xo_tail_features). Guard: features outside the training range
 (widened by 10 %) or an ensemble disagreement above tau send the crystal to the
-full band sum, which is also the judge of the network's error.
+full band sum, which is also the reference for the network's error.
 
 Every arithmetic step runs in libxo kernels (rho, chi0, features, MLP forward,
 backward, MSE, Adam, apply, guard); this module allocates device buffers,

@@ -1,4 +1,4 @@
-"""Train the learned band tail on the GPU and judge it on held-out crystals.
+"""Train the learned band tail on the GPU and evaluate it on held-out crystals.
 
     python -m paper_1902_03837_amd.train_tail --out tail_model.npz [--train 64 --test 16 --epochs 12]
 
@@ -6,12 +6,12 @@ Training data: chi0 of seeded crystals of the learned-tail workload (fcc, 4
 k-points, q = X_z, 8 occupied bands, 59 G-vectors, 8 imaginary frequencies)
 summed over 50, 100 and all 1000 empty bands by the plain FP64 path. Features
 and targets come from xo_tail_features, the two ensemble members are trained
-with the xo MLP kernels (Adam, MSE), and each held-out crystal is judged by the
+with the xo MLP kernels (Adam, MSE), and each held-out crystal is evaluated by the
 relative error of eps~^-1 against the full band sum for (a) the truncated sum,
 (b) the truncated sum plus the Bruneval-Gonze terminator (App. B, extrapolar
 energy 1.5 Ha above the last explicit band) and (c) the truncated sum plus the
 learned tail, with the time of each path. With --model the training is skipped
-and the given model is judged.
+and the given model is evaluated.
 """
 
 from __future__ import annotations
@@ -101,7 +101,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--report", default=None)
-    ap.add_argument("--model", default=None, help="judge this trained model instead of training one")
+    ap.add_argument("--model", default=None, help="evaluate this trained model instead of training one")
     ap.add_argument("--base", default="bg", choices=("trunc", "bg"),
                     help="what the network corrects: the truncated sum or it plus the terminator")
     args = ap.parse_args(argv)
@@ -116,10 +116,10 @@ def main(argv=None):
     if args.model:
         model = T.TailModel.load(args.model)
         t_train, hists, geo = 0.0, [[float("nan")], [float("nan")]], None
-        log(f"[tail] judging {args.model}")
+        log(f"[tail] evaluating {args.model}")
     else:
         model, t_train, hists, geo = _train(args, train_seeds, ntrunc, nhalf)
-    # ---- held-out judgement
+    # ---- held-out evaluation
     rows = []
     for i, s in enumerate(test_seeds):
         cr = crystal_for(args.workload, seed=s)
