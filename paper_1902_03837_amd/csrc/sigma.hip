@@ -13,7 +13,8 @@
 //                  elements per thread), one state n and a chunk of bands m, and writes
 //                  one partial per frequency
 //   sigma_reduce   fixed-order sum of the partials into Sigma_c
-//   sigma_x_sum    Sigma_x,nn = -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G
+//   sigma_x_part   Sigma_x,nn = -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G: partial sums over
+//   + sigma_x_sum  chunks of eight bands, then their fixed-order sum
 
 #include <algorithm>
 #include <cmath>
@@ -217,21 +218,22 @@ __global__ void __launch_bounds__(64) sigma_reduce(const z* __restrict__ part, i
   }
 }
 
-// One 1024-thread workgroup per state n over the flattened (m, G) index:
-// -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G, per-thread sums then a fixed LDS tree.
-__global__ void __launch_bounds__(1024) sigma_x_sum(const z* __restrict__ rho, const double* __restrict__ fm,
+// Sigma_x partial sums: workgroup (n, chunk) over kXB bands and all G (flat index,
+// stepped without divisions): part[n][chunk] = sum_m f_m sum_G |rho_nm(G)|^2 v_G.
+constexpr int kXB = 8;
+
+__global__ void __launch_bounds__(256) sigma_x_part(const z* __restrict__ rho, const double* __restrict__ fm,
                                                     const double* __restrict__ vs, double head, int nm, int nn,
-                                                    int ng, double pref, int accumulate, double* __restrict__ out) {
-  __shared__ double red[1024];
-  const int n = blockIdx.x;
+                                                    int ng, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int n = blockIdx.x, ch = blockIdx.y;
+  const int mb = ch * kXB, me = min(nm, mb + kXB);
   double s = 0.0;
-  // (m, g) of flat index threadIdx.x + 1024 k, stepped without divisions
-  const int dm = 1024 / ng, dg = 1024 % ng;
-  for (int m = threadIdx.x / ng, g = threadIdx.x % ng; m < nm;) {
-    const double f = fm[m];
+  const int dm = 256 / ng, dg = 256 % ng;
+  for (int m = mb + threadIdx.x / ng, g = threadIdx.x % ng; m < me;) {
     const double v = (g == 0 && head >= 0.0) ? head : vs[g] * vs[g];
     const z a = rho[((size_t)m * nn + n) * ng + g];
-    s = fma(f * v, fma(a.x, a.x, a.y * a.y), s);
+    s = fma(fm[m] * v, fma(a.x, a.x, a.y * a.y), s);
     g += dg;
     m += dm;
     if (g >= ng) {
@@ -241,11 +243,21 @@ __global__ void __launch_bounds__(1024) sigma_x_sum(const z* __restrict__ rho, c
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int h = 512; h > 0; h >>= 1) {
+  for (int h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[n] = (accumulate ? out[n] : 0.0) - pref * red[0];
+  if (threadIdx.x == 0) part[(size_t)n * gridDim.y + ch] = red[0];
+}
+
+// One wave per state: out[n] (+)= -pref * sum over chunks (fixed order).
+__global__ void __launch_bounds__(64) sigma_x_sum(const double* __restrict__ part, int nch, double pref,
+                                                  int accumulate, double* __restrict__ out) {
+  const int n = blockIdx.x;
+  double x = 0.0;
+  for (int c = threadIdx.x; c < nch; c += 64) x += part[(size_t)n * nch + c];
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if (threadIdx.x == 0) out[n] = (accumulate ? out[n] : 0.0) - pref * x;
 }
 
 }  // namespace
@@ -296,10 +308,21 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
     XO_ARG(std::isfinite(a->head), "xo_sigma: head must be finite (negative for none)");
     const void* dvs = nullptr;
     XO_RET(device_table(a->vsqrt, sizeof(double) * a->ng, s, &dvs));
-    KernelTimer kt_("sigma_x_sum", s);
-    hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(1024), 0, s, static_cast<const z*>(a->rho), a->f_m,
-                       static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, a->pref, a->accumulate,
-                       a->sigx);
+    const int nch = (a->nm + kXB - 1) / kXB;
+    XO_ARG(nch <= 65535, "xo_sigma: too many bands per call (nm=%d)", a->nm);
+    void* wx = nullptr;
+    XO_RET(workspace(s, 8, (size_t)a->nn * nch * sizeof(double), &wx));
+    {
+      KernelTimer kt_("sigma_x_part", s);
+      hipLaunchKernelGGL(sigma_x_part, dim3(a->nn, nch), dim3(256), 0, s, static_cast<const z*>(a->rho), a->f_m,
+                         static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, static_cast<double*>(wx));
+    }
+    XO_CHECK_LAUNCH();
+    {
+      KernelTimer kt_("sigma_x_sum", s);
+      hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(64), 0, s, static_cast<const double*>(wx), nch, a->pref,
+                         a->accumulate, a->sigx);
+    }
     XO_CHECK_LAUNCH();
   }
   if (a->nz == 0) return XO_OK;
