@@ -118,6 +118,7 @@ class SigmaPlan:
         self.dc, self.crs, self.ik0, self.states = dc, crs, ik0, states
         dev = dc.coef[0].device
         self.nn = states.stop - states.start
+        self.rho_plan = None
         self.qs = []
         for cr in crs:
             ik, ikp, g0 = cr.pairs[ik0]
@@ -138,40 +139,24 @@ class SigmaPlan:
 
 
 def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0, stream=None):
-    """Sigma_x and Sigma_c of the planned states, summed over q: per q one xo_rho
-    (states at k against every band at k - q, no q -> 0 substitution), one
-    xo_ppa_fit on eps~^-1 at (0, i omega_p) and one xo_sigma."""
+    """Sigma_x and Sigma_c of the planned states, summed over q: the oscillator strengths
+    of every q in one xo_rho_batch (states at k against every band at k - q, no q -> 0
+    substitution), then per q one xo_ppa_fit on eps~^-1 at (0, i omega_p) and one xo_sigma."""
     dc, st = plan.dc, plan.states
+    if plan.rho_plan is None:
+        calls = []
+        for Q in plan.qs:
+            cr, ikp = Q["cr"], Q["ikp"]
+            calls.append(dict(coef_c=dc.coef[plan.ik0][st], mill_c=cr.mill[plan.ik0], e_c=None,
+                              coef_v=dc.coef[ikp], mill_v=cr.mill[ikp], e_v=None, gmill=cr.gmill, g0=Q["g0"],
+                              grid=cr.grid, out=Q["rho"], prec="fp64", kcart=cr.kcart(plan.ik0),
+                              bvec=cr.lat.bvec))
+        plan.rho_plan = xo.RhoPlan(calls, batch=True)
+    xo.launch_plan(plan.rho_plan, stream=stream)
     for iq, Q in enumerate(plan.qs):
         cr, ikp = Q["cr"], Q["ikp"]
-        xo.rho(dc.coef[plan.ik0][st], cr.mill[plan.ik0], None, dc.coef[ikp], cr.mill[ikp], None,
-               cr.gmill, Q["g0"], cr.grid, out=Q["rho"], prec="fp64", kcart=cr.kcart(plan.ik0),
-               bvec=cr.lat.bvec, stream=stream)
         E = einv_by_q[iq]
         xo.ppa_fit(E[0], E[1], omega_p, Q["vsqrt"], Q["head"], wr=Q["wr"], om=Q["om"], stream=stream)
         xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, 1.0 / (cr.nk * cr.lat.omega),
                  sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, stream=stream)
     return sigc, sigx
-
-
-def run_crystal_real(dc: DeviceCrystal, omegas, eta: float, nempty=None, chi_prec=None, M=None, dE=None,
-                     chi=None, E=None, check_dE=True, stream=None):
-    """The path at real frequencies w + i eta: rho for all pairs, xo_chi0_real and
-    xo_epsinv with the LU fallback (eps~ is not Hermitian there); returns (M, dE, chi0, eps~^-1)."""
-    cr = dc.cr
-    ng, nw = cr.gmill.shape[0], len(omegas)
-    K = ntrans(cr, nempty)
-    dev = dc.coef[0].device
-    if M is None:
-        M = torch.empty((K, ng), dtype=CDTYPE[dc.prec], device=dev)
-    if dE is None:
-        dE = torch.empty(K, dtype=torch.float64, device=dev)
-    if chi is None:
-        chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
-    if E is None:
-        E = torch.empty_like(chi)
-    rho_all(dc, M, dE, nempty, stream=stream)
-    xo.chi0_real(M, dE, omegas, eta, cr.pref, out=chi, prec=chi_prec or dc.prec, check_dE=check_dE,
-                 stream=stream)
-    xo.epsinv(chi, cr.qpg(), out=E, flags=xo.XO_EPS_SYM | xo.XO_EPS_LU_FALLBACK, stream=stream)
-    return M, dE, chi, E
