@@ -160,3 +160,26 @@ def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0
         xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, 1.0 / (cr.nk * cr.lat.omega),
                  sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, stream=stream)
     return sigc, sigx
+
+
+def run_crystal_real(dc: DeviceCrystal, omegas, eta: float, nempty=None, chi_prec=None, M=None, dE=None,
+                     chi=None, E=None, check_dE=True, stream=None):
+    """The path at real frequencies w + i eta: rho for all pairs, xo_chi0_real and
+    xo_epsinv with the LU fallback (eps~ is not Hermitian there); returns (M, dE, chi0, eps~^-1)."""
+    cr = dc.cr
+    ng, nw = cr.gmill.shape[0], len(omegas)
+    K = ntrans(cr, nempty)
+    dev = dc.coef[0].device
+    if M is None:
+        M = torch.empty((K, ng), dtype=CDTYPE[dc.prec], device=dev)
+    if dE is None:
+        dE = torch.empty(K, dtype=torch.float64, device=dev)
+    if chi is None:
+        chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
+    if E is None:
+        E = torch.empty_like(chi)
+    rho_all(dc, M, dE, nempty, stream=stream)
+    xo.chi0_real(M, dE, omegas, eta, cr.pref, out=chi, prec=chi_prec or dc.prec, check_dE=check_dE,
+                 stream=stream)
+    xo.epsinv(chi, cr.qpg(), out=E, flags=xo.XO_EPS_SYM | xo.XO_EPS_LU_FALLBACK, stream=stream)
+    return M, dE, chi, E
