@@ -20,6 +20,11 @@ bf16 on MFMA: three products, FP32 accumulation) and BF16 (operands rounded to
 bf16, one product, FP32 accumulation); eps^-1 is FP64 in all. The reported form
 is the fastest whose eps~^-1 stays within 1e-4 (relative Frobenius, worst
 frequency) of the plain FP64 path timed in the same run. Output: one JSON line.
+
+Other workloads (--workload): c3 (27 q-points with uneven G-sets in one batched
+launch), c5 (large cell), sigma (plasmon-pole W and the GW self-energy of eight
+states summed over all 64 q of the c2 crystal), real (the c2 path at 100 real
+frequencies); each prints its own JSON line.
 """
 
 from __future__ import annotations
