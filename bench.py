@@ -191,14 +191,14 @@ def cpu_baseline(cr, npairs):
                        f"numpy FFT single-threaded, BLAS on all cores")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch (read + write) from the committed counter summary, or None.
+def measured_traffic(kernel, summary="c2_hbm_traffic.txt"):
+    """HBM bytes per launch (read + write) from a committed counter summary, or None.
 
     Only used when the kernel's source file still has the hash recorded with the
     counters; otherwise the figures describe an older kernel and are not reported.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     src, tr = {}, {}
@@ -506,7 +506,8 @@ def run_sigma(args):
            "sigma_x": gx.tolist(), "sigma_c_at_e": [[c.real, c.imag] for c in gc[:, 1]],
            "kernels_ms_per_launch": {k: v["avg_ms"] for k, v in kern.items()},
            "roofline": {"kernel": "sigma_c_tiles", "bound": "alu", "achieved": ach, "peak": PEAK["valu"] / 1e12,
-                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK["valu"], "traffic": None,
+                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK["valu"],
+                        "traffic": measured_traffic("sigma_c_tiles", "sigma_hbm_traffic.txt"),
                         "note": "algorithmic FP64 flops per launch (ng^2 nb nn (12 + 16 nz), a reciprocal "
                                 "counted as one) over the FP64 vector peak"}}
     if not args.no_cpu:
@@ -520,6 +521,13 @@ def run_sigma(args):
         res["cpu_baseline"] = {"value": nn * nz * len(crs) * frac / dt, "unit": "elements/s",
                                "cores": torch.get_num_threads(), "kind": "oracle",
                                "sample": f"one q of {len(crs)}, {len(pick)} of {nn} states ({dt:.1f} s)"}
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = 2 * a.numel() * 8
     print(json.dumps(res), flush=True)
 
 
