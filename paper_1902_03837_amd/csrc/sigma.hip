@@ -92,9 +92,15 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
                                                      const z* __restrict__ om, const double* __restrict__ em,
                                                      const double* __restrict__ fm, const z* __restrict__ zz,
                                                      int nm, int nn, int ng, int nz, double eta, int ntc,
-                                                     int mchunk, z* __restrict__ part) {
+                                                     int mchunk, int ntile, int nmc, int per_xcd,
+                                                     z* __restrict__ part) {
   __shared__ double red[2 * kMaxZ][8];
-  const int tile = blockIdx.x, n = blockIdx.y, mc = blockIdx.z;
+  // Workgroups go to the eight XCDs in turn (linear id mod 8); work item u = (state, band
+  // chunk, block) in state-major order is given to XCD u / per_xcd, so that each XCD reads
+  // the oscillator strengths of its own states, which then stay in its L2.
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= ntile * nmc * nn) return;
+  const int tile = u % ntile, mc = (u / ntile) % nmc, n = u / (ntile * nmc);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int r0 = (tile / ntc) * kTR, c0 = (tile % ntc) * kTC;
   int G[kSR], Gp[kSC];
@@ -187,8 +193,7 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
     const int j = threadIdx.x;
     const double x = (red[2 * j][0] + red[2 * j][1]) + (red[2 * j][2] + red[2 * j][3]);
     const double y = (red[2 * j + 1][0] + red[2 * j + 1][1]) + (red[2 * j + 1][2] + red[2 * j + 1][3]);
-    const int ntile = gridDim.x;
-    part[(((size_t)n * gridDim.z + mc) * ntile + tile) * nz + j] = {x, y};
+    part[(((size_t)n * nmc + mc) * ntile + tile) * nz + j] = {x, y};
   }
 }
 
@@ -331,16 +336,18 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
   int nmc = std::max(1, std::min(a->nm, (2048 + ntile * a->nn - 1) / (ntile * a->nn)));
   const int mchunk = (a->nm + nmc - 1) / nmc;
   nmc = (a->nm + mchunk - 1) / mchunk;
-  XO_ARG(a->nn <= 65535 && nmc <= 65535, "xo_sigma: too many states per call (nn=%d)", a->nn);
   const int nparts = nmc * ntile;
   void* ws = nullptr;
   XO_RET(workspace(s, 6, (size_t)a->nn * nparts * a->nz * sizeof(z), &ws));
   {
     KernelTimer kt_("sigma_c_tiles", s);
-    hipLaunchKernelGGL(sigma_c_tiles, dim3(ntile, a->nn, nmc), dim3(256), 0, s, static_cast<const z*>(a->rho),
+    const long total = (long)ntile * nmc * a->nn;
+    const long per_xcd = (total + 7) / 8;
+    XO_ARG(8 * per_xcd < (1L << 31), "xo_sigma: too many blocks (%ld)", total);
+    hipLaunchKernelGGL(sigma_c_tiles, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, static_cast<const z*>(a->rho),
                        static_cast<const z*>(a->wr), static_cast<const z*>(a->om), a->e_m, a->f_m,
-                       static_cast<const z*>(a->z), a->nm, a->nn, a->ng, a->nz, a->eta, ntc, mchunk,
-                       static_cast<z*>(ws));
+                       static_cast<const z*>(a->z), a->nm, a->nn, a->ng, a->nz, a->eta, ntc, mchunk, ntile, nmc,
+                       (int)per_xcd, static_cast<z*>(ws));
   }
   XO_CHECK_LAUNCH();
   {
