@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <map>
 #include <vector>
 
 #include "bf16x3.h"
@@ -377,7 +378,8 @@ constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 template <int NP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
-            const int* __restrict__ queue, int nunits, int* __restrict__ counter, float* __restrict__ part) {
+            const int* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
+            float* __restrict__ part) {
   __shared__ u4 Bs[2][2][4][4][16];        // [buffer][hi, lo][column tile][q][column]
   __shared__ float4 As[2][kBlk][9];        // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
   __shared__ float4 Ws[2][kBW][4];         // [buffer][frequency][transition quad]
@@ -386,12 +388,30 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int fn = tid >> 6, fq = (tid >> 4) & 3, fj = tid & 15;  // right-operand slot filled by this thread
   const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition quad
+  // The queue has one segment per XCD (qoff[x] .. qoff[x + 1]), holding the units whose
+  // transition slices were given to XCD x. Workgroup b runs on XCD b mod 8 (launch order),
+  // starts on that segment and moves to the next once it is exhausted; it stops after
+  // finding all eight exhausted in a row. Every counter only grows, so all workgroups stop.
+  int home = blockIdx.x & 7, misses = 0;
   for (;;) {
-    if (tid == 0) su = atomicAdd(counter, 1);
+    if (tid == 0) {
+      int p = -1;
+      while (misses < 8) {
+        const int c = qoff[home] + atomicAdd(&counters[home], 1);
+        if (c < qoff[home + 1]) {
+          p = c;
+          misses = 0;
+          break;
+        }
+        home = (home + 1) & 7;
+        ++misses;
+      }
+      su = p;
+    }
     __syncthreads();
     const int qpos = __builtin_amdgcn_readfirstlane(su);
     __syncthreads();
-    if (qpos >= nunits) break;
+    if (qpos < 0) break;
     const int uid = queue[qpos];
     const Unit U = units[uid];
     const Item I = items[U.item];
@@ -748,7 +768,8 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     if (tune && tune->kper > 0) {
       kper = tune->kper;
     } else {
-      const long slices = std::max(1L, (want_units + total_blocks - 1) / std::max(1L, total_blocks));
+      long slices = std::max(1L, (want_units + total_blocks - 1) / std::max(1L, total_blocks));
+      if (blk) slices = (slices + 7) / 8 * 8;  // whole slices per XCD
       kper = (int)((a[it].nt + slices - 1) / slices);
     }
     kper = std::max(64, (kper + 63) / 64 * 64);
@@ -792,6 +813,32 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     if (cost[x] != cost[y]) return cost[x] > cost[y];
     return units[x].k0 < units[y].k0;
   });
+  // block form: the units of one (item, transition slice) go to one XCD, whose L2 then
+  // serves that slice of rho to all of them; slices are dealt to the XCDs costliest first,
+  // each to the XCD with the least work so far, and keep the order above inside a segment
+  int qoff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (blk) {
+    std::map<std::pair<int, int>, long> gcost;
+    for (size_t u = 0; u < units.size(); ++u) gcost[{units[u].item, units[u].k0}] += cost[u];
+    std::vector<std::pair<long, std::pair<int, int>>> groups;
+    for (const auto& g : gcost) groups.push_back({g.second, g.first});
+    std::stable_sort(groups.begin(), groups.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::map<std::pair<int, int>, int> xcd_of;
+    long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (const auto& g : groups) {
+      const int x = (int)(std::min_element(load, load + 8) - load);
+      xcd_of[g.second] = x;
+      load[x] += g.first;
+    }
+    std::vector<int> seg[8];
+    for (int u : queue) seg[xcd_of[{units[u].item, units[u].k0}]].push_back(u);
+    queue.clear();
+    for (int x = 0; x < 8; ++x) {
+      qoff[x] = (int)queue.size();
+      queue.insert(queue.end(), seg[x].begin(), seg[x].end());
+    }
+    qoff[8] = (int)queue.size();
+  }
   const int nunits = (int)units.size();
   const size_t per = blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
   const size_t pbytes = per * nunits;
@@ -867,18 +914,22 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   const int grid = std::min(nunits, num_cus() * grid_per_cu);
   const int nreds = (int)reds.size();
   if (blk) {
-    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 1);
+    const void* dqoff = nullptr;
+    XO_RET(device_table(qoff, sizeof(qoff), s, &dqoff));
+    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 8);
     XO_CHECK_LAUNCH();
     if (mode == MODE_BF16) {
       KernelTimer kt_("chi0_blocks_bf16", s);
       hipLaunchKernelGGL(chi0_blocks<1>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
                          static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
-                         static_cast<const int*>(dqueue), nunits, counter, static_cast<float*>(part));
+                         static_cast<const int*>(dqueue), static_cast<const int*>(dqoff), counter,
+                         static_cast<float*>(part));
     } else {
       KernelTimer kt_("chi0_blocks_bf16x3", s);
       hipLaunchKernelGGL(chi0_blocks<3>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
                          static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
-                         static_cast<const int*>(dqueue), nunits, counter, static_cast<float*>(part));
+                         static_cast<const int*>(dqueue), static_cast<const int*>(dqoff), counter,
+                         static_cast<float*>(part));
     }
     XO_CHECK_LAUNCH();
     {
