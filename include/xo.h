@@ -410,7 +410,12 @@ int xo_ppa_fit(const xo_ppa_args* a, void* stream);
  * on the conduction side (at k) and the bands m on the valence side (at k-q).
  * pref = 1/(N_k Omega); e_m in Ha on the scale of z; f_m in [0, 1] per spin.
  * Sum over q by calling once per q with accumulate = 1 after the first.
- *   rho: [device] [nm][nn][ng] complex128; wr, om: [device] [ng][ng] complex128
+ * rho_swapped = 1: rho holds instead the mirrored strengths
+ * <m k-q| e^{i(-q+G').r} |n k> for G' = -G, which equal conj(rho_nm(G)), in
+ * [nn][nm][ng], as xo_rho writes them with the bands m on the conduction side
+ * (at k-q), the states on the valence side, G0 negated and the G-set negated
+ * (the wide side on the conduction side suits the gathered-product kernel).
+ *   rho: [device] [nm][nn][ng] complex128 ([nn][nm][ng] when swapped); wr, om: [device] [ng][ng] complex128
  *   (from xo_ppa_fit); e_m, f_m: [device] [nm]; z: [device] [nn][nz] complex128
  *   (nz <= 4; z may be complex, e.g. i nu with eta = 0 on the imaginary axis);
  *   vsqrt: [host] [ng] (needed when sigx is set); sigx: [device] [nn] or NULL;
@@ -431,6 +436,7 @@ typedef struct {
   double* sigx;
   void* sigc;
   int accumulate;
+  int rho_swapped;
 } xo_sigma_args;
 
 int xo_sigma(const xo_sigma_args* a, void* stream);

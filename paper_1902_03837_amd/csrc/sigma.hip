@@ -88,6 +88,7 @@ __device__ __forceinline__ void add_pole(z& acc, z P, double dx, double dy, doub
   acc.y = fma(fma(P.y, dx, -P.x * dy), inv, acc.y);
 }
 
+template <bool SWAPPED>
 __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, const z* __restrict__ wr,
                                                      const z* __restrict__ om, const double* __restrict__ em,
                                                      const double* __restrict__ fm, const z* __restrict__ zz,
@@ -125,11 +126,18 @@ __global__ void __launch_bounds__(256) sigma_c_tiles(const z* __restrict__ rho, 
   // oscillator strengths of band m for the block's rows and columns, loaded one band ahead
   z a[kSR], b[kSC];
   auto load = [&](int m, z* a_, z* b_) {
-    const z* rm = rho + ((size_t)m * nn + n) * ng;
+    // rho_nm(G) from [m][n][G], or as conj of the mirrored strengths in [n][m][G]
+    const z* rm = rho + (SWAPPED ? ((size_t)n * nm + m) : ((size_t)m * nn + n)) * ng;
 #pragma unroll
-    for (int r = 0; r < kSR; ++r) a_[r] = rm[G[r]];
+    for (int r = 0; r < kSR; ++r) {
+      a_[r] = rm[G[r]];
+      if constexpr (SWAPPED) a_[r].y = -a_[r].y;
+    }
 #pragma unroll
-    for (int c = 0; c < kSC; ++c) b_[c] = rm[Gp[c]];
+    for (int c = 0; c < kSC; ++c) {
+      b_[c] = rm[Gp[c]];
+      if constexpr (SWAPPED) b_[c].y = -b_[c].y;
+    }
   };
   if (m0 < m1) load(m0, a, b);
   for (int m = m0; m < m1; ++m) {
@@ -229,7 +237,7 @@ constexpr int kXB = 8;
 
 __global__ void __launch_bounds__(256) sigma_x_part(const z* __restrict__ rho, const double* __restrict__ fm,
                                                     const double* __restrict__ vs, double head, int nm, int nn,
-                                                    int ng, double* __restrict__ part) {
+                                                    int ng, int swapped, double* __restrict__ part) {
   __shared__ double red[256];
   const int n = blockIdx.x, ch = blockIdx.y;
   const int mb = ch * kXB, me = min(nm, mb + kXB);
@@ -237,7 +245,7 @@ __global__ void __launch_bounds__(256) sigma_x_part(const z* __restrict__ rho, c
   const int dm = 256 / ng, dg = 256 % ng;
   for (int m = mb + threadIdx.x / ng, g = threadIdx.x % ng; m < me;) {
     const double v = (g == 0 && head >= 0.0) ? head : vs[g] * vs[g];
-    const z a = rho[((size_t)m * nn + n) * ng + g];
+    const z a = rho[(swapped ? ((size_t)n * nm + m) : ((size_t)m * nn + n)) * ng + g];  // |rho|^2 either way
     s = fma(fm[m] * v, fma(a.x, a.x, a.y * a.y), s);
     g += dg;
     m += dm;
@@ -320,7 +328,8 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
     {
       KernelTimer kt_("sigma_x_part", s);
       hipLaunchKernelGGL(sigma_x_part, dim3(a->nn, nch), dim3(256), 0, s, static_cast<const z*>(a->rho), a->f_m,
-                         static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, static_cast<double*>(wx));
+                         static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, a->rho_swapped ? 1 : 0,
+                         static_cast<double*>(wx));
     }
     XO_CHECK_LAUNCH();
     {
@@ -344,10 +353,10 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
     const long total = (long)ntile * nmc * a->nn;
     const long per_xcd = (total + 7) / 8;
     XO_ARG(8 * per_xcd < (1L << 31), "xo_sigma: too many blocks (%ld)", total);
-    hipLaunchKernelGGL(sigma_c_tiles, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s, static_cast<const z*>(a->rho),
-                       static_cast<const z*>(a->wr), static_cast<const z*>(a->om), a->e_m, a->f_m,
-                       static_cast<const z*>(a->z), a->nm, a->nn, a->ng, a->nz, a->eta, ntc, mchunk, ntile, nmc,
-                       (int)per_xcd, static_cast<z*>(ws));
+    hipLaunchKernelGGL(a->rho_swapped ? sigma_c_tiles<true> : sigma_c_tiles<false>, dim3((unsigned)(8 * per_xcd)),
+                       dim3(256), 0, s, static_cast<const z*>(a->rho), static_cast<const z*>(a->wr),
+                       static_cast<const z*>(a->om), a->e_m, a->f_m, static_cast<const z*>(a->z), a->nm, a->nn, a->ng,
+                       a->nz, a->eta, ntc, mchunk, ntile, nmc, (int)per_xcd, static_cast<z*>(ws));
   }
   XO_CHECK_LAUNCH();
   {

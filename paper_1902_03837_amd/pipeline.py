@@ -133,24 +133,27 @@ class SigmaPlan:
             f = torch.zeros(nb, dtype=torch.float64, device=dev)
             f[:cr.nocc_at(ikp)] = 1.0
             self.qs.append(dict(ikp=ikp, g0=g0, ng=ng, nb=nb, vsqrt=s, head=head, f=f, cr=cr,
-                                rho=torch.empty((nb, self.nn, ng), dtype=torch.complex128, device=dev),
+                                rho=torch.empty((self.nn, nb, ng), dtype=torch.complex128, device=dev),
                                 wr=torch.empty((ng, ng), dtype=torch.complex128, device=dev),
                                 om=torch.empty((ng, ng), dtype=torch.complex128, device=dev)))
 
 
 def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0, stream=None):
     """Sigma_x and Sigma_c of the planned states, summed over q: the oscillator strengths
-    of every q in one xo_rho_batch (states at k against every band at k - q, no q -> 0
-    substitution), then per q one xo_ppa_fit on eps~^-1 at (0, i omega_p) and one xo_sigma."""
+    of every q in one xo_rho_batch (in their mirrored form, every band at k - q on the
+    conduction side against the states at k; no q -> 0 substitution), then per q one
+    xo_ppa_fit on eps~^-1 at (0, i omega_p) and one xo_sigma."""
     dc, st = plan.dc, plan.states
     if plan.rho_plan is None:
         calls = []
         for Q in plan.qs:
             cr, ikp = Q["cr"], Q["ikp"]
-            calls.append(dict(coef_c=dc.coef[plan.ik0][st], mill_c=cr.mill[plan.ik0], e_c=None,
-                              coef_v=dc.coef[ikp], mill_v=cr.mill[ikp], e_v=None, gmill=cr.gmill, g0=Q["g0"],
-                              grid=cr.grid, out=Q["rho"], prec="fp64", kcart=cr.kcart(plan.ik0),
-                              bvec=cr.lat.bvec))
+            # mirrored strengths <m k-q| e^{i(-q-G).r} |n k> = conj(rho_nm(q, G)): the bands on
+            # the conduction side, the states on the valence side, G0 and the G-set negated
+            calls.append(dict(coef_c=dc.coef[ikp], mill_c=cr.mill[ikp], e_c=None,
+                              coef_v=dc.coef[plan.ik0][st], mill_v=cr.mill[plan.ik0], e_v=None,
+                              gmill=-np.asarray(cr.gmill), g0=-np.asarray(Q["g0"]), grid=cr.grid, out=Q["rho"],
+                              prec="fp64", kcart=cr.kcart(ikp), bvec=cr.lat.bvec))
         plan.rho_plan = xo.RhoPlan(calls, batch=True)
     xo.launch_plan(plan.rho_plan, stream=stream)
     for iq, Q in enumerate(plan.qs):
@@ -158,7 +161,8 @@ def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0
         E = einv_by_q[iq]
         xo.ppa_fit(E[0], E[1], omega_p, Q["vsqrt"], Q["head"], wr=Q["wr"], om=Q["om"], stream=stream)
         xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, 1.0 / (cr.nk * cr.lat.omega),
-                 sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, stream=stream)
+                 sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, swapped=True,
+                 stream=stream)
     return sigc, sigx
 
 

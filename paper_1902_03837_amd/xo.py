@@ -86,7 +86,8 @@ class SigmaArgs(C.Structure):
     _fields_ = [("nm", C.c_int), ("nn", C.c_int), ("ng", C.c_int), ("nz", C.c_int), ("rho", C.c_void_p),
                 ("wr", C.c_void_p), ("om", C.c_void_p), ("e_m", C.c_void_p), ("f_m", C.c_void_p),
                 ("z", C.c_void_p), ("eta", C.c_double), ("pref", C.c_double), ("vsqrt", _f64p),
-                ("head", C.c_double), ("sigx", C.c_void_p), ("sigc", C.c_void_p), ("accumulate", C.c_int)]
+                ("head", C.c_double), ("sigx", C.c_void_p), ("sigc", C.c_void_p), ("accumulate", C.c_int),
+                ("rho_swapped", C.c_int)]
 
 
 class Tune(C.Structure):
@@ -465,13 +466,17 @@ def ppa_fit(einv0, einvp, omega_p, vsqrt, head=None, *, wr, om, stream=None):
 
 
 def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=None, head=None,
-          accumulate=False, stream=None):
+          accumulate=False, swapped=False, stream=None):
     """xo_sigma for one q: sigc[nn][nz] (complex128) and sigx[nn] (float64), (+)=.
 
-    rho_m [nm][nn][ng] complex128 (xo_rho with the states n on the conduction side),
-    e_m, f_m [nm] float64 and z [nn][nz] complex128 on the device."""
+    rho_m [nm][nn][ng] complex128 (xo_rho with the states n on the conduction side), or with
+    swapped=True [nn][nm][ng] from xo_rho with the bands on the conduction side, G0 and the
+    G-set negated; e_m, f_m [nm] float64 and z [nn][nz] complex128 on the device."""
     import torch
-    nm, nn, ng = rho_m.shape
+    if swapped:
+        nn, nm, ng = rho_m.shape
+    else:
+        nm, nn, ng = rho_m.shape
     assert rho_m.dtype == torch.complex128 and rho_m.is_contiguous()
     assert e_m.dtype == f_m.dtype == torch.float64 and e_m.numel() == nm and f_m.numel() == nm
     nz = 0 if z is None else z.shape[1]
@@ -493,6 +498,7 @@ def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=
     a.sigx = _ptr(sigx) if sigx is not None else None
     a.sigc = _ptr(sigc) if nz else None
     a.accumulate = 1 if accumulate else 0
+    a.rho_swapped = 1 if swapped else 0
     _check(lib().xo_sigma(C.byref(a), _stream(stream)))
     return sigc, sigx
 

@@ -174,7 +174,7 @@ def test_empty_and_degenerate_inputs_are_rejected():
 def test_ppa_and_sigma_argument_errors():
     L = xo.lib()
     assert C.sizeof(xo.PpaArgs) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert C.sizeof(xo.SigmaArgs) == 4 * 4 + 6 * 8 + 2 * 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(xo.SigmaArgs) == 4 * 4 + 6 * 8 + 2 * 8 + 8 + 8 + 8 + 8 + 4 + 4
     a = xo.PpaArgs()
     rc, msg = _rc(L.xo_ppa_fit, a)
     assert rc == xo.XO_ERR_ARG and "positive" in msg

@@ -123,6 +123,29 @@ def test_sigma_matches_oracle(nm, nn, ng, nz, frac):
         assert np.max(np.abs(sigc.cpu().numpy() - 2 * sc_ref)) <= 2 * TOL * np.max(np.abs(sc_ref))
 
 
+def test_sigma_swapped_layout_equals_plain():
+    say("sigma swapped layout")
+    nm, nn, ng, nz = 23, 3, 70, 2
+    e0, ep = _einv_pair(55, ng)
+    s = rng(56).uniform(0.2, 3.0, ng)
+    rho = random_complex(57, (nm, nn, ng), 0.2)
+    e = np.linspace(-0.9, 1.4, nm)
+    f = (e < 0.05).astype(float)
+    z = random_complex(58, (nn, nz), 0.3)
+    wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
+    om = torch.empty_like(wr)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, None, wr=wr, om=om)
+    outs = []
+    for sw, r in ((False, rho), (True, np.conj(rho).transpose(1, 0, 2))):
+        sigc = torch.empty((nn, nz), dtype=torch.complex128, device=DEV)
+        sigx = torch.empty((nn,), dtype=torch.float64, device=DEV)
+        xo.sigma(_to(r), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, 0.3,
+                 sigc=sigc, sigx=sigx, vsqrt=s, swapped=sw)
+        torch.cuda.synchronize()
+        outs.append((sigc.cpu().numpy(), sigx.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_sigma_head_override_at_q0():
     say("sigma q=0 head override")
     nm, nn, ng = 6, 2, 40
