@@ -101,7 +101,7 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
     (xo_chi0_real, Dyson step with the LU fallback) instead of the crystal's imaginary ones."""
     import torch
     from paper_1902_03837_amd import xo
-    from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE
+    from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE, chi0_pref, qpg as qpg_of
 
     dc = DeviceCrystal.upload(cr, prec)
     ng, nw = cr.gmill.shape[0], len(cr.omegas) if real is None else len(real[0])
@@ -112,7 +112,8 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
     chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
     E = torch.empty_like(chi)
     info = torch.zeros(nw, dtype=torch.int32, device=dev)   # pivot flags, read after the timed steps
-    qpg = cr.qpg()
+    qpg = qpg_of(cr)
+    pref = chi0_pref(cr)
     st = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -122,9 +123,9 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
         if ev:
             ev[1].record(st)
         if real is None:
-            xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=prec, check_dE=False)
+            xo.chi0(M, dE, cr.omegas, pref, out=chi, prec=prec, check_dE=False)
         else:
-            xo.chi0_real(M, dE, real[0], real[1], cr.pref, out=chi, prec=prec, check_dE=False)
+            xo.chi0_real(M, dE, real[0], real[1], pref, out=chi, prec=prec, check_dE=False)
         if ev:
             ev[2].record(st)
         xo.epsinv(chi, qpg, out=E, info=info, flags=xo.XO_EPS_SYM if real is None else xo.XO_EPS_LU_FALLBACK)
@@ -171,8 +172,8 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
 def cpu_baseline(cr, npairs):
     """The FP64 oracle as it stands, on the host cores, for the first npairs k-pairs."""
     from oracle.pipeline import rho_pair
-    from oracle.chi0 import chi0_from_rho
-    from oracle.epsinv import epsinv_sym
+    from oracle.chi0 import chi0_from_rho, crystal_prefactor
+    from oracle.epsinv import epsinv_sym, crystal_qpg
     t0 = time.perf_counter()
     Ms, ds = [], []
     for ip in range(npairs):
@@ -180,8 +181,8 @@ def cpu_baseline(cr, npairs):
         Ms.append(m)
         ds.append(d)
     M, dE = np.concatenate(Ms), np.concatenate(ds)
-    chi = chi0_from_rho(M, dE, cr.omegas, cr.pref)
-    epsinv_sym(chi, cr.qpg(), check=False)
+    chi = chi0_from_rho(M, dE, cr.omegas, crystal_prefactor(cr))
+    epsinv_sym(chi, crystal_qpg(cr), check=False)
     dt = time.perf_counter() - t0
     ng, nw = cr.gmill.shape[0], len(cr.omegas)
     K = M.shape[0]
@@ -313,7 +314,7 @@ def run_c3(args):
     import torch
     from synth.configs import crystal_q_set
     from paper_1902_03837_amd import xo, tune
-    from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE
+    from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE, chi0_pref, qpg
 
     t0 = time.perf_counter()
     crs = crystal_q_set("c3", nq=args.nq)
@@ -347,14 +348,14 @@ def run_c3(args):
             rho_all(dc, b["M"], b["dE"])
         if ev:
             ev[1].record(st)
-        xo.chi0_batch([(b["M"], b["dE"], dc.cr.pref, b["chi"]) for dc, b in zip(dcs, bufs)], crs[0].omegas,
+        xo.chi0_batch([(b["M"], b["dE"], chi0_pref(dc.cr), b["chi"]) for dc, b in zip(dcs, bufs)], crs[0].omegas,
                       prec=prec, tune=tn, check_dE=False)
         if ev:
             ev[2].record(st)
         for sd in side:
             sd.wait_stream(st)
         for j, (dc, b) in enumerate(zip(dcs, bufs)):
-            xo.epsinv(b["chi"], dc.cr.qpg(), out=b["E"], info=b["info"], stream=side[j % len(side)])
+            xo.epsinv(b["chi"], qpg(dc.cr), out=b["E"], info=b["info"], stream=side[j % len(side)])
         for sd in side:
             st.wait_stream(sd)
         if ev:
@@ -368,7 +369,7 @@ def run_c3(args):
         if prec != "fp64":
             for dc, b in zip(dcs, bufs):
                 rho_all(dc, b["M"], b["dE"])
-            items = [(b["M"], b["dE"], dc.cr.pref, b["chi"]) for dc, b in zip(dcs, bufs)]
+            items = [(b["M"], b["dE"], chi0_pref(dc.cr), b["chi"]) for dc, b in zip(dcs, bufs)]
             tn, tms, cached = tune.tuned(items, crs[0].omegas, prec, path=args.tune_cache)
             print(f"[bench] c3 {prec}: tuned chi0 launch {tn} ({tms:.2f} ms on a sample, cached={cached})",
                   file=sys.stderr, flush=True)

@@ -379,21 +379,27 @@ int xo_xterm(const xo_xterm_args* a, void* stream);
  *   Om = omega_p sqrt(Xp / (X0 - Xp))  (principal root),  R = -X0 Om / 2,
  * where Re(Xp conj(X0 - Xp)) > 0 (evaluated without fused operations); any
  * other element keeps its static value: Om = omega_p, R = -X0 omega_p / 2.
- * Output is the residue of the screened part of W, Wr = R vsqrt_G vsqrt_G',
- * and Om. At q = 0 pass vsqrt[0] = 0 (wings) and the cell average of 4pi/q^2
- * as head (>= 0), which replaces vsqrt_0^2 for the (0, 0) element; head < 0
- * means no override. FP64.
+ * Output is the residue of the screened part of W, Wr = R v^1/2_G v^1/2_G', and
+ * Om. The library forms the Coulomb factors (Coulomb interaction subsection):
+ * v^1/2_G = sqrt(4 pi)/|q+G|; at q = 0 (q0 = 1, G = 0 the first entry of the
+ * G-set) v^1/2_0 = 0 (the wings, odd in q, average to zero over the small cell
+ * around q = 0) and the (0, 0) element takes the mean of 4 pi/q^2 over the sphere
+ * of volume (2 pi)^3/(N_k Omega), 12 pi/q_c^2, q_c = (6 pi^2/(N_k Omega))^(1/3)
+ * (a reading: the paper leaves the q = 0 treatment to the Coulomb options). FP64.
  *   einv0, einvp: [device] [ng][ng] complex128 (eps~^-1 at 0 and i omega_p)
- *   vsqrt: [host] [ng] sqrt(4 pi)/|q+G| (finite, >= 0)
+ *   qpg: [host] [ng] |q+G| in 1/bohr, positive and finite (entry 0 not read when q0)
+ *   nk_omega: N_k Omega in bohr^3 (read when q0)
  *   wr, om: [device] [ng][ng] complex128, written (may not alias the inputs).
- * Errors: XO_ERR_ARG for ng <= 0, null pointers, omega_p <= 0, bad vsqrt. */
+ * Errors: XO_ERR_ARG for ng <= 0, null pointers, omega_p <= 0, a bad |q+G|, or
+ * nk_omega <= 0 at q = 0. */
 typedef struct {
   int ng;
   const void* einv0;
   const void* einvp;
   double omega_p;
-  const double* vsqrt;
-  double head;
+  const double* qpg;
+  int q0;
+  double nk_omega;
   void* wr;
   void* om;
 } xo_ppa_args;
@@ -405,10 +411,12 @@ int xo_ppa_fit(const xo_ppa_args* a, void* stream);
  * for the index order):
  *   sigc[n][j] (+)= pref sum_m sum_{G,G'} rho_nm(G) conj(rho_nm(G')) Wr_GG'
  *                   [ f_m / (z_nj - e_m + Om_GG' - i eta) + (1 - f_m) / (z_nj - e_m - Om_GG' + i eta) ]
- *   sigx[n]    (+)= -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G,  v_G = vsqrt_G^2 (head at G = 0 if >= 0)
+ *   sigx[n]    (+)= -pref sum_m f_m sum_G |rho_nm(G)|^2 v_G,  v_G = 4 pi/|q+G|^2 (q = 0: the head
+ *                   mean of 4 pi/q^2 at G = 0, as in xo_ppa_fit)
  * rho_nm(G) = <n k| e^{i(q+G).r} |m k-q> as written by xo_rho with the states n
  * on the conduction side (at k) and the bands m on the valence side (at k-q).
- * pref = 1/(N_k Omega); e_m in Ha on the scale of z; f_m in [0, 1] per spin.
+ * pref = 1/(N_k Omega) from nk_omega = N_k Omega (bohr^3); e_m in Ha on the scale
+ * of z; f_m in [0, 1] per spin.
  * Sum over q by calling once per q with accumulate = 1 after the first.
  * rho_swapped = 1: rho holds instead the mirrored strengths
  * <m k-q| e^{i(-q+G').r} |n k> for G' = -G, which equal conj(rho_nm(G)), in
@@ -418,9 +426,10 @@ int xo_ppa_fit(const xo_ppa_args* a, void* stream);
  *   rho: [device] [nm][nn][ng] complex128 ([nn][nm][ng] when swapped); wr, om: [device] [ng][ng] complex128
  *   (from xo_ppa_fit); e_m, f_m: [device] [nm]; z: [device] [nn][nz] complex128
  *   (nz <= 4; z may be complex, e.g. i nu with eta = 0 on the imaginary axis);
- *   vsqrt: [host] [ng] (needed when sigx is set); sigx: [device] [nn] or NULL;
+ *   qpg: [host] [ng] |q+G| (needed when sigx is set; q0 as in xo_ppa_fit); sigx: [device] [nn] or NULL;
  *   sigc: [device] [nn][nz] complex128 (unused when nz = 0).
- * Errors: XO_ERR_ARG for bad sizes, nz > 4, null pointers, pref <= 0, eta < 0. */
+ * Errors: XO_ERR_ARG for bad sizes, nz > 4, null pointers, nk_omega <= 0, eta < 0,
+ * a bad |q+G|. */
 typedef struct {
   int nm, nn, ng, nz;
   const void* rho;
@@ -430,9 +439,9 @@ typedef struct {
   const double* f_m;
   const void* z;
   double eta;
-  double pref;
-  const double* vsqrt;
-  double head;
+  double nk_omega;
+  const double* qpg;
+  int q0;
   double* sigx;
   void* sigc;
   int accumulate;

@@ -29,7 +29,7 @@ unpinned: the oracle is the reference.
 """
 
 from .rho import rho_direct, rho_fft, orbitals_real_space, rho_head_q0  # noqa: F401
-from .chi0 import chi0_from_rho, pole_weights, chi0_real_axis  # noqa: F401
-from .epsinv import epsinv_sym, epsinv_nonsym, eps_tilde  # noqa: F401
+from .chi0 import chi0_from_rho, pole_weights, chi0_real_axis, chi0_prefactor, crystal_prefactor  # noqa: F401
+from .epsinv import epsinv_sym, epsinv_nonsym, eps_tilde, crystal_qpg  # noqa: F401
 from .pipeline import rho_all_pairs, chi0_crystal, epsinv_crystal  # noqa: F401
 from .metrics import rel_fro, err_table  # noqa: F401

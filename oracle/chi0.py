@@ -23,6 +23,25 @@ from __future__ import annotations
 import numpy as np
 
 
+SPIN_FACTOR = 2.0   # f_s: spin-unpolarised, two electrons per occupied band
+
+
+def cell_volume(avec) -> float:
+    """Omega = |det(a1, a2, a3)|, the volume of the primitive cell (rows of avec, bohr)."""
+    return float(abs(np.linalg.det(np.asarray(avec, dtype=np.float64))))
+
+
+def chi0_prefactor(nk: int, avec) -> float:
+    """pref = f_s / (N_k Omega) of Eq. (X_IP): the spin factor over the number of
+    k-points times the cell volume (the Brillouin-zone sum as an average)."""
+    return SPIN_FACTOR / (int(nk) * cell_volume(avec))
+
+
+def crystal_prefactor(cr) -> float:
+    """pref of a crystal: its k-point count and its lattice vectors."""
+    return chi0_prefactor(len(cr.kf), cr.lat.avec)
+
+
 def pole_weights(dE: np.ndarray, w: float) -> np.ndarray:
     """2 Delta / (w^2 + Delta^2) for each transition (the magnitude of -F_t(i w))."""
     dE = np.asarray(dE, dtype=np.float64)

@@ -20,6 +20,20 @@ import numpy as np
 import scipy.linalg
 
 
+def qpg_norms(bvec, qf, gmill) -> np.ndarray:
+    """|q+G| in 1/bohr for the G-set (q and G in units of the reciprocal vectors, rows of
+    bvec). At q = 0 the G = 0 entry is 1: the head and wings of chi0 there are the
+    q-normalised limits (rho / |q|), so s_0 = sqrt(4 pi)."""
+    qg = (np.asarray(qf, dtype=np.float64)[None, :] + np.asarray(gmill, dtype=np.float64)) @ np.asarray(bvec, float)
+    n = np.sqrt(np.einsum("ij,ij->i", qg, qg))
+    n[n < 1e-12] = 1.0
+    return n
+
+
+def crystal_qpg(cr) -> np.ndarray:
+    return qpg_norms(cr.lat.bvec, cr.qf, cr.gmill)
+
+
 def coulomb_sqrt(qpg: np.ndarray) -> np.ndarray:
     return np.sqrt(4.0 * np.pi) / np.asarray(qpg, dtype=np.float64)
 

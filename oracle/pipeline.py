@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 from .rho import rho_direct, rho_fft, rho_head_q0
-from .chi0 import chi0_from_rho
-from .epsinv import epsinv_sym
+from .chi0 import chi0_from_rho, crystal_prefactor
+from .epsinv import epsinv_sym, crystal_qpg
 
 
 def rho_pair(cr, ipair, route="fft", nempty=None, band_lo=None, qhat=(1.0, 0.0, 0.0)):
@@ -46,9 +46,9 @@ def rho_all_pairs(cr, route="fft", nempty=None, band_lo=None):
 
 def chi0_crystal(cr, route="fft", nempty=None):
     M, dE = rho_all_pairs(cr, route, nempty)
-    return chi0_from_rho(M, dE, cr.omegas, cr.pref)
+    return chi0_from_rho(M, dE, cr.omegas, crystal_prefactor(cr))
 
 
 def epsinv_crystal(cr, route="fft", nempty=None):
     chi = chi0_crystal(cr, route, nempty)
-    return epsinv_sym(chi, cr.qpg()), chi
+    return epsinv_sym(chi, crystal_qpg(cr)), chi

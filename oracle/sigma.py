@@ -43,6 +43,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from .chi0 import cell_volume
+
 
 def ppa_fit(einv0, einvp, omega_p: float):
     """Plasmon-pole parameters (R, Om) of every element from eps~^-1 at 0 and i omega_p."""
@@ -116,6 +118,13 @@ def sigma_x(rho, f_m, vsqrt, head, pref: float):
     return out
 
 
+def sigma_prefactor(nk: int, avec) -> float:
+    """pref = 1 / (N_k Omega): the q-sum of Eq. (sigma_c) as a Brillouin-zone average over
+    the N_k points of the grid, with the cell volume from the lattice vectors. Sigma is per
+    spin (f_m in [0, 1]), so there is no spin factor."""
+    return 1.0 / (int(nk) * cell_volume(avec))
+
+
 def coulomb_head_average(nk: int, omega: float) -> float:
     """Cell average of 4 pi / q^2 at q = 0, over the sphere whose volume is the
     Brillouin-zone share of one k-point, (2 pi)^3 / (N_k Omega) (a reading: the paper
@@ -148,14 +157,14 @@ def sigma_kpoint(crs, einv_by_q, ik0: int, states, z, eta: float = 0.0, omega_p:
         if cr.q0:
             s = np.zeros_like(nrm)
             s[1:] = np.sqrt(4.0 * np.pi) / nrm[1:]
-            head = coulomb_head_average(cr.nk, cr.lat.omega)
+            head = coulomb_head_average(cr.nk, cell_volume(cr.lat.avec))
         else:
             s = np.sqrt(4.0 * np.pi) / nrm
         R, Om = ppa_fit(E[0], E[1], omega_p)
         Wr = R * coulomb_factor(s, head)
         f = np.zeros(nb)
         f[:cr.nocc_at(ikp)] = 1.0
-        pref = 1.0 / (cr.nk * cr.lat.omega)
+        pref = sigma_prefactor(cr.nk, cr.lat.avec)
         sx += sigma_x(rho, f, s, head, pref)
         sc += sigma_c_ppa(rho, Wr, Om, cr.eps[ikp], f, z, eta, pref)
     return sx, sc

@@ -28,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 
 from .rho import rho_direct
-from .chi0 import pole_weights
+from .chi0 import pole_weights, crystal_prefactor
 
 
 def density_elements(coef, mill, kmill):
@@ -51,6 +51,7 @@ def xterm_bg(cr, nempty_explicit: int, shift: float = 1.5, rho_route=None):
     kuniq, kidx = np.unique(diff, axis=0, return_inverse=True)
     kidx = kidx.reshape(ng, ng)
     out = np.zeros((nw, ng, ng), dtype=np.complex128)
+    pref = crystal_prefactor(cr)
     for ik, ikp, g0 in cr.pairs:
         nb = cr.nocc_at(ik) + nempty_explicit          # explicit bands n <= N_b' at k
         ebar = cr.eps[ik][nb - 1] + shift
@@ -61,5 +62,5 @@ def xterm_bg(cr, nempty_explicit: int, shift: float = 1.5, rho_route=None):
         S = np.einsum("vng,vnh->vgh", R, np.conj(R))
         for j, w in enumerate(cr.omegas):
             wt = pole_weights(ebar - ev, w)
-            out[j] += -cr.pref * np.einsum("v,vgh->gh", wt, D - S)
+            out[j] += -pref * np.einsum("v,vgh->gh", wt, D - S)
     return out

@@ -7,6 +7,11 @@
 //                  Om = wp sqrt(Xp / (X0 - Xp)), R = -X0 Om / 2 where
 //                  Re(Xp conj(X0 - Xp)) > 0, else Om = wp, R = -X0 wp / 2;
 //                  writes Wr = R v^1/2_G v^1/2_G' (head override at G = G' = 0)
+//   Coulomb factors v^1/2_G = sqrt(4 pi)/|q+G| (Coulomb interaction subsection) are formed
+//   here from |q+G|; at q = 0 the G = 0 entry is 0 (the wings, odd in q, average to zero
+//   over the small cell around q = 0) and the (0, 0) element takes the mean of 4 pi/q^2
+//   over the sphere of volume (2 pi)^3/(N_k Omega), 12 pi/q_c^2 with
+//   q_c = (6 pi^2/(N_k Omega))^(1/3); pref = 1/(N_k Omega).
 //   sigma_c_tiles  Sigma_c,nn(z) = pref sum_m sum_GG' rho_nm(G) conj(rho_nm(G')) Wr_GG'
 //                  [f_m / (z - e_m + Om - i eta) + (1 - f_m) / (z - e_m - Om + i eta)];
 //                  a workgroup owns a 32 x 32 block of (G, G') held in registers (four
@@ -273,6 +278,24 @@ __global__ void __launch_bounds__(64) sigma_x_sum(const double* __restrict__ par
   if (threadIdx.x == 0) out[n] = (accumulate ? out[n] : 0.0) - pref * x;
 }
 
+// v^1/2 table and q = 0 head from |q+G| (host, during the call); returns the head or -1.
+static int coulomb_tables(const char* who, const double* qpg, int ng, int q0, double nk_omega,
+                          std::vector<double>& vs, double* head) {
+  XO_ARG(qpg, "%s: null qpg", who);
+  vs.assign(ng, 0.0);
+  for (int g = q0 ? 1 : 0; g < ng; ++g) {
+    XO_ARG(std::isfinite(qpg[g]) && qpg[g] > 0.0, "%s: |q+G| at %d must be positive and finite", who, g);
+    vs[g] = std::sqrt(4.0 * M_PI) / qpg[g];
+  }
+  *head = -1.0;
+  if (q0) {
+    XO_ARG(nk_omega > 0.0 && std::isfinite(nk_omega), "%s: nk_omega must be positive at q = 0", who);
+    const double qc = std::cbrt(6.0 * M_PI * M_PI / nk_omega);
+    *head = 12.0 * M_PI / (qc * qc);
+  }
+  return XO_OK;
+}
+
 }  // namespace
 }  // namespace xo
 
@@ -282,20 +305,19 @@ extern "C" int xo_ppa_fit(const xo_ppa_args* a, void* stream) {
   XO_ARG(a, "xo_ppa_fit: null argument block");
   XO_ARG(a->ng > 0, "xo_ppa_fit: ng must be positive (got %d)", a->ng);
   XO_ARG(a->einv0 && a->einvp && a->wr && a->om, "xo_ppa_fit: null device pointer");
-  XO_ARG(a->vsqrt, "xo_ppa_fit: null vsqrt");
   XO_ARG(a->omega_p > 0.0 && std::isfinite(a->omega_p), "xo_ppa_fit: omega_p must be positive");
-  for (int g = 0; g < a->ng; ++g)
-    XO_ARG(std::isfinite(a->vsqrt[g]) && a->vsqrt[g] >= 0.0, "xo_ppa_fit: vsqrt[%d] must be finite and >= 0", g);
-  XO_ARG(std::isfinite(a->head), "xo_ppa_fit: head must be finite (negative for none)");
+  std::vector<double> vs;
+  double head = -1.0;
+  XO_RET(coulomb_tables("xo_ppa_fit", a->qpg, a->ng, a->q0, a->nk_omega, vs, &head));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* dvs = nullptr;
-  XO_RET(device_table(a->vsqrt, sizeof(double) * a->ng, s, &dvs));
+  XO_RET(device_table(vs.data(), sizeof(double) * a->ng, s, &dvs));
   const size_t ne = (size_t)a->ng * a->ng;
   {
     KernelTimer kt_("ppa_fit", s);
     hipLaunchKernelGGL(ppa_fit, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s,
                        static_cast<const z*>(a->einv0), static_cast<const z*>(a->einvp), a->ng, a->omega_p,
-                       static_cast<const double*>(dvs), a->head, static_cast<z*>(a->wr), static_cast<z*>(a->om));
+                       static_cast<const double*>(dvs), head, static_cast<z*>(a->wr), static_cast<z*>(a->om));
   }
   XO_CHECK_LAUNCH();
   return XO_OK;
@@ -310,17 +332,18 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
   XO_ARG(a->nz <= kMaxZ, "xo_sigma: at most %d frequencies per state (got %d)", kMaxZ, a->nz);
   XO_ARG(a->rho && a->e_m && a->f_m, "xo_sigma: null device pointer");
   XO_ARG(a->nz == 0 || (a->wr && a->om && a->z && a->sigc), "xo_sigma: null device pointer for Sigma_c");
-  XO_ARG(a->vsqrt || !a->sigx, "xo_sigma: Sigma_x needs vsqrt");
-  XO_ARG(a->pref > 0.0 && std::isfinite(a->pref), "xo_sigma: pref must be positive");
+  XO_ARG(a->qpg || !a->sigx, "xo_sigma: Sigma_x needs qpg");
+  XO_ARG(a->nk_omega > 0.0 && std::isfinite(a->nk_omega), "xo_sigma: nk_omega must be positive");
+  const double pref = 1.0 / a->nk_omega;
   XO_ARG(a->eta >= 0.0 && std::isfinite(a->eta), "xo_sigma: eta must be finite and >= 0");
   XO_ARG((size_t)a->nm * a->nn * a->ng < ((size_t)1 << 40), "xo_sigma: rho too large");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (a->sigx) {
-    for (int g = 0; g < a->ng; ++g)
-      XO_ARG(std::isfinite(a->vsqrt[g]) && a->vsqrt[g] >= 0.0, "xo_sigma: vsqrt[%d] must be finite and >= 0", g);
-    XO_ARG(std::isfinite(a->head), "xo_sigma: head must be finite (negative for none)");
+    std::vector<double> vs;
+    double head = -1.0;
+    XO_RET(coulomb_tables("xo_sigma", a->qpg, a->ng, a->q0, a->nk_omega, vs, &head));
     const void* dvs = nullptr;
-    XO_RET(device_table(a->vsqrt, sizeof(double) * a->ng, s, &dvs));
+    XO_RET(device_table(vs.data(), sizeof(double) * a->ng, s, &dvs));
     const int nch = (a->nm + kXB - 1) / kXB;
     XO_ARG(nch <= 65535, "xo_sigma: too many bands per call (nm=%d)", a->nm);
     void* wx = nullptr;
@@ -328,13 +351,13 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
     {
       KernelTimer kt_("sigma_x_part", s);
       hipLaunchKernelGGL(sigma_x_part, dim3(a->nn, nch), dim3(256), 0, s, static_cast<const z*>(a->rho), a->f_m,
-                         static_cast<const double*>(dvs), a->head, a->nm, a->nn, a->ng, a->rho_swapped ? 1 : 0,
+                         static_cast<const double*>(dvs), head, a->nm, a->nn, a->ng, a->rho_swapped ? 1 : 0,
                          static_cast<double*>(wx));
     }
     XO_CHECK_LAUNCH();
     {
       KernelTimer kt_("sigma_x_sum", s);
-      hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(64), 0, s, static_cast<const double*>(wx), nch, a->pref,
+      hipLaunchKernelGGL(sigma_x_sum, dim3(a->nn), dim3(64), 0, s, static_cast<const double*>(wx), nch, pref,
                          a->accumulate, a->sigx);
     }
     XO_CHECK_LAUNCH();
@@ -362,7 +385,7 @@ extern "C" int xo_sigma(const xo_sigma_args* a, void* stream) {
   {
     KernelTimer kt_("sigma_reduce", s);
     hipLaunchKernelGGL(sigma_reduce, dim3(a->nn * a->nz), dim3(64), 0, s, static_cast<const z*>(ws), a->nn,
-                       a->nz, nparts, a->pref, a->accumulate, static_cast<z*>(a->sigc));
+                       a->nz, nparts, pref, a->accumulate, static_cast<z*>(a->sigc));
   }
   XO_CHECK_LAUNCH();
   return XO_OK;

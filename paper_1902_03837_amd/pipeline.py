@@ -38,6 +38,26 @@ class DeviceCrystal:
         return cls(cr, prec, coef, eps)
 
 
+def chi0_pref(cr) -> float:
+    """Prefactor of Eq. (X_IP) passed to xo_chi0: f_s / (N_k Omega), f_s = 2 (spin-unpolarised),
+    Omega the primitive-cell volume |det(a1, a2, a3)|."""
+    return 2.0 / (len(cr.kf) * abs(float(np.linalg.det(cr.lat.avec))))
+
+
+def nk_omega(cr) -> float:
+    """N_k Omega (bohr^3) of the crystal's k-grid, passed to the self-energy calls."""
+    return len(cr.kf) * abs(float(np.linalg.det(cr.lat.avec)))
+
+
+def qpg(cr) -> np.ndarray:
+    """|q+G| (1/bohr) over the G-set for xo_epsinv; at q = 0 the G = 0 entry is 1, the head and
+    wings of chi0 being the q-normalised limits there."""
+    g = (np.asarray(cr.qf, float)[None, :] + cr.gmill.astype(np.float64)) @ cr.lat.bvec
+    n = np.sqrt(np.einsum("ij,ij->i", g, g))
+    n[n < 1e-12] = 1.0
+    return n
+
+
 def band_ranges(cr, nempty: Optional[int] = None, band_lo: Optional[int] = None):
     """Per pair: (ik, ik', g0, conduction slice, valence count) in transition order."""
     out = []
@@ -98,16 +118,9 @@ def run_crystal(dc: DeviceCrystal, nempty=None, chi_prec=None, M=None, dE=None, 
     if E is None:
         E = torch.empty_like(chi)
     rho_all(dc, M, dE, nempty, stream=stream)
-    xo.chi0(M, dE, cr.omegas, cr.pref, out=chi, prec=chi_prec or dc.prec, check_dE=check_dE, stream=stream)
-    xo.epsinv(chi, cr.qpg(), out=E, stream=stream)
+    xo.chi0(M, dE, cr.omegas, chi0_pref(cr), out=chi, prec=chi_prec or dc.prec, check_dE=check_dE, stream=stream)
+    xo.epsinv(chi, qpg(cr), out=E, stream=stream)
     return M, dE, chi, E
-
-
-def q0_coulomb_head(nk: int, omega: float) -> float:
-    """Mean of 4 pi / q^2 over a sphere of volume (2 pi)^3 / (N_k Omega) around q = 0:
-    (3 / qc^3) * 4 pi * qc with qc the sphere's radius."""
-    qc = (6.0 * np.pi ** 2 / (nk * omega)) ** (1.0 / 3.0)
-    return 12.0 * np.pi / (qc * qc)
 
 
 class SigmaPlan:
@@ -124,15 +137,9 @@ class SigmaPlan:
             ik, ikp, g0 = cr.pairs[ik0]
             assert ik == ik0 and np.all(cr.gmill[0] == 0)
             ng, nb = cr.gmill.shape[0], dc.coef[ikp].shape[0]
-            qpg = cr.qpg()
-            s = np.sqrt(4.0 * np.pi) / qpg
-            head = None
-            if cr.q0:
-                s[0] = 0.0
-                head = q0_coulomb_head(cr.nk, cr.lat.omega)
             f = torch.zeros(nb, dtype=torch.float64, device=dev)
             f[:cr.nocc_at(ikp)] = 1.0
-            self.qs.append(dict(ikp=ikp, g0=g0, ng=ng, nb=nb, vsqrt=s, head=head, f=f, cr=cr,
+            self.qs.append(dict(ikp=ikp, g0=g0, ng=ng, nb=nb, qpg=qpg(cr), q0=cr.q0, nko=nk_omega(cr), f=f, cr=cr,
                                 rho=torch.empty((self.nn, nb, ng), dtype=torch.complex128, device=dev),
                                 wr=torch.empty((ng, ng), dtype=torch.complex128, device=dev),
                                 om=torch.empty((ng, ng), dtype=torch.complex128, device=dev)))
@@ -159,10 +166,10 @@ def sigma_kpoint(plan: SigmaPlan, einv_by_q, z, sigc, sigx, eta=0.0, omega_p=1.0
     for iq, Q in enumerate(plan.qs):
         cr, ikp = Q["cr"], Q["ikp"]
         E = einv_by_q[iq]
-        xo.ppa_fit(E[0], E[1], omega_p, Q["vsqrt"], Q["head"], wr=Q["wr"], om=Q["om"], stream=stream)
-        xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, 1.0 / (cr.nk * cr.lat.omega),
-                 sigc=sigc, sigx=sigx, vsqrt=Q["vsqrt"], head=Q["head"], accumulate=iq > 0, swapped=True,
-                 stream=stream)
+        xo.ppa_fit(E[0], E[1], omega_p, Q["qpg"], q0=Q["q0"], nk_omega=Q["nko"], wr=Q["wr"], om=Q["om"],
+                   stream=stream)
+        xo.sigma(Q["rho"], Q["wr"], Q["om"], dc.eps[ikp], Q["f"], z, eta, Q["nko"], sigc=sigc, sigx=sigx,
+                 qpg=Q["qpg"], q0=Q["q0"], accumulate=iq > 0, swapped=True, stream=stream)
     return sigc, sigx
 
 
@@ -183,7 +190,7 @@ def run_crystal_real(dc: DeviceCrystal, omegas, eta: float, nempty=None, chi_pre
     if E is None:
         E = torch.empty_like(chi)
     rho_all(dc, M, dE, nempty, stream=stream)
-    xo.chi0_real(M, dE, omegas, eta, cr.pref, out=chi, prec=chi_prec or dc.prec, check_dE=check_dE,
+    xo.chi0_real(M, dE, omegas, eta, chi0_pref(cr), out=chi, prec=chi_prec or dc.prec, check_dE=check_dE,
                  stream=stream)
-    xo.epsinv(chi, cr.qpg(), out=E, flags=xo.XO_EPS_SYM | xo.XO_EPS_LU_FALLBACK, stream=stream)
+    xo.epsinv(chi, qpg(cr), out=E, flags=xo.XO_EPS_SYM | xo.XO_EPS_LU_FALLBACK, stream=stream)
     return M, dE, chi, E

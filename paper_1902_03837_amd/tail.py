@@ -23,7 +23,7 @@ import numpy as np
 import torch
 
 from . import xo
-from .pipeline import DeviceCrystal, band_ranges
+from .pipeline import DeviceCrystal, band_ranges, chi0_pref, qpg
 
 DIMS = [9, 256, 256, 256, 2]   # 3 hidden layers of 256, SiLU
 NFEAT = 9
@@ -77,7 +77,7 @@ def chi0_blocks(dc: DeviceCrystal, cuts: List[int], prec: str = "fp64", stream=N
     for i, (a, b) in enumerate(spans):
         if i > 0:
             chi = chi.clone()
-        xo.chi0(M[a:b], dE[a:b], cr.omegas, cr.pref, out=chi, prec=prec, accumulate=i > 0, check_dE=False,
+        xo.chi0(M[a:b], dE[a:b], cr.omegas, chi0_pref(cr), out=chi, prec=prec, accumulate=i > 0, check_dE=False,
                 stream=stream)
         out.append(chi)
     return out
@@ -99,7 +99,7 @@ def xterm_chi0(dc: DeviceCrystal, nempty: int, chi_trunc, shift: float = 1.5, st
                cr.gmill, g0, cr.grid, out=M.view(nv, nb, ng), prec="fp64", kcart=cr.kcart(ik), bvec=cr.lat.bvec,
                stream=stream)
         ebar = float(cr.eps[ik][nb - 1]) + shift
-        xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], ebar, cr.gmill, cr.omegas, cr.pref, M, nb, out,
+        xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], ebar, cr.gmill, cr.omegas, chi0_pref(cr), M, nb, out,
                  stream=stream)
     return out
 
@@ -190,7 +190,7 @@ def build_features(cr, chis, mu, isd, tsc, dev="cuda"):
     n = nw * ng * ng
     X = torch.empty((n, NFEAT), dtype=torch.float32, device=dev)
     T = torch.empty((n, 2), dtype=torch.float32, device=dev) if len(chis) > 2 else None
-    xo.tail_features(chis[1], chis[0], cr.qpg(), gdiff_table(cr), cr.omegas, mu, isd, X,
+    xo.tail_features(chis[1], chis[0], qpg(cr), gdiff_table(cr), cr.omegas, mu, isd, X,
                      chi_f=chis[2] if len(chis) > 2 else None, T=T, tsc=tsc)
     return X, T
 
@@ -286,5 +286,5 @@ def predict(model: TailModel, cr, chis_trunc, dev="cuda"):
     if st[0] > 0 or dis > model.tau:
         return None, info
     out = torch.empty_like(chis_trunc[1])
-    xo.tail_apply(chis_trunc[1], Ys[0], cr.qpg(), model.tsc, out, Y2=Ys[1] if len(Ys) > 1 else None)
+    xo.tail_apply(chis_trunc[1], Ys[0], qpg(cr), model.tsc, out, Y2=Ys[1] if len(Ys) > 1 else None)
     return out, info

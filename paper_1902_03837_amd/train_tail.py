@@ -27,7 +27,7 @@ import torch
 
 from . import xo
 from . import tail as T
-from .pipeline import DeviceCrystal
+from .pipeline import DeviceCrystal, qpg as qpg_of
 
 
 def log(msg):
@@ -50,7 +50,7 @@ def _train(args, train_seeds, ntrunc, nhalf):
         t2 = time.time()
         chis, _ = T.crystal_tensors(cr, ntrunc, nhalf, base=args.base)
         torch.cuda.synchronize()
-        geo.append((cr.qpg(), T.gdiff_table(cr), cr.omegas, cr.gmill.shape[0]))
+        geo.append((qpg_of(cr), T.gdiff_table(cr), cr.omegas, cr.gmill.shape[0]))
         chis_all.append(chis)
         log(f"[tail] train crystal {i + 1}/{len(train_seeds)} seed {s}: fixture {t2 - t1:.1f} s, "
             f"gpu {time.time() - t2:.2f} s")
@@ -123,7 +123,7 @@ def main(argv=None):
     rows = []
     for i, s in enumerate(test_seeds):
         cr = crystal_for(args.workload, seed=s)
-        qpg = cr.qpg()
+        qpg = qpg_of(cr)
         dc = DeviceCrystal.upload(cr, "fp64")
         ng, nw = cr.gmill.shape[0], len(cr.omegas)
         E = {k: torch.empty((nw, ng, ng), dtype=torch.complex128, device="cuda")

@@ -79,14 +79,14 @@ class Chi0RealArgs(C.Structure):
 
 class PpaArgs(C.Structure):
     _fields_ = [("ng", C.c_int), ("einv0", C.c_void_p), ("einvp", C.c_void_p), ("omega_p", C.c_double),
-                ("vsqrt", _f64p), ("head", C.c_double), ("wr", C.c_void_p), ("om", C.c_void_p)]
+                ("qpg", _f64p), ("q0", C.c_int), ("nk_omega", C.c_double), ("wr", C.c_void_p), ("om", C.c_void_p)]
 
 
 class SigmaArgs(C.Structure):
     _fields_ = [("nm", C.c_int), ("nn", C.c_int), ("ng", C.c_int), ("nz", C.c_int), ("rho", C.c_void_p),
                 ("wr", C.c_void_p), ("om", C.c_void_p), ("e_m", C.c_void_p), ("f_m", C.c_void_p),
-                ("z", C.c_void_p), ("eta", C.c_double), ("pref", C.c_double), ("vsqrt", _f64p),
-                ("head", C.c_double), ("sigx", C.c_void_p), ("sigc", C.c_void_p), ("accumulate", C.c_int),
+                ("z", C.c_void_p), ("eta", C.c_double), ("nk_omega", C.c_double), ("qpg", _f64p),
+                ("q0", C.c_int), ("sigx", C.c_void_p), ("sigc", C.c_void_p), ("accumulate", C.c_int),
                 ("rho_swapped", C.c_int)]
 
 
@@ -450,28 +450,30 @@ def _host_f64(a, n):
     return v
 
 
-def ppa_fit(einv0, einvp, omega_p, vsqrt, head=None, *, wr, om, stream=None):
-    """xo_ppa_fit: plasmon-pole residue of W_c (wr) and pole energies (om), [ng][ng] complex128."""
+def ppa_fit(einv0, einvp, omega_p, qpg, *, q0=False, nk_omega=0.0, wr, om, stream=None):
+    """xo_ppa_fit: plasmon-pole residue of W_c (wr) and pole energies (om), [ng][ng] complex128.
+    qpg: |q+G| per G (host); q0: q = 0 with G = 0 first (then nk_omega = N_k Omega is used)."""
     import torch
     ng = einv0.shape[-1]
     for t in (einv0, einvp, wr, om):
         assert tuple(t.shape) == (ng, ng) and t.dtype == torch.complex128 and t.is_contiguous()
-    vs = _host_f64(vsqrt, ng)
+    qg = _host_f64(qpg, ng)
     a = PpaArgs()
     a.ng, a.einv0, a.einvp, a.omega_p = ng, _ptr(einv0), _ptr(einvp), float(omega_p)
-    a.vsqrt, a.head = vs.ctypes.data_as(_f64p), -1.0 if head is None else float(head)
+    a.qpg, a.q0, a.nk_omega = qg.ctypes.data_as(_f64p), 1 if q0 else 0, float(nk_omega)
     a.wr, a.om = _ptr(wr), _ptr(om)
     _check(lib().xo_ppa_fit(C.byref(a), _stream(stream)))
     return wr, om
 
 
-def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=None, head=None,
+def sigma(rho_m, wr, om, e_m, f_m, z, eta, nk_omega, *, sigc=None, sigx=None, qpg=None, q0=False,
           accumulate=False, swapped=False, stream=None):
     """xo_sigma for one q: sigc[nn][nz] (complex128) and sigx[nn] (float64), (+)=.
 
     rho_m [nm][nn][ng] complex128 (xo_rho with the states n on the conduction side), or with
     swapped=True [nn][nm][ng] from xo_rho with the bands on the conduction side, G0 and the
-    G-set negated; e_m, f_m [nm] float64 and z [nn][nz] complex128 on the device."""
+    G-set negated; e_m, f_m [nm] float64 and z [nn][nz] complex128 on the device; nk_omega =
+    N_k Omega (the prefactor is its inverse); qpg (host, |q+G|) is needed for Sigma_x."""
     import torch
     if swapped:
         nn, nm, ng = rho_m.shape
@@ -486,15 +488,15 @@ def sigma(rho_m, wr, om, e_m, f_m, z, eta, pref, *, sigc=None, sigx=None, vsqrt=
         for t in (wr, om):
             assert tuple(t.shape) == (ng, ng) and t.dtype == torch.complex128 and t.is_contiguous()
     if sigx is not None:
-        assert tuple(sigx.shape) == (nn,) and sigx.dtype == torch.float64 and vsqrt is not None
-    vs = _host_f64(vsqrt, ng) if vsqrt is not None else None
+        assert tuple(sigx.shape) == (nn,) and sigx.dtype == torch.float64 and qpg is not None
+    qg = _host_f64(qpg, ng) if qpg is not None else None
     a = SigmaArgs()
     a.nm, a.nn, a.ng, a.nz = nm, nn, ng, nz
     a.rho, a.wr, a.om = _ptr(rho_m), _ptr(wr) if nz else None, _ptr(om) if nz else None
     a.e_m, a.f_m, a.z = _ptr(e_m), _ptr(f_m), _ptr(z) if nz else None
-    a.eta, a.pref = float(eta), float(pref)
-    a.vsqrt = vs.ctypes.data_as(_f64p) if vs is not None else None
-    a.head = -1.0 if head is None else float(head)
+    a.eta, a.nk_omega = float(eta), float(nk_omega)
+    a.qpg = qg.ctypes.data_as(_f64p) if qg is not None else None
+    a.q0 = 1 if q0 else 0
     a.sigx = _ptr(sigx) if sigx is not None else None
     a.sigc = _ptr(sigc) if nz else None
     a.accumulate = 1 if accumulate else 0

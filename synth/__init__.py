@@ -9,7 +9,7 @@ oscillator strengths, no response function, no Dyson equation).
 
 from .crystal import (  # noqa: F401
     Lattice, Crystal, fcc_lattice, sc_lattice, make_crystal, gset_sorted,
-    kgrid_gamma, frequencies, qpg_norms,
+    kgrid_gamma, frequencies,
 )
 from .configs import CONFIGS, crystal_for  # noqa: F401
 from .rand import rng, random_complex  # noqa: F401

@@ -98,7 +98,7 @@ def crystal_q_set(name: str = "c3", seed: int = None, nq: int = None, **over):
     configured range, so the set has uneven G-set sizes.
     """
     from dataclasses import replace
-    from .crystal import find_pairs, qpg_norms
+    from .crystal import find_pairs
     spec = dict(CONFIGS[name], **over)
     seed = spec["seed"] if seed is None else seed
     kf = _kset(spec)

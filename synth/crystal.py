@@ -124,15 +124,6 @@ def frequencies(nw: int) -> np.ndarray:
     return np.tan(np.pi * j / (2.0 * nw))
 
 
-def qpg_norms(lat: Lattice, qf: np.ndarray, gmill: np.ndarray) -> np.ndarray:
-    """|q+G| for the G-set; at q = 0 the G = 0 entry is set to 1 (head normalised)."""
-    qg = np.asarray(qf, float)[None, :] @ lat.bvec + gmill.astype(np.float64) @ lat.bvec
-    n = np.sqrt(np.einsum("ij,ij->i", qg, qg))
-    zero = n < 1e-12
-    n[zero] = 1.0
-    return n
-
-
 # ----------------------------------------------------------------------------
 # Model potentials
 # ----------------------------------------------------------------------------
@@ -231,19 +222,11 @@ class Crystal:
     def q0(self) -> bool:
         return bool(np.all(np.abs(self.qf) < 1e-12))
 
-    @property
-    def pref(self) -> float:
-        """f_s / (N_k Omega) with f_s = 2 (spin-unpolarised)."""
-        return 2.0 / (self.nk * self.lat.omega)
-
     def kcart(self, ik: int) -> np.ndarray:
         return self.kf[ik] @ self.lat.bvec
 
     def qcart(self) -> np.ndarray:
         return self.qf @ self.lat.bvec
-
-    def qpg(self) -> np.ndarray:
-        return qpg_norms(self.lat, self.qf, self.gmill)
 
     def ntrans(self, nempty: Optional[int] = None) -> int:
         tot = 0

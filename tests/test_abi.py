@@ -173,34 +173,43 @@ def test_empty_and_degenerate_inputs_are_rejected():
 
 def test_ppa_and_sigma_argument_errors():
     L = xo.lib()
-    assert C.sizeof(xo.PpaArgs) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert C.sizeof(xo.SigmaArgs) == 4 * 4 + 6 * 8 + 2 * 8 + 8 + 8 + 8 + 8 + 4 + 4
+    assert C.sizeof(xo.PpaArgs) == 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(xo.SigmaArgs) == 4 * 4 + 6 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 4 + 4
     a = xo.PpaArgs()
     rc, msg = _rc(L.xo_ppa_fit, a)
     assert rc == xo.XO_ERR_ARG and "positive" in msg
-    vs = np.array([1.0, -2.0])
+    qg = np.array([1.0, -2.0])
     a.ng, a.einv0, a.einvp, a.wr, a.om = 2, 8, 8, 8, 8   # never dereferenced
-    a.vsqrt = vs.ctypes.data_as(C.POINTER(C.c_double))
     a.omega_p = 0.0
     rc, msg = _rc(L.xo_ppa_fit, a)
     assert rc == xo.XO_ERR_ARG and "omega_p" in msg
     a.omega_p = 1.0
     rc, msg = _rc(L.xo_ppa_fit, a)
-    assert rc == xo.XO_ERR_ARG and "vsqrt[1]" in msg
+    assert rc == xo.XO_ERR_ARG and "null qpg" in msg
+    a.qpg = qg.ctypes.data_as(C.POINTER(C.c_double))
+    rc, msg = _rc(L.xo_ppa_fit, a)
+    assert rc == xo.XO_ERR_ARG and "|q+G| at 1" in msg
+    # at q = 0 the G = 0 entry is not read, but N_k Omega must be given
+    qg0 = np.array([-5.0, 2.0])
+    a.qpg, a.q0 = qg0.ctypes.data_as(C.POINTER(C.c_double)), 1
+    rc, msg = _rc(L.xo_ppa_fit, a)
+    assert rc == xo.XO_ERR_ARG and "nk_omega" in msg
     s = xo.SigmaArgs()
     rc, msg = _rc(L.xo_sigma, s)
     assert rc == xo.XO_ERR_ARG and "positive" in msg
     s.nm, s.nn, s.ng, s.nz = 3, 2, 2, 5
     s.rho = s.e_m = s.f_m = s.wr = s.om = s.z = s.sigc = 8
-    s.pref = 1.0
     rc, msg = _rc(L.xo_sigma, s)
     assert rc == xo.XO_ERR_ARG and "at most 4" in msg
-    s.nz, s.eta = 2, -0.1
+    s.nz = 2
+    rc, msg = _rc(L.xo_sigma, s)
+    assert rc == xo.XO_ERR_ARG and "nk_omega" in msg
+    s.nk_omega, s.eta = 100.0, -0.1
     rc, msg = _rc(L.xo_sigma, s)
     assert rc == xo.XO_ERR_ARG and "eta" in msg
     s.eta, s.sigx = 0.0, 8
     rc, msg = _rc(L.xo_sigma, s)
-    assert rc == xo.XO_ERR_ARG and "vsqrt" in msg
+    assert rc == xo.XO_ERR_ARG and "qpg" in msg
 
 
 def test_chi0_real_argument_errors():

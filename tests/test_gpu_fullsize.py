@@ -12,8 +12,8 @@ pytestmark = pytest.mark.gpu
 
 from synth import crystal_for  # noqa: E402
 from oracle.rho import rho_direct  # noqa: E402
-from oracle.chi0 import chi0_from_rho  # noqa: E402
-from oracle.epsinv import eps_tilde  # noqa: E402
+from oracle.chi0 import chi0_from_rho, crystal_prefactor  # noqa: E402
+from oracle.epsinv import eps_tilde, crystal_qpg  # noqa: E402
 from paper_1902_03837_amd import xo  # noqa: E402
 from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal  # noqa: E402
 
@@ -38,7 +38,7 @@ def c2():
         Ms.append(r.reshape(-1, len(SAMPLE)))
         dEs.append((cr.eps[ik][cr.nocc:][None, :] - cr.eps[ikp][:cr.nocc][:, None]).reshape(-1))
     Mref, dEref = np.concatenate(Ms), np.concatenate(dEs)
-    chiref = chi0_from_rho(Mref, dEref, cr.omegas, cr.pref)
+    chiref = chi0_from_rho(Mref, dEref, cr.omegas, crystal_prefactor(cr))
     return cr, Mref, dEref, chiref, {}
 
 
@@ -68,8 +68,8 @@ def test_c2_full_size_sampled(c2, prec, rtol_rho, rtol_chi):
         assert np.abs(Mg - Mref).max() <= d
         a = np.abs(Mref)
         f = 1 + np.sqrt(2.0) * (2 * U + U * U + 65536 * 2.0 ** -24)
-        hi = np.abs(chi0_from_rho((a + d).astype(np.complex128), dEref, cr.omegas, cr.pref))
-        lo = np.abs(chi0_from_rho(a.astype(np.complex128), dEref, cr.omegas, cr.pref))
+        hi = np.abs(chi0_from_rho((a + d).astype(np.complex128), dEref, cr.omegas, crystal_prefactor(cr)))
+        lo = np.abs(chi0_from_rho(a.astype(np.complex128), dEref, cr.omegas, crystal_prefactor(cr)))
         ratio = (np.abs(chig - chiref) / (f * hi - lo)).max()
         say(f"  sampled chi0 err / elementwise bound {ratio:.2e}")
         assert ratio <= 1.0
@@ -77,7 +77,7 @@ def test_c2_full_size_sampled(c2, prec, rtol_rho, rtol_chi):
         assert erho < rtol_rho and echi < rtol_chi
     # eps~^-1 at full size: inverse of the eps~ built from the returned chi0, Hermitian, spectrum in (0, 1]
     chi_h, E_h = chi.cpu().numpy(), E.cpu().numpy()
-    et = eps_tilde(chi_h, cr.qpg())
+    et = eps_tilde(chi_h, crystal_qpg(cr))
     for j in range(len(cr.omegas)):
         assert np.abs(et[j] @ E_h[j] - np.eye(et.shape[-1])).max() < 1e-10
         assert np.abs(E_h[j] - E_h[j].conj().T).max() < 1e-10
@@ -110,7 +110,7 @@ def c5s():
         Ms.append(rho_direct(cc, cr.mill[ik], cv, cr.mill[ikp], cr.gmill[C5S], g0).reshape(-1, len(C5S)))
         dEs.append((cr.eps[ik][cr.nocc:][None, :] - cr.eps[ikp][:cr.nocc][:, None]).reshape(-1))
     Mref, dEref = np.concatenate(Ms), np.concatenate(dEs)
-    return cr, Mref, dEref, chi0_from_rho(Mref, dEref, cr.omegas, cr.pref), {}
+    return cr, Mref, dEref, chi0_from_rho(Mref, dEref, cr.omegas, crystal_prefactor(cr)), {}
 
 
 def check_plain_bf16(cr, Mg, Mref, dEref, chig, chiref):
@@ -119,8 +119,8 @@ def check_plain_bf16(cr, Mg, Mref, dEref, chig, chiref):
     assert np.abs(Mg - Mref).max() <= d
     a = np.abs(Mref)
     f = 1 + np.sqrt(2.0) * (2 * U + U * U + 65536 * 2.0 ** -24)
-    hi = np.abs(chi0_from_rho((a + d).astype(np.complex128), dEref, cr.omegas, cr.pref))
-    lo = np.abs(chi0_from_rho(a.astype(np.complex128), dEref, cr.omegas, cr.pref))
+    hi = np.abs(chi0_from_rho((a + d).astype(np.complex128), dEref, cr.omegas, crystal_prefactor(cr)))
+    lo = np.abs(chi0_from_rho(a.astype(np.complex128), dEref, cr.omegas, crystal_prefactor(cr)))
     ratio = (np.abs(chig - chiref) / (f * hi - lo)).max()
     say(f"  sampled chi0 err / elementwise bound {ratio:.2e}")
     assert ratio <= 1.0
@@ -148,7 +148,7 @@ def test_c5_small_real_gset(c5s, prec, rtol_rho, rtol_chi):
         # FP64 eps~^-1 of one frequency against the oracle's inverse of the same chi0
         from oracle.epsinv import epsinv_sym
         c64, E64 = keep["fp64"]
-        ref = epsinv_sym(c64[1:2], cr.qpg())
+        ref = epsinv_sym(c64[1:2], crystal_qpg(cr))
         assert np.abs(E64[1] - ref[0]).max() < 1e-10 * np.abs(ref[0]).max()
     elif "fp64" in keep:
         # reduced precision against the plain FP64 path on the whole eps~^-1

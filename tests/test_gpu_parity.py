@@ -18,6 +18,7 @@ from oracle.chi0 import chi0_from_rho  # noqa: E402
 from oracle.epsinv import epsinv_sym, epsinv_nonsym  # noqa: E402
 from oracle.metrics import err_table, rel_fro  # noqa: E402
 from paper_1902_03837_amd import xo  # noqa: E402
+from oracle.epsinv import crystal_qpg  # noqa: E402
 from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal, rho_all, ntrans  # noqa: E402
 
 DEV = "cuda"
@@ -322,7 +323,7 @@ def test_epsinv_parity(name):
     cr = crystal_for(name)
     say(f"epsinv parity {name}")
     chi = chi0_crystal(cr)
-    qpg = cr.qpg()
+    qpg = crystal_qpg(cr)
     ref = epsinv_sym(chi, qpg)
     out = torch.empty(chi.shape, dtype=torch.complex128, device=DEV)
     xo.epsinv(_to(chi), qpg, out=out)
@@ -398,7 +399,7 @@ def _oracle_eps(name):
     if name not in _ORC:
         cr = crystal_for(name)
         chi = chi0_crystal(cr)
-        _ORC[name] = (epsinv_sym(chi, cr.qpg()), chi)
+        _ORC[name] = (epsinv_sym(chi, crystal_qpg(cr)), chi)
     return _ORC[name]
 
 
@@ -414,7 +415,7 @@ def test_alloc_failure_is_reported_and_recovers():
     finally:
         del os.environ["XO_FAULT"]
     M, dE, chi, E = run_crystal(dc)
-    Eref = epsinv_sym(chi0_crystal(cr), cr.qpg())
+    Eref = epsinv_sym(chi0_crystal(cr), crystal_qpg(cr))
     assert rel_fro(E.cpu().numpy(), Eref) < 1e-11
 
 

@@ -15,8 +15,8 @@ pytestmark = pytest.mark.gpu
 
 from synth import crystal_for  # noqa: E402
 from synth.rand import random_complex, random_positive  # noqa: E402
-from oracle.chi0 import chi0_real_axis, pole_factor_real_axis  # noqa: E402
-from oracle.epsinv import epsinv_sym  # noqa: E402
+from oracle.chi0 import chi0_real_axis, pole_factor_real_axis, crystal_prefactor  # noqa: E402
+from oracle.epsinv import epsinv_sym, crystal_qpg  # noqa: E402
 from oracle.pipeline import rho_all_pairs  # noqa: E402
 from paper_1902_03837_amd import xo  # noqa: E402
 from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal_real  # noqa: E402
@@ -110,8 +110,8 @@ def test_real_axis_chain_c1_small():
     eta = 0.0037   # 0.1 eV
     say("real-axis chain: oracle")
     M, dE = rho_all_pairs(cr)
-    chi_ref = chi0_real_axis(M, dE, ws, eta, cr.pref)
-    E_ref = epsinv_sym(chi_ref, cr.qpg(), check=False)
+    chi_ref = chi0_real_axis(M, dE, ws, eta, crystal_prefactor(cr))
+    E_ref = epsinv_sym(chi_ref, crystal_qpg(cr), check=False)
     Es = {}
     for prec in ["fp64", "bf16x3", "bf16"]:
         say(f"real-axis chain: {prec}")

@@ -19,7 +19,9 @@ pytestmark = pytest.mark.gpu
 from synth import crystal_for  # noqa: E402
 from synth.crystal import find_pairs  # noqa: E402
 from synth.rand import random_complex, rng  # noqa: E402
-from oracle.sigma import ppa_fit, coulomb_factor, sigma_c_ppa, sigma_x, sigma_kpoint  # noqa: E402
+from oracle.sigma import (ppa_fit, coulomb_factor, sigma_c_ppa, sigma_x, sigma_kpoint,  # noqa: E402
+                          coulomb_head_average, sigma_prefactor)
+from oracle.chi0 import cell_volume  # noqa: E402
 from oracle.pipeline import epsinv_crystal  # noqa: E402
 from paper_1902_03837_amd import xo  # noqa: E402
 from paper_1902_03837_amd.pipeline import DeviceCrystal, run_crystal, SigmaPlan, sigma_kpoint as sigma_gpu  # noqa: E402
@@ -53,18 +55,29 @@ def _einv_pair(seed, ng):
     return X0 + np.eye(ng), Xp + np.eye(ng)
 
 
-@pytest.mark.parametrize("ng,head", [(1, None), (1, 3.0), (130, None), (130, 2.5), (400, None)])
-def test_ppa_fit_matches_oracle(ng, head):
-    say(f"ppa_fit ng={ng} head={head}")
-    e0, ep = _einv_pair(10 + ng, ng)
-    s = rng(ng).uniform(0.2, 3.0, ng)
-    if head is not None:
+def _coulomb(seed, ng, q0, nk=8, L=7.3):
+    """|q+G| of a seeded G-set and the oracle's Coulomb factors, q = 0 head and prefactor for
+    a simple-cubic cell of side L sampled by nk k-points; nk_omega is what the library gets."""
+    qpg = rng(seed).uniform(0.3, 5.0, ng)
+    avec = L * np.eye(3)
+    s = np.sqrt(4 * np.pi) / qpg
+    head = None
+    if q0:
         s[0] = 0.0
+        head = coulomb_head_average(nk, cell_volume(avec))
+    return qpg, s, head, nk * L ** 3, sigma_prefactor(nk, avec)
+
+
+@pytest.mark.parametrize("ng,q0", [(1, False), (1, True), (130, False), (130, True), (400, False)])
+def test_ppa_fit_matches_oracle(ng, q0):
+    say(f"ppa_fit ng={ng} q0={q0}")
+    e0, ep = _einv_pair(10 + ng, ng)
+    qpg, s, head, nko, _ = _coulomb(ng, ng, q0)
     R, Om = ppa_fit(e0, ep, 1.0)
     Wr_ref = R * coulomb_factor(s, head)
     wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
     om = torch.empty_like(wr)
-    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, head, wr=wr, om=om)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, qpg, q0=q0, nk_omega=nko, wr=wr, om=om)
     torch.cuda.synchronize()
     wr, om = wr.cpu().numpy(), om.cpu().numpy()
     # same fit decision everywhere (the fallback pole sits exactly at omega_p)
@@ -90,7 +103,7 @@ def test_sigma_matches_oracle(nm, nn, ng, nz, frac):
     say(f"sigma nm={nm} nn={nn} ng={ng} nz={nz} frac={frac}")
     seed = nm * 1000 + ng
     e0, ep = _einv_pair(seed, ng)
-    s = rng(seed + 2).uniform(0.2, 3.0, ng)
+    qpg, s, _, nko, pref = _coulomb(seed + 2, ng, False)
     R, Om = ppa_fit(e0, ep, 1.0)
     Wr = R * coulomb_factor(s)
     rho = random_complex(seed + 3, (nm, nn, ng), 0.2)
@@ -100,15 +113,15 @@ def test_sigma_matches_oracle(nm, nn, ng, nz, frac):
     if frac:
         f[g.integers(0, nm, 5)] = 0.5
     z = (g.uniform(-0.5, 0.8, (nn, max(nz, 1))) + 1j * g.uniform(-0.05, 0.05, (nn, max(nz, 1))))[:, :nz]
-    eta, pref = 0.02, 0.013
+    eta = 0.02
     sx_ref = sigma_x(rho, f, s, None, pref)
     wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
     om = torch.empty_like(wr)
-    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, None, wr=wr, om=om)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, qpg, wr=wr, om=om)
     sigc = torch.full((nn, nz), 7.0 + 7.0j, dtype=torch.complex128, device=DEV) if nz else None
     sigx = torch.full((nn,), 7.0, dtype=torch.float64, device=DEV)
-    args = (_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z) if nz else None, eta, pref)
-    xo.sigma(*args, sigc=sigc, sigx=sigx, vsqrt=s)
+    args = (_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z) if nz else None, eta, nko)
+    xo.sigma(*args, sigc=sigc, sigx=sigx, qpg=qpg)
     torch.cuda.synchronize()
     assert np.max(np.abs(sigx.cpu().numpy() - sx_ref)) <= TOL * np.max(np.abs(sx_ref))
     if nz:
@@ -116,7 +129,7 @@ def test_sigma_matches_oracle(nm, nn, ng, nz, frac):
         got = sigc.cpu().numpy()
         assert np.max(np.abs(got - sc_ref)) <= TOL * np.max(np.abs(sc_ref)), (got, sc_ref)
     # accumulate: a second call adds the same values
-    xo.sigma(*args, sigc=sigc, sigx=sigx, vsqrt=s, accumulate=True)
+    xo.sigma(*args, sigc=sigc, sigx=sigx, qpg=qpg, accumulate=True)
     torch.cuda.synchronize()
     assert np.max(np.abs(sigx.cpu().numpy() - 2 * sx_ref)) <= TOL * np.max(np.abs(sx_ref))
     if nz:
@@ -127,20 +140,20 @@ def test_sigma_swapped_layout_equals_plain():
     say("sigma swapped layout")
     nm, nn, ng, nz = 23, 3, 70, 2
     e0, ep = _einv_pair(55, ng)
-    s = rng(56).uniform(0.2, 3.0, ng)
+    qpg, _, _, nko, _ = _coulomb(56, ng, False)
     rho = random_complex(57, (nm, nn, ng), 0.2)
     e = np.linspace(-0.9, 1.4, nm)
     f = (e < 0.05).astype(float)
     z = random_complex(58, (nn, nz), 0.3)
     wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
     om = torch.empty_like(wr)
-    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, None, wr=wr, om=om)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, qpg, wr=wr, om=om)
     outs = []
     for sw, r in ((False, rho), (True, np.conj(rho).transpose(1, 0, 2))):
         sigc = torch.empty((nn, nz), dtype=torch.complex128, device=DEV)
         sigx = torch.empty((nn,), dtype=torch.float64, device=DEV)
-        xo.sigma(_to(r), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, 0.3,
-                 sigc=sigc, sigx=sigx, vsqrt=s, swapped=sw)
+        xo.sigma(_to(r), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, nko,
+                 sigc=sigc, sigx=sigx, qpg=qpg, swapped=sw)
         torch.cuda.synchronize()
         outs.append((sigc.cpu().numpy(), sigx.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
@@ -150,9 +163,7 @@ def test_sigma_head_override_at_q0():
     say("sigma q=0 head override")
     nm, nn, ng = 6, 2, 40
     e0, ep = _einv_pair(77, ng)
-    s = rng(78).uniform(0.2, 3.0, ng)
-    s[0] = 0.0
-    head = 4.2
+    qpg, s, head, nko, pref = _coulomb(78, ng, True, nk=27, L=10.0)
     R, Om = ppa_fit(e0, ep, 1.0)
     Wr = R * coulomb_factor(s, head)
     rho = random_complex(79, (nm, nn, ng), 0.2)
@@ -161,14 +172,14 @@ def test_sigma_head_override_at_q0():
     z = np.array([[0.1 + 0.01j, 0.3 + 0.0j], [-0.2 + 0.0j, 0.5 + 0.02j]])
     wr = torch.empty((ng, ng), dtype=torch.complex128, device=DEV)
     om = torch.empty_like(wr)
-    xo.ppa_fit(_to(e0), _to(ep), 1.0, s, head, wr=wr, om=om)
+    xo.ppa_fit(_to(e0), _to(ep), 1.0, qpg, q0=True, nk_omega=nko, wr=wr, om=om)
     sigc = torch.empty((nn, 2), dtype=torch.complex128, device=DEV)
     sigx = torch.empty((nn,), dtype=torch.float64, device=DEV)
-    xo.sigma(_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, 0.5,
-             sigc=sigc, sigx=sigx, vsqrt=s, head=head)
+    xo.sigma(_to(rho), wr, om, _to(e, torch.float64), _to(f, torch.float64), _to(z), 0.01, nko,
+             sigc=sigc, sigx=sigx, qpg=qpg, q0=True)
     torch.cuda.synchronize()
-    sc_ref = sigma_c_ppa(rho, Wr, Om, e, f, z, 0.01, 0.5)
-    sx_ref = sigma_x(rho, f, s, head, 0.5)
+    sc_ref = sigma_c_ppa(rho, Wr, Om, e, f, z, 0.01, pref)
+    sx_ref = sigma_x(rho, f, s, head, pref)
     assert np.max(np.abs(sigc.cpu().numpy() - sc_ref)) <= TOL * np.max(np.abs(sc_ref))
     assert np.max(np.abs(sigx.cpu().numpy() - sx_ref)) <= TOL * np.max(np.abs(sx_ref))
 

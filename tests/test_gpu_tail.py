@@ -14,6 +14,7 @@ from synth.rand import mlp_init, flatten_params, rng  # noqa: E402
 from oracle import mlp as omlp  # noqa: E402
 from paper_1902_03837_amd import xo  # noqa: E402
 from paper_1902_03837_amd import tail as T  # noqa: E402
+from paper_1902_03837_amd.pipeline import chi0_pref, qpg as qpg_of  # noqa: E402
 
 DEV = "cuda"
 MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1902_03837_amd",
@@ -113,10 +114,10 @@ def small():
 def test_band_blocks_are_cumulative_sums(small):
     cr, chis, _ = small
     from oracle.pipeline import rho_all_pairs
-    from oracle.chi0 import chi0_from_rho
+    from oracle.chi0 import chi0_from_rho, crystal_prefactor
     for nb, ref_i in ((10, 0), (20, 1), (None, 2)):
         M, dE = rho_all_pairs(cr, "fft", nempty=nb)
-        ref = chi0_from_rho(M, dE, cr.omegas, cr.pref)
+        ref = chi0_from_rho(M, dE, cr.omegas, crystal_prefactor(cr))
         assert np.abs(chis[ref_i] - ref).max() < 1e-12 * np.abs(ref).max()
     # more bands -> closer to the full sum (monotone convergence of the truncated sum)
     e10 = np.linalg.norm(chis[0] - chis[2])
@@ -131,7 +132,7 @@ def test_features_targets_and_apply(small):
     isd = np.linspace(0.5, 2.0, 9).astype(np.float32)
     tsc = 3.0
     X, Tt = T.build_features(cr, dchis, mu, isd, tsc)
-    qpg = cr.qpg()
+    qpg = qpg_of(cr)
     ss = 4 * np.pi / np.outer(qpg, qpg)
     gd = T.gdiff_table(cr)
     ref = np.zeros((nw, ng, ng, 9))
@@ -233,7 +234,7 @@ def test_xterm_rejects_extrapolar_energy_below_occupied(small):
     out = dchis[1].clone()
     with pytest.raises(xo.XoError):
         xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], float(cr.eps[ikp][0]) - 1.0, cr.gmill,
-                 cr.omegas, cr.pref, M, nb, out)
+                 cr.omegas, chi0_pref(cr), M, nb, out)
 
 
 def test_fallback_returns_the_full_sum(small):
@@ -265,7 +266,7 @@ def test_trained_tail_beats_its_base_on_held_out():
         chis, _ = T.crystal_tensors(cr, 100, 50, base=model.base)
         out, info = T.predict(model, cr, chis[:2])
         assert out is not None, info
-        qpg = cr.qpg()
+        qpg = qpg_of(cr)
         E = {}
         for k, c in (("t", chis[1]), ("l", out), ("f", chis[2])):   # t: the base the network corrects
             E[k] = torch.empty_like(c)

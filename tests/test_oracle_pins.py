@@ -6,6 +6,8 @@ case (free electrons), each chosen so that a dropped term, a wrong sign or index
 a transposed operand or a wrong normalisation fails at least one of them.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 import scipy.linalg
@@ -15,8 +17,8 @@ from synth.crystal import (fcc_lattice, hamiltonian, make_crystal, shell_potenti
                            kgrid_gamma, ecut_for_npw)
 from synth.configs import FCC4, A_FCC
 from oracle.rho import rho_direct, rho_fft, rho_head_q0
-from oracle.chi0 import chi0_from_rho, pole_weights
-from oracle.epsinv import epsinv_sym, epsinv_nonsym, eps_tilde
+from oracle.chi0 import chi0_from_rho, pole_weights, crystal_prefactor
+from oracle.epsinv import epsinv_sym, epsinv_nonsym, eps_tilde, crystal_qpg
 from oracle.pipeline import rho_pair, rho_all_pairs, chi0_crystal
 
 TOL = 1e-12
@@ -97,7 +99,7 @@ def test_p1_umklapp_equals_unfolded_basis():
     ecut = ecut_for_npw(lat, 200)
     cr = make_crystal(lat, pot, FCC4, q, (16,) * 3, ecut, 8, 20, 27, 2, 11, scissor_min=None)
     M, dE = rho_all_pairs(cr, "fft")
-    ref = chi0_from_rho(M, dE, cr.omegas, cr.pref)
+    ref = chi0_from_rho(M, dE, cr.omegas, crystal_prefactor(cr))
     # unfolded: for each k build the k - q orbitals on their own sphere, G0 = 0
     Ms, dEs = [], []
     for ik in range(cr.nk):
@@ -108,7 +110,7 @@ def test_p1_umklapp_equals_unfolded_basis():
                        cru.gmill, np.zeros(3, np.int32))
         Ms.append(r.reshape(-1, r.shape[-1]))
         dEs.append((cru.eps[0][8:][None, :] - cru.eps[1][:8][:, None]).reshape(-1))
-    alt = chi0_from_rho(np.concatenate(Ms), np.concatenate(dEs), cr.omegas, cr.pref)
+    alt = chi0_from_rho(np.concatenate(Ms), np.concatenate(dEs), cr.omegas, crystal_prefactor(cr))
     assert np.abs(alt - ref).max() < 1e-10 * np.abs(ref).max()
 
 
@@ -254,6 +256,67 @@ def _pot(cr):
 
 
 # --------------------------------------------------------------------------
+# f-sum rule on chi0 itself: w^2 chi0_GG(q, i w) -> -n |q+G|^2 as w -> infinity, with
+# n the electron density (two electrons per occupied band, over the crystal volume).
+# This fixes the prefactor of Eq. (X_IP) (spin factor, k-point count, cell volume), the
+# large-frequency form of the weights and the normalisation of rho together.
+# --------------------------------------------------------------------------
+
+W_BIG = 1.0e4   # Ha; the limit is reached up to (max Delta / w)^2 ~ 1e-7 here
+
+
+def _fsum_chi0_ratio(cr, igs, nocc_total):
+    """w^2 chi0_GG(i w) / (-n |q+G|^2) for the G indices igs (the oracle's full chain)."""
+    big = dataclasses.replace(cr, omegas=np.array([W_BIG]))
+    chi = chi0_crystal(big)[0]
+    # the density counted here from the bands and the cell volume (fcc primitive cell a^3/4)
+    n = 2.0 * nocc_total / (cr.nk * A_FCC ** 3 / 4.0)
+    qg = cr.qf @ cr.lat.bvec + cr.gmill[igs] @ cr.lat.bvec
+    return W_BIG ** 2 * np.diag(chi)[igs].real / (-n * np.einsum("gi,gi->g", qg, qg))
+
+
+def _free_electron_x():
+    lat = fcc_lattice(A_FCC)
+    q = np.array([.5, .5, 0.])
+    # every band of the sphere, E_F between free-electron levels at each k (9 states below
+    # at Gamma, 6 at each X): the occupied set is closed under p -> -p
+    return make_crystal(lat, shell_potential(lat, 0, zero=True), FCC4, q, (16,) * 3,
+                        ecut_for_npw(lat, 230), 9, None, 27, 2, 21, scissor_min=None,
+                        nocc_k=[9, 6, 6, 6])
+
+
+def test_fsum_rule_on_chi0_free_electrons():
+    """Exact for free electrons when every final plane wave p_v + q + G lies in the basis:
+    occupied-to-occupied terms cancel in pairs and the sum over v of p_v vanishes."""
+    cr = _free_electron_x()
+    ratio = _fsum_chi0_ratio(cr, list(range(15)), sum(cr.nocc_k))
+    assert np.abs(ratio - 1.0).max() < 1e-6, ratio
+
+
+def test_fsum_rule_on_chi0_model_crystal():
+    """With the model potential, up to basis truncation (the P5 level)."""
+    cr = crystal_for("c1_small", nb_all=True, npw=800, grid=24)
+    ratio = _fsum_chi0_ratio(cr, [0, 3, 10], cr.nk * cr.nocc)
+    assert np.abs(ratio - 1.0).max() < 0.05, ratio
+
+
+def test_fsum_rule_catches_a_wrong_prefactor(monkeypatch):
+    """Planted in the oracle: a spin factor of 1, a missing k-point average or the cubic
+    volume a^3 in place of the primitive one each break the free-electron f-sum rule."""
+    import oracle.chi0 as oc
+    import oracle.pipeline as op
+    cr = _free_electron_x()
+    good = oc.crystal_prefactor
+    for wrong in (lambda c: 0.5 * good(c),                      # f_s = 1
+                  lambda c: good(c) * len(c.kf),                # no 1/N_k
+                  lambda c: good(c) / 4.0):                     # Omega = a^3
+        monkeypatch.setattr(op, "crystal_prefactor", wrong)
+        ratio = _fsum_chi0_ratio(cr, [1, 5], sum(cr.nocc_k))
+        assert np.abs(ratio - 1.0).min() > 0.4, ratio
+    monkeypatch.setattr(op, "crystal_prefactor", good)
+
+
+# --------------------------------------------------------------------------
 # P6: free electrons -> Lindhard closed form, chi0 diagonal in G
 # --------------------------------------------------------------------------
 
@@ -267,7 +330,9 @@ def test_p6_free_electron_lindhard():
     cr = make_crystal(lat, pot, FCC4, q, (16,) * 3, ecut, 9, None, 27, 3, 21,
                       scissor_min=None, nocc_k=nocc_k)
     chi = chi0_crystal(cr)
-    # closed form from plane-wave kinematics only
+    # closed form from plane-wave kinematics only; prefactor: two electrons per band over
+    # the 4 k-points times the fcc primitive volume a^3 / 4
+    pref = 2.0 / (4 * A_FCC ** 3 / 4.0)
     u = lat.unit
     EF = 0.5 * 3.5 * u * u
     qc = q @ lat.bvec
@@ -284,7 +349,7 @@ def test_p6_free_electron_lindhard():
             ok = occ & (ec > EF) & (ec <= ecut)
             d = ec[ok] - ev[ok]
             for j, w in enumerate(cr.omegas):
-                ref[j, ig] += -cr.pref * np.sum(2 * d / (w * w + d * d))
+                ref[j, ig] += -pref * np.sum(2 * d / (w * w + d * d))
     for j in range(len(cr.omegas)):
         off = chi[j] - np.diag(np.diag(chi[j]))
         assert np.abs(off).max() < 1e-12
@@ -297,7 +362,7 @@ def test_p6_free_electron_lindhard():
 
 def test_p7_p10_epsinv(c1s):
     chi = chi0_crystal(c1s)
-    qpg = c1s.qpg()
+    qpg = crystal_qpg(c1s)
     E = epsinv_sym(chi, qpg)
     et = eps_tilde(chi, qpg)
     s = np.sqrt(4 * np.pi) / qpg
@@ -376,7 +441,8 @@ def test_p9_head_velocity_vs_finite_q():
 
 def test_p11_degenerate_pole_grouping(c1s):
     M, dE = rho_all_pairs(c1s)
-    ref = chi0_from_rho(M, dE, c1s.omegas, c1s.pref)
+    pref = crystal_prefactor(c1s)
+    ref = chi0_from_rho(M, dE, c1s.omegas, pref)
     thr = 1e-5
     order = np.argsort(dE)
     groups, cur = [], [order[0]]
@@ -390,9 +456,9 @@ def test_p11_degenerate_pole_grouping(c1s):
     assert len(groups) < len(dE)   # the symmetric crystal has degenerate poles
     out = np.zeros_like(ref)
     for gidx in groups:
-        R = c1s.pref * M[gidx].T @ np.conj(M[gidx])        # internal frequency-free sum
+        R = pref * M[gidx].T @ np.conj(M[gidx])        # internal frequency-free sum
         for j, w in enumerate(c1s.omegas):
             out[j] += -pole_weights(dE[gidx[0]], w) * R    # one F per group
     spread = max(dE[g].max() - dE[g].min() for g in groups)
-    bound = spread * 2.0 / min(dE) ** 2 * c1s.pref * np.sum(np.abs(M) ** 2)
+    bound = spread * 2.0 / min(dE) ** 2 * pref * np.sum(np.abs(M) ** 2)
     assert np.abs(out - ref).max() <= bound + 1e-14

@@ -2,17 +2,24 @@
 
 None of these retypes the oracle's formulas: the fit is checked against data made
 from known pole parameters, the closed-form correlation self-energy against a
-quadrature of the GW product on the imaginary axis, and the exchange against the
-Fock sum of free electrons computed without oscillator strengths.
+quadrature of the GW product on the imaginary axis, the exchange against the
+Fock sum of free electrons computed without oscillator strengths, and the whole
+composition over q (prefactor, q = 0 head, Coulomb factors) against the
+continuum limit of a band that fills the Brillouin zone, a closed form.
 """
+
+import dataclasses
+import functools
 
 import numpy as np
 import pytest
-from scipy.integrate import quad
+from scipy.integrate import dblquad, quad
 
-from synth.crystal import sc_lattice, miller_sphere, kgrid_gamma, find_pairs, gset_sorted, qpg_norms
+from synth.crystal import sc_lattice, miller_sphere, kgrid_gamma, find_pairs, gset_sorted, make_crystal
 from oracle.rho import rho_direct
+from oracle.epsinv import qpg_norms
 from oracle.sigma import ppa_fit, ppa_eval_imag, coulomb_factor, sigma_c_ppa, sigma_x
+import oracle.sigma as osig
 
 WP = 1.0
 HEAD = 2.5   # stands for the cell average of 4 pi / q^2 at q = 0
@@ -132,7 +139,7 @@ def test_sigma_x_of_plane_waves_is_the_fock_sum():
         cn = np.eye(mills[ik0].shape[0], dtype=np.complex128)[:nstate]
         cm = np.eye(mills[ikp].shape[0], dtype=np.complex128)[:nocc + 2]     # two empty bands too
         rho = rho_direct(cn, mills[ik0], cm, mills[ikp], gm, g0)      # [m, n, G]
-        s = np.sqrt(4 * np.pi) / qpg_norms(lat, qf, gm)
+        s = np.sqrt(4 * np.pi) / qpg_norms(lat.bvec, qf, gm)
         q0 = np.all(np.abs(qf) < 1e-12)
         if q0:
             s[0] = 0.0
@@ -154,3 +161,95 @@ def test_sigma_x_of_plane_waves_is_the_fock_sum():
     # the G-set holds every momentum transfer between the two spheres
     assert np.allclose(sx, direct, rtol=1e-12, atol=0), (sx, direct)
     assert np.all(direct < 0)
+
+
+# --------------------------------------------------------------------------
+# The composition over q: prefactor 1/(N_k Omega), the q = 0 head and the Coulomb
+# factors, against a closed form. One free-electron band fills the Brillouin zone of a
+# simple-cubic lattice (side L): on an odd Gamma-centred n^3 grid every k is interior,
+# so the occupied plane waves are exactly the grid points k of the zone. The exchange of
+# the state at Gamma is then a midpoint-rule sum of -4 pi / |k|^2 over the cubic zone,
+# whose singular centre cell is the q = 0 head, and as n grows it tends to
+#     -(1 / (2 pi)^3) int_BZ 4 pi / k^2 d^3k = -c / (pi L),
+#     c = int_{[-1/2, 1/2]^3} d^3x / |x|^2 = 3 int int_{[-1, 1]^2} du dv / (1 + u^2 + v^2)
+# (the cube as six pyramids with apex at the centre). The sum approaches its limit as
+# C / n + D / n^2, so three grids fix the limit; the head sets C, so the error at the
+# largest grid (about 1.3 % at n = 9) and its sign check the head.
+# --------------------------------------------------------------------------
+
+L_SC = 6.0
+
+
+@functools.lru_cache(maxsize=None)
+def _bz_crystals(n):
+    lat = sc_lattice(L_SC)
+    kf = kgrid_gamma(n)
+
+    class Zero:
+        def __call__(self, m):
+            return np.zeros(m.shape[0])
+
+    # one band per k (the lowest plane wave k + 0); a sphere wide enough for the G-set
+    base = make_crystal(lat, Zero(), kf, np.zeros(3), (8,) * 3, 0.5 * (2.6 * 2 * np.pi / L_SC) ** 2, 1, 1,
+                        27, 2, 1, scissor_min=None, check_alias=False)
+    ki = np.round(kf * n).astype(np.int64)            # integer grid coordinates
+    index = np.full((n, n, n), -1, np.int64)
+    index[tuple((ki % n).T)] = np.arange(len(kf))
+    crs = []
+    for iq in range(len(kf)):
+        d = ki - ki[iq]                                  # k - q in grid units
+        ikp = index[tuple((d % n).T)]
+        g0 = ((d - ki[ikp]) // n).astype(np.int32)       # k - q = k' + G0
+        pairs = [(ik, int(ikp[ik]), g0[ik]) for ik in range(len(kf))]
+        crs.append(dataclasses.replace(base, qf=kf[iq].copy(), pairs=pairs))
+    return crs, int(np.nonzero(np.all(ki == 0, axis=1))[0][0])
+
+
+def _bz_band_sigma_x(n):
+    crs, ik0 = _bz_crystals(n)
+    eye = np.stack([np.eye(27), np.eye(27)]).astype(np.complex128)   # no screening: Sigma_c = 0
+    sx, sc = osig.sigma_kpoint(crs, [eye] * len(crs), ik0, [0], np.zeros((1, 1)))
+    assert np.all(sc == 0)
+    return sx[0]
+
+
+def _bz_limit():
+    A = dblquad(lambda v, u: 1.0 / (1.0 + u * u + v * v), -1, 1, -1, 1, epsabs=1e-13, epsrel=1e-13)[0]
+    return -3.0 * A / (np.pi * L_SC)
+
+
+def _extrapolate(vals):
+    ns = sorted(vals)
+    A = np.array([[1.0, 1.0 / n, 1.0 / n ** 2] for n in ns])
+    return float(np.linalg.solve(A, np.array([vals[n] for n in ns]))[0])
+
+
+def test_sigma_x_composition_brillouin_zone_limit():
+    lim = _bz_limit()
+    vals = {n: _bz_band_sigma_x(n) for n in (5, 7, 9)}
+    err = {n: (v - lim) / abs(lim) for n, v in vals.items()}
+    # converges from above (less negative), monotonically, to within 1.6 % at n = 9 ...
+    assert 0 < err[9] < err[7] < err[5] < 0.025, err
+    assert err[9] < 0.016, err
+    # ... and its extrapolated limit is the closed form
+    assert abs(_extrapolate(vals) - lim) < 5e-4 * abs(lim), (_extrapolate(vals), lim)
+
+
+def test_sigma_x_composition_catches_planted_mistakes(monkeypatch):
+    """A head averaged over twice or half the k-point's share of the zone, no head, or a
+    spin factor in the prefactor each fail the criteria of the limit test."""
+    lim = _bz_limit()
+    head, pref = osig.coulomb_head_average, osig.sigma_prefactor
+    wrong = [("coulomb_head_average", lambda nk, om: head(nk, om / 2.0)),
+             ("coulomb_head_average", lambda nk, om: head(nk, om * 2.0)),
+             ("coulomb_head_average", lambda nk, om: 0.0),
+             ("sigma_prefactor", lambda nk, av: 2.0 * pref(nk, av))]
+    for name, fn in wrong:
+        monkeypatch.setattr(osig, name, fn)
+        vals = {n: _bz_band_sigma_x(n) for n in (5, 7, 9)}
+        err = {n: (v - lim) / abs(lim) for n, v in vals.items()}
+        ok = (0 < err[9] < err[7] < err[5] < 0.025 and err[9] < 0.016
+              and abs(_extrapolate(vals) - lim) < 5e-4 * abs(lim))
+        assert not ok, (name, err)
+        monkeypatch.setattr(osig, "coulomb_head_average", head)
+        monkeypatch.setattr(osig, "sigma_prefactor", pref)
