@@ -33,6 +33,7 @@
 #ifndef XO_H
 #define XO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -45,7 +46,9 @@ enum {
   XO_ERR_ALLOC = 2,        /* device allocation failed                         */
   XO_ERR_HIP = 3,          /* a HIP runtime call or kernel launch failed       */
   XO_ERR_NOTPD = 4,        /* eps~ not positive definite at some frequency     */
-  XO_ERR_UNSUPPORTED = 5   /* size or option outside what the kernels handle   */
+  XO_ERR_UNSUPPORTED = 5,  /* size or option outside what the kernels handle   */
+  XO_ERR_SINGULAR = 6      /* xo_epsinv, general eps~: a diagonal block of the
+                              elimination is numerically singular            */
 };
 
 /* Arithmetic of rho and chi0 (eps^-1 is FP64 in every form):
@@ -234,7 +237,8 @@ typedef struct {
 int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream);
 /* Times a grid of xo_tune candidates on the given batch (each after a warm-up
  * run; results overwrite the outputs) and returns the fastest with its time in
- * milliseconds. Synchronises the stream. */
+ * milliseconds. Synchronises the stream. Items with accumulate set are rejected
+ * (XO_ERR_ARG): every candidate run would add its update again. */
 int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* best_ms, void* stream);
 
 /* ------------------------------------------------------------------------- */
@@ -244,12 +248,16 @@ int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* be
  *                                          Eq. (W_def) scales by 4pi/(|q+G||q+G'|))
  *   out  = (I - v chi0)^-1 = diag(s) eps~^-1 diag(1/s)   (XO_EPS_NONSYM)
  * Always FP64. eps~ is Hermitian positive definite at imaginary frequencies;
- * the inversion is a blocked Gauss-Jordan without pivoting whose pivots are
- * the LDL^H diagonal, so a non-positive pivot proves eps~ is not PD: the call
- * then returns XO_ERR_NOTPD naming the first such frequency. With
- * XO_EPS_LU_FALLBACK the sign test is skipped (an exactly zero pivot still
- * fails). With info NULL the call synchronises the stream to read the pivot
- * flags; with info set it does not synchronise and leaves them to the caller.
+ * the inversion is a blocked Gauss-Jordan (64-wide blocks) without pivoting
+ * whose pivots are the LDL^H diagonal, so a non-positive pivot proves eps~ is
+ * not PD: the call then returns XO_ERR_NOTPD naming the first such frequency.
+ * XO_EPS_LU_FALLBACK is the form for general (non-Hermitian) eps~, e.g. at real
+ * frequencies: each diagonal block is inverted with partial pivoting inside the
+ * block, and a pivot below 1e-13 of the block's largest entry (a numerically
+ * singular block: the elimination does not pivot across blocks) returns
+ * XO_ERR_SINGULAR instead of an inaccurate inverse. With info NULL the call
+ * synchronises the stream to read the pivot flags; with info set it does not
+ * synchronise and leaves them to the caller.
  * qpg: [host] [ng] |q+G| (at q = 0 the G = 0 entry is 1 and chi0's G = 0 row and
  *      column are the q-normalised head and wings).
  * chi0: [device] [nw][ng][ng] complex128 (read only); out: [device] same shape.
@@ -449,6 +457,24 @@ typedef struct {
 } xo_sigma_args;
 
 int xo_sigma(const xo_sigma_args* a, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Workspace size queries. Each returns in *bytes the device workspace that the
+ * matching call with the same arguments takes from the library's per-stream
+ * cache (before the cache's own rounding), so that a caller can budget device
+ * memory ahead of the call. Small constant tables (Coulomb factors, gather
+ * tables, launch plans) are cached apart and not counted. Host computation
+ * only: no device work, no allocation, no GPU needed. Errors: the argument
+ * errors of the matching call (XO_ERR_ARG), and XO_ERR_UNSUPPORTED where the
+ * call would return it.
+ *   xo_rho_workspace_size:   xo_rho_batch over npairs pairs (xo_rho: npairs = 1);
+ *                            the kernel path is chosen as the call chooses it.
+ *   xo_chi0_workspace_size:  xo_chi0_batch over n items with tune (xo_chi0: n = 1,
+ *                            tune NULL).
+ *   xo_epsinv_workspace_size: xo_epsinv (only ng and nw are read). */
+int xo_rho_workspace_size(const xo_rho_args* pairs, int npairs, size_t* bytes);
+int xo_chi0_workspace_size(const xo_chi0_args* items, int n, const xo_tune* tune, size_t* bytes);
+int xo_epsinv_workspace_size(const xo_eps_args* a, size_t* bytes);
 
 #ifdef __cplusplus
 }

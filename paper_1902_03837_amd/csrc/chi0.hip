@@ -719,8 +719,11 @@ static int launch_nwg(int nwg, int nt_tiles, const void* ditems, const void* dti
 // Every item of a batch shares the precision and the frequencies.
 // With wreal set (host, nw / 2 real frequencies) the nw slots carry the real-axis factor
 // pairs of pole_factors_real instead of the imaginary-axis factors.
+// With size_only set, the call stops after planning (host work only) and stores there the
+// workspace bytes it would request.
 static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hipStream_t s,
-                          bool signed_pref = false, const double* wreal = nullptr, double eta = 0.0) {
+                          bool signed_pref = false, const double* wreal = nullptr, double eta = 0.0,
+                          size_t* size_only = nullptr) {
   for (int i = 0; i < n; ++i) XO_RET(validate(&a[i], signed_pref));
   const int prec = a[0].prec;
   for (int i = 1; i < n; ++i) {
@@ -842,14 +845,18 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   const int nunits = (int)units.size();
   const size_t per = blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
   const size_t pbytes = per * nunits;
+  bool any_check = false;
+  for (int it = 0; it < n; ++it) any_check |= a[it].check_dE != 0;
+  if (size_only) {
+    *size_only = wbytes + pbytes + 256 + (any_check ? 256 : 0);
+    return XO_OK;
+  }
   void* ws = nullptr;
   XO_RET(workspace(s, 1, wbytes + pbytes + 256, &ws));
   char* wbase = static_cast<char*>(ws);
   void* part = wbase + wbytes;
   int* counter = reinterpret_cast<int*>(wbase + wbytes + pbytes);
 
-  bool any_check = false;
-  for (int it = 0; it < n; ++it) any_check |= a[it].check_dE != 0;
   int* bad = nullptr;
   if (any_check) {
     void* wsb = nullptr;
@@ -1015,9 +1022,7 @@ extern "C" int xo_chi0_real(const xo_chi0_real_args* a, void* stream) {
   return xo::chi0_real_run(a, static_cast<hipStream_t>(stream));
 }
 
-extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream) {
-  xo::clear_error();
-  XO_ARG(items && n > 0, "xo_chi0_batch: need a non-empty array of items");
+static int check_tune(const xo_chi0_args* items, const xo_tune* tune) {
   if (tune) {
     XO_ARG(tune->nt_tiles == 0 || tune->nt_tiles == 1 || tune->nt_tiles == 2 || tune->nt_tiles == 4,
            "xo_chi0_batch: nt_tiles must be 0, 1, 2 or 4");
@@ -1025,12 +1030,30 @@ extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tu
            "xo_chi0_batch: nt_tiles 4 is the bf16 block form (XO_BF16X3, XO_BF16)");
     XO_ARG(tune->kper >= 0 && tune->wg_per_cu >= 0 && tune->wg_per_cu <= 16, "xo_chi0_batch: bad tune values");
   }
+  return XO_OK;
+}
+
+extern "C" int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream) {
+  xo::clear_error();
+  XO_ARG(items && n > 0, "xo_chi0_batch: need a non-empty array of items");
+  XO_RET(check_tune(items, tune));
   return xo::chi0_batch_run(items, n, tune, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int xo_chi0_workspace_size(const xo_chi0_args* items, int n, const xo_tune* tune, size_t* bytes) {
+  xo::clear_error();
+  XO_ARG(items && n > 0 && bytes, "xo_chi0_workspace_size: need a non-empty array of items and an output");
+  XO_RET(check_tune(items, tune));
+  return xo::chi0_batch_run(items, n, tune, nullptr, false, nullptr, 0.0, bytes);
 }
 
 extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* best_ms, void* stream) {
   xo::clear_error();
   XO_ARG(items && n > 0 && best, "xo_chi0_autotune: bad arguments");
+  // every candidate run overwrites the outputs, so an accumulating item would collect
+  // the update once per run
+  for (int i = 0; i < n; ++i)
+    XO_ARG(items[i].accumulate == 0, "xo_chi0_autotune: item %d has accumulate set (tuning overwrites outputs)", i);
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<xo_tune> cands;
   std::vector<int> nts = {1};

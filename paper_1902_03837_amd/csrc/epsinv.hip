@@ -3,8 +3,10 @@
 //   eps~ = I - diag(s) chi0 diag(s),   s_G = sqrt(4 pi) / |q+G|
 //
 // eps~ is Hermitian positive definite at imaginary frequencies. It is inverted
-// in place by blocked Gauss-Jordan elimination without pivoting, all frequencies
-// in the same launches. Per block column K (width b = 64), three launches:
+// in place by blocked Gauss-Jordan elimination, all frequencies in the same
+// launches; the diagonal blocks are inverted without pivoting (positive definite
+// input) or, with XO_EPS_LU_FALLBACK (general eps~), with partial pivoting inside
+// the block. Per block column K (width b = 64), three launches:
 //   P = A_KK^-1                      diag_inverse: one 1024-thread workgroup per
 //                                    frequency, the block in registers, one barrier
 //                                    per pivot
@@ -13,6 +15,7 @@
 //   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update
 // The pivots met inside the diagonal blocks are the diagonal of eps~ = L D L^H,
 // so a pivot with non-positive real part proves eps~ is not positive definite.
+// In the pivoted form a numerically singular diagonal block is reported instead.
 
 #include <algorithm>
 #include <cmath>
@@ -44,65 +47,121 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
 // In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
 // (kb <= 64). 4096 / E threads per frequency: thread t holds row t / (64 / E),
 // columns E (t % (64 / E)) .. + E - 1 in registers (identity outside kb). Per
-// pivot k the owners publish column k and row k (values before the step) in LDS,
-// double buffered, and every thread updates its own E entries after one barrier.
-// The pivot row is stored transposed ([j][column group]) so that a wave reads it
-// without bank conflicts.
-template <int E>
+// pivot k the owners publish column k and the pivot row (values before the step) in
+// LDS, double buffered, and every thread updates its own E entries. The pivot row
+// is stored transposed ([j][column group]) so that a wave reads it without bank
+// conflicts.
+//
+// PIV = false (Hermitian positive definite eps~): the pivot of column k is row k,
+// one barrier per pivot; the pivots are the diagonal of eps~ = L D L^H, so a pivot
+// with non-positive real part proves eps~ is not positive definite (flagged).
+// PIV = true (general eps~, real frequencies): partial pivoting inside the block.
+// The pivot of column k is the row of largest modulus among the rows not yet used;
+// rows stay in place (the sweep is applied to row p_k and column k), so the result
+// R holds R[p_k][j] = B^-1[k][p_j] (B the block) and is written back with that
+// permutation undone. A pivot below 1e-13 of the block's largest entry marks the
+// block as numerically singular (flagged): the blocked elimination has no pivoting
+// across blocks, so the caller gets an error instead of an inaccurate inverse.
+template <int E, bool PIV>
 __global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
                                                             int check_sign, int* __restrict__ flag) {
   constexpr int CG = kB / E;  // column groups
   __shared__ z pcol[2][kB];
   __shared__ z prow[2][E][CG];
+  __shared__ int perm[kB], inv[kB];   // PIV: pivot row of column k, and its inverse
+  __shared__ double wmax[kB * kB / E / 64];
   const int w = blockIdx.x;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
-  const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq;
+  const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq, lane = t & 63;
   z a[E];
+  double amax = 0.0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
     a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
+    if (PIV && r < kb && c < kb) amax = fmax(amax, a[j].x * a[j].x + a[j].y * a[j].y);
   }
+  double thr2 = 0.0;  // PIV: squared singularity threshold
+  if constexpr (PIV) {
+    for (int m = 32; m >= 1; m >>= 1) amax = fmax(amax, __shfl_xor(amax, m, 64));
+    if (lane == 0) wmax[t >> 6] = amax;
+    __syncthreads();
+    amax = 0.0;
+#pragma unroll
+    for (int i = 0; i < kB * kB / E / 64; ++i) amax = fmax(amax, wmax[i]);
+    thr2 = 1e-26 * amax;
+  }
+  uint64_t used = 0;  // PIV: rows already pivoted (the same in every wave)
   for (int kq = 0; kq < CG; ++kq) {
 #pragma unroll
     for (int kk = 0; kk < E; ++kk) {
       const int k = E * kq + kk;
       if (k >= kb) break;
       const int b = k & 1;
+      int p = k;
       if (cq == kq) pcol[b][r] = a[kk];
-      if (r == k) {
+      if constexpr (PIV) {
+        __syncthreads();
+        // every wave finds the pivot row: lane l looks at row l (rows past kb and used
+        // rows excluded), then a butterfly maximum; ties go to the lower row
+        const z v = pcol[b][lane];
+        double m2 = (lane < kb && !((used >> lane) & 1)) ? v.x * v.x + v.y * v.y : -1.0;
+        int idx = lane;
+        for (int m = 32; m >= 1; m >>= 1) {
+          const double om = __shfl_xor(m2, m, 64);
+          const int oi = __shfl_xor(idx, m, 64);
+          if (om > m2 || (om == m2 && oi < idx)) {
+            m2 = om;
+            idx = oi;
+          }
+        }
+        p = __builtin_amdgcn_readfirstlane(idx);
+        used |= (uint64_t)1 << p;
+        if (t == 0) {
+          perm[k] = p;
+          inv[p] = k;
+          if (!(m2 > thr2)) atomicCAS(flag + w, 0, o + k + 1);  // first singular pivot of this frequency
+        }
+      }
+      if (r == p) {
 #pragma unroll
         for (int j = 0; j < E; ++j) prow[b][j][cq] = a[j];
       }
       __syncthreads();
-      const z piv = pcol[b][k];
-      if (t == 0) {
+      const z piv = pcol[b][p];
+      if (!PIV && t == 0) {
         const bool bad = check_sign ? !(piv.x > 0.0) : (piv.x == 0.0 && piv.y == 0.0);
         if (bad) atomicCAS(flag + w, 0, o + k + 1);  // first bad pivot of this frequency
       }
       const double den = piv.x * piv.x + piv.y * piv.y;
       const double rd = den > 0.0 ? 1.0 / den : 0.0;
       const z ip = z{piv.x * rd, -piv.y * rd};
-      // one instruction stream for every row: the pivot row is 0 - (-1/p) A_kj,
-      // the others A_rj - (A_rk / p) A_kj; column k is set afterwards
-      const bool prow_k = r == k;
+      // one instruction stream for every row: the pivot row is 0 - (-1/p) A_pj,
+      // the others A_rj - (A_rk / p) A_pj; column k is set afterwards
+      const bool prow_p = r == p;
       const z gr = cmul(pcol[b][r], ip);
-      const z g = prow_k ? z{-ip.x, -ip.y} : gr;
-      const double keep = prow_k ? 0.0 : 1.0;
+      const z g = prow_p ? z{-ip.x, -ip.y} : gr;
+      const double keep = prow_p ? 0.0 : 1.0;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const z pr = prow[b][j][cq];
         a[j].x = fma(-g.x, pr.x, fma(g.y, pr.y, keep * a[j].x));
         a[j].y = fma(-g.x, pr.y, fma(-g.y, pr.x, keep * a[j].y));
       }
-      if (cq == kq) a[kk] = prow_k ? ip : z{-gr.x, -gr.y};
+      if (cq == kq) a[kk] = prow_p ? ip : z{-gr.x, -gr.y};
     }
   }
+  if constexpr (PIV) __syncthreads();  // perm and inv complete
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
-    if (r < kb && c < kb) A[(size_t)(o + r) * n + o + c] = a[j];
+    if (r < kb && c < kb) {
+      if constexpr (PIV)
+        A[(size_t)(o + inv[r]) * n + o + perm[c]] = a[j];
+      else
+        A[(size_t)(o + r) * n + o + c] = a[j];
+    }
   }
 }
 constexpr int kDiagE = 8;  // entries per thread of diag_inverse (512 threads: two waves per SIMD)
@@ -263,6 +322,25 @@ __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ 
 }  // namespace
 }  // namespace xo
 
+namespace xo {
+namespace {
+// Workspace of one call: the pivot flags and, with more than one block, the saved column panel.
+size_t eps_ws_bytes(int n, int nw) {
+  const int nblk = (n + kB - 1) / kB;
+  return align_up(sizeof(int) * nw, 256) + (nblk > 1 ? (size_t)nw * n * kB * sizeof(z) : 0);
+}
+}  // namespace
+}  // namespace xo
+
+extern "C" int xo_epsinv_workspace_size(const xo_eps_args* a, size_t* bytes) {
+  using namespace xo;
+  clear_error();
+  XO_ARG(a && bytes, "xo_epsinv_workspace_size: null argument");
+  XO_ARG(a->ng > 0 && a->nw > 0, "xo_epsinv_workspace_size: sizes must be positive (ng=%d nw=%d)", a->ng, a->nw);
+  *bytes = eps_ws_bytes(a->ng, a->nw);
+  return XO_OK;
+}
+
 extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   using namespace xo;
   clear_error();
@@ -287,8 +365,7 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   const int nblk = (n + kB - 1) / kB;
   void* ws = nullptr;
   const size_t fbytes = align_up(sizeof(int) * a->nw, 256);
-  const size_t sbytes = nblk > 1 ? (size_t)a->nw * n * kB * sizeof(z) : 0;
-  XO_RET(workspace(st, 2, fbytes + sbytes, &ws));
+  XO_RET(workspace(st, 2, eps_ws_bytes(n, a->nw), &ws));
   // pivot flags: the caller's info array (deferred check) or library workspace
   int* flag = a->info ? a->info : static_cast<int*>(ws);
   double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + fbytes);
@@ -312,8 +389,12 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
     const int kb = std::min(kB, n - K * kB);
     {
       KernelTimer kt_("eps_diag_inverse", st);
-      hipLaunchKernelGGL(diag_inverse<kDiagE>, dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n, K, kb,
-                         check_sign, flag);
+      if (check_sign)
+        hipLaunchKernelGGL((diag_inverse<kDiagE, false>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
+                           K, kb, check_sign, flag);
+      else
+        hipLaunchKernelGGL((diag_inverse<kDiagE, true>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
+                           K, kb, check_sign, flag);
     }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
@@ -346,8 +427,13 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   XO_TRY_HIP(hipStreamSynchronize(st));
   for (int w = 0; w < a->nw; ++w) {
     if (hf[w]) {
-      set_error("xo_epsinv: eps~ is not positive definite at frequency %d (pivot %d)", w, hf[w] - 1);
-      return XO_ERR_NOTPD;
+      if (check_sign) {
+        set_error("xo_epsinv: eps~ is not positive definite at frequency %d (pivot %d)", w, hf[w] - 1);
+        return XO_ERR_NOTPD;
+      }
+      set_error("xo_epsinv: a diagonal block of the elimination is numerically singular at frequency %d "
+                "(pivot %d)", w, hf[w] - 1);
+      return XO_ERR_SINGULAR;
     }
   }
   return XO_OK;

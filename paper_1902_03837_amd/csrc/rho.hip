@@ -467,6 +467,33 @@ int validate_rho(const xo_rho_args* a, Extent* pxc, Extent* pxv, Extent* pxe) {
 int rho_head_f32(const xo_rho_args* a, hipStream_t s) { return launch_head_q0<float>(a, s); }
 int rho_head_f64(const xo_rho_args* a, hipStream_t s) { return launch_head_q0<double>(a, s); }
 
+// Workspace bytes the VALU path requests for one pair (U_c, U_v and one chunk of the
+// y-z partial sums), as rho_run sizes them. Host only.
+int rho_valu_ws_bytes(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, size_t* bytes) {
+  const int no = std::max(xc.hi[2] - xc.lo[2] + 1, xv.hi[2] - xv.lo[2] + 1);
+  if (no > 32) {
+    set_error("rho: plane-wave sphere spans %d Miller steps along z (max 32)", no);
+    return XO_ERR_UNSUPPORTED;
+  }
+  const int NO = no <= 16 ? 16 : (no <= 24 ? 24 : 32);
+  const size_t cs = a->prec == XO_FP64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  const int Nx = a->n[0], Ny = a->n[1];
+  const int nz = xe.hi[2] - xe.lo[2] + 1;
+  std::vector<char> seen((size_t)Ny * nz, 0);
+  size_t nyz = 0;
+  for (int g = 0; g < a->ng; ++g) {
+    const int ey = a->mill_g[3 * g + 1] - a->g0[1], ez = a->mill_g[3 * g + 2] - a->g0[2];
+    char& f = seen[(size_t)pmod(ey, Ny) * nz + (ez - xe.lo[2])];
+    nyz += f == 0;
+    f = 1;
+  }
+  const size_t ub = (size_t)Nx * Ny * NO * cs;
+  const size_t per_c = (size_t)a->nv * Nx * nyz * cs;
+  const size_t ncc = std::max<size_t>(1, std::min<size_t>(a->nc, ((size_t)1 << 30) / per_c));
+  *bytes = align_up(ub * a->nc, 256) + align_up(ub * a->nv, 256) + per_c * ncc;
+  return XO_OK;
+}
+
 // VALU path for one pair (FP64 and FP32).
 int rho_valu(const xo_rho_args* a, hipStream_t s) {
   Extent xc, xv, xe;

@@ -46,6 +46,9 @@ int rho_head_f64(const xo_rho_args* a, hipStream_t s);
 int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                    hipStream_t s);
 int rho_batch_finish(const xo_rho_args* p, int n, hipStream_t s);
+int rho_gemm_ws_bytes(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                      size_t* bytes);
+int rho_valu_ws_bytes(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, size_t* bytes);
 int rho_batch_gemm_fp(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                       hipStream_t s);
 
@@ -571,6 +574,35 @@ static int pair_entry(const xo_rho_args* a, const Extent& xc, const Extent& xv, 
   return XO_OK;
 }
 
+// LDS bytes of the axis-factorised kernel for a batch whose largest row-tile count is MT.
+static size_t mfma_lds(int Nx, const PairGeo& g, int MT) {
+  return (size_t)3 * ((Nx + 1) & ~1) * sizeof(float2) + (size_t)((g.Kp / 4 + 3) & ~3) * 4 + (size_t)8 * g.CS * 4 +
+         (size_t)4 * MT * 16 * kPS * sizeof(float2);
+}
+
+// Workspace bytes the axis-factorised path requests for the batch, or XO_ERR_UNSUPPORTED
+// when it cannot take it. Host geometry only.
+static int mfma_ws_bytes(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                         size_t* bytes) {
+  const int Nx = p[0].n[0], GPT = p[0].ng <= 128 ? 2 : 8;
+  std::vector<PairGeo> g(n);
+  int MT = 1;
+  for (int i = 0; i < n; ++i) {
+    const SphereBox bc = sphere_box(p[i].mill_c, p[i].npw_c, xc[i]);
+    const SphereBox bv = sphere_box(p[i].mill_v, p[i].npw_v, xv[i]);
+    if (!pair_geo(&p[i], xc[i], xv[i], xe[i], bc, bv, GPT, &g[i]) || g[i].ncb > kBlock * kMaxPF || g[i].MT > 8)
+      return XO_ERR_UNSUPPORTED;
+    MT = std::max(MT, g[i].MT);
+  }
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (mfma_lds(Nx, g[i], MT) > 160 * 1024) return XO_ERR_UNSUPPORTED;
+    tot += align_up((size_t)p[i].nc * Nx * g[i].ncb, 64) + align_up((size_t)p[i].nv * Nx * g[i].Kp, 64);
+  }
+  *bytes = 2 * tot * sizeof(uint32_t);
+  return XO_OK;
+}
+
 static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
                           hipStream_t s) {
   const int Nx = p[0].n[0], ng = p[0].ng;
@@ -582,6 +614,9 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     if (!ge[i]) return XO_ERR_UNSUPPORTED;
     MT = std::max(MT, ge[i]->g.MT);
   }
+  // LDS fit checked before anything is enqueued
+  for (int i = 0; i < n; ++i)
+    if (mfma_lds(Nx, ge[i]->g, MT) > 160 * 1024) return XO_ERR_UNSUPPORTED;
   std::vector<float2> tw(Nx);
   for (int k = 0; k < Nx; ++k) {
     const double th = 2.0 * M_PI * k / Nx;
@@ -667,11 +702,8 @@ static int rho_batch_mfma(const xo_rho_args* p, int n, const Extent* xc, const E
     for (int e = 0; e < kMaxGroups; ++e) d.mte[e] = e < g.nE ? g.mte[e] : 0;
     d.wg0 = nwg;
     nwg += d.nc * d.nvt * d.nE;
-    const size_t need = (size_t)3 * ((Nx + 1) & ~1) * sizeof(float2) + (size_t)((g.Kp / 4 + 3) & ~3) * 4 +
-                        (size_t)8 * g.CS * 4 + (size_t)4 * MT * 16 * kPS * sizeof(float2);
-    lds = std::max(lds, need);
+    lds = std::max(lds, mfma_lds(Nx, g, MT));
   }
-  if (lds > 160 * 1024) return XO_ERR_UNSUPPORTED;
   const void* dpairs = nullptr;
   XO_RET(device_table(pd.data(), pd.size() * sizeof(PairDesc), s, &dpairs));
   if (GPT == 2)
@@ -721,6 +753,30 @@ static int rho_kernel_choice() {
   return 0;
 }
 
+// Workspace bytes xo_rho_batch requests for this batch (the path it would take; the
+// per-pair VALU path reuses one buffer, so its largest pair counts). Host only.
+int rho_batch_ws_bytes(const xo_rho_args* p, int n, size_t* bytes) {
+  std::vector<Extent> xc(n), xv(n), xe(n);
+  for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
+  if (mfma_eligible(p, n)) {
+    const int choice = rho_kernel_choice();
+    if (p[0].prec == XO_BF16X3 || p[0].prec == XO_BF16) {
+      if (choice != 2 && rho_gemm_ws_bytes(p, n, xc.data(), xv.data(), xe.data(), bytes) == XO_OK) return XO_OK;
+      if (choice != 1 && mfma_ws_bytes(p, n, xc.data(), xv.data(), xe.data(), bytes) == XO_OK) return XO_OK;
+    } else if (choice != 2 && rho_gemm_ws_bytes(p, n, xc.data(), xv.data(), xe.data(), bytes) == XO_OK) {
+      return XO_OK;
+    }
+  }
+  size_t mx = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t b = 0;
+    XO_RET(rho_valu_ws_bytes(&p[i], xc[i], xv[i], xe[i], &b));
+    mx = std::max(mx, b);
+  }
+  *bytes = mx;
+  return XO_OK;
+}
+
 int rho_batch(const xo_rho_args* p, int n, hipStream_t s) {
   std::vector<Extent> xc(n), xv(n), xe(n);
   for (int i = 0; i < n; ++i) XO_RET(validate_rho(&p[i], &xc[i], &xv[i], &xe[i]));
@@ -753,6 +809,15 @@ extern "C" int xo_rho(const xo_rho_args* a, void* stream) {
     return XO_ERR_ARG;
   }
   return xo::rho_batch(a, 1, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int xo_rho_workspace_size(const xo_rho_args* pairs, int npairs, size_t* bytes) {
+  xo::clear_error();
+  if (!pairs || npairs <= 0 || !bytes) {
+    xo::set_error("xo_rho_workspace_size: need a non-empty array of pairs and an output");
+    return XO_ERR_ARG;
+  }
+  return xo::rho_batch_ws_bytes(pairs, npairs, bytes);
 }
 
 extern "C" int xo_rho_batch(const xo_rho_args* pairs, int npairs, void* stream) {

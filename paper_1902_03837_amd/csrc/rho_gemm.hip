@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <tuple>
@@ -695,6 +696,59 @@ static int rho_batch_gemm_t(const xo_rho_args* p, int n, const Extent* xc, const
   }
   XO_CHECK_LAUNCH();
   return rho_batch_finish(p, n, s);
+}
+
+// LDS bytes of one gathered-product workgroup for pair a (host geometry only), or 0
+// when its gather box does not fit.
+static size_t gemm_lds(const xo_rho_args* a, const Extent& xc, const Extent& xv, const Extent& xe, size_t bs_bytes,
+                       size_t vrow_bytes) {
+  GemmGeo g;
+  gemm_geo(a, xc, xv, xe, &g);
+  if (!g.ok) return 0;
+  int nbs = 1;
+  const int nrows = a->nv * a->ng;
+  for (int r0 = 0; r0 < nrows; r0 += kRows)
+    nbs = std::max(nbs, std::min(a->nv - 1, (r0 + kRows - 1) / a->ng) - r0 / a->ng + 1);
+  return bs_bytes + (size_t)nbs * vrow_bytes + g.T.size() * 2;
+}
+
+// Workspace bytes the gathered-product path requests for the batch (0 for FP64 / FP32,
+// which read the coefficients in place), or XO_ERR_UNSUPPORTED when it cannot take it.
+// Host computation only (no device tables are built).
+int rho_gemm_ws_bytes(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,
+                      size_t* bytes) {
+  const bool bf = p[0].prec == XO_BF16X3 || p[0].prec == XO_BF16;
+  const int kW = p[0].prec == XO_BF16X3 ? 2 : 1;
+  size_t bs = 0;
+  if (p[0].prec == XO_BF16X3) {
+    bs = GemmShape<3, kCT>::bs_bytes;
+  } else if (p[0].prec == XO_BF16) {
+    int nct = 1;
+    for (int i = 0; i < n; ++i) nct = std::max(nct, (p[i].nc + 15) / 16);
+    bs = (nct + 6) / 7 == (nct + 7) / 8 ? GemmShape<1, 7>::bs_bytes : GemmShape<1, 8>::bs_bytes;
+  } else {
+    const int CT = p[0].prec == XO_FP64 ? 4 : 8;
+    bs = (size_t)2 * CT * kBsTile * (p[0].prec == XO_FP64 ? 16 : 8);
+  }
+  for (int i = 0; i < n; ++i) {
+    const size_t vrow = bf ? (size_t)padded_row(p[i].npw_v) * kW * 4
+                           : ((size_t)(p[i].npw_v + 2) & ~(size_t)1) * (p[0].prec == XO_FP64 ? 16 : 8);
+    const size_t lds = gemm_lds(&p[i], xc[i], xv[i], xe[i], bs, vrow);
+    if (lds == 0 || lds > kLdsMax) return XO_ERR_UNSUPPORTED;
+  }
+  *bytes = 0;
+  if (!bf) return XO_OK;
+  std::set<std::tuple<const void*, int, int>> sets;
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int side = 0; side < 2; ++side) {
+      const void* c = side ? p[i].coef_v : p[i].coef_c;
+      const int nb = side ? p[i].nv : p[i].nc, npw = side ? p[i].npw_v : p[i].npw_c;
+      if (sets.insert(std::make_tuple(c, nb, npw)).second) tot += (size_t)nb * padded_row(npw);
+    }
+  }
+  *bytes = tot * kW * 4;
+  return XO_OK;
 }
 
 int rho_batch_gemm(const xo_rho_args* p, int n, const Extent* xc, const Extent* xv, const Extent* xe,

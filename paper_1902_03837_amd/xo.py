@@ -16,12 +16,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxo.so")
 
-XO_OK, XO_ERR_ARG, XO_ERR_ALLOC, XO_ERR_HIP, XO_ERR_NOTPD, XO_ERR_UNSUPPORTED = range(6)
+XO_OK, XO_ERR_ARG, XO_ERR_ALLOC, XO_ERR_HIP, XO_ERR_NOTPD, XO_ERR_UNSUPPORTED, XO_ERR_SINGULAR = range(7)
 XO_FP64, XO_FP32, XO_BF16X3, XO_BF16 = 0, 1, 2, 3
 XO_EPS_SYM, XO_EPS_NONSYM, XO_EPS_LU_FALLBACK = 0, 1, 2
 
 PREC = {"fp64": XO_FP64, "fp32": XO_FP32, "bf16x3": XO_BF16X3, "bf16": XO_BF16}
-ERRNAME = {1: "XO_ERR_ARG", 2: "XO_ERR_ALLOC", 3: "XO_ERR_HIP", 4: "XO_ERR_NOTPD", 5: "XO_ERR_UNSUPPORTED"}
+ERRNAME = {1: "XO_ERR_ARG", 2: "XO_ERR_ALLOC", 3: "XO_ERR_HIP", 4: "XO_ERR_NOTPD", 5: "XO_ERR_UNSUPPORTED", 6: "XO_ERR_SINGULAR"}
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -105,7 +105,8 @@ _LIB = None
 EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_enable", "xo_timing_report",
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
-           "xo_xterm", "xo_ppa_fit", "xo_sigma", "xo_chi0_real")
+           "xo_xterm", "xo_ppa_fit", "xo_sigma", "xo_chi0_real", "xo_rho_workspace_size",
+           "xo_chi0_workspace_size", "xo_epsinv_workspace_size")
 
 
 def lib():
@@ -265,6 +266,33 @@ def launch_plan(plan: RhoPlan, stream=None):
     else:
         for i in range(len(plan.built)):
             _check(lib().xo_rho(C.byref(plan.arr[i]), st))
+
+
+def rho_workspace_size(arr, n=None):
+    """xo_rho_workspace_size over a RhoPlan or a ctypes array of RhoArgs: device bytes."""
+    if isinstance(arr, RhoPlan):
+        arr, n = arr.arr, len(arr.built)
+    out = C.c_size_t(0)
+    _check(lib().xo_rho_workspace_size(arr, int(n if n is not None else len(arr)), C.byref(out)))
+    return out.value
+
+
+def chi0_workspace_size(items, tune=None):
+    """xo_chi0_workspace_size over a list of Chi0Args (and an optional Tune): device bytes."""
+    arr = (Chi0Args * len(items))(*items)
+    out = C.c_size_t(0)
+    _check(lib().xo_chi0_workspace_size(arr, len(items), C.byref(tune) if tune is not None else None,
+                                        C.byref(out)))
+    return out.value
+
+
+def epsinv_workspace_size(ng, nw):
+    """xo_epsinv_workspace_size for ng G-vectors and nw frequencies: device bytes."""
+    a = EpsArgs()
+    a.ng, a.nw = int(ng), int(nw)
+    out = C.c_size_t(0)
+    _check(lib().xo_epsinv_workspace_size(C.byref(a), C.byref(out)))
+    return out.value
 
 
 def rho_batch(pairs, stream=None):

@@ -228,3 +228,80 @@ def test_chi0_real_argument_errors():
     a.eta = 0.01
     rc, msg = _rc(L.xo_chi0_real, a)
     assert rc == xo.XO_ERR_ARG and "frequency 1" in msg
+
+
+def _rho_block(cr, ip, prec, mills):
+    """Argument block of pair ip with fake device pointers (the size query reads none)."""
+    ik, ikp, g0 = cr.pairs[ip]
+    nv, nc = cr.nocc_at(ikp), cr.coef[ik].shape[0] - cr.nocc_at(ik)
+    a = xo.RhoArgs()
+    a.n[:] = list(cr.grid)
+    a.prec = xo.PREC[prec]
+    mc = np.ascontiguousarray(cr.mill[ik], dtype=np.int32)
+    mv = np.ascontiguousarray(cr.mill[ikp], dtype=np.int32)
+    mg = np.ascontiguousarray(cr.gmill, dtype=np.int32)
+    mills += [mc, mv, mg]
+    a.npw_c, a.mill_c, a.nc, a.coef_c, a.e_c = mc.shape[0], mc.ctypes.data_as(C.POINTER(C.c_int32)), nc, 4096, 4096
+    a.npw_v, a.mill_v, a.nv, a.coef_v, a.e_v = mv.shape[0], mv.ctypes.data_as(C.POINTER(C.c_int32)), nv, 8192, 8192
+    a.g0[:] = [int(x) for x in g0]
+    a.ng, a.mill_g = mg.shape[0], mg.ctypes.data_as(C.POINTER(C.c_int32))
+    a.rho = 16384
+    return a, nc, nv
+
+
+def test_workspace_size_queries():
+    """Host-only size queries: consistent with what the calls allocate and with each other."""
+    from synth import crystal_for
+    cr = crystal_for("c1_small")
+    mills = []
+    sizes = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        blocks = [_rho_block(cr, ip, prec, mills) for ip in range(len(cr.pairs))]
+        arr = (xo.RhoArgs * len(blocks))(*[b[0] for b in blocks])
+        sizes[prec] = xo.rho_workspace_size(arr, len(blocks))
+        # one pair alone takes no more than the batch
+        assert xo.rho_workspace_size(arr, 1) <= sizes[prec]
+    # FP64 / FP32 read the coefficients in place; the bf16 forms convert every distinct band
+    # set once (hi + lo words for bf16x3, one word for bf16): 8 and 4 bytes per entry
+    assert sizes["fp64"] == 0 and sizes["fp32"] == 0
+    assert sizes["bf16x3"] == 2 * sizes["bf16"] > 0
+    ent = 0
+    seen = set()
+    for ik, ikp, _ in cr.pairs:
+        for k, nb in ((ik, cr.coef[ik].shape[0] - cr.nocc_at(ik)), (ikp, cr.nocc_at(ikp))):
+            if (k, nb) not in seen:   # distinct band sets (here: per k-point and side)
+                seen.add((k, nb))
+                ent += nb * ((cr.mill[k].shape[0] + 1 + 15) // 16 * 16)
+    assert sizes["bf16"] <= 4 * ent
+    # chi0: grows with the transitions and is the same for xo_chi0's single item
+    w = np.array([0.0, 0.5, 1.0, 2.0])
+    def item(nt, ng, prec, check=0):
+        a = xo.Chi0Args()
+        a.nt, a.ng, a.nw, a.prec = nt, ng, 4, xo.PREC[prec]
+        a.rho, a.dE, a.chi0 = 8, 8, 8
+        a.w, a.pref, a.check_dE = w.ctypes.data_as(C.POINTER(C.c_double)), 1.0, check
+        return a
+    for prec in ("fp64", "bf16x3"):
+        small = xo.chi0_workspace_size([item(1000, 100, prec)])
+        big = xo.chi0_workspace_size([item(50000, 100, prec)])
+        assert 0 < small <= big
+        assert xo.chi0_workspace_size([item(1000, 100, prec, check=1)]) == small + 256
+        assert xo.chi0_workspace_size([item(1000, 100, prec), item(3000, 300, prec)]) > big * 0 + small
+    # epsinv: pivot flags, plus the saved column panel [nw][ng][64] complex128 past one block
+    assert xo.epsinv_workspace_size(64, 3) == 256
+    assert xo.epsinv_workspace_size(400, 8) == 256 + 8 * 400 * 64 * 16
+    with pytest.raises(xo.XoError):
+        xo.epsinv_workspace_size(0, 1)
+
+
+def test_autotune_rejects_accumulating_items():
+    L = xo.lib()
+    w = np.array([0.0, 1.0])
+    a = xo.Chi0Args()
+    a.nt, a.ng, a.nw, a.prec = 64, 16, 2, xo.PREC["bf16"]
+    a.rho, a.dE, a.chi0 = 8, 8, 8
+    a.w, a.pref, a.accumulate = w.ctypes.data_as(C.POINTER(C.c_double)), 1.0, 1
+    best = xo.Tune()
+    ms = C.c_double(0)
+    rc = L.xo_chi0_autotune(C.byref(a), 1, C.byref(best), C.byref(ms), None)
+    assert rc == xo.XO_ERR_ARG and b"accumulate" in L.xo_last_error()

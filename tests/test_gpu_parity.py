@@ -371,6 +371,57 @@ def test_epsinv_not_positive_definite():
     assert np.abs(out.cpu().numpy()[0] - ref).max() < 1e-9 * np.abs(ref).max()
 
 
+def _chi_for_eps(M, qpg):
+    """chi0 whose eps~ = I - s chi0 s is the given matrix M (per frequency)."""
+    s = np.sqrt(4 * np.pi) / qpg
+    return (np.eye(M.shape[-1])[None] - M) / (s[:, None] * s[None, :])[None]
+
+
+@pytest.mark.parametrize("ng", [5, 64, 97, 200])
+def test_epsinv_lu_fallback_pivots_inside_blocks(ng):
+    """General (non-Hermitian) well-conditioned eps~ whose leading pivots are tiny or zero
+    in the unpivoted order: frequency 0 has eps~_00 = 1e-14, frequency 1 has pairs of rows
+    swapped inside each 64-block (zero diagonal where two rows meet), so elimination
+    without pivoting fails or loses accuracy; the pivoted form matches numpy's LU inverse."""
+    say(f"epsinv LU fallback pivoting ng={ng}")
+    g = np.random.default_rng(ng)
+    base = np.eye(ng) + 0.3 * (g.standard_normal((ng, ng)) + 1j * g.standard_normal((ng, ng))) / np.sqrt(ng)
+    m0 = base.copy()
+    m0[0, 0] = 1e-14
+    perm = np.arange(ng)
+    for i in range(0, ng - 1, 2):
+        perm[i], perm[i + 1] = perm[i + 1], perm[i]
+    m1 = np.eye(ng)[perm] @ (np.eye(ng) + 0.2 * (base - np.eye(ng)))
+    M = np.stack([m0, m1])
+    assert all(np.linalg.cond(m) < 500 for m in M)
+    qpg = np.linspace(0.7, 2.5, ng)
+    out = torch.empty(M.shape, dtype=torch.complex128, device=DEV)
+    xo.epsinv(_to(_chi_for_eps(M, qpg)), qpg, out=out, flags=xo.XO_EPS_LU_FALLBACK)
+    got = out.cpu().numpy()
+    for j in range(2):
+        ref = np.linalg.inv(M[j])
+        assert np.linalg.norm(got[j] - ref) < 1e-11 * np.linalg.norm(ref), j
+
+
+def test_epsinv_lu_fallback_reports_singular_block():
+    """Invertible eps~ whose leading 64 x 64 block is zero: the blocked elimination does
+    not pivot across blocks, so it reports XO_ERR_SINGULAR (or flags it in info) rather
+    than returning a wrong inverse."""
+    ng = 128
+    M = np.zeros((1, ng, ng), complex)
+    M[0, :64, 64:] = np.eye(64)
+    M[0, 64:, :64] = np.eye(64)
+    assert abs(np.linalg.det(M[0])) == 1.0
+    qpg = np.ones(ng)
+    out = torch.empty(M.shape, dtype=torch.complex128, device=DEV)
+    with pytest.raises(xo.XoError) as e:
+        xo.epsinv(_to(_chi_for_eps(M, qpg)), qpg, out=out, flags=xo.XO_EPS_LU_FALLBACK)
+    assert e.value.code == xo.XO_ERR_SINGULAR
+    info = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    xo.epsinv(_to(_chi_for_eps(M, qpg)), qpg, out=out, flags=xo.XO_EPS_LU_FALLBACK, info=info)
+    assert info.item() == 1   # the first pivot of the first block
+
+
 # ---------------------------------------------------------------------- end to end
 
 # plain bf16 at these small transition counts: the operand rounding (2^-8) is averaged
