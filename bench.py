@@ -1,29 +1,34 @@
 #!/usr/bin/env python
 """Benchmark of the chi0 / eps^-1 hot path on one MI355X.
 
-Workload (default): the "plain vs split precision" crystal: fcc, 4x4x4 k-points,
-q = b1/4, 16 occupied + 200 empty bands, 36^3 FFT grid, 400 G-vectors, 8
-imaginary frequencies; K = 204 800 transitions. One step is the whole path on
-inputs already resident in HBM: oscillator strengths for all 64 k-pairs
-(xo_rho), chi0 for all frequencies (xo_chi0) and the FP64 Dyson inversion
-(xo_epsinv). The positive-definiteness flags of the inversion go to a device
-array and are checked once after the timed steps, so the host enqueues the next
-step while the GPU inverts.
+Default workload (the large cell): simple-cubic 2a supercell with 32 displaced fcc
+sites, 2x2x2 k-points, q = b1/2, 128 occupied + 2000 empty bands, 72^3 FFT grid,
+NG = 3000, 16 imaginary frequencies; K = 2 048 000 transitions. One step is the whole
+path on inputs already resident in HBM: oscillator strengths for all 8 k-pairs
+(xo_rho_batch), chi0 for all frequencies (xo_chi0) and the FP64 Dyson inversion
+(xo_epsinv). The positive-definiteness flags of the inversion go to a device array and
+are checked once after the timed steps, so the host enqueues the next step while the
+GPU inverts.
 
-Each form runs its warm-up steps, the timed steps (HIP events at the stage
-boundaries only) and then as many steps again with the library's per-kernel HIP
-event brackets on (xo_timing_enable), which give the kernel durations of the
-roofline entries without weighing on the timed steps.
+Reported form: split bf16 ("bf16x3": operands split into bf16 hi + lo, three MFMA
+products, FP32 accumulation over transition slices of at most 65 536 and FP64 across
+slices), with the q -> 0 head and eps^-1 in FP64. The plain FP64 path is timed once in
+the same run; its eps~^-1 is the error reference (e_F_vs_fp64, relative Frobenius,
+worst frequency) and its step time gives speedup_vs_fp64. Plain bf16 (operands rounded
+to bf16, one product) is timed beside it for reference only.
 
-Every form is timed: plain FP64, FP32 (FP32-MFMA rho and chi0), BF16x3 (split
-bf16 on MFMA: three products, FP32 accumulation) and BF16 (operands rounded to
-bf16, one product, FP32 accumulation); eps^-1 is FP64 in all. The reported form
-is the fastest whose eps~^-1 stays within 1e-4 (relative Frobenius, worst
-frequency) of the plain FP64 path timed in the same run. Output: one JSON line.
+Each form runs its warm-up steps, the timed steps (HIP events at the stage boundaries
+only) and then a few steps with the library's per-kernel HIP event brackets on
+(xo_timing_enable), which give the kernel durations of the roofline entries without
+weighing on the timed steps.
 
-Other workloads (--workload): c3 (27 q-points with uneven G-sets in one batched
-launch), c5 (large cell), sigma (plasmon-pole W and the GW self-energy of eight
-states summed over all 64 q of the c2 crystal), real (the c2 path at 100 real
+cpu_baseline: the FP64 oracle on the host cores, timed on a sample of the same workload
+(one k-pair, a band subset, four frequencies, eps~^-1 of two) and extrapolated linearly in
+the transitions and frequencies, which is exact for this work.
+
+Other workloads (--workload): c2 (fcc 4x4x4 k, NG = 400: every form), c3 (27 q-points with
+uneven G-sets in one batched launch), sigma (plasmon-pole W and the GW self-energy of
+eight states summed over all 64 q of the c2 crystal), real (the c2 path at 100 real
 frequencies); each prints its own JSON line.
 """
 
@@ -96,9 +101,10 @@ def rho_zy_flops(cr, pairs_meta):
     return 8.0 * Nx * (Ny * s1 + nyz * Ny)
 
 
-def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
+def run_form(cr, prec, steps, warmup, ref_E=None, real=None, kernel_steps=None, keep_E=True):
     """One form of the path on crystal cr; real = (frequencies, eta) runs it at real frequencies
-    (xo_chi0_real, Dyson step with the LU fallback) instead of the crystal's imaginary ones."""
+    (xo_chi0_real, Dyson step with the LU fallback) instead of the crystal's imaginary ones.
+    kernel_steps: steps of the per-kernel timing pass (default: as many as timed)."""
     import torch
     from paper_1902_03837_amd import xo
     from paper_1902_03837_amd.pipeline import DeviceCrystal, rho_all, ntrans, CDTYPE, chi0_pref, qpg as qpg_of
@@ -143,14 +149,17 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
         step(evs[i])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    # the same steps again with every kernel bracketed by HIP events on its launch stream
-    xo.timing_report()            # drop anything recorded before
-    xo.timing_enable(True)
-    for i in range(steps):
-        step()
-    torch.cuda.synchronize()
-    xo.timing_enable(False)
-    kern = xo.timing_report()
+    # steps again with every kernel bracketed by HIP events on its launch stream
+    ksteps = steps if kernel_steps is None else kernel_steps
+    kern = {}
+    if ksteps > 0:
+        xo.timing_report()            # drop anything recorded before
+        xo.timing_enable(True)
+        for i in range(ksteps):
+            step()
+        torch.cuda.synchronize()
+        xo.timing_enable(False)
+        kern = xo.timing_report()
     if int(info.abs().sum().item()):
         raise RuntimeError(f"eps~ inversion failed ({prec}): pivot flags {info.tolist()}")
     stages = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) for j in range(3)] for i in range(steps)])
@@ -158,9 +167,9 @@ def run_form(cr, prec, steps, warmup, ref_E=None, real=None):
     out = dict(prec=prec, K=K, ms_per_step=float(np.median(step_ms)), wall_ms_per_step=wall * 1e3,
                t_rho_ms=float(np.median(stages[:, 0])), t_chi0_ms=float(np.median(stages[:, 1])),
                t_eps_ms=float(np.median(stages[:, 2])),
-               kernels={k: dict(launches=v[0] // steps, ms_per_step=v[1] / steps,
+               kernels={k: dict(launches=v[0] // max(1, ksteps), ms_per_step=v[1] / max(1, ksteps),
                                 avg_launch_ms=v[1] / v[0]) for k, v in kern.items()})
-    E_host = E.cpu().numpy()
+    E_host = E.cpu().numpy() if keep_E or ref_E is not None else None
     if ref_E is not None:
         from_ref = [float(np.linalg.norm(E_host[j] - ref_E[j]) / np.linalg.norm(ref_E[j])) for j in range(nw)]
         out["e_F_vs_fp64"] = max(from_ref)
@@ -216,8 +225,9 @@ def measured_traffic(kernel, summary="c2_hbm_traffic.txt"):
     return tr[kernel] if cur == h else None
 
 
-def roofline(cr, form, K, nw, ng, name=None):
-    """Roofline entry of one kernel (default: the one with the largest time per step)."""
+def roofline(cr, form, K, nw, ng, name=None, summary="c2_hbm_traffic.txt"):
+    """Roofline entry of one kernel (default: the one with the largest time per step); traffic
+    comes from the committed counter summary of the workload while the kernel source is unchanged."""
     kern = form["kernels"]
     if name is None:
         name = max(kern, key=lambda k: kern[k]["ms_per_step"])
@@ -229,7 +239,7 @@ def roofline(cr, form, K, nw, ng, name=None):
         fl = chi0_flops(K, ng, nw if name.startswith("chi0_blocks") else min(nw, 8))
         peak = MFMA_PEAK[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                    frac=fl / t / peak, traffic=measured_traffic(name),
+                    frac=fl / t / peak, traffic=measured_traffic(name, summary),
                     note="algorithmic flops 4 NG^2 K per frequency (Hermitian half)")
     if name == "rho_zy":
         per_t = np.mean([rho_zy_flops(cr, p) for p in cr.pairs])
@@ -242,7 +252,7 @@ def roofline(cr, form, K, nw, ng, name=None):
         fl = 8.0 * rho_direct_terms(cr) / k["launches"]   # per launch (all pairs of the step in one)
         peak = MFMA_PEAK[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12,
-                    unit="TFLOP/s", frac=fl / t / peak, traffic=measured_traffic(name),
+                    unit="TFLOP/s", frac=fl / t / peak, traffic=measured_traffic(name, summary),
                     note="algorithmic flops: the nonzero terms of the direct plane-wave sum (8 per complex "
                          "multiply-add) over the dense MFMA peak of the precision; the kernel also executes "
                          "the zero terms of its dense tiles" + (" and three split-bf16 products per term"
@@ -252,58 +262,126 @@ def roofline(cr, form, K, nw, ng, name=None):
         nr = float(np.prod(cr.grid))
         fl = 5.0 * nr * np.log2(nr) * K / k["launches"]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=PEAK["bf16_mfma"] / 1e12,
-                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name),
+                    unit="TFLOP/s", frac=fl / t / PEAK["bf16_mfma"], traffic=measured_traffic(name, summary),
                     note="algorithmic flops 5 N_r log2 N_r per transition (FFT-equivalent) over the bf16 "
                          "dense peak; the kernel executes the y-z correlation as split-bf16 (x3) 16x16x32 tiles")
     return dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None)
 
 
-def run_c5(args):
-    """Large cell: 32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occupied + 2000 empty
-    bands, 72^3 grid, NG = 3000, 16 frequencies, K = 2 048 000: the split-precision path timed,
-    the plain FP64 path once for the error of eps~^-1."""
-    from synth import crystal_for
+def cpu_baseline_sampled(cr, nv_s=8, nc_s=64, nw_s=4, nw_eps=2):
+    """The FP64 oracle as it stands on the host cores, on a sample of the workload: rho of
+    nv_s x nc_s transitions of the first k-pair (FFT route), chi0 of those at nw_s frequencies
+    (zgemm), eps~^-1 at nw_eps frequencies. Each stage is timed and scaled linearly to the
+    whole step (rho and chi0 with the transitions, chi0 and eps~^-1 with the frequencies)."""
+    from oracle.rho import rho_fft
+    from oracle.chi0 import chi0_from_rho, crystal_prefactor
+    from oracle.epsinv import epsinv_sym, crystal_qpg
+    ik, ikp, g0 = cr.pairs[0]
+    nv = cr.nocc_at(ikp)
+    cc = cr.coef[ik][cr.nocc_at(ik):cr.nocc_at(ik) + nc_s]
+    cv = cr.coef[ikp][:nv_s]
     t0 = time.perf_counter()
-    cr = crystal_for("c5", progress=lambda m: print(f"[bench] c5 fixture {m}", file=sys.stderr, flush=True))
+    r = rho_fft(cc, cr.mill[ik], cv, cr.mill[ikp], cr.gmill, g0, cr.grid)
+    t1 = time.perf_counter()
+    M = r.reshape(-1, r.shape[-1])
+    dE = (cr.eps[ik][cr.nocc_at(ik):cr.nocc_at(ik) + nc_s][None, :] - cr.eps[ikp][:nv_s][:, None]).reshape(-1)
+    chi = chi0_from_rho(M, dE, cr.omegas[:nw_s], crystal_prefactor(cr))
+    t2 = time.perf_counter()
+    epsinv_sym(chi[:nw_eps], crystal_qpg(cr), check=False)
+    t3 = time.perf_counter()
+    K = sum((cr.coef[a].shape[0] - cr.nocc_at(a)) * cr.nocc_at(b) for a, b, _ in cr.pairs)
+    ks, nw = M.shape[0], len(cr.omegas)
+    t_full = (t1 - t0) * K / ks + (t2 - t1) * (K / ks) * (nw / nw_s) + (t3 - t2) * nw / nw_eps
+    ng = cr.gmill.shape[0]
+    return dict(value=chi0_flops(K, ng, nw) / t_full / 1e9, unit="GFLOP/s", cores=len(os.sched_getaffinity(0)),
+                kind="oracle", extrapolated=True, seconds_sampled=t3 - t0, seconds_extrapolated_step=t_full,
+                transitions_per_s_per_qw=K * nw / t_full,
+                sample=f"k-pair 0: {nv_s} valence x {nc_s} conduction bands ({ks} of {K} transitions), rho by "
+                       f"the FFT route ({t1 - t0:.1f} s), chi0 at {nw_s} of {nw} frequencies ({t2 - t1:.1f} s), "
+                       f"eps~^-1 at {nw_eps} ({t3 - t2:.1f} s); scaled linearly in transitions and frequencies; "
+                       f"scipy.fft on all cores, BLAS threads as set for the process")
+
+
+def run_c5(args):
+    """Headline: the large cell (32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occupied +
+    2000 empty bands, 72^3 grid, NG = 3000, 16 frequencies, K = 2 048 000) in the split-bf16 form,
+    the plain FP64 path once for the error of eps~^-1 and the speedup."""
+    import torch
+    from synth.cache import cached_crystal
+    t0 = time.perf_counter()
+    cr = cached_crystal("c5", args.fixture_cache,
+                        progress=lambda m: print(f"[bench] c5 fixture {m}", file=sys.stderr, flush=True))
     t_fix = time.perf_counter() - t0
     ng, nw = cr.gmill.shape[0], len(cr.omegas)
-    print(f"[bench] c5 fixture built in {t_fix:.1f} s", file=sys.stderr, flush=True)
-    out, Es = {}, {}
-    forms = args.c5_forms.split(",")
-    for prec in [p for p in forms if p != "fp64"] + (["fp64"] if "fp64" in forms else []):
-        steps, warm = (args.steps, args.warmup) if prec != "fp64" else (1, 0)
-        r, Es[prec] = run_form(cr, prec, steps, warm)
-        print(f"[bench] c5 {prec}: {r['ms_per_step']:.1f} ms/step (rho {r['t_rho_ms']:.1f}, chi0 "
-              f"{r['t_chi0_ms']:.1f}, eps {r['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
-        out[prec] = r
-    if "fp64" in out:
-        E64 = Es["fp64"]
-        for prec, r in out.items():
-            if prec != "fp64":
-                r["e_F_vs_fp64"] = max(float(np.linalg.norm(Es[prec][j] - E64[j]) / np.linalg.norm(E64[j]))
-                                       for j in range(nw))
-                r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / r["ms_per_step"]
-                print(f"[bench] c5 {prec}: e_F vs fp64 {r['e_F_vs_fp64']:.2e}", file=sys.stderr, flush=True)
-    K = next(iter(out.values()))["K"]
+    print(f"[bench] c5 fixture ready in {t_fix:.1f} s", file=sys.stderr, flush=True)
+    form = args.c5_form
+    kst = args.kernel_steps
+    res_form, E = run_form(cr, form, args.steps, args.warmup, kernel_steps=kst)
+    print(f"[bench] c5 {form}: {res_form['ms_per_step']:.1f} ms/step (rho {res_form['t_rho_ms']:.1f}, chi0 "
+          f"{res_form['t_chi0_ms']:.1f}, eps {res_form['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
+    others = {}
+    for p in [x for x in args.c5_beside.split(",") if x and x != form]:
+        r, _ = run_form(cr, p, min(args.steps, 3), 1, kernel_steps=1, keep_E=False)
+        others[p] = r
+        print(f"[bench] c5 {p} (beside): {r['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64, E64 = run_form(cr, "fp64", 1, 1, kernel_steps=1)
+        print(f"[bench] c5 fp64: {r64['ms_per_step']:.1f} ms/step (rho {r64['t_rho_ms']:.1f}, chi0 "
+              f"{r64['t_chi0_ms']:.1f}, eps {r64['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
+        res_form["e_F_vs_fp64"] = max(float(np.linalg.norm(E[j] - E64[j]) / np.linalg.norm(E64[j]))
+                                      for j in range(nw))
+        res_form["e_S_vs_fp64"] = max(float(np.linalg.norm(E[j] - E64[j]) / np.linalg.norm(E64[j] - np.eye(ng)))
+                                      for j in range(nw))
+        res_form["e_head_vs_fp64"] = max(float(abs(E[j, 0, 0] - E64[j, 0, 0]) / abs(E64[j, 0, 0]))
+                                         for j in range(nw))
+        del E64
+        print(f"[bench] c5 {form}: e_F vs fp64 {res_form['e_F_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+    del E
+    K = res_form["K"]
+    t = res_form["ms_per_step"] * 1e-3
     fl = chi0_flops(K, ng, nw)
-    for prec, r in out.items():
-        r["chi0_GFLOPs_over_step"] = fl / (r["ms_per_step"] * 1e-3) / 1e9
-        ck = [k for k in r["kernels"] if k.startswith("chi0_tiles") or k.startswith("chi0_blocks")]
-        if ck:
-            t = sum(r["kernels"][k]["ms_per_step"] for k in ck) * 1e-3
-            peak = MFMA_PEAK[prec]
-            r["chi0_kernel_TFLOPs"] = fl / t / 1e12
-            r["chi0_kernel_frac_of_peak"] = fl / t / peak
-    res = {"metric": "chi0 GFLOP/s + transitions/s per q,w; speedup vs FP64 at eps^-1 rel err<=1e-4",
-           "workload": f"c5: sc 2a supercell (32 displaced fcc sites), 2x2x2 k, q = b1/2, 128 occ + 2000 empty "
-                       f"bands, FFT 72^3, NG={ng}, {nw} imaginary frequencies, K={K} transitions",
-           "forms": out, "fixture_s": t_fix,
-           "note": "chi0_kernel_frac_of_peak is algorithmic (4 NG^2 K per frequency, Hermitian half) over the "
-                   "dense peak of the executed precision; the split-bf16 form executes three products, "
-                   "the plain-bf16 form one"}
+    res = {
+        "metric": "chi0 GFLOP/s + transitions/s per q,w; speedup vs FP64 at eps^-1 rel err<=1e-4",
+        "value": fl / t / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res_form["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[form],
+        "data": "synthetic",
+        "config": {"workload": f"c5: sc 2a supercell (32 displaced fcc sites), 2x2x2 k, q = b1/2, 128 occ + "
+                               f"2000 empty bands, FFT 72^3, NG={ng}, {nw} imaginary frequencies, K={K} "
+                               f"transitions",
+                   "form": form, "global_batch": K, "parallelism": "single GPU"},
+        "transitions_per_s_per_qw": K * nw / t,
+        "speedup_vs_fp64": (r64["ms_per_step"] / res_form["ms_per_step"]) if r64 else None,
+        "e_F_vs_fp64": res_form.get("e_F_vs_fp64"),
+        "e_S_vs_fp64": res_form.get("e_S_vs_fp64"),
+        "gate": GATE,
+        "stage_ms": {"rho": res_form["t_rho_ms"], "chi0": res_form["t_chi0_ms"], "eps": res_form["t_eps_ms"]},
+        "fp64_ms_per_step": r64["ms_per_step"] if r64 else None,
+        "full_matrix_equivalent_GFLOPs": 2 * fl / t / 1e9,
+        "roofline": roofline(cr, res_form, K, nw, ng, summary="c5_hbm_traffic.txt"),
+        "fixture_s": t_fix,
+        "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in res_form["kernels"].items()},
+    }
+    rk = [k for k in res_form["kernels"] if k.startswith("rho_gemm") or k in ("rho_yz", "rho_zy")]
+    if rk and rk[0] != res["roofline"]["kernel"]:
+        res["roofline_rho"] = roofline(cr, res_form, K, nw, ng, name=rk[0], summary="c5_hbm_traffic.txt")
+    res["beside"] = {p: dict(ms_per_step=r["ms_per_step"], stage_ms={"rho": r["t_rho_ms"], "chi0": r["t_chi0_ms"],
+                                                                      "eps": r["t_eps_ms"]},
+                             note="timed for reference, not the reported form")
+                     for p, r in others.items()}
+    if r64:
+        res["roofline_fp64"] = roofline(cr, r64, K, nw, ng, name=next(
+            k for k in r64["kernels"] if k.startswith("chi0_tiles")), summary="c5_hbm_traffic.txt")
+    if not args.no_cpu:
+        print("[bench] timing the oracle on the host cores (sampled)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline_sampled(cr)
     if args.detail:
         with open(args.detail, "w") as fh:
-            json.dump(res, fh, indent=1)
+            json.dump(dict(result=res, form=res_form, fp64=r64, beside=others), fh, indent=1)
     print(json.dumps(res), flush=True)
 
 
@@ -584,7 +662,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--forms", default="fp64,fp32,bf16x3,bf16")
     ap.add_argument("--cpu-pairs", type=int, default=6, help="k-pairs of the oracle's CPU timing (about 13 s)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -592,7 +670,11 @@ def main():
     ap.add_argument("--nq", type=int, default=27, help="c3: number of q-points")
     ap.add_argument("--c3-forms", default="bf16,bf16x3,fp64", help="c3: forms to time (fp64 is the reference)")
     ap.add_argument("--tune-cache", default=None, help="c3: JSON file for autotuned launch shapes")
-    ap.add_argument("--c5-forms", default="bf16,bf16x3,fp64", help="c5: forms (fp64 gives the error reference)")
+    ap.add_argument("--c5-form", default="bf16x3", help="c5: the reported form")
+    ap.add_argument("--c5-beside", default="bf16", help="c5: forms timed beside it for reference (comma list)")
+    ap.add_argument("--no-fp64", action="store_true", help="c5: skip the FP64 reference run")
+    ap.add_argument("--kernel-steps", type=int, default=2, help="c5: steps of the per-kernel timing pass")
+    ap.add_argument("--fixture-cache", default=None, help="directory to keep generated crystals in (npz)")
     ap.add_argument("--real-forms", default="bf16,bf16x3,fp64", help="real: forms (fp64 gives the error reference)")
     ap.add_argument("--real-nw", type=int, default=100, help="real: number of real frequencies")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -610,6 +692,8 @@ def main():
         return run_c3(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload != "c2":
+        raise SystemExit(f"bench.py: unknown workload {args.workload}")
     if args.workload == "sigma":
         return run_sigma(args)
     if args.workload == "real":
@@ -630,8 +714,11 @@ def main():
               f"{f['t_chi0_ms']:.2f}, eps {f['t_eps_ms']:.2f}) e_F={f.get('e_F_vs_fp64')}", file=sys.stderr,
               flush=True)
     K = forms[next(iter(forms))]["K"]
-    ok = [p for p in forms if p == "fp64" or "fp64" not in forms or forms[p].get("e_F_vs_fp64", 1.0) <= GATE]
-    best = min(ok, key=lambda p: forms[p]["ms_per_step"])
+    # the reported form is the split-bf16 one when it was timed and passes the gate; plain bf16
+    # (no split correction) is timed beside it but never reported
+    ok = [p for p in forms if p != "bf16" and (p == "fp64" or "fp64" not in forms
+                                               or forms[p].get("e_F_vs_fp64", 1.0) <= GATE)]
+    best = "bf16x3" if "bf16x3" in ok else min(ok, key=lambda p: forms[p]["ms_per_step"])
     fb = forms[best]
     t = fb["ms_per_step"] * 1e-3
     res = {

@@ -20,6 +20,10 @@ and serves to pin the first.
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
+
+# FFTs on every host core (the same transform as numpy's; threads only split the batch)
+FFT_WORKERS = -1
 
 
 def _lookup(mill: np.ndarray):
@@ -56,7 +60,7 @@ def orbitals_real_space(coef, mill, grid):
     ix = tuple(np.mod(mill[:, a], grid[a]) for a in range(3))
     box[:, ix[0], ix[1], ix[2]] = coef
     # numpy ifftn carries exp(+i) and 1/N_r; multiply back by N_r
-    return np.fft.ifftn(box, axes=(1, 2, 3)) * nr
+    return scipy.fft.ifftn(box, axes=(1, 2, 3), workers=FFT_WORKERS) * nr
 
 
 def rho_fft(coef_c, mill_c, coef_v, mill_v, gmill, g0, grid):
@@ -70,7 +74,7 @@ def rho_fft(coef_c, mill_c, coef_v, mill_v, gmill, g0, grid):
     for v in range(nv):
         prod = np.conj(uc) * uv[v][None]
         # (1/N_r) sum_r p(r) exp(+i(G-G0).r)
-        f = np.fft.ifftn(prod, axes=(1, 2, 3))
+        f = scipy.fft.ifftn(prod, axes=(1, 2, 3), workers=FFT_WORKERS)
         out[v] = f[:, sel[0], sel[1], sel[2]]
     return out
 

@@ -44,6 +44,33 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
   o[1] = -f * c[1];
 }
 
+// Largest squared modulus of each frequency's eps~ (before the elimination), as the bits
+// of a non-negative double (ordered like the values) in gmax2[w]; gmax2 starts at 0.
+__global__ void zero_flags(int* __restrict__ flag, unsigned long long* __restrict__ gmax2, int nw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nw) {
+    flag[i] = 0;
+    gmax2[i] = 0ull;
+  }
+}
+
+__global__ void eps_absmax(const double* __restrict__ A, int n, unsigned long long* __restrict__ gmax2) {
+  __shared__ double red[256];
+  const size_t w = blockIdx.y;
+  const size_t nn = (size_t)n * n;
+  const z* a = reinterpret_cast<const z*>(A) + w * nn;
+  double m = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x)
+    m = fmax(m, a[e].x * a[e].x + a[e].y * a[e].y);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(gmax2 + w, __double_as_longlong(red[0]));
+}
+
 // In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
 // (kb <= 64). 4096 / E threads per frequency: thread t holds row t / (64 / E),
 // columns E (t % (64 / E)) .. + E - 1 in registers (identity outside kb). Per
@@ -59,12 +86,14 @@ __global__ void build_eps(const double* __restrict__ chi0, const double* __restr
 // The pivot of column k is the row of largest modulus among the rows not yet used;
 // rows stay in place (the sweep is applied to row p_k and column k), so the result
 // R holds R[p_k][j] = B^-1[k][p_j] (B the block) and is written back with that
-// permutation undone. A pivot below 1e-13 of the block's largest entry marks the
-// block as numerically singular (flagged): the blocked elimination has no pivoting
-// across blocks, so the caller gets an error instead of an inaccurate inverse.
+// permutation undone. A pivot below 1e-13 of the largest entry of the block or of the
+// whole eps~ (gmax2: squared, per frequency) marks the block as numerically singular
+// (flagged): the blocked elimination has no pivoting across blocks, so the caller gets
+// an error instead of an inaccurate inverse.
 template <int E, bool PIV>
 __global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
-                                                            int check_sign, int* __restrict__ flag) {
+                                                            int check_sign, int* __restrict__ flag,
+                                                            const unsigned long long* __restrict__ gmax2) {
   constexpr int CG = kB / E;  // column groups
   __shared__ z pcol[2][kB];
   __shared__ z prow[2][E][CG];
@@ -90,7 +119,7 @@ __global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__
     amax = 0.0;
 #pragma unroll
     for (int i = 0; i < kB * kB / E / 64; ++i) amax = fmax(amax, wmax[i]);
-    thr2 = 1e-26 * amax;
+    thr2 = 1e-26 * fmax(amax, __longlong_as_double(gmax2[w]));
   }
   uint64_t used = 0;  // PIV: rows already pivoted (the same in every wave)
   for (int kq = 0; kq < CG; ++kq) {
@@ -325,9 +354,10 @@ __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ 
 namespace xo {
 namespace {
 // Workspace of one call: the pivot flags and, with more than one block, the saved column panel.
+size_t eps_head_bytes(int nw) { return align_up(sizeof(int) * nw, 256) + align_up(sizeof(double) * nw, 256); }
 size_t eps_ws_bytes(int n, int nw) {
   const int nblk = (n + kB - 1) / kB;
-  return align_up(sizeof(int) * nw, 256) + (nblk > 1 ? (size_t)nw * n * kB * sizeof(z) : 0);
+  return eps_head_bytes(nw) + (nblk > 1 ? (size_t)nw * n * kB * sizeof(z) : 0);
 }
 }  // namespace
 }  // namespace xo
@@ -368,8 +398,10 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   XO_RET(workspace(st, 2, eps_ws_bytes(n, a->nw), &ws));
   // pivot flags: the caller's info array (deferred check) or library workspace
   int* flag = a->info ? a->info : static_cast<int*>(ws);
-  double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + fbytes);
-  XO_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int) * a->nw, st));
+  unsigned long long* gmax2 = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + fbytes);
+  double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + eps_head_bytes(a->nw));
+  hipLaunchKernelGGL(zero_flags, dim3((a->nw + 255) / 256), dim3(256), 0, st, flag, gmax2, a->nw);
+  XO_CHECK_LAUNCH();
   const size_t nn = (size_t)n * n;
   {
     KernelTimer kt_("eps_build", st);
@@ -378,6 +410,14 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   }
   XO_CHECK_LAUNCH();
   const int check_sign = (a->flags & XO_EPS_LU_FALLBACK) ? 0 : 1;
+  if (!check_sign) {
+    {
+      KernelTimer kt_("eps_absmax", st);
+      hipLaunchKernelGGL(eps_absmax, dim3((unsigned)std::min<size_t>(256, (nn + 4095) / 4096), a->nw), dim3(256),
+                         0, st, a->out, n, gmax2);
+    }
+    XO_CHECK_LAUNCH();
+  }
   const size_t lds2 = (size_t)2 * kB * (kB + 1) * sizeof(z);
   static bool attr = false;
   if (!attr) {
@@ -391,10 +431,10 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
       KernelTimer kt_("eps_diag_inverse", st);
       if (check_sign)
         hipLaunchKernelGGL((diag_inverse<kDiagE, false>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
-                           K, kb, check_sign, flag);
+                           K, kb, check_sign, flag, gmax2);
       else
         hipLaunchKernelGGL((diag_inverse<kDiagE, true>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
-                           K, kb, check_sign, flag);
+                           K, kb, check_sign, flag, gmax2);
     }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {

@@ -287,9 +287,10 @@ def test_workspace_size_queries():
         assert 0 < small <= big
         assert xo.chi0_workspace_size([item(1000, 100, prec, check=1)]) == small + 256
         assert xo.chi0_workspace_size([item(1000, 100, prec), item(3000, 300, prec)]) > big * 0 + small
-    # epsinv: pivot flags, plus the saved column panel [nw][ng][64] complex128 past one block
-    assert xo.epsinv_workspace_size(64, 3) == 256
-    assert xo.epsinv_workspace_size(400, 8) == 256 + 8 * 400 * 64 * 16
+    # epsinv: pivot flags and scales, plus the saved column panel [nw][ng][64] complex128 past one block
+    # (the flags and the per-frequency scale of the pivot test take 256 bytes each at this nw)
+    assert xo.epsinv_workspace_size(64, 3) == 512
+    assert xo.epsinv_workspace_size(400, 8) == 512 + 8 * 400 * 64 * 16
     with pytest.raises(xo.XoError):
         xo.epsinv_workspace_size(0, 1)
 
