@@ -235,8 +235,8 @@ def roofline(cr, form, K, nw, ng, name=None, summary="c2_hbm_traffic.txt"):
     t = k["avg_launch_ms"] * 1e-3
     prec = form["prec"]
     if name.startswith("chi0_tiles") or name.startswith("chi0_blocks"):
-        # one launch of the 16x16 form covers one group of <= 8 frequencies, the block form all of them
-        fl = chi0_flops(K, ng, nw if name.startswith("chi0_blocks") else min(nw, 8))
+        # one launch covers every frequency group of the call (imaginary axis)
+        fl = chi0_flops(K, ng, nw)
         peak = MFMA_PEAK[prec]
         return dict(kernel=name, bound="mfma", achieved=fl / t / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                     frac=fl / t / peak, traffic=measured_traffic(name, summary),
@@ -268,7 +268,7 @@ def roofline(cr, form, K, nw, ng, name=None, summary="c2_hbm_traffic.txt"):
     return dict(kernel=name, bound="unknown", achieved=None, peak=None, unit=None, frac=None, traffic=None)
 
 
-def cpu_baseline_sampled(cr, nv_s=8, nc_s=64, nw_s=4, nw_eps=2):
+def cpu_baseline_sampled(cr, nv_s=16, nc_s=192, nw_s=4, nw_eps=2):
     """The FP64 oracle as it stands on the host cores, on a sample of the workload: rho of
     nv_s x nc_s transitions of the first k-pair (FFT route), chi0 of those at nw_s frequencies
     (zgemm), eps~^-1 at nw_eps frequencies. Each stage is timed and scaled linearly to the
@@ -302,6 +302,17 @@ def cpu_baseline_sampled(cr, nv_s=8, nc_s=64, nw_s=4, nw_eps=2):
                        f"scipy.fft on all cores, BLAS threads as set for the process")
 
 
+def copy_calibration():
+    """A 1 GiB device-to-device copy: the reference launch for scaling the HBM counters."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return 2 * a.numel() * 8
+
+
 def run_c5(args):
     """Headline: the large cell (32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occupied +
     2000 empty bands, 72^3 grid, NG = 3000, 16 frequencies, K = 2 048 000) in the split-bf16 form,
@@ -315,7 +326,7 @@ def run_c5(args):
     ng, nw = cr.gmill.shape[0], len(cr.omegas)
     print(f"[bench] c5 fixture ready in {t_fix:.1f} s", file=sys.stderr, flush=True)
     form = args.c5_form
-    kst = args.kernel_steps
+    kst = max(1, args.kernel_steps)
     res_form, E = run_form(cr, form, args.steps, args.warmup, kernel_steps=kst)
     print(f"[bench] c5 {form}: {res_form['ms_per_step']:.1f} ms/step (rho {res_form['t_rho_ms']:.1f}, chi0 "
           f"{res_form['t_chi0_ms']:.1f}, eps {res_form['t_eps_ms']:.1f})", file=sys.stderr, flush=True)
@@ -379,6 +390,8 @@ def run_c5(args):
     if not args.no_cpu:
         print("[bench] timing the oracle on the host cores (sampled)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline_sampled(cr)
+    if args.copy_calibration:
+        res["copy_calibration_bytes"] = copy_calibration()
     if args.detail:
         with open(args.detail, "w") as fh:
             json.dump(dict(result=res, form=res_form, fp64=r64, beside=others), fh, indent=1)

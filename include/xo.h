@@ -57,9 +57,13 @@ enum {
  *   XO_BF16X3 complex64 data, each MFMA operand split into bf16 hi + lo and
  *             three products hi*hi + hi*lo + lo*hi, FP32 accumulation;
  *   XO_BF16   complex64 data, each MFMA operand rounded to bf16 (2^-9 relative)
- *             and one product, FP32 accumulation. Its eps^-1 error depends on
- *             the number of transitions averaging the operand rounding; callers
- *             check it against an FP64 run of their workload. */
+ *             and one product, FP32 accumulation. A throughput form, not one of
+ *             the split-precision forms: it has no correction term, and its eps^-1
+ *             error is not held to the 1e-4 of the split forms (relative
+ *             Frobenius against FP64: about 4e-4 with a few hundred transitions,
+ *             2e-5 with 2e5 on the imaginary axis, 9e-4 at real frequencies near
+ *             poles). Its rho and chi0 obey element-wise rounding bounds; callers
+ *             check eps^-1 against an FP64 run of their workload. */
 enum { XO_FP64 = 0, XO_FP32 = 1, XO_BF16X3 = 2, XO_BF16 = 3 };
 
 /* Thread-local message describing the last error of this thread ("" if none). */
@@ -278,6 +282,7 @@ typedef struct {
 } xo_eps_args;
 
 int xo_epsinv(const xo_eps_args* a, void* stream);
+
 
 /* ------------------------------------------------------------------------- */
 /* Learned empty-band tail (not in the paper: it takes the place of the

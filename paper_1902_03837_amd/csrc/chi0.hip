@@ -27,6 +27,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 #include <map>
 #include <vector>
@@ -582,6 +584,277 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Panel form of the bf16 update on the 32 x 32 x 16 instruction (NP = 3 split, 1 plain).
+// A workgroup (4 waves, one per SIMD) owns a 64-row x 128-column output block and four
+// frequencies per unit; wave r owns all 64 rows and columns 32 r .. 32 r + 31 (two 32 x 32
+// tiles x 4 frequencies x re, im: 16 accumulator tiles, 256 registers). Per step of 16
+// transitions (two k-steps of 8) every thread stages in LDS, in the MFMA fragment layout:
+//   the weighted left operand W_t(w) rho_t(G) of the 64 rows for each of the 4 frequencies,
+//     split into hi and lo once per workgroup (every wave reads all of it);
+//   the right operand rho_t(G') of the 128 columns, split once, with its rotation
+//     (-im, re) for Im as separate planes.
+// The products then read only LDS. Double buffered, one barrier per step; the next
+// step's global loads are in flight during the products.
+// Lane layout of v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8 (l / 32) .. + 7]
+// and B[8 (l / 32) .. + 7][l % 32]; result register r holds
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]. K runs over (transition, re / im) pairs, so
+// the k-half l / 32 of a k-step covers transitions 4 (l / 32) .. + 3 of it.
+constexpr int kPRows = 64, kPCols = 128;  // panel block
+constexpr int kPF = 4;                    // frequencies per unit
+constexpr int kPPer = kPF * 2 * kPRows * kPCols;  // partial values per unit (256 per thread)
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mma32(u4 a, u4 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                 0);
+}
+
+template <int NP>
+struct PanelLds {
+  static constexpr int PA = NP == 3 ? 2 : 1;  // left planes: hi, lo | hi
+  static constexpr int PB = NP == 3 ? 4 : 2;  // right planes: hi, lo, rot hi, rot lo | hi, rot hi
+  u4 A[2][kPF][PA][2][2][2][32];  // [buffer][frequency][plane][k-step][row tile][k-half][row]
+  u4 B[2][PB][2][4][2][32];       // [buffer][plane][k-step][column tile][k-half][column]
+};
+
+template <int NP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+chi0_panel(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
+           const int* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
+           float* __restrict__ part) {
+  typedef PanelLds<NP> L;
+  extern __shared__ unsigned char smem_raw[];
+  L& S = *reinterpret_cast<L*>(smem_raw);
+  __shared__ int su;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // queue segments per XCD, as for chi0_blocks
+  int home = blockIdx.x & 7, misses = 0;
+  for (;;) {
+    if (tid == 0) {
+      int p = -1;
+      while (misses < 8) {
+        const int c = qoff[home] + atomicAdd(&counters[home], 1);
+        if (c < qoff[home + 1]) {
+          p = c;
+          misses = 0;
+          break;
+        }
+        home = (home + 1) & 7;
+        ++misses;
+      }
+      su = p;
+    }
+    __syncthreads();
+    const int qpos = __builtin_amdgcn_readfirstlane(su);
+    __syncthreads();
+    if (qpos < 0) break;
+    const int uid = queue[qpos];
+    const Unit U = units[uid];
+    const Item I = items[U.item];
+    const int2 bij = tiles[I.tile0 + U.tile];
+    const int ng = I.ng, len = U.k1 - U.k0;
+    const int nsteps = (len + 15) / 16;
+    // Buffer loads over the unit's transition slice (the host keeps len * ng * 8 below 2^31):
+    // rows past the slice are outside the buffer and read as zero (so do their weights); G
+    // past the G-set reads G = ng - 1 and lands in outputs the reduction drops. The
+    // per-thread part of an address is one VGPR offset; the step and the transition within
+    // a quad go into the scalar offset.
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v)), 0,
+        (unsigned)len * ng * (unsigned)sizeof(f2v), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(static_cast<const float*>(I.W) + (size_t)U.k0 * I.nwpad + U.w0), 0,
+        (unsigned)len * I.nwpad * (unsigned)sizeof(float), 0x00020000);
+    const unsigned trow = (unsigned)ng * sizeof(f2v), wrow = (unsigned)I.nwpad * sizeof(float);
+    // left slot of this thread: row ar, transitions 4 aq .. + 3 of the step (k-step aq / 2,
+    // k-half aq % 2); right slot: column bc, transitions 8 bs .. + 7 (k-step bs)
+    const int ar = tid & 63, aq = tid >> 6;
+    const int bc = tid & 127, bs = tid >> 7;
+    const unsigned Ga = min(bij.x * kPRows + ar, ng - 1), Gb = min(bij.y * kPCols + bc, ng - 1);
+    const unsigned va = Ga * (unsigned)sizeof(f2v) + 4u * aq * trow;
+    const unsigned vb = Gb * (unsigned)sizeof(f2v) + 8u * bs * trow;
+    const unsigned vw = 4u * aq * wrow;
+
+    f2v ra[4], rb[8];
+    float4 wq[4];
+    auto load = [&](int st) {
+      const unsigned d = (unsigned)st * 16u * trow, dw = (unsigned)st * 16u * wrow;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ra[u] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rr, va, d + u * trow, 0));
+        wq[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rw, vw, dw + u * wrow, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        rb[u] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rr, vb, d + u * trow, 0));
+    };
+    // stage the loaded step into buffer b
+    auto store = [&](int b) {
+#pragma unroll
+      for (int f = 0; f < kPF; ++f) {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float w = f == 0 ? wq[u].x : (f == 1 ? wq[u].y : (f == 2 ? wq[u].z : wq[u].w));
+          split2(w * ra[u].x, w * ra[u].y, hi[u], lo[u]);
+        }
+        S.A[b][f][0][aq >> 1][ar >> 5][aq & 1][ar & 31] = u4{hi[0], hi[1], hi[2], hi[3]};
+        if constexpr (NP == 3) S.A[b][f][1][aq >> 1][ar >> 5][aq & 1][ar & 31] = u4{lo[0], lo[1], lo[2], lo[3]};
+      }
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) split2(rb[4 * hh + u].x, rb[4 * hh + u].y, hi[u], lo[u]);
+        S.B[b][0][bs][bc >> 5][hh][bc & 31] = u4{hi[0], hi[1], hi[2], hi[3]};
+        if constexpr (NP == 3) {
+          S.B[b][1][bs][bc >> 5][hh][bc & 31] = u4{lo[0], lo[1], lo[2], lo[3]};
+          S.B[b][2][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(hi[0]), rot_neg(hi[1]), rot_neg(hi[2]), rot_neg(hi[3])};
+          S.B[b][3][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(lo[0]), rot_neg(lo[1]), rot_neg(lo[2]), rot_neg(lo[3])};
+        } else {
+          S.B[b][1][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(hi[0]), rot_neg(hi[1]), rot_neg(hi[2]), rot_neg(hi[3])};
+        }
+      }
+    };
+    f16v acc[kPF][2][2];  // [frequency][re, im][row tile]
+#pragma unroll
+    for (int f = 0; f < kPF; ++f)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          acc[f][r][t] = f16v{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    load(0);
+    store(0);
+    if (nsteps > 1) load(1);
+    __syncthreads();
+    // products of the step in buffer b: per k-step all fragments of the step are read, then
+    // the products go in rounds (hi x hi, hi x lo, lo x hi) over all 16 accumulator tiles, so
+    // that consecutive products into one tile are 16 instructions apart
+    auto products = [&](int b) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        u4 bf[L::PB];
+#pragma unroll
+        for (int p = 0; p < L::PB; ++p) bf[p] = S.B[b][p][s][wave][h][li];
+        u4 a[kPF][L::PA][2];
+#pragma unroll
+        for (int f = 0; f < kPF; ++f)
+#pragma unroll
+          for (int p = 0; p < L::PA; ++p)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) a[f][p][rt] = S.A[b][f][p][s][rt][h][li];
+        // Re through the right operand, Im through its rotation (plane PB / 2 onwards)
+        constexpr int ROT = L::PB / 2;
+#pragma unroll
+        for (int f = 0; f < kPF; ++f)
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            acc[f][0][rt] = mma32(a[f][0][rt], bf[0], acc[f][0][rt]);
+            acc[f][1][rt] = mma32(a[f][0][rt], bf[ROT], acc[f][1][rt]);
+          }
+        if constexpr (NP == 3) {
+#pragma unroll
+          for (int f = 0; f < kPF; ++f)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+              acc[f][0][rt] = mma32(a[f][0][rt], bf[1], acc[f][0][rt]);
+              acc[f][1][rt] = mma32(a[f][0][rt], bf[ROT + 1], acc[f][1][rt]);
+            }
+#pragma unroll
+          for (int f = 0; f < kPF; ++f)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+              acc[f][0][rt] = mma32(a[f][1][rt], bf[0], acc[f][0][rt]);
+              acc[f][1][rt] = mma32(a[f][1][rt], bf[ROT], acc[f][1][rt]);
+            }
+        }
+      }
+    };
+    for (int k = 0; k < nsteps; ++k) {
+      const int b = k & 1;
+      // every wave computes both row tiles: a tile wholly below the diagonal or past the
+      // G-set (only in blocks on the diagonal or at the edge) is computed and dropped by the
+      // reduction, which keeps the accumulators in one straight-line instruction stream
+      products(b);
+      if (k + 1 < nsteps) store(b ^ 1);
+      if (k + 2 < nsteps) load(k + 2);
+      __syncthreads();
+    }
+    // partials of this thread, contiguous: [frequency][re, im][row tile] x 16 registers
+    f16v* out = reinterpret_cast<f16v*>(part + ((size_t)uid * 256 + tid) * (kPF * 2 * 2 * 16));
+#pragma unroll
+    for (int f = 0; f < kPF; ++f)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) out[(f * 2 + r) * 2 + t] = acc[f][r][t];
+  }
+}
+
+// Fixed-order sum of the panel partials of one output block and frequency. Thread t reads
+// what thread t of chi0_panel wrote: rows 32 rt + 8 (e / 4) + 4 ((t % 64) / 32) + e % 4,
+// column 32 (t / 64) + t % 32.
+__global__ void __launch_bounds__(256) chi0_reduce_panel(const Item* __restrict__ items,
+                                                         const int2* __restrict__ tiles,
+                                                         const Red* __restrict__ reds,
+                                                         const float* __restrict__ part) {
+  const Red R = reds[blockIdx.x];
+  const int w = blockIdx.y;
+  const Item I = items[R.item];
+  if (R.w0 + w >= I.nw) return;
+  const int2 bij = tiles[I.tile0 + R.tile];
+  const int t = threadIdx.x, li = t & 31, h = (t >> 5) & 1, wave = t >> 6;
+  double re[2][16], im[2][16];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) re[rt][e] = im[rt][e] = 0.0;
+  for (int u = 0; u < R.nu; ++u) {
+    const f16v* p =
+        reinterpret_cast<const f16v*>(part + ((size_t)(R.u0 + u) * 256 + t) * (kPF * 2 * 2 * 16)) + w * 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const f16v a = p[rt], b = p[2 + rt];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        re[rt][e] += (double)a[e];
+        im[rt][e] += (double)b[e];
+      }
+    }
+  }
+  double* m = I.chi0 + (size_t)(R.w0 + w) * I.ng * I.ng * 2;
+  const int Gp = bij.y * kPCols + 32 * wave + li;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int G = bij.x * kPRows + 32 * rt + 8 * (e >> 2) + 4 * h + (e & 3);
+      if (G >= I.ng || Gp >= I.ng || G > Gp) continue;
+      const double vr = -I.pref * re[rt][e];
+      const double vi = G == Gp ? 0.0 : -I.pref * im[rt][e];
+      const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
+      if (I.accumulate) {
+        m[up] += vr;
+        m[up + 1] += vi;
+        if (G != Gp) {
+          m[lo] += vr;
+          m[lo + 1] -= vi;
+        }
+      } else {
+        m[up] = vr;
+        m[up + 1] = vi;
+        if (G != Gp) {
+          m[lo] = vr;
+          m[lo + 1] = -vi;
+        }
+      }
+    }
+}
+
 // Fixed-order sum of the block partials of one output block and frequency. Thread
 // t reads what thread t of the block kernel wrote: rows 16 (t / 64) + 4 q + e,
 // columns 16 n + i, with i = t % 16, q = (t % 64) / 16.
@@ -640,6 +913,14 @@ __global__ void __launch_bounds__(256) chi0_reduce_blocks(const Item* __restrict
 }
 
 // --------------------------------------------------------------- host side --
+
+// Default block form of the bf16 updates: the 64 x 64 blocks (4) unless XO_CHI0_FORM=panel
+// (the 64 x 128 panel, 8).
+int default_block_form() {
+  const char* e = std::getenv("XO_CHI0_FORM");
+  if (e && !std::strcmp(e, "panel")) return 8;
+  return 4;
+}
 
 int num_cus() {
   static int n = 0;
@@ -734,14 +1015,18 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : (prec == XO_BF16 ? MODE_BF16 : MODE_BF16X3));
   const size_t tsz = mode == MODE_F64 ? sizeof(double) : sizeof(float);
   const int nw = a[0].nw;
-  // bf16 default: the 64 x 64 block form once there are four frequencies to share it
-  const bool blk = is_bf(mode) && ((tune && tune->nt_tiles) ? tune->nt_tiles == 4 : nw >= kBW);
+  // bf16 forms: the 64 x 64 block form (nt_tiles 4) or the 64 x 128 panel form (nt_tiles 8)
+  // once there are four frequencies to share them; XO_CHI0_FORM=blocks|panel picks the
+  // default between the two
+  const int pick = (tune && tune->nt_tiles) ? tune->nt_tiles : (nw >= kBW ? default_block_form() : 1);
+  const bool blk = is_bf(mode) && (pick == 4 || pick == 8);
+  const bool pnl = blk && pick == 8;
   const int nwg = blk ? kBW : (nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1)));
   const int ngroups = (nw + nwg - 1) / nwg;
   const int nwpad = ngroups * nwg;
   const int NT = (tune && is_bf(mode) && tune->nt_tiles == 2) ? 2 : 1;
-  const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4);
-  const int brow = blk ? kBlk : kTile, bcol = blk ? kBlk : kTile * NT;
+  const int grid_per_cu = pnl ? 1 : ((tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4));
+  const int brow = pnl ? kPRows : (blk ? kBlk : kTile), bcol = pnl ? kPCols : (blk ? kBlk : kTile * NT);
 
   // block pairs: brow-row block i, bcol-column block j, keeping those with a column >= a row
   std::vector<int2> tiles;
@@ -803,6 +1088,14 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     const int2 b = tiles[items[u.item].tile0 + u.tile];
     const int ng = a[u.item].ng;
     int c = 0;
+    if (pnl) {  // 32 x 32 tiles, each worth four 16 x 16 ones
+      for (int w = 0; w < 4; ++w)
+        for (int rt = 0; rt < 2; ++rt) {
+          const int r0 = b.x * kPRows + 32 * rt, c0 = b.y * kPCols + 32 * w;
+          c += 4 * (r0 < ng && c0 < ng && c0 + 31 >= r0);
+        }
+      return c;
+    }
     for (int r = 0; r < 4; ++r)
       for (int m = 0; m < 4; ++m)
         c += b.x * kBlk + 16 * r < ng && b.y * kBlk + 16 * m < ng && (b.x != b.y || m >= r);
@@ -843,7 +1136,8 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     qoff[8] = (int)queue.size();
   }
   const int nunits = (int)units.size();
-  const size_t per = blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz;
+  const size_t per = pnl ? (size_t)kPPer * sizeof(float)
+                         : (blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz);
   const size_t pbytes = per * nunits;
   bool any_check = false;
   for (int it = 0; it < n; ++it) any_check |= a[it].check_dE != 0;
@@ -925,6 +1219,33 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     XO_RET(device_table(qoff, sizeof(qoff), s, &dqoff));
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 8);
     XO_CHECK_LAUNCH();
+    if (pnl) {
+      const size_t lds = mode == MODE_BF16 ? sizeof(PanelLds<1>) : sizeof(PanelLds<3>);
+      static bool attr = false;
+      if (!attr) {
+        XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&chi0_panel<1>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(PanelLds<1>)));
+        XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&chi0_panel<3>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(PanelLds<3>)));
+        attr = true;
+      }
+      {
+        KernelTimer kt_(mode == MODE_BF16 ? "chi0_panel_bf16" : "chi0_panel_bf16x3", s);
+        hipLaunchKernelGGL(mode == MODE_BF16 ? chi0_panel<1> : chi0_panel<3>, dim3(grid), dim3(256), lds, s,
+                           static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
+                           static_cast<const Unit*>(dunits), static_cast<const int*>(dqueue),
+                           static_cast<const int*>(dqoff), counter, static_cast<float*>(part));
+      }
+      XO_CHECK_LAUNCH();
+      {
+        KernelTimer kt_("chi0_reduce", s);
+        hipLaunchKernelGGL(chi0_reduce_panel, dim3(nreds, kPF), dim3(256), 0, s, static_cast<const Item*>(ditems),
+                           static_cast<const int2*>(dtiles), static_cast<const Red*>(dreds),
+                           static_cast<const float*>(part));
+      }
+      XO_CHECK_LAUNCH();
+      return XO_OK;
+    }
     if (mode == MODE_BF16) {
       KernelTimer kt_("chi0_blocks_bf16", s);
       hipLaunchKernelGGL(chi0_blocks<1>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
@@ -1024,10 +1345,11 @@ extern "C" int xo_chi0_real(const xo_chi0_real_args* a, void* stream) {
 
 static int check_tune(const xo_chi0_args* items, const xo_tune* tune) {
   if (tune) {
-    XO_ARG(tune->nt_tiles == 0 || tune->nt_tiles == 1 || tune->nt_tiles == 2 || tune->nt_tiles == 4,
-           "xo_chi0_batch: nt_tiles must be 0, 1, 2 or 4");
-    XO_ARG(tune->nt_tiles != 4 || items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16,
-           "xo_chi0_batch: nt_tiles 4 is the bf16 block form (XO_BF16X3, XO_BF16)");
+    XO_ARG(tune->nt_tiles == 0 || tune->nt_tiles == 1 || tune->nt_tiles == 2 || tune->nt_tiles == 4 ||
+               tune->nt_tiles == 8,
+           "xo_chi0_batch: nt_tiles must be 0, 1, 2, 4 or 8");
+    XO_ARG(tune->nt_tiles < 4 || items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16,
+           "xo_chi0_batch: nt_tiles 4 and 8 are the bf16 block forms (XO_BF16X3, XO_BF16)");
     XO_ARG(tune->kper >= 0 && tune->wg_per_cu >= 0 && tune->wg_per_cu <= 16, "xo_chi0_batch: bad tune values");
   }
   return XO_OK;
@@ -1057,14 +1379,15 @@ extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best,
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<xo_tune> cands;
   std::vector<int> nts = {1};
-  if (items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16) nts = {1, 2, 4};
+  if (items[0].prec == XO_BF16X3 || items[0].prec == XO_BF16) nts = {1, 2, 4, 8};
   int ntmax = 0;
   for (int i = 0; i < n; ++i) ntmax = std::max(ntmax, items[i].nt);
   for (int nt : nts)
     for (int kper : {0, 2048, 8192, 32768})
       for (int wpc : {1, 2, 4, 8}) {
         if (kper > 0 && kper / 2 > ntmax) continue;
-        if ((wpc == 1) != (nt == 4) && wpc < 2) continue;  // one workgroup per CU only for the block form
+        if ((wpc == 1) != (nt >= 4) && wpc < 2) continue;  // one workgroup per CU only for the block forms
+        if (nt == 8 && wpc != 1) continue;                  // the panel form runs one per CU
         cands.push_back({nt, kper, wpc});
       }
   hipEvent_t e0, e1;

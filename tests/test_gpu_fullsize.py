@@ -156,3 +156,38 @@ def test_c5_small_real_gset(c5s, prec, rtol_rho, rtol_chi):
         e_f = max(np.linalg.norm(Er[j] - E64[j]) / np.linalg.norm(E64[j]) for j in range(len(cr.omegas)))
         say(f"  eps~^-1 {prec} vs fp64: {e_f:.2e}")
         assert e_f < 1e-4
+
+
+# --------------------------------------------------------------------------------------
+# Every form's eps~^-1 at full size against the oracle's (c2: all 64 k-pairs, 204 800
+# transitions, NG = 400, 8 frequencies; the oracle's FFT route, zgemm and LU on the host
+# cores, about half a minute). The chosen forms (FP32, split bf16) are held to the 1e-4 target
+# of the relative Frobenius error at every frequency, plain FP64 to 1e-6 (it reaches ~1e-14).
+# Plain bf16 is not a chosen form (no split correction; its element-wise rounding bounds are
+# asserted above): its error here is reported and held to the bound measured for this
+# workload, 5e-5.
+
+@pytest.fixture(scope="module")
+def c2_oracle_eps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    xo.lib()
+    from oracle.pipeline import epsinv_crystal
+    cr = crystal_for("c2")
+    say("oracle eps~^-1 of c2 at full size (host cores)")
+    E, _ = epsinv_crystal(cr)
+    return cr, E
+
+
+@pytest.mark.parametrize("prec,gate", [("fp64", 1e-6), ("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16", 5e-5)])
+def test_c2_eps_every_form_vs_oracle(c2_oracle_eps, prec, gate):
+    cr, Eref = c2_oracle_eps
+    dc = DeviceCrystal.upload(cr, prec)
+    _, _, _, E = run_crystal(dc, check_dE=False)
+    torch.cuda.synchronize()
+    Eg = E.cpu().numpy()
+    e_f = max(np.linalg.norm(Eg[j] - Eref[j]) / np.linalg.norm(Eref[j]) for j in range(len(cr.omegas)))
+    say(f"  c2 full size {prec}: e_F(eps~^-1) vs oracle {e_f:.2e}")
+    assert e_f <= gate
+    if prec == "fp64":
+        assert e_f < 1e-11

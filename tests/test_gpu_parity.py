@@ -251,12 +251,15 @@ def test_chi0_reduced_precision_random(prec, tol, nt, ng, nw):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 @pytest.mark.parametrize("nt,ng,nw,tune", [(1, 1, 1, None), (1, 1, 1, (4, 0, 0)), (33, 17, 1, (4, 0, 0)),
-                                           (700, 65, 3, (4, 256, 1)), (130, 129, 6, None)])
+                                           (700, 65, 3, (4, 256, 1)), (130, 129, 6, None),
+                                           (1, 1, 1, (8, 0, 0)), (33, 17, 1, (8, 0, 0)), (700, 65, 3, (8, 256, 1)),
+                                           (130, 129, 6, (8, 0, 0)), (517, 200, 5, (8, 64, 1)),
+                                           (300, 129, 4, (4, 0, 0))])
 def test_chi0_bf16_edges(prec, nt, ng, nw, tune):
     """Degenerate and ragged shapes of the bf16 forms: one transition, one G-vector, one
-    frequency in the 64 x 64 block form (three padded frequency slots), G-sets one past a
-    block edge, transition slices shorter than a step; within the bf16 rounding bound
-    (plain) or 2e-4 (split), exactly Hermitian."""
+    frequency in the 64 x 64 block form and the 64 x 128 panel form (three padded frequency
+    slots), G-sets one past a block edge, transition slices shorter than a step; within the
+    bf16 rounding bound (plain) or 2e-4 (split), exactly Hermitian."""
     say(f"chi0 {prec} edge nt={nt} ng={ng} nw={nw} tune={tune}")
     M = random_complex(300 + nt, (nt, ng)).astype(np.complex64).astype(np.complex128)
     dE = random_positive(400 + nt, nt, 0.05, 3.0)
@@ -424,8 +427,10 @@ def test_epsinv_lu_fallback_reports_singular_block():
 
 # ---------------------------------------------------------------------- end to end
 
-# plain bf16 at these small transition counts: the operand rounding (2^-8) is averaged
-# over few transitions, about 3e-4 on eps~^-1 (the 1e-4 gate applies to the full workload)
+# FP64 against the 1e-6 target, the split forms (FP32, bf16x3) against the 1e-4 target.
+# Plain bf16 is not a split form (no correction): its element-wise rounding bounds are
+# asserted by the chi0 and rho tests; here its measured eps~^-1 error on this small workload
+# (a few hundred transitions average its 2^-9 operand rounding, about 3e-4) is held to 1e-3.
 @pytest.mark.parametrize("name,prec,gate", [("c1", "fp64", 1e-6), ("c2_small", "fp64", 1e-6),
                                             ("c1", "fp32", 1e-4), ("c2_small", "fp32", 1e-4),
                                             ("c2_small", "bf16x3", 1e-4), ("c2_small", "bf16", 1e-3)])
@@ -473,11 +478,12 @@ def test_alloc_failure_is_reported_and_recovers():
 # ------------------------------------------------------------- batched persistent
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("bf16x3", 2e-4), ("bf16", None)])
-@pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8), (4, 256, 1), (4, 0, 0)])
+@pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8), (4, 256, 1), (4, 0, 0), (8, 0, 0),
+                                  (8, 256, 1)])
 def test_chi0_batch_uneven_items(prec, tol, tune):
     """Items with different G-set sizes and transition counts in one persistent launch."""
-    if prec == "fp64" and tune is not None and tune[0] in (2, 4):
-        pytest.skip("two column tiles per wave and the 64 x 64 block form exist for the bf16 forms only")
+    if prec == "fp64" and tune is not None and tune[0] in (2, 4, 8):
+        pytest.skip("two column tiles per wave and the block and panel forms exist for the bf16 forms only")
     say(f"chi0 batch {prec} tune={tune}")
     shapes = [(700, 17), (1300, 33), (96, 50), (2000, 41)]
     w = [0.0, 0.3, 1.0]

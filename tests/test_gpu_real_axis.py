@@ -127,4 +127,6 @@ def test_real_axis_chain_c1_small():
         else:
             eF = max(np.linalg.norm(Es[prec][j] - Es["fp64"][j]) / np.linalg.norm(Es["fp64"][j]) for j in range(len(ws)))
             say(f"  e_F vs fp64 {eF:.2e}")
+            # split bf16 against the 1e-4 target; plain bf16 (not a split form, no correction)
+            # against its measured error near the poles on this small chain, about 1.5e-3
             assert eF < (1e-4 if prec == "bf16x3" else 2e-3)
