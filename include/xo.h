@@ -283,6 +283,22 @@ typedef struct {
 
 int xo_epsinv(const xo_eps_args* a, void* stream);
 
+/* xo_epsinv for callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same arguments,
+ * results and errors as xo_epsinv, but the call allocates nothing (no hipMalloc,
+ * no host or device workspace, no table cache). Its flags, scales, |q+G| copy and
+ * saved column panel live in a static device array of 64 MiB that every GPU the
+ * library runs on holds until the process ends; (align_up(4 nw, 256) +
+ * align_up(8 nw, 256) + align_up(8 ng, 256) + 1024 nw ng bytes when ng > 64) must
+ * fit in it, and without info nw <= 1024 (the flags are read back into a fixed host
+ * array); larger calls return XO_ERR_UNSUPPORTED before anything is enqueued.
+ * Every call on a GPU shares that GPU's array and leaves its contents behind (the
+ * flags and scales are cleared by each call): calls that overlap on one GPU, on any
+ * streams, race and must be ordered by the caller. |q+G| is copied from the host
+ * array with hipMemcpyAsync, and without info the call synchronises the stream as
+ * xo_epsinv does. */
+int xo_epsinv_noalloc(const xo_eps_args* a, void* stream);
+
 
 /* ------------------------------------------------------------------------- */
 /* Learned empty-band tail (not in the paper: it takes the place of the

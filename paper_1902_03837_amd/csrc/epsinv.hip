@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "xo_common.h"
@@ -30,14 +31,17 @@ constexpr int kB = 64;  // block width
 
 typedef cplx<double> z;
 
-__global__ void build_eps(const double* __restrict__ chi0, const double* __restrict__ s, int n,
+// s_G = sqrt(4 pi) / |q+G| (Coulomb interaction subsection)
+__device__ __forceinline__ double coulomb_s(const double* qpg, int i) { return 3.5449077018110318 / qpg[i]; }
+
+__global__ void build_eps(const double* __restrict__ chi0, const double* __restrict__ qpg, int n,
                           double* __restrict__ A) {
   const size_t w = blockIdx.y;
   const size_t nn = (size_t)n * n;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const int i = (int)(e / n), j = (int)(e - (e / n) * n);
-  const double f = s[i] * s[j];
+  const double f = coulomb_s(qpg, i) * coulomb_s(qpg, j);
   const double* c = chi0 + (w * nn + e) * 2;
   double* o = A + (w * nn + e) * 2;
   o[0] = (i == j ? 1.0 : 0.0) - f * c[0];
@@ -336,13 +340,13 @@ __global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, in
     }
 }
 
-__global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ s, int n) {
+__global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ qpg, int n) {
   const size_t w = blockIdx.y;
   const size_t nn = (size_t)n * n;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const int i = (int)(e / n), j = (int)(e - (e / n) * n);
-  const double f = s[i] / s[j];
+  const double f = coulomb_s(qpg, i) / coulomb_s(qpg, j);
   double* o = A + (w * nn + e) * 2;
   o[0] *= f;
   o[1] *= f;
@@ -371,42 +375,98 @@ extern "C" int xo_epsinv_workspace_size(const xo_eps_args* a, size_t* bytes) {
   return XO_OK;
 }
 
-extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
-  using namespace xo;
-  clear_error();
-  XO_ARG(a, "xo_epsinv: null argument block");
-  XO_ARG(a->ng > 0 && a->nw > 0, "xo_epsinv: sizes must be positive (ng=%d nw=%d)", a->ng, a->nw);
-  XO_ARG(a->qpg && a->chi0 && a->out, "xo_epsinv: null pointer");
-  XO_ARG((a->flags & ~(XO_EPS_NONSYM | XO_EPS_LU_FALLBACK)) == 0, "xo_epsinv: unknown flags 0x%x", a->flags);
-  XO_ARG(a->chi0 != a->out, "xo_epsinv: chi0 and out must not alias");
+namespace xo {
+namespace {
+
+// Static scratch of the no-allocation entry point (xo_epsinv_noalloc): the pivot flags,
+// the per-frequency scales, |q+G| and the saved column panel. Each device holds its own
+// copy for the life of the process; host code uses only the device address obtained from
+// hipGetSymbolAddress, kept per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+int scratch_address(void** out) {
+  int dev = 0;
+  XO_TRY_HIP(hipGetDevice(&dev));
+  XO_ARG(dev >= 0 && dev < kMaxDevices, "xo_epsinv_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("xo_epsinv_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return XO_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return XO_OK;
+}
+
+size_t noalloc_bytes(int n, int nw) { return eps_ws_bytes(n, nw) + align_up(sizeof(double) * n, 256); }
+constexpr int kNoallocHostFlags = 1024;  // frequencies whose flags the no-allocation call reads back
+
+// noalloc = false: workspace and |q+G| table from the library caches (may allocate);
+// noalloc = true: everything in the static scratch, no allocation of any kind.
+int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
+  const char* who = noalloc ? "xo_epsinv_noalloc" : "xo_epsinv";
+  XO_ARG(a, "%s: null argument block", who);
+  XO_ARG(a->ng > 0 && a->nw > 0, "%s: sizes must be positive (ng=%d nw=%d)", who, a->ng, a->nw);
+  XO_ARG(a->qpg && a->chi0 && a->out, "%s: null pointer", who);
+  XO_ARG((a->flags & ~(XO_EPS_NONSYM | XO_EPS_LU_FALLBACK)) == 0, "%s: unknown flags 0x%x", who, a->flags);
+  XO_ARG(a->chi0 != a->out, "%s: chi0 and out must not alias", who);
   if (a->ng > 16384 || (size_t)a->ng * a->ng * a->nw > ((size_t)1 << 31)) {
-    set_error("xo_epsinv: ng=%d x nw=%d is beyond the supported size", a->ng, a->nw);
+    set_error("%s: ng=%d x nw=%d is beyond the supported size", who, a->ng, a->nw);
     return XO_ERR_UNSUPPORTED;
   }
   const int n = a->ng;
-  std::vector<double> s(n);
-  for (int i = 0; i < n; ++i) {
-    XO_ARG(a->qpg[i] > 0.0 && std::isfinite(a->qpg[i]), "xo_epsinv: |q+G| at %d must be positive", i);
-    s[i] = std::sqrt(4.0 * M_PI) / a->qpg[i];
+  for (int i = 0; i < n; ++i)
+    XO_ARG(a->qpg[i] > 0.0 && std::isfinite(a->qpg[i]), "%s: |q+G| at %d must be positive", who, i);
+  if (noalloc) {
+    if (noalloc_bytes(n, a->nw) > kScratchBytes) {
+      set_error("%s: ng=%d x nw=%d needs %zu bytes of scratch, more than its %zu", who, a->ng, a->nw,
+                noalloc_bytes(n, a->nw), kScratchBytes);
+      return XO_ERR_UNSUPPORTED;
+    }
+    if (!a->info && a->nw > kNoallocHostFlags) {
+      set_error("%s: more than %d frequencies need a device info array", who, kNoallocHostFlags);
+      return XO_ERR_UNSUPPORTED;
+    }
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const void* ds = nullptr;
-  XO_RET(device_table(s.data(), sizeof(double) * n, st, &ds));
   const int nblk = (n + kB - 1) / kB;
-  void* ws = nullptr;
   const size_t fbytes = align_up(sizeof(int) * a->nw, 256);
-  XO_RET(workspace(st, 2, eps_ws_bytes(n, a->nw), &ws));
-  // pivot flags: the caller's info array (deferred check) or library workspace
-  int* flag = a->info ? a->info : static_cast<int*>(ws);
-  unsigned long long* gmax2 = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + fbytes);
-  double* S = reinterpret_cast<double*>(static_cast<char*>(ws) + eps_head_bytes(a->nw));
+  char* ws = nullptr;
+  const double* dq = nullptr;
+  if (noalloc) {
+    void* base = nullptr;
+    XO_RET(scratch_address(&base));
+    ws = static_cast<char*>(base);
+    double* q = reinterpret_cast<double*>(ws + eps_ws_bytes(n, a->nw));
+    XO_TRY_HIP(hipMemcpyAsync(q, a->qpg, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    dq = q;
+  } else {
+    const void* t = nullptr;
+    XO_RET(device_table(a->qpg, sizeof(double) * n, st, &t));
+    dq = static_cast<const double*>(t);
+    void* w = nullptr;
+    XO_RET(workspace(st, 2, eps_ws_bytes(n, a->nw), &w));
+    ws = static_cast<char*>(w);
+  }
+  // pivot flags: the caller's info array (deferred check) or the call's own
+  int* flag = a->info ? a->info : reinterpret_cast<int*>(ws);
+  unsigned long long* gmax2 = reinterpret_cast<unsigned long long*>(ws + fbytes);
+  double* S = reinterpret_cast<double*>(ws + eps_head_bytes(a->nw));
   hipLaunchKernelGGL(zero_flags, dim3((a->nw + 255) / 256), dim3(256), 0, st, flag, gmax2, a->nw);
   XO_CHECK_LAUNCH();
   const size_t nn = (size_t)n * n;
   {
     KernelTimer kt_("eps_build", st);
-    hipLaunchKernelGGL(build_eps, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->chi0,
-                       static_cast<const double*>(ds), n, a->out);
+    hipLaunchKernelGGL(build_eps, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->chi0, dq, n,
+                       a->out);
   }
   XO_CHECK_LAUNCH();
   const int check_sign = (a->flags & XO_EPS_LU_FALLBACK) ? 0 : 1;
@@ -455,26 +515,39 @@ extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
   if (a->flags & XO_EPS_NONSYM) {
     {
       KernelTimer kt_("eps_unsymmetrise", st);
-      hipLaunchKernelGGL(unsymmetrise, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->out,
-                         static_cast<const double*>(ds), n);
+      hipLaunchKernelGGL(unsymmetrise, dim3((unsigned)((nn + 255) / 256), a->nw), dim3(256), 0, st, a->out, dq, n);
     }
     XO_CHECK_LAUNCH();
   }
   if (a->info) return XO_OK;  // the caller reads the flags when it needs them
-  int* hf = nullptr;
-  XO_RET(host_flags(st, sizeof(int) * a->nw, reinterpret_cast<void**>(&hf)));
+  int local[kNoallocHostFlags];
+  int* hf = local;
+  if (!noalloc) XO_RET(host_flags(st, sizeof(int) * a->nw, reinterpret_cast<void**>(&hf)));
   XO_TRY_HIP(hipMemcpyAsync(hf, flag, sizeof(int) * a->nw, hipMemcpyDeviceToHost, st));
   XO_TRY_HIP(hipStreamSynchronize(st));
   for (int w = 0; w < a->nw; ++w) {
     if (hf[w]) {
       if (check_sign) {
-        set_error("xo_epsinv: eps~ is not positive definite at frequency %d (pivot %d)", w, hf[w] - 1);
+        set_error("%s: eps~ is not positive definite at frequency %d (pivot %d)", who, w, hf[w] - 1);
         return XO_ERR_NOTPD;
       }
-      set_error("xo_epsinv: a diagonal block of the elimination is numerically singular at frequency %d "
-                "(pivot %d)", w, hf[w] - 1);
+      set_error("%s: a diagonal block of the elimination is numerically singular at frequency %d (pivot %d)",
+                who, w, hf[w] - 1);
       return XO_ERR_SINGULAR;
     }
   }
   return XO_OK;
+}
+
+}  // namespace
+}  // namespace xo
+
+extern "C" int xo_epsinv(const xo_eps_args* a, void* stream) {
+  xo::clear_error();
+  return xo::epsinv_run(a, static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" int xo_epsinv_noalloc(const xo_eps_args* a, void* stream) {
+  xo::clear_error();
+  return xo::epsinv_run(a, static_cast<hipStream_t>(stream), true);
 }

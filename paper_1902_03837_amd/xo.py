@@ -106,7 +106,7 @@ EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_ena
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
            "xo_xterm", "xo_ppa_fit", "xo_sigma", "xo_chi0_real", "xo_rho_workspace_size",
-           "xo_chi0_workspace_size", "xo_epsinv_workspace_size")
+           "xo_chi0_workspace_size", "xo_epsinv_workspace_size", "xo_epsinv_noalloc")
 
 
 def lib():
@@ -353,11 +353,12 @@ def chi0_autotune(items, omegas, *, prec="fp64", stream=None):
     return (t.nt_tiles, t.kper, t.wg_per_cu), ms.value
 
 
-def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, info=None, stream=None):
+def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, info=None, stream=None, noalloc=False):
     """xo_epsinv: out = eps~^-1 (or (I - v chi0)^-1 with XO_EPS_NONSYM), complex128.
 
     info: optional int32 device tensor [nw]; when given the call does not synchronise and
-    the pivot flags land there (0: frequency passed, else 1 + its first failing pivot)."""
+    the pivot flags land there (0: frequency passed, else 1 + its first failing pivot).
+    noalloc: call xo_epsinv_noalloc (static scratch, no allocation) instead."""
     import torch
     q = np.ascontiguousarray(np.asarray(qpg, dtype=np.float64))
     assert chi0_m.ndim == 3 and chi0_m.shape[1] == chi0_m.shape[2] == q.shape[0]
@@ -369,7 +370,8 @@ def epsinv(chi0_m, qpg, *, out, flags=XO_EPS_SYM, info=None, stream=None):
     if info is not None:
         assert info.dtype == torch.int32 and info.numel() == a.nw and info.is_contiguous()
         a.info = _ptr(info)
-    _check(lib().xo_epsinv(C.byref(a), _stream(stream)))
+    fn = lib().xo_epsinv_noalloc if noalloc else lib().xo_epsinv
+    _check(fn(C.byref(a), _stream(stream)))
     return out
 
 
