@@ -56,7 +56,7 @@ enum {
  *   XO_FP32   FP32 MFMA / VALU (complex64);
  *   XO_BF16X3 complex64 data, each MFMA operand split into bf16 hi + lo and
  *             three products hi*hi + hi*lo + lo*hi, FP32 accumulation;
- *   XO_BF16   complex64 data, each MFMA operand rounded to bf16 (2^-9 relative)
+ *   XO_BF16   complex64 data, each MFMA operand rounded to bf16 (at most 2^-8 relative)
  *             and one product, FP32 accumulation. A throughput form, not one of
  *             the split-precision forms: it has no correction term, and its eps^-1
  *             error is not held to the 1e-4 of the split forms (relative
@@ -333,14 +333,16 @@ int xo_gather_rows(const float* src, const int* idx, int n, int F, float* dst, v
  * |G - G'|, w, delta_GG' (s_G = sqrt(4 pi)/|q+G|). chi_t: truncated sum; chi_h:
  * the sum over the lower part of the same bands (its difference is the
  * contribution of the last block). When chi_f and T are given, also writes the
- * target T [n][2] = tsc * s_G (chi_f - chi_t) s_G'. Device: chi_*, X, T;
- * host: qpg [ng], gdiff [ng][ng], w [nw], mu [9], isd [9]. */
+ * target T [n][2] = tsc * s_G (chi_f - chi_t) s_G'. |G - G'| is taken from the
+ * Cartesian G = sum_k m_k b_k (FP64). Device: chi_*, X, T; host: qpg [ng],
+ * mill_g [ng][3], bvec [3][3] (rows b_1, b_2, b_3), w [nw], mu [9], isd [9]. */
 typedef struct {
   const double* chi_t;
   const double* chi_h;
   const double* chi_f;
   const double* qpg;
-  const double* gdiff;
+  const int32_t* mill_g;
+  const double* bvec;
   const double* w;
   int ng, nw;
   const float* mu;
@@ -351,6 +353,42 @@ typedef struct {
 } xo_tail_args;
 
 int xo_tail_features(const xo_tail_args* a, void* stream);
+
+/* Fused inference of the learned tail: for every element e = (w, G, G') of
+ * [nw][ng][ng], the features of xo_tail_features (from chi_t and chi_h, normalised
+ * with mu and isd) go through each ensemble member's MLP
+ *   dims = [F <= 16, 256, ..., 256, 2] (nl = len(dims) - 1 >= 2 layers, SiLU between),
+ * and Y[e] = the members' mean output. The layer products run on bf16 matrix cores
+ * (weights and activations rounded to nearest even, FP32 accumulation, biases and
+ * SiLU in FP32). Guard statistics, as xo_tail_guard computes them over the same
+ * features and member outputs (two members; with one, stats[1] = 0 and stats[2] =
+ * sum |Y|^2): stats[0] = features outside [lo - m, hi + m], stats[1] = sum |Y1 - Y2|^2,
+ * stats[2] = sum |(Y1 + Y2)/2|^2. The corrected chi0 is then xo_tail_apply(chi_t, Y).
+ * Errors: XO_ERR_ARG for null pointers or bad sizes, XO_ERR_UNSUPPORTED for other
+ * widths. params [device] [nmem][P] FP32 flat parameters (W_l [out][in] row-major then
+ * b_l, layer by layer), nmem 1 or 2; chi_t, chi_h, Y [n][2], stats [3]: device; qpg,
+ * mill_g, bvec, w, mu, isd, lo, hi, dims: host. */
+typedef struct {
+  const double* chi_t;
+  const double* chi_h;
+  const double* qpg;
+  const int32_t* mill_g;
+  const double* bvec;
+  const double* w;
+  int ng, nw;
+  const float* mu;
+  const float* isd;
+  const float* lo;
+  const float* hi;
+  int nl;
+  const int* dims;
+  int nmem;
+  const float* params;
+  float* Y;
+  double* stats;
+} xo_tail_predict_args;
+
+int xo_tail_predict(const xo_tail_predict_args* a, void* stream);
 /* out = chi_t + Hermitian part of Y / (tsc s_G s_G'), Y = Y1 or (Y1 + Y2)/2 when Y2
  * is not NULL; Y1, Y2 [device] [nw][ng][ng][2]; qpg [host] [ng]; out must not alias chi_t. */
 int xo_tail_apply(const double* chi_t, const float* Y1, const float* Y2, const double* qpg, int ng, int nw,
@@ -375,12 +413,15 @@ int xo_tail_guard(const float* X, long n, int F, const float* lo, const float* h
  * minus the explicit bands, occupied ones included. rho holds rho_nv(G) of the
  * nn explicit bands at k against the nv occupied bands at k', as written by
  * xo_rho with the conduction side set to bands 0 .. nn-1 (rows t = v nn + n).
- * Passing the truncated chi0 as out yields the corrected chi0. FP64 only;
- * q = 0 (head and wings) is not treated. Errors: XO_ERR_ARG for bad sizes or an
- * ebar not above every e_v (checked on the device; the call then synchronises).
- *   mill_v [host] [npw_v][3]; coef_v [device] [nv][npw_v] complex128;
+ * Passing the truncated chi0 as out yields the corrected chi0. The density
+ * elements are plane-wave sums in FP64; the explicit-band update runs in prec
+ * (XO_FP64: complex128 coef_v and rho; the other precisions: complex64, with the
+ * products of xo_chi0 in that precision). q = 0 (head and wings) is not treated.
+ * Errors: XO_ERR_ARG for bad sizes or an ebar not above every e_v (checked on the
+ * device; the call then synchronises).
+ *   mill_v [host] [npw_v][3]; coef_v [device] [nv][npw_v];
  *   e_v [device] [nv]; mill_g [host] [ng][3]; w [host] [nw];
- *   rho [device] [nv*nn][ng] complex128; out [device] [nw][ng][ng] complex128. */
+ *   rho [device] [nv*nn][ng]; out [device] [nw][ng][ng] complex128. */
 typedef struct {
   int npw_v;
   const int32_t* mill_v;
@@ -396,6 +437,7 @@ typedef struct {
   int nn;
   const void* rho;
   double* out;
+  int prec;
 } xo_xterm_args;
 
 int xo_xterm(const xo_xterm_args* a, void* stream);

@@ -4,7 +4,7 @@
 // even); a product is formed as hi*hi + hi*lo + lo*hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation, dropping the lo*lo term
 // (about 2^-16 relative). The plain form keeps hi only and forms hi*hi (operand
-// rounding 2^-9 relative). Complex numbers are packed as (re, im) bf16 pairs in
+// rounding at most 2^-8 relative). Complex numbers are packed as (re, im) bf16 pairs in
 // one 32-bit word, element 0 in the low half.
 #pragma once
 

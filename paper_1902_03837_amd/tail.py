@@ -29,12 +29,6 @@ DIMS = [9, 256, 256, 256, 2]   # 3 hidden layers of 256, SiLU
 NFEAT = 9
 
 
-def gdiff_table(cr) -> np.ndarray:
-    g = cr.gmill.astype(np.float64) @ cr.lat.bvec
-    d = g[:, None, :] - g[None, :, :]
-    return np.sqrt(np.einsum("ijk,ijk->ij", d, d))
-
-
 def chi0_blocks(dc: DeviceCrystal, cuts: List[int], prec: str = "fp64", stream=None):
     """chi0 summed over empty bands [0, cuts[0]), [0, cuts[1]), ... (cumulative).
 
@@ -86,21 +80,22 @@ def chi0_blocks(dc: DeviceCrystal, cuts: List[int], prec: str = "fp64", stream=N
 def xterm_chi0(dc: DeviceCrystal, nempty: int, chi_trunc, shift: float = 1.5, stream=None):
     """chi0 with the Bruneval-Gonze terminator (App. B): chi_trunc, summed over the
     nempty lowest empty bands, plus the correction of every k-pair (xo_rho over the
-    explicit bands at k, occupied included, then xo_xterm). FP64 crystal only;
+    explicit bands at k, occupied included, then xo_xterm), in the crystal's precision;
     ebar = highest explicit band energy at k + shift."""
     cr = dc.cr
-    assert dc.prec == "fp64" and not cr.q0
+    assert not cr.q0
     ng = cr.gmill.shape[0]
+    cdt = torch.complex128 if dc.prec == "fp64" else torch.complex64
     out = chi_trunc.clone()
     for ik, ikp, g0, _, _, nv in band_ranges(cr):
         nb = cr.nocc_at(ik) + nempty
-        M = torch.empty((nv * nb, ng), dtype=torch.complex128, device=out.device)
+        M = torch.empty((nv * nb, ng), dtype=cdt, device=out.device)
         xo.rho(dc.coef[ik][:nb], cr.mill[ik], dc.eps[ik][:nb], dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv],
-               cr.gmill, g0, cr.grid, out=M.view(nv, nb, ng), prec="fp64", kcart=cr.kcart(ik), bvec=cr.lat.bvec,
+               cr.gmill, g0, cr.grid, out=M.view(nv, nb, ng), prec=dc.prec, kcart=cr.kcart(ik), bvec=cr.lat.bvec,
                stream=stream)
         ebar = float(cr.eps[ik][nb - 1]) + shift
         xo.xterm(dc.coef[ikp][:nv], cr.mill[ikp], dc.eps[ikp][:nv], ebar, cr.gmill, cr.omegas, chi0_pref(cr), M, nb, out,
-                 stream=stream)
+                 prec=dc.prec, stream=stream)
     return out
 
 
@@ -190,7 +185,7 @@ def build_features(cr, chis, mu, isd, tsc, dev="cuda"):
     n = nw * ng * ng
     X = torch.empty((n, NFEAT), dtype=torch.float32, device=dev)
     T = torch.empty((n, 2), dtype=torch.float32, device=dev) if len(chis) > 2 else None
-    xo.tail_features(chis[1], chis[0], qpg(cr), gdiff_table(cr), cr.omegas, mu, isd, X,
+    xo.tail_features(chis[1], chis[0], qpg(cr), cr.gmill, cr.lat.bvec, cr.omegas, mu, isd, X,
                      chi_f=chis[2] if len(chis) > 2 else None, T=T, tsc=tsc)
     return X, T
 
@@ -269,22 +264,24 @@ def feature_range(X):
     return s[:, 2].astype(np.float32), s[:, 3].astype(np.float32)
 
 
-def predict(model: TailModel, cr, chis_trunc, dev="cuda"):
+def predict(model: TailModel, cr, chis_trunc, dev="cuda", stream=None):
     """chi0 = chi0_trunc + learned tail, or None if the guard asks for the full sum.
 
-    chis_trunc = [chi_half, chi_trunc] from chi0_blocks. Returns (chi, stats)."""
-    X, _ = build_features(cr, chis_trunc[:2], model.mu, model.isd, model.tsc, dev)
-    Ys = []
-    for p in model.members:
-        net = MLP(p, model.dims, dev)
-        Ys.append(net.forward(X).clone())
+    chis_trunc = [chi_ref, chi_base] (the slope reference and the sum the network corrects).
+    One fused launch (xo_tail_predict) forms the features, runs both ensemble members on the
+    matrix cores and sums the guard statistics; xo_tail_apply adds the tail. Returns (chi, stats)."""
+    ng, nw = cr.gmill.shape[0], len(cr.omegas)
+    Y = torch.empty((nw * ng * ng, 2), dtype=torch.float32, device=dev)
     stats = torch.empty(3, dtype=torch.float64, device=dev)
-    xo.tail_guard(X, model.lo, model.hi, Ys[0], Ys[1], stats)
+    params = torch.from_numpy(np.ascontiguousarray(np.stack(model.members), np.float32)).to(dev)
+    q = qpg(cr)
+    xo.tail_predict(chis_trunc[1], chis_trunc[0], q, cr.gmill, cr.lat.bvec, cr.omegas, model.mu, model.isd,
+                    model.lo, model.hi, model.dims, params, Y, stats, stream=stream)
     st = stats.cpu().numpy()
     dis = float(np.sqrt(st[1] / max(st[2], 1e-300)))
     info = dict(out_of_range=int(st[0]), disagreement=dis)
     if st[0] > 0 or dis > model.tau:
         return None, info
     out = torch.empty_like(chis_trunc[1])
-    xo.tail_apply(chis_trunc[1], Ys[0], qpg(cr), model.tsc, out, Y2=Ys[1] if len(Ys) > 1 else None)
+    xo.tail_apply(chis_trunc[1], Y, q, model.tsc, out, stream=stream)
     return out, info

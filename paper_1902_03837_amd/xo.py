@@ -56,9 +56,20 @@ class EpsArgs(C.Structure):
 
 class TailArgs(C.Structure):
     _fields_ = [
-        ("chi_t", C.c_void_p), ("chi_h", C.c_void_p), ("chi_f", C.c_void_p), ("qpg", _f64p), ("gdiff", _f64p),
-        ("w", _f64p), ("ng", C.c_int), ("nw", C.c_int), ("mu", C.POINTER(C.c_float)),
-        ("isd", C.POINTER(C.c_float)), ("tsc", C.c_double), ("X", C.c_void_p), ("T", C.c_void_p),
+        ("chi_t", C.c_void_p), ("chi_h", C.c_void_p), ("chi_f", C.c_void_p), ("qpg", _f64p),
+        ("mill_g", C.POINTER(C.c_int32)), ("bvec", _f64p), ("w", _f64p), ("ng", C.c_int), ("nw", C.c_int),
+        ("mu", C.POINTER(C.c_float)), ("isd", C.POINTER(C.c_float)), ("tsc", C.c_double), ("X", C.c_void_p),
+        ("T", C.c_void_p),
+    ]
+
+
+class TailPredictArgs(C.Structure):
+    _fields_ = [
+        ("chi_t", C.c_void_p), ("chi_h", C.c_void_p), ("qpg", _f64p), ("mill_g", C.POINTER(C.c_int32)),
+        ("bvec", _f64p), ("w", _f64p), ("ng", C.c_int), ("nw", C.c_int), ("mu", C.POINTER(C.c_float)),
+        ("isd", C.POINTER(C.c_float)), ("lo", C.POINTER(C.c_float)), ("hi", C.POINTER(C.c_float)),
+        ("nl", C.c_int), ("dims", C.POINTER(C.c_int)), ("nmem", C.c_int), ("params", C.c_void_p),
+        ("Y", C.c_void_p), ("stats", C.c_void_p),
     ]
 
 
@@ -67,7 +78,7 @@ class XtermArgs(C.Structure):
         ("npw_v", C.c_int), ("mill_v", C.POINTER(C.c_int32)), ("nv", C.c_int), ("coef_v", C.c_void_p),
         ("e_v", C.c_void_p), ("ebar", C.c_double), ("ng", C.c_int), ("mill_g", C.POINTER(C.c_int32)),
         ("nw", C.c_int), ("w", _f64p), ("pref", C.c_double), ("nn", C.c_int), ("rho", C.c_void_p),
-        ("out", C.c_void_p),
+        ("out", C.c_void_p), ("prec", C.c_int),
     ]
 
 
@@ -106,7 +117,7 @@ EXPORTS = ("xo_last_error", "xo_version", "xo_release_workspace", "xo_timing_ena
            "xo_rho", "xo_rho_batch", "xo_chi0", "xo_chi0_batch", "xo_chi0_autotune", "xo_epsinv", "xo_mlp_forward", "xo_mlp_backward", "xo_mse",
            "xo_adam_step", "xo_gather_rows", "xo_col_stats", "xo_tail_features", "xo_tail_apply", "xo_tail_guard",
            "xo_xterm", "xo_ppa_fit", "xo_sigma", "xo_chi0_real", "xo_rho_workspace_size",
-           "xo_chi0_workspace_size", "xo_epsinv_workspace_size", "xo_epsinv_noalloc")
+           "xo_chi0_workspace_size", "xo_epsinv_workspace_size", "xo_epsinv_noalloc", "xo_tail_predict")
 
 
 def lib():
@@ -134,10 +145,11 @@ def lib():
         L.xo_col_stats.argtypes = [vp, l, i, vp, vp]
         L.xo_col_stats.restype = C.c_int
         L.xo_tail_features.argtypes = [C.POINTER(TailArgs), vp]
+        L.xo_tail_predict.argtypes = [C.POINTER(TailPredictArgs), vp]
         L.xo_tail_apply.argtypes = [vp, vp, vp, _f64p, i, i, C.c_double, vp, vp]
         L.xo_tail_guard.argtypes = [vp, l, i, fp, fp, vp, vp, i, vp, vp]
         for nm in ("xo_mlp_forward", "xo_mlp_backward", "xo_mse", "xo_adam_step", "xo_gather_rows",
-                   "xo_tail_features", "xo_tail_apply", "xo_tail_guard"):
+                   "xo_tail_features", "xo_tail_apply", "xo_tail_guard", "xo_tail_predict"):
             getattr(L, nm).restype = C.c_int
         L.xo_rho_batch.argtypes = [C.POINTER(RhoArgs), C.c_int, C.c_void_p]
         L.xo_chi0_batch.argtypes = [C.POINTER(Chi0Args), C.c_int, C.POINTER(Tune), C.c_void_p]
@@ -409,21 +421,57 @@ def gather_rows(src, idx, dst, stream=None):
     _check(lib().xo_gather_rows(_ptr(src), _ptr(idx), n, F, _ptr(dst), _stream(stream)))
 
 
-def tail_features(chi_t, chi_h, qpg, gdiff, w, mu, isd, X, chi_f=None, T=None, tsc=1.0, stream=None):
+def _geo(qpg, mill_g, bvec, w, ng, nw):
+    q = np.ascontiguousarray(np.asarray(qpg, np.float64))
+    m = np.ascontiguousarray(np.asarray(mill_g, np.int32))
+    b = np.ascontiguousarray(np.asarray(bvec, np.float64))
+    ww = np.ascontiguousarray(np.asarray(w, np.float64))
+    assert q.size == ng and m.shape == (ng, 3) and b.shape == (3, 3) and ww.size == nw
+    return q, m, b, ww
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def tail_features(chi_t, chi_h, qpg, mill_g, bvec, w, mu, isd, X, chi_f=None, T=None, tsc=1.0, stream=None):
     nw, ng = chi_t.shape[0], chi_t.shape[1]
     assert X.shape == (nw * ng * ng, 9) and chi_h.shape == chi_t.shape
     if T is not None:
         assert chi_f is not None and T.shape == (nw * ng * ng, 2)
-    keep = [np.ascontiguousarray(np.asarray(a, np.float64)) for a in (qpg, gdiff, w)]
-    keepf = [np.ascontiguousarray(np.asarray(a, np.float32)) for a in (mu, isd)]
-    assert keep[0].size == ng and keep[1].size == ng * ng and keep[2].size == nw
+    q, m, b, ww = _geo(qpg, mill_g, bvec, w, ng, nw)
+    keepf = [_f32(mu), _f32(isd)]
     a = TailArgs()
     a.chi_t, a.chi_h, a.chi_f = _ptr(chi_t), _ptr(chi_h), _ptr(chi_f)
-    a.qpg, a.gdiff, a.w = (k.ctypes.data_as(_f64p) for k in keep)
+    a.qpg, a.bvec, a.w = (k.ctypes.data_as(_f64p) for k in (q, b, ww))
+    a.mill_g = m.ctypes.data_as(C.POINTER(C.c_int32))
     a.ng, a.nw = ng, nw
     a.mu, a.isd = (k.ctypes.data_as(C.POINTER(C.c_float)) for k in keepf)
     a.tsc, a.X, a.T = float(tsc), _ptr(X), _ptr(T)
     _check(lib().xo_tail_features(C.byref(a), _stream(stream)))
+
+
+def tail_predict(chi_t, chi_h, qpg, mill_g, bvec, w, mu, isd, lo, hi, dims, params, Y, stats, stream=None):
+    """xo_tail_predict: Y [n][2] = ensemble mean of the tail MLPs (bf16 matrix cores) on the
+    features of every element, stats [3] = guard sums. params: FP32 device tensor [nmem][P]."""
+    import torch
+    nw, ng = chi_t.shape[0], chi_t.shape[1]
+    assert chi_h.shape == chi_t.shape and Y.shape == (nw * ng * ng, 2) and stats.numel() >= 3
+    assert params.dim() == 2 and params.is_contiguous() and params.dtype == torch.float32
+    assert params.shape[1] == sum(a * b + b for a, b in zip(dims[:-1], dims[1:])), "params do not match dims"
+    q, m, b, ww = _geo(qpg, mill_g, bvec, w, ng, nw)
+    keepf = [_f32(mu), _f32(isd), _f32(lo), _f32(hi)]
+    d = np.ascontiguousarray(np.asarray(dims, np.int32))
+    a = TailPredictArgs()
+    a.chi_t, a.chi_h = _ptr(chi_t), _ptr(chi_h)
+    a.qpg, a.bvec, a.w = (k.ctypes.data_as(_f64p) for k in (q, b, ww))
+    a.mill_g = m.ctypes.data_as(C.POINTER(C.c_int32))
+    a.ng, a.nw = ng, nw
+    a.mu, a.isd, a.lo, a.hi = (k.ctypes.data_as(C.POINTER(C.c_float)) for k in keepf)
+    a.nl, a.dims = len(d) - 1, d.ctypes.data_as(C.POINTER(C.c_int))
+    a.nmem, a.params = params.shape[0], _ptr(params)
+    a.Y, a.stats = _ptr(Y), _ptr(stats)
+    _check(lib().xo_tail_predict(C.byref(a), _stream(stream)))
 
 
 def tail_apply(chi_t, Y1, qpg, tsc, out, Y2=None, stream=None):
@@ -452,13 +500,15 @@ def col_stats(X, out, stream=None):
     _check(lib().xo_col_stats(_ptr(X), n, F, _ptr(out), _stream(stream)))
 
 
-def xterm(coef_v, mill_v, e_v, ebar, gmill, omegas, pref, rho_m, nn, out, stream=None):
+def xterm(coef_v, mill_v, e_v, ebar, gmill, omegas, pref, rho_m, nn, out, prec="fp64", stream=None):
     """xo_xterm: out[nw][ng][ng] (complex128) += Bruneval-Gonze correction of one k-pair.
 
-    coef_v [nv][npw_v] complex128 and e_v [nv] float64 on the device; rho_m
-    [nv*nn][ng] complex128 from xo_rho over the nn explicit bands at k."""
+    coef_v [nv][npw_v] and e_v [nv] float64 on the device; rho_m [nv*nn][ng] from xo_rho
+    over the nn explicit bands at k; coef_v and rho_m are complex128 for "fp64", complex64
+    for the other precisions (the explicit-band update then runs in that precision)."""
     import torch
-    assert coef_v.dtype == torch.complex128 and e_v.dtype == torch.float64 and rho_m.dtype == torch.complex128
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    assert coef_v.dtype == cdt and e_v.dtype == torch.float64 and rho_m.dtype == cdt
     nv, npw = coef_v.shape
     mv = _host_i32(mill_v)
     mg = _host_i32(gmill)
@@ -470,6 +520,7 @@ def xterm(coef_v, mill_v, e_v, ebar, gmill, omegas, pref, rho_m, nn, out, stream
     a.coef_v, a.e_v, a.ebar = _ptr(coef_v), _ptr(e_v), float(ebar)
     a.ng, a.mill_g, a.nw, a.w = mg.shape[0], mg.ctypes.data_as(C.POINTER(C.c_int32)), w.shape[0], w.ctypes.data_as(_f64p)
     a.pref, a.nn, a.rho, a.out = float(pref), int(nn), _ptr(rho_m), _ptr(out)
+    a.prec = PREC[prec]
     _check(lib().xo_xterm(C.byref(a), _stream(stream)))
     return out
 

@@ -38,14 +38,14 @@ def load_crystal(path: str) -> Crystal:
                    scissor=meta["scissor"], seed=meta["seed"], meta=meta["meta"], nocc_k=meta["nocc_k"])
 
 
-def cached_crystal(name: str, cache_dir=None, progress=None):
-    """crystal_for(name), kept in cache_dir/<name>.npz when a directory is given."""
+def cached_crystal(name: str, cache_dir=None, progress=None, seed=None):
+    """crystal_for(name, seed), kept in cache_dir/<name>[_s<seed>].npz when a directory is given."""
     from .configs import crystal_for
     if cache_dir:
-        path = os.path.join(cache_dir, f"{name}.npz")
+        path = os.path.join(cache_dir, f"{name}.npz" if seed is None else f"{name}_s{seed}.npz")
         if os.path.exists(path):
             return load_crystal(path)
-    cr = crystal_for(name, progress=progress)
+    cr = crystal_for(name, seed=seed, progress=progress)
     if cache_dir:
         os.makedirs(cache_dir, exist_ok=True)
         save_crystal(cr, path)

@@ -7,8 +7,8 @@ c3  batched: 3x3x3 k, all 27 q, 32 occ + 400 empty, 48^3, NG per q from the clos
     counts in [150, 900], 16 freqs.
 c4  learned tail: c1 family on a 20^3 grid (N_pw ~ 1100), 8 occ + 1000 empty (full) / 100 (truncated),
     NG = 59, 8 freqs; train seeds 1000..1063, held-out 2000..2015.
-c5  large cell: 32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occ + 2000 empty,
-    72^3, NG = 3000, 16 freqs (c5_small: the same cell, G-set and grid with k = {Gamma, b1/2},
+c5  large cell: 32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occ + 2000 empty
+    (200 explicit for the learned tail), 72^3, NG = 3000, 16 freqs (c5_small: the same cell, G-set and grid with k = {Gamma, b1/2},
     N_pw ~ 1500, 200 empty bands, 4 freqs).
 """
 
@@ -32,7 +32,7 @@ CONFIGS = {
                npw=900, ng=(150, 900), nw=16, seed=3),
     "c4": dict(lattice="fcc", kset="fcc4", q=(.5, .5, 0.), nocc=8, nempty=1000, ntrunc=100,
                grid=20, npw=1100, ng=59, nw=8, seed=1000),
-    "c5": dict(lattice="sc32", kset=2, q=(.5, 0., 0.), nocc=128, nempty=2000, grid=72,
+    "c5": dict(lattice="sc32", kset=2, q=(.5, 0., 0.), nocc=128, nempty=2000, ntrunc=200, grid=72,
                npw=4000, ng=3000, nw=16, seed=5),
 }
 

@@ -306,3 +306,33 @@ def test_autotune_rejects_accumulating_items():
     ms = C.c_double(0)
     rc = L.xo_chi0_autotune(C.byref(a), 1, C.byref(best), C.byref(ms), None)
     assert rc == xo.XO_ERR_ARG and b"accumulate" in L.xo_last_error()
+
+
+def test_tail_predict_argument_errors():
+    L = xo.lib()
+    a = xo.TailPredictArgs()
+    rc, msg = _rc(L.xo_tail_predict, a)
+    assert rc == xo.XO_ERR_ARG and "null" in msg
+    f64 = np.zeros(9)
+    f32 = np.zeros(9, np.float32)
+    m = np.zeros((3, 3), np.int32)
+    a.chi_t = a.chi_h = a.params = a.Y = a.stats = 8   # never dereferenced: validation fails first
+    a.qpg = a.bvec = a.w = f64.ctypes.data_as(C.POINTER(C.c_double))
+    a.mill_g = m.ctypes.data_as(C.POINTER(C.c_int32))
+    a.mu = a.isd = a.lo = a.hi = f32.ctypes.data_as(C.POINTER(C.c_float))
+    dims = np.array([9, 256, 256, 256, 2], np.int32)
+    a.dims = dims.ctypes.data_as(C.POINTER(C.c_int))
+    a.ng, a.nw, a.nl, a.nmem = 3, 1, 4, 3
+    rc, msg = _rc(L.xo_tail_predict, a)
+    assert rc == xo.XO_ERR_ARG and "nmem" in msg
+    a.nmem = 2
+    dims[2] = 128                       # hidden widths other than 256
+    rc, msg = _rc(L.xo_tail_predict, a)
+    assert rc == xo.XO_ERR_UNSUPPORTED and "256" in msg
+    dims[2], dims[0] = 256, 8           # not the 9 tail features
+    rc, msg = _rc(L.xo_tail_predict, a)
+    assert rc == xo.XO_ERR_UNSUPPORTED and "9" in msg
+    dims[0] = 9
+    a.nl = 6                            # more than three hidden 256 -> 256 layers
+    rc, msg = _rc(L.xo_tail_predict, a)
+    assert rc == xo.XO_ERR_ARG

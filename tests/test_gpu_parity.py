@@ -430,7 +430,7 @@ def test_epsinv_lu_fallback_reports_singular_block():
 # FP64 against the 1e-6 target, the split forms (FP32, bf16x3) against the 1e-4 target.
 # Plain bf16 is not a split form (no correction): its element-wise rounding bounds are
 # asserted by the chi0 and rho tests; here its measured eps~^-1 error on this small workload
-# (a few hundred transitions average its 2^-9 operand rounding, about 3e-4) is held to 1e-3.
+# (a few hundred transitions average its operand rounding (at most 2^-8 each), about 3e-4) is held to 1e-3.
 @pytest.mark.parametrize("name,prec,gate", [("c1", "fp64", 1e-6), ("c2_small", "fp64", 1e-6),
                                             ("c1", "fp32", 1e-4), ("c2_small", "fp32", 1e-4),
                                             ("c2_small", "bf16x3", 1e-4), ("c2_small", "bf16", 1e-3)])
