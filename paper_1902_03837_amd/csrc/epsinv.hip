@@ -6,13 +6,12 @@
 // in place by blocked Gauss-Jordan elimination, all frequencies in the same
 // launches; the diagonal blocks are inverted without pivoting (positive definite
 // input) or, with XO_EPS_LU_FALLBACK (general eps~), with partial pivoting inside
-// the block. Per block column K (width b = 64), three launches:
-//   P = A_KK^-1                      diag_inverse: one 1024-thread workgroup per
-//                                    frequency, the block in registers, one barrier
-//                                    per pivot
-//   A_Kj = P A_Kj  (j outside K)     row_col: row tiles of the panel, and
-//   S_iK = A_iK,  A_iK = -A_iK P     column tiles (old column saved in S)
-//   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update
+// the block. Per block column K (width b = 64):
+//   P = A_KK^-1                      diag_block: one workgroup per frequency, the
+//                                    block in registers, one barrier per pivot
+//   A_Kj = P A_Kj  (j outside K)     row_col: row half-tiles of the panel, and
+//   S_iK = A_iK,  A_iK = -A_iK P     column half-tiles (old column saved in S)
+//   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update, 32 x 32 tiles
 // The pivots met inside the diagonal blocks are the diagonal of eps~ = L D L^H,
 // so a pivot with non-positive real part proves eps~ is not positive definite.
 // In the pivoted form a numerically singular diagonal block is reported instead.
@@ -94,17 +93,15 @@ __global__ void eps_absmax(const double* __restrict__ A, int n, unsigned long lo
 // whole eps~ (gmax2: squared, per frequency) marks the block as numerically singular
 // (flagged): the blocked elimination has no pivoting across blocks, so the caller gets
 // an error instead of an inaccurate inverse.
+// The body runs on the kB * kB / E threads of a workgroup for the matrix A of frequency w.
 template <int E, bool PIV>
-__global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
-                                                            int check_sign, int* __restrict__ flag,
-                                                            const unsigned long long* __restrict__ gmax2) {
+__device__ __forceinline__ void diag_block(z* __restrict__ A, int n, int K, int kb, int check_sign, int w,
+                                           int* __restrict__ flag, const unsigned long long* __restrict__ gmax2) {
   constexpr int CG = kB / E;  // column groups
   __shared__ z pcol[2][kB];
   __shared__ z prow[2][E][CG];
   __shared__ int perm[kB], inv[kB];   // PIV: pivot row of column k, and its inverse
   __shared__ double wmax[kB * kB / E / 64];
-  const int w = blockIdx.x;
-  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const int o = K * kB;
   const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq, lane = t & 63;
   z a[E];
@@ -197,106 +194,131 @@ __global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__
     }
   }
 }
+
+template <int E, bool PIV>
+__global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
+                                                            int check_sign, int* __restrict__ flag,
+                                                            const unsigned long long* __restrict__ gmax2) {
+  const int w = blockIdx.x;
+  diag_block<E, PIV>(reinterpret_cast<z*>(Aall) + (size_t)w * n * n, n, K, kb, check_sign, w, flag, gmax2);
+}
 constexpr int kDiagE = 8;  // entries per thread of diag_inverse (512 threads: two waves per SIMD)
 
-// One 64 x 64 tile product L R (L: 64 x kb, R: kb x 64, in LDS). Thread t owns
-// rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 4): a wave reads four rows
-// of L (broadcast) and 16 consecutive entries of each row of R per step.
-__device__ __forceinline__ void tile_product(const z (*L)[kB + 1], const z (*R)[kB + 1], int kb, z acc[4][4]) {
+// Tile product acc = L R over m < kb (L: 16 RU rows x kb, leading dimension LL; R: kb x 16 RV
+// columns, leading dimension LR; both in LDS). Thread t owns rows t / 16 + 16 u and columns
+// t % 16 + 16 v: a wave reads four rows of L (broadcast) and 16 consecutive entries of R.
+template <int RU, int RV, int LL, int LR>
+__device__ __forceinline__ void tile_product(const z* __restrict__ L, const z* __restrict__ R, int kb,
+                                             z (&acc)[RU][RV]) {
   const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < RU; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = z{0.0, 0.0};
+    for (int v = 0; v < RV; ++v) acc[u][v] = z{0.0, 0.0};
   for (int m = 0; m < kb; ++m) {
-    z l[4], rr[4];
+    z l[RU], rr[RV];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      l[u] = L[rr0 + 16 * u][m];
-      rr[u] = R[m][cc0 + 16 * u];
-    }
+    for (int u = 0; u < RU; ++u) l[u] = L[(rr0 + 16 * u) * LL + m];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < RV; ++v) rr[v] = R[m * LR + cc0 + 16 * v];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cfma(acc[u][v], l[u], rr[v]);
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int v = 0; v < RV; ++v) cfma(acc[u][v], l[u], rr[v]);
   }
 }
 
-// Row tiles (blockIdx.x < nt): A_Kj <- P A_Kj for the 64 columns of tile j != K.
-// Column tiles (blockIdx.x >= nt): S_iK <- A_iK, A_iK <- -A_iK P for the 64 rows
-// of tile i != K. S: [nw][n][kB].
+// Panel of block column K, each 64-wide tile in two halves (twice the workgroups of whole
+// tiles: the panel is small and latency-bound). blockIdx.x = 2 * tile + half.
+// Row tiles (tile < nt): A_Kj <- P A_Kj for the 32 columns of half h of tile j != K.
+// Column tiles (tile >= nt): S_iK <- A_iK, A_iK <- -A_iK P for the 32 rows of half h of
+// tile i != K (a row's 64 pivot columns stay in one workgroup: it reads them all before
+// writing any). S: [nw][n][kB].
+constexpr int kH = kB / 2;
 __global__ void __launch_bounds__(256) row_col(double* __restrict__ Aall, int n, int K, int kb, int nt,
                                               double* __restrict__ Sall) {
   extern __shared__ unsigned char smem[];
-  z (*P)[kB + 1] = reinterpret_cast<z (*)[kB + 1]>(smem);
-  z (*T)[kB + 1] = P + kB;
+  z* P = reinterpret_cast<z*>(smem);   // [kB][kB + 1]: the inverted diagonal block
+  z* T = P + kB * (kB + 1);            // row tile: [kB][kH + 1]; column tile: [kH][kB + 1]
   const int w = blockIdx.y;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   z* S = reinterpret_cast<z*>(Sall) + (size_t)w * n * kB;
-  const bool rowt = (int)blockIdx.x < nt;
-  const int tile = rowt ? (int)blockIdx.x : (int)blockIdx.x - nt;
+  const int tb = (int)blockIdx.x >> 1, h = (int)blockIdx.x & 1;
+  const bool rowt = tb < nt;
+  const int tile = rowt ? tb : tb - nt;
   if (tile == K) return;
-  const int o = K * kB, x0 = tile * kB;
+  const int o = K * kB, x0 = tile * kB + h * kH;
   {
-    // all sixteen loads of each operand in flight before the LDS stores
-    z vp[16], vt[16];
+    // every load of both operands in flight before the LDS stores
+    z vp[16], vt[8];
 #pragma unroll
     for (int f = 0; f < 16; ++f) {
       const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
       vp[f] = (i < kb && j < kb) ? A[(size_t)(o + i) * n + o + j] : z{0.0, 0.0};
-      if (rowt)  // T[m][c] = A[o + m][x0 + c]
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      if (rowt) {  // T[m][c] = A[o + m][x0 + c], 64 x 32
+        const int i = e >> 5, j = e & 31;
         vt[f] = (i < kb && x0 + j < n) ? A[(size_t)(o + i) * n + x0 + j] : z{0.0, 0.0};
-      else       // T[r][m] = A[x0 + r][o + m]
+      } else {     // T[r][m] = A[x0 + r][o + m], 32 x 64
+        const int i = e >> 6, j = e & 63;
         vt[f] = (x0 + i < n && j < kb) ? A[(size_t)(x0 + i) * n + o + j] : z{0.0, 0.0};
+      }
     }
 #pragma unroll
     for (int f = 0; f < 16; ++f) {
-      const int e = threadIdx.x + 256 * f, i = e >> 6, j = e & 63;
-      P[i][j] = vp[f];
-      T[i][j] = vt[f];
+      const int e = threadIdx.x + 256 * f;
+      P[(e >> 6) * (kB + 1) + (e & 63)] = vp[f];
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int e = threadIdx.x + 256 * f;
+      if (rowt)
+        T[(e >> 5) * (kH + 1) + (e & 31)] = vt[f];
+      else
+        T[(e >> 6) * (kB + 1) + (e & 63)] = vt[f];
     }
   }
   __syncthreads();
   const int t = threadIdx.x, rr0 = t >> 4, cc0 = t & 15;
-  z acc[4][4];
   if (rowt) {
-    tile_product(P, T, kb, acc);
+    z acc[4][2];
+    tile_product<4, 2, kB + 1, kH + 1>(P, T, kb, acc);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < 2; ++v) {
         const int r = rr0 + 16 * u, c = x0 + cc0 + 16 * v;
         if (r < kb && c < n) A[(size_t)(o + r) * n + c] = acc[u][v];
       }
   } else {
-    tile_product(T, P, kb, acc);
+    z acc[2][4];
+    tile_product<2, 4, kB + 1, kB + 1>(T, P, kb, acc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rr0 + 16 * u, m = cc0 + 16 * v;
         if (x0 + r < n && m < kb) {
           const size_t i = x0 + r;
-          S[i * kB + m] = T[r][m];
+          S[i * kB + m] = T[r * (kB + 1) + m];
           A[i * n + o + m] = z{-acc[u][v].x, -acc[u][v].y};
         }
       }
   }
 }
 
-// Rank-kb update of every 32 x 32 tile outside row block K and column block K:
+// Rank-kb update of one 32 x 32 tile outside row block K and column block K:
 //   A_ij -= S_iK A_Kj   (S old column, A_Kj new row).
-// Thread t owns rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 2).
+// Thread t owns rows t / 16 + 16 u and columns t % 16 + 16 v (u, v < 2). Ends with a barrier,
+// so a workgroup may update several tiles in a row.
 constexpr int kT = 32;
-__global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, int n, int K, int kb,
-                                                  const double* __restrict__ Sall) {
+__device__ __forceinline__ void update_tile(z* __restrict__ A, const z* __restrict__ S, int n, int o, int kb, int i0,
+                                            int j0) {
   __shared__ z L[kT][kB + 1];
   __shared__ z R[kB][kT + 1];
-  const int w = blockIdx.z;
-  const int o = K * kB, i0 = blockIdx.y * kT, j0 = blockIdx.x * kT;
-  if ((i0 >= o && i0 < o + kB) || (j0 >= o && j0 < o + kB)) return;  // 32-tiles sit inside 64-blocks
-  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
-  const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
   {
     z vl[8], vr[8];
 #pragma unroll
@@ -338,6 +360,20 @@ __global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, in
         x = z{x.x - acc[u][v].x, x.y - acc[u][v].y};
       }
     }
+  __syncthreads();
+}
+
+// The rank update of block step K: one workgroup per 32 x 32 tile (blockIdx.x = tile row,
+// blockIdx.y = tile column) outside row block K and column block K.
+__global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, int n, int K, int kb,
+                                                  const double* __restrict__ Sall) {
+  const int w = blockIdx.z;
+  const int o = K * kB;
+  const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+  if ((i0 >= o && i0 < o + kB) || (j0 >= o && j0 < o + kB)) return;  // 32-tiles sit inside 64-blocks
+  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
+  const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
+  update_tile(A, S, n, o, kb, i0, j0);
 }
 
 __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ qpg, int n) {
@@ -478,7 +514,7 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
     }
     XO_CHECK_LAUNCH();
   }
-  const size_t lds2 = (size_t)2 * kB * (kB + 1) * sizeof(z);
+  const size_t lds2 = ((size_t)kB * (kB + 1) + (size_t)kB * (kH + 1) + kH) * sizeof(z);
   static bool attr = false;
   if (!attr) {
     XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&row_col),
@@ -500,7 +536,7 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
     if (nblk > 1) {
       {
         KernelTimer kt_("eps_row_col", st);
-        hipLaunchKernelGGL(row_col, dim3(2 * nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb, nblk, S);
+        hipLaunchKernelGGL(row_col, dim3(4 * nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb, nblk, S);
       }
       XO_CHECK_LAUNCH();
       {
