@@ -149,35 +149,37 @@ class TailModel:
     tau: float = 0.25
     dims: List[int] = field(default_factory=lambda: list(DIMS))
     base: str = "trunc"             # what the network corrects: the truncated sum, or it plus the terminator
+    shift: float = 1.5              # terminator: extrapolar energy above the last explicit band (Ha)
     info: dict = field(default_factory=dict)
 
     def save(self, path):
         np.savez(path, members=np.stack(self.members), mu=self.mu, isd=self.isd, tsc=self.tsc, lo=self.lo,
-                 hi=self.hi, tau=self.tau, dims=np.array(self.dims), base=np.array(self.base))
+                 hi=self.hi, tau=self.tau, dims=np.array(self.dims), base=np.array(self.base), shift=self.shift)
 
     @classmethod
     def load(cls, path):
         z = np.load(path, allow_pickle=False)
         base = str(z["base"]) if "base" in z.files else "trunc"
+        shift = float(z["shift"]) if "shift" in z.files else 1.5
         return cls(list(z["members"]), z["mu"], z["isd"], float(z["tsc"]), z["lo"], z["hi"], float(z["tau"]),
-                   [int(x) for x in z["dims"]], base)
+                   [int(x) for x in z["dims"]], base, shift)
 
 
-def crystal_tensors(cr, ntrunc, nhalf, with_full=True, prec="fp64", base="trunc"):
+def crystal_tensors(cr, ntrunc, nhalf, with_full=True, prec="fp64", base="trunc", shift=1.5):
     """[reference, base, (full)] chi0 of one crystal on the device.
 
     base "trunc": [sum over nhalf, sum over ntrunc, full sum] (the network corrects
     the truncated sum; the slope feature is the last block of bands).
     base "bg": [sum over ntrunc, that plus the Bruneval-Gonze terminator, full sum]
-    (the network corrects the terminator; the slope feature is the terminator's
-    own correction)."""
+    (the network corrects the terminator, extrapolar energy `shift` above the last explicit
+    band; the slope feature is the terminator's own correction)."""
     dc = DeviceCrystal.upload(cr, prec)
     full = [cr.coef[0].shape[0] - cr.nocc] if with_full else []
     if base == "trunc":
         return chi0_blocks(dc, [nhalf, ntrunc] + full, prec), dc
     assert base == "bg"
     chis = chi0_blocks(dc, [ntrunc] + full, prec)
-    return [chis[0], xterm_chi0(dc, ntrunc, chis[0])] + chis[1:], dc
+    return [chis[0], xterm_chi0(dc, ntrunc, chis[0], shift=shift)] + chis[1:], dc
 
 
 def build_features(cr, chis, mu, isd, tsc, dev="cuda"):

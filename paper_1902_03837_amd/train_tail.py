@@ -72,7 +72,7 @@ def _train(args, train_seeds, ntrunc, nhalf):
         t1 = time.time()
         cr = _crystal(args.workload, s, args.fixture_cache)
         t2 = time.time()
-        chis, _ = T.crystal_tensors(cr, ntrunc, nhalf, base=args.base, prec=args.prec)
+        chis, _ = T.crystal_tensors(cr, ntrunc, nhalf, base=args.base, prec=args.prec, shift=args.shift)
         torch.cuda.synchronize()
         ng, nw = cr.gmill.shape[0], len(cr.omegas)
         n = nw * ng * ng
@@ -123,7 +123,7 @@ def _train(args, train_seeds, ntrunc, nhalf):
         hists.append(h)
     torch.cuda.synchronize()
     t_train = time.time() - t3
-    model = T.TailModel(members, mu, isd, tsc, lo, hi, base=args.base)
+    model = T.TailModel(members, mu, isd, tsc, lo, hi, base=args.base, shift=args.shift)
     model.save(args.out)
     log(f"[tail] trained 2 members in {t_train:.1f} s -> {args.out}")
     return model, t_train, hists, int(X.shape[0])
@@ -176,12 +176,12 @@ def evaluate(model, cr, ntrunc, prec):
     xo.epsinv(chi, q, out=E["trunc"])
     tm.mark()
     chi = _trunc_chi(dc, ntrunc)
-    chi_bg = T.xterm_chi0(dc, ntrunc, chi)
+    chi_bg = T.xterm_chi0(dc, ntrunc, chi, shift=model.shift)
     xo.epsinv(chi_bg, q, out=E["bg"])
     tm.mark()
     if model.base == "bg":    # the network corrects the terminator-corrected sum
         chi = _trunc_chi(dc, ntrunc)
-        chis_in = [chi, T.xterm_chi0(dc, ntrunc, chi)]
+        chis_in = [chi, T.xterm_chi0(dc, ntrunc, chi, shift=model.shift)]
     else:                     # it corrects the truncated sum; the slope is its upper half
         chis_in = T.chi0_blocks(dc, [ntrunc // 2, ntrunc], prec)
     tm.mark()
@@ -222,6 +222,8 @@ def main(argv=None):
     ap.add_argument("--model", default=None, help="evaluate this trained model instead of training one")
     ap.add_argument("--base", default="bg", choices=("trunc", "bg"),
                     help="what the network corrects: the truncated sum or it plus the terminator")
+    ap.add_argument("--shift", type=float, default=1.5,
+                    help="terminator: extrapolar energy above the last explicit band (Ha)")
     args = ap.parse_args(argv)
     from synth import CONFIGS
     spec = CONFIGS[args.workload]
@@ -257,7 +259,7 @@ def main(argv=None):
     summ = dict(workload=args.workload, prec=args.prec, ntrunc=ntrunc, train=len(train_seeds),
                 train_seeds=[train_seeds[0], train_seeds[-1]], test_seeds=test_seeds, samples_per_crystal=args.samples,
                 training_samples=nsamp, epochs=args.epochs, batch=args.batch, model=args.model or args.out,
-                base=model.base, t_train_s=t_train, final_loss=[h[-1] for h in hists],
+                base=model.base, shift=model.shift, t_train_s=t_train, final_loss=[h[-1] for h in hists],
                 median_e_full=med("e_full"), median_e_trunc=med("e_trunc"), median_e_bg=med("e_bg"),
                 median_e_learned=med("e_learned"), worst_e_learned=float(max(r["e_learned"] for r in rows)),
                 median_t_full_ms=med("t_full_ms"), median_t_trunc_ms=med("t_trunc_ms"), median_t_bg_ms=med("t_bg_ms"),
