@@ -336,3 +336,18 @@ def test_tail_predict_argument_errors():
     a.nl = 6                            # more than three hidden 256 -> 256 layers
     rc, msg = _rc(L.xo_tail_predict, a)
     assert rc == xo.XO_ERR_ARG
+
+
+def test_xterm_rejects_unknown_precision():
+    L = xo.lib()
+    a = xo.XtermArgs()
+    mv = np.zeros((1, 3), np.int32)
+    w = np.array([0.5])
+    a.npw_v, a.nv, a.ng, a.nw, a.nn = 1, 1, 1, 1, 1
+    a.mill_v = a.mill_g = mv.ctypes.data_as(C.POINTER(C.c_int32))
+    a.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    a.coef_v = a.e_v = a.rho = a.out = 8   # never dereferenced: validation fails first
+    a.pref, a.ebar = 1.0, 1.0
+    a.prec = 9
+    rc, msg = _rc(L.xo_xterm, a)
+    assert rc == xo.XO_ERR_ARG and "precision" in msg

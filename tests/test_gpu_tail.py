@@ -428,6 +428,41 @@ def test_fused_predict_every_element_vs_oracle(small, nmem):
         assert abs(st[2] - (Yo * Yo).sum()) <= (2 * np.abs(Yo) * Eo + Eo * Eo).sum()
 
 
+@pytest.mark.parametrize("dims", [[9, 256, 2], [9, 256, 256, 2], [9, 256, 256, 256, 256, 2]])
+def test_fused_predict_other_depths(small, dims):
+    """The instantiations for one, two and four hidden layers (no hidden-to-hidden layer, one,
+    three), every element of c4_small within the 6 sigma band of the oracle."""
+    cr, chis, dchis = small
+    members = [flatten_params(mlp_init(dims, s)) for s in (41, 42)]
+    n = chis[1].size
+    raw = _feats(cr, chis[1], chis[0], np.zeros(9, np.float32), np.ones(9, np.float32), np.arange(n))
+    mu = raw.mean(0).astype(np.float32)
+    isd = (1.0 / np.maximum(raw.std(0), 1e-12)).astype(np.float32)
+    X = _feats(cr, chis[1], chis[0], mu, isd, np.arange(n))
+    lo, hi = X.min(0), X.max(0)
+    Yg, st = _run_predict(cr, dchis[1], dchis[0], members, dims, mu, isd, lo, hi)
+    Ys, Es = _oracle_ensemble(members, dims, X)
+    Yo = 0.5 * (Ys[0] + Ys[1])
+    Eo = 6 * 0.5 * np.sqrt(Es[0] ** 2 + Es[1] ** 2) + 2.0 ** -23 * np.abs(Yo)
+    ratio = np.abs(Yg - Yo) / Eo
+    say(f"fused predict dims={dims}: max |err| / 6 sigma {ratio.max():.3f}")
+    assert ratio.max() <= 1.0 and st[0] == 0
+
+
+def test_fused_predict_two_column_blocks_is_bitwise_the_default(small, monkeypatch):
+    """XO_TAIL_NC=2 (four waves, two 32-element blocks each) computes every element with the
+    same arithmetic as the default eight-wave form: bitwise equal outputs and guard sums."""
+    cr, chis, dchis = small
+    members = [flatten_params(mlp_init(T.DIMS, s)) for s in (51, 52)]
+    mu, isd = np.zeros(9, np.float32), np.ones(9, np.float32)
+    lo, hi = np.full(9, -5.0, np.float32), np.full(9, 5.0, np.float32)
+    Y1, s1 = _run_predict(cr, dchis[1], dchis[0], members, T.DIMS, mu, isd, lo, hi)
+    monkeypatch.setenv("XO_TAIL_NC", "2")
+    Y2, s2 = _run_predict(cr, dchis[1], dchis[0], members, T.DIMS, mu, isd, lo, hi)
+    assert np.array_equal(Y1, Y2) and s1[0] == s2[0]
+    assert abs(s1[1] - s2[1]) <= 1e-12 * s1[1] and abs(s1[2] - s2[2]) <= 1e-12 * s1[2]
+
+
 @pytest.fixture(scope="module")
 def c5s_blocks():
     """The large cell's real G-set (NG = 3000, 4 frequencies, 36 M elements): chi0 over 100 and
