@@ -477,13 +477,15 @@ def test_alloc_failure_is_reported_and_recovers():
 
 # ------------------------------------------------------------- batched persistent
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("bf16x3", 2e-4), ("bf16", None)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-5), ("bf16x3", 2e-4), ("bf16", None)])
 @pytest.mark.parametrize("tune", [None, (1, 256, 2), (2, 512, 4), (2, 0, 8), (4, 256, 1), (4, 0, 0), (8, 0, 0),
                                   (8, 256, 1)])
 def test_chi0_batch_uneven_items(prec, tol, tune):
     """Items with different G-set sizes and transition counts in one persistent launch."""
     if prec == "fp64" and tune is not None and tune[0] in (2, 4, 8):
         pytest.skip("two column tiles per wave and the block and panel forms exist for the bf16 forms only")
+    if prec == "fp32" and tune is not None and tune[0] in (4, 8):
+        pytest.skip("the block and panel forms exist for the bf16 forms only (a 2-tile tune runs the 1-tile form)")
     say(f"chi0 batch {prec} tune={tune}")
     shapes = [(700, 17), (1300, 33), (96, 50), (2000, 41)]
     w = [0.0, 0.3, 1.0]
