@@ -230,10 +230,12 @@ int xo_chi0_real(const xo_chi0_real_args* a, void* stream);
  * column blocks with up to 8 frequencies per unit, one wave per transition
  * quarter; nt_tiles 4 (XO_BF16X3 and XO_BF16 only) gives 64 x 64 blocks with 4
  * frequencies per unit and the right operand converted once per workgroup in
- * LDS. With nt_tiles 0 the bf16 forms take the 64 x 64 form when there are at
- * least four frequencies, every other case 16 x 16. items: [host] array. */
+ * LDS; nt_tiles 8 (same forms) gives 64 x 128 strips with 2 frequencies per unit
+ * (half the left-operand conversion per product, twice the right-operand reads).
+ * With nt_tiles 0 the bf16 forms take the 64 x 64 form when there are at least
+ * four frequencies, every other case 16 x 16. items: [host] array. */
 typedef struct {
-  int nt_tiles;   /* 0 (default), 1, 2, or 4 (XO_BF16X3 / XO_BF16 only)           */
+  int nt_tiles;   /* 0 (default), 1, 2, or 4 / 8 (XO_BF16X3 / XO_BF16 only)       */
   int kper;       /* transitions per unit; 0 = chosen to fill the chip            */
   int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 2 (64 x 64), 4   */
 } xo_tune;

@@ -26,6 +26,17 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t&
   const float ah = __builtin_bit_cast(float, hi << 16), bh = __builtin_bit_cast(float, hi & 0xffff0000u);
   lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a - ah, b - bh}, bf2v));
 }
+// (a, b) -> packed hi and lo pairs as split2, and the pairs of the rotation (b, -a) of
+// both, converted from the same values (rounding is odd-symmetric, so they equal
+// rot_pos(hi) and rot_pos(lo))
+__device__ __forceinline__ void split2_rot(float a, float b, uint32_t& hi, uint32_t& lo, uint32_t& rhi,
+                                           uint32_t& rlo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf2v));
+  const float la = a - __builtin_bit_cast(float, hi << 16), lb = b - __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{la, lb}, bf2v));
+  rhi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{b, -a}, bf2v));
+  rlo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{lb, -la}, bf2v));
+}
 // (re, im) -> (-im, re)
 __device__ __forceinline__ uint32_t rot_neg(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16) ^ 0x8000u; }
 // (re, im) -> (im, -re)

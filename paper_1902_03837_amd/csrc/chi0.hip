@@ -585,51 +585,31 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
 }
 
 // ------------------------------------------------------------------------------------------
-// Panel form of the bf16 update on the 32 x 32 x 16 instruction (NP = 3 split, 1 plain).
-// A workgroup (4 waves, one per SIMD) owns a 64-row x 128-column output block and four
-// frequencies per unit; wave r owns all 64 rows and columns 32 r .. 32 r + 31 (two 32 x 32
-// tiles x 4 frequencies x re, im: 16 accumulator tiles, 256 registers). Per step of 16
-// transitions (two k-steps of 8) every thread stages in LDS, in the MFMA fragment layout:
-//   the weighted left operand W_t(w) rho_t(G) of the 64 rows for each of the 4 frequencies,
-//     split into hi and lo once per workgroup (every wave reads all of it);
-//   the right operand rho_t(G') of the 128 columns, split once, with its rotation
-//     (-im, re) for Im as separate planes.
-// The products then read only LDS. Double buffered, one barrier per step; the next
-// step's global loads are in flight during the products.
-// Lane layout of v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8 (l / 32) .. + 7]
-// and B[8 (l / 32) .. + 7][l % 32]; result register r holds
-// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]. K runs over (transition, re / im) pairs, so
-// the k-half l / 32 of a k-step covers transitions 4 (l / 32) .. + 3 of it.
-constexpr int kPRows = 64, kPCols = 128;  // panel block
-constexpr int kPF = 4;                    // frequencies per unit
-constexpr int kPPer = kPF * 2 * kPRows * kPCols;  // partial values per unit (256 per thread)
-
-typedef float f16v __attribute__((ext_vector_type(16)));
-
-__device__ __forceinline__ f16v mma32(u4 a, u4 b, f16v c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
-                                                 0);
-}
+// Strip form of the bf16 update (NP = 3 split, 1 plain). A unit is a 64-row x 128-column
+// block, two frequencies and a transition slice; four waves, wave r owns rows 16 r .. + 15
+// and all eight 16-column tiles (2 frequencies x (re, im) x 8 tiles: 32 accumulators). Each
+// weighted, split left-operand value feeds eight column tiles instead of four, so the split
+// costs half as many instructions per product as in the 64 x 64 form; Im takes the
+// rotation (im, -re) of the left operand, converted in the same split from the same
+// products, so the right operand enters the products as staged. The staging, the
+// transition steps and the loads follow chi0_blocks.
+constexpr int kSRows = 64, kSCols = 128, kSF = 2;
+constexpr int kSPer = kSF * 2 * kSRows * kSCols;  // partial values per unit (128 per thread)
 
 template <int NP>
-struct PanelLds {
-  static constexpr int PA = NP == 3 ? 2 : 1;  // left planes: hi, lo | hi
-  static constexpr int PB = NP == 3 ? 4 : 2;  // right planes: hi, lo, rot hi, rot lo | hi, rot hi
-  u4 A[2][kPF][PA][2][2][2][32];  // [buffer][frequency][plane][k-step][row tile][k-half][row]
-  u4 B[2][PB][2][4][2][32];       // [buffer][plane][k-step][column tile][k-half][column]
-};
-
-template <int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-chi0_panel(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
-           const int* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
-           float* __restrict__ part) {
-  typedef PanelLds<NP> L;
-  extern __shared__ unsigned char smem_raw[];
-  L& S = *reinterpret_cast<L*>(smem_raw);
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+chi0_strips(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
+            const int* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
+            float* __restrict__ part) {
+  constexpr int PB = NP == 3 ? 2 : 1;
+  __shared__ u4 Bs[2][PB][8][4][16];   // [buffer][hi, lo][column tile][q][column]
+  __shared__ float4 As[2][kSRows][9];  // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
+  __shared__ float4 Ws[2][kSF][4];     // [buffer][frequency][transition quad]
   __shared__ int su;
-  const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
+  const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int bc = tid & 127, bh = tid >> 7;  // right-operand slot: column bc, transitions 8 bh .. + 7
+  const int ar = tid & 63, aq = tid >> 6;   // left-operand slot: row ar, transitions 4 aq .. + 3
   // queue segments per XCD, as for chi0_blocks
   int home = blockIdx.x & 7, misses = 0;
   for (;;) {
@@ -657,201 +637,208 @@ chi0_panel(const Item* __restrict__ items, const int2* __restrict__ tiles, const
     const int2 bij = tiles[I.tile0 + U.tile];
     const int ng = I.ng, len = U.k1 - U.k0;
     const int nsteps = (len + 15) / 16;
-    // Buffer loads over the unit's transition slice (the host keeps len * ng * 8 below 2^31):
-    // rows past the slice are outside the buffer and read as zero (so do their weights); G
-    // past the G-set reads G = ng - 1 and lands in outputs the reduction drops. The
-    // per-thread part of an address is one VGPR offset; the step and the transition within
-    // a quad go into the scalar offset.
-    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v)), 0,
-        (unsigned)len * ng * (unsigned)sizeof(f2v), 0x00020000);
-    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(static_cast<const float*>(I.W) + (size_t)U.k0 * I.nwpad + U.w0), 0,
-        (unsigned)len * I.nwpad * (unsigned)sizeof(float), 0x00020000);
-    const unsigned trow = (unsigned)ng * sizeof(f2v), wrow = (unsigned)I.nwpad * sizeof(float);
-    // left slot of this thread: row ar, transitions 4 aq .. + 3 of the step (k-step aq / 2,
-    // k-half aq % 2); right slot: column bc, transitions 8 bs .. + 7 (k-step bs)
-    const int ar = tid & 63, aq = tid >> 6;
-    const int bc = tid & 127, bs = tid >> 7;
-    const unsigned Ga = min(bij.x * kPRows + ar, ng - 1), Gb = min(bij.y * kPCols + bc, ng - 1);
-    const unsigned va = Ga * (unsigned)sizeof(f2v) + 4u * aq * trow;
-    const unsigned vb = Gb * (unsigned)sizeof(f2v) + 8u * bs * trow;
-    const unsigned vw = 4u * aq * wrow;
-
-    f2v ra[4], rb[8];
-    float4 wq[4];
-    auto load = [&](int st) {
-      const unsigned d = (unsigned)st * 16u * trow, dw = (unsigned)st * 16u * wrow;
+    // 16 x 16 tiles of this wave: inside the G-set and not wholly below the diagonal
+    const int r0 = bij.x * kSRows + 16 * wave;
+    int nmask = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ra[u] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rr, va, d + u * trow, 0));
-        wq[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rw, vw, dw + u * wrow, 0));
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        rb[u] = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(rr, vb, d + u * trow, 0));
-    };
-    // stage the loaded step into buffer b
-    auto store = [&](int b) {
-#pragma unroll
-      for (int f = 0; f < kPF; ++f) {
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float w = f == 0 ? wq[u].x : (f == 1 ? wq[u].y : (f == 2 ? wq[u].z : wq[u].w));
-          split2(w * ra[u].x, w * ra[u].y, hi[u], lo[u]);
-        }
-        S.A[b][f][0][aq >> 1][ar >> 5][aq & 1][ar & 31] = u4{hi[0], hi[1], hi[2], hi[3]};
-        if constexpr (NP == 3) S.A[b][f][1][aq >> 1][ar >> 5][aq & 1][ar & 31] = u4{lo[0], lo[1], lo[2], lo[3]};
-      }
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh) {
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) split2(rb[4 * hh + u].x, rb[4 * hh + u].y, hi[u], lo[u]);
-        S.B[b][0][bs][bc >> 5][hh][bc & 31] = u4{hi[0], hi[1], hi[2], hi[3]};
-        if constexpr (NP == 3) {
-          S.B[b][1][bs][bc >> 5][hh][bc & 31] = u4{lo[0], lo[1], lo[2], lo[3]};
-          S.B[b][2][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(hi[0]), rot_neg(hi[1]), rot_neg(hi[2]), rot_neg(hi[3])};
-          S.B[b][3][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(lo[0]), rot_neg(lo[1]), rot_neg(lo[2]), rot_neg(lo[3])};
-        } else {
-          S.B[b][1][bs][bc >> 5][hh][bc & 31] = u4{rot_neg(hi[0]), rot_neg(hi[1]), rot_neg(hi[2]), rot_neg(hi[3])};
-        }
-      }
-    };
-    f16v acc[kPF][2][2];  // [frequency][re, im][row tile]
-#pragma unroll
-    for (int f = 0; f < kPF; ++f)
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[f][r][t] = f16v{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    load(0);
-    store(0);
-    if (nsteps > 1) load(1);
-    __syncthreads();
-    // products of the step in buffer b: per k-step all fragments of the step are read, then
-    // the products go in rounds (hi x hi, hi x lo, lo x hi) over all 16 accumulator tiles, so
-    // that consecutive products into one tile are 16 instructions apart
-    auto products = [&](int b) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        u4 bf[L::PB];
-#pragma unroll
-        for (int p = 0; p < L::PB; ++p) bf[p] = S.B[b][p][s][wave][h][li];
-        u4 a[kPF][L::PA][2];
-#pragma unroll
-        for (int f = 0; f < kPF; ++f)
-#pragma unroll
-          for (int p = 0; p < L::PA; ++p)
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt) a[f][p][rt] = S.A[b][f][p][s][rt][h][li];
-        // Re through the right operand, Im through its rotation (plane PB / 2 onwards)
-        constexpr int ROT = L::PB / 2;
-#pragma unroll
-        for (int f = 0; f < kPF; ++f)
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt) {
-            acc[f][0][rt] = mma32(a[f][0][rt], bf[0], acc[f][0][rt]);
-            acc[f][1][rt] = mma32(a[f][0][rt], bf[ROT], acc[f][1][rt]);
-          }
-        if constexpr (NP == 3) {
-#pragma unroll
-          for (int f = 0; f < kPF; ++f)
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-              acc[f][0][rt] = mma32(a[f][0][rt], bf[1], acc[f][0][rt]);
-              acc[f][1][rt] = mma32(a[f][0][rt], bf[ROT + 1], acc[f][1][rt]);
-            }
-#pragma unroll
-          for (int f = 0; f < kPF; ++f)
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt) {
-              acc[f][0][rt] = mma32(a[f][1][rt], bf[0], acc[f][0][rt]);
-              acc[f][1][rt] = mma32(a[f][1][rt], bf[ROT], acc[f][1][rt]);
-            }
-        }
-      }
-    };
-    for (int k = 0; k < nsteps; ++k) {
-      const int b = k & 1;
-      // every wave computes both row tiles: a tile wholly below the diagonal or past the
-      // G-set (only in blocks on the diagonal or at the edge) is computed and dropped by the
-      // reduction, which keeps the accumulators in one straight-line instruction stream
-      products(b);
-      if (k + 1 < nsteps) store(b ^ 1);
-      if (k + 2 < nsteps) load(k + 2);
-      __syncthreads();
+    for (int n = 0; n < 8; ++n) {
+      const int c0 = bij.y * kSCols + 16 * n;
+      if (r0 < ng && c0 < ng && c0 >= r0) nmask |= 1 << n;
     }
-    // partials of this thread, contiguous: [frequency][re, im][row tile] x 16 registers
-    f16v* out = reinterpret_cast<f16v*>(part + ((size_t)uid * 256 + tid) * (kPF * 2 * 2 * 16));
+    // Loads address the unit's transition slice by 32-bit byte offsets (the host keeps
+    // len * ng * 8 below 2^31); rows past the slice and G past the G-set are clamped to
+    // valid entries: the former carry a zero weight, the latter land in outputs the
+    // reduction drops.
+    const char* rbase = static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v);
+    const char* wbase = static_cast<const char*>(I.W) + ((size_t)U.k0 * I.nwpad + U.w0) * sizeof(float);
+    const unsigned trow = (unsigned)ng * sizeof(f2v), rstep = 16u * trow, wstep = 16u * I.nwpad * sizeof(float);
+    const unsigned Ga = min(bij.x * kSRows + ar, ng - 1), Gb = min(bij.y * kSCols + bc, ng - 1);
+    const unsigned amax = ((unsigned)(len - 1) * ng + Ga) * sizeof(f2v);
+    const unsigned bmax = ((unsigned)(len - 1) * ng + Gb) * sizeof(f2v);
+    const unsigned oa = ((unsigned)(4 * aq) * ng + Ga) * sizeof(f2v);
+    const unsigned ob = ((unsigned)(8 * bh) * ng + Gb) * sizeof(f2v);
+    // frequency factors: transition wt, frequency wf of the unit's two (every wave issues
+    // the same loads; the first 32 threads store them); rows past the slice read its last
+    // row and are zeroed when stored
+    const int wt = tid & 15, wf = (tid >> 4) & 1;
+    const unsigned ow = ((unsigned)wt * I.nwpad + wf) * sizeof(float);
+    const unsigned wmax = ((unsigned)(len - 1) * I.nwpad + wf) * sizeof(float);
+
+    f2v raA[4], rbA[8], raB[4], rbB[8];
+    float wvA = 0.f, wvB = 0.f;
+    // ---- load step s into register set (ra, rb, wv)
+#define CHI0_STR_LOAD(s_, ra_, rb_, wv_)                                                    \
+    {                                                                                       \
+      const unsigned d_ = (unsigned)(s_) * rstep;                                           \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) ra_[u] = gld<f2v>(rbase + min(oa + (d_ + u * trow), amax)); \
+      _Pragma("unroll") for (int u = 0; u < 8; ++u) rb_[u] = gld<f2v>(rbase + min(ob + (d_ + u * trow), bmax)); \
+      wv_ = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));                     \
+    }
+    // ---- store step s from register set (ra, rb, wv) into buffer b
+#define CHI0_STR_STORE(b_, s_, ra_, rb_, wv_)                                               \
+    {                                                                                       \
+      _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                       \
+        uint32_t h_[4], l_[4];                                                              \
+        _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb_[4 * h + u].x, rb_[4 * h + u].y, h_[u], l_[u]); \
+        Bs[b_][0][bc >> 4][2 * bh + h][bc & 15] = u4{h_[0], h_[1], h_[2], h_[3]};           \
+        if constexpr (NP == 3) Bs[b_][1][bc >> 4][2 * bh + h][bc & 15] = u4{l_[0], l_[1], l_[2], l_[3]}; \
+      }                                                                                     \
+      As[b_][ar][2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);              \
+      As[b_][ar][2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y);          \
+      if (tid < 32) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 16 * (s_) + wt < len ? wv_ : 0.f; \
+    }
+    f4 acc[kSF][2][8];
 #pragma unroll
-    for (int f = 0; f < kPF; ++f)
+    for (int f = 0; f < kSF; ++f)
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) out[(f * 2 + r) * 2 + t] = acc[f][r][t];
+        for (int n = 0; n < 8; ++n) acc[f][r][n] = f4{0.f, 0.f, 0.f, 0.f};
+    // products of the step held in buffer buf
+    auto products = [&](int buf) {
+      if (!nmask) return;
+      // weighted left operand of both frequencies and its rotation, converted once and
+      // shared by the eight column tiles
+      const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
+      u4 ah[kSF], al[kSF], rh[kSF], rl[kSF];
+#pragma unroll
+      for (int f = 0; f < kSF; ++f) {
+        const float4 wq = Ws[buf][f][q];
+        uint32_t h[4], l[4], x[4], y[4];
+        split2_rot(wq.x * a01.x, wq.x * a01.y, h[0], l[0], x[0], y[0]);
+        split2_rot(wq.y * a01.z, wq.y * a01.w, h[1], l[1], x[1], y[1]);
+        split2_rot(wq.z * a23.x, wq.z * a23.y, h[2], l[2], x[2], y[2]);
+        split2_rot(wq.w * a23.z, wq.w * a23.w, h[3], l[3], x[3], y[3]);
+        ah[f] = u4{h[0], h[1], h[2], h[3]};
+        al[f] = u4{l[0], l[1], l[2], l[3]};
+        rh[f] = u4{x[0], x[1], x[2], x[3]};
+        rl[f] = u4{y[0], y[1], y[2], y[3]};
+      }
+      // column tiles: Re through the left operand, Im through its rotation; the next
+      // tile's right operand is read ahead of the products
+      u4 b0 = Bs[buf][0][0][q][i], b1 = b0;
+      if constexpr (NP == 3) b1 = Bs[buf][1][0][q][i];
+#pragma unroll
+      for (int n = 0; n < 8; ++n) {
+        u4 nb0 = b0, nb1 = b1;
+        if (n < 7) {
+          nb0 = Bs[buf][0][n + 1][q][i];
+          if constexpr (NP == 3) nb1 = Bs[buf][1][n + 1][q][i];
+        }
+        if (nmask & (1 << n)) {
+#pragma unroll
+          for (int f = 0; f < kSF; ++f) {
+            acc[f][0][n] = mma_np<NP>(ah[f], al[f], b0, b1, acc[f][0][n]);
+            acc[f][1][n] = mma_np<NP>(rh[f], rl[f], b0, b1, acc[f][1][n]);
+          }
+        }
+        b0 = nb0;
+        b1 = nb1;
+      }
+    };
+    CHI0_STR_LOAD(0, raA, rbA, wvA);
+    CHI0_STR_STORE(0, 0, raA, rbA, wvA);
+    if constexpr (NP == 1) {
+      // step k sits in buffer k % 2; entering an even k, step k + 1 is in set B and
+      // step k + 2 in set A
+      CHI0_STR_LOAD(1, raB, rbB, wvB);
+      CHI0_STR_LOAD(2, raA, rbA, wvA);
+      __syncthreads();
+      for (int k = 0; k < nsteps; k += 2) {
+        products(0);
+        if (k + 1 < nsteps) CHI0_STR_STORE(1, k + 1, raB, rbB, wvB);
+        __syncthreads();
+        if (k + 1 >= nsteps) break;
+        CHI0_STR_LOAD(k + 3, raB, rbB, wvB);
+        products(1);
+        if (k + 2 < nsteps) CHI0_STR_STORE(0, k + 2, raA, rbA, wvA);
+        __syncthreads();
+        CHI0_STR_LOAD(k + 4, raA, rbA, wvA);
+      }
+    } else {
+      // the split form has no registers for a second set: one step ahead
+      __syncthreads();
+      for (int k = 0; k < nsteps; ++k) {
+        const int buf = k & 1;
+        if (k + 1 < nsteps) CHI0_STR_LOAD(k + 1, raA, rbA, wvA);
+        products(buf);
+        if (k + 1 < nsteps) CHI0_STR_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
+        __syncthreads();
+      }
+    }
+#undef CHI0_STR_LOAD
+#undef CHI0_STR_STORE
+    // partials of this thread, contiguous: [frequency][re, im][column tile] x 4 rows
+    f4* out = reinterpret_cast<f4*>(part + ((size_t)uid * 256 + tid) * (kSF * 2 * 8 * 4));
+#pragma unroll
+    for (int f = 0; f < kSF; ++f)
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int n = 0; n < 8; ++n) out[(f * 2 + r) * 8 + n] = acc[f][r][n];
   }
 }
 
-// Fixed-order sum of the panel partials of one output block and frequency. Thread t reads
-// what thread t of chi0_panel wrote: rows 32 rt + 8 (e / 4) + 4 ((t % 64) / 32) + e % 4,
-// column 32 (t / 64) + t % 32.
-__global__ void __launch_bounds__(256) chi0_reduce_panel(const Item* __restrict__ items,
-                                                         const int2* __restrict__ tiles,
-                                                         const Red* __restrict__ reds,
-                                                         const float* __restrict__ part) {
+// Write one reduced element of the upper half and its Hermitian mirror: chi0 = -pref * sum.
+__device__ __forceinline__ void put_pair(const Item& I, double* m, int G, int Gp, double sre, double sim) {
+  const double vr = -I.pref * sre;
+  const double vi = G == Gp ? 0.0 : -I.pref * sim;
+  const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
+  if (I.accumulate) {
+    m[up] += vr;
+    m[up + 1] += vi;
+    if (G != Gp) {
+      m[lo] += vr;
+      m[lo + 1] -= vi;
+    }
+  } else {
+    m[up] = vr;
+    m[up + 1] = vi;
+    if (G != Gp) {
+      m[lo] = vr;
+      m[lo + 1] = -vi;
+    }
+  }
+}
+
+// Fixed-order sum of the strip partials of one output block and frequency. Thread t reads
+// what thread t of chi0_strips wrote: rows 16 (t / 64) + 4 q + e, columns 16 n + i, with
+// i = t % 16, q = (t % 64) / 16.
+__global__ void __launch_bounds__(256) chi0_reduce_strips(const Item* __restrict__ items,
+                                                          const int2* __restrict__ tiles,
+                                                          const Red* __restrict__ reds,
+                                                          const float* __restrict__ part) {
   const Red R = reds[blockIdx.x];
   const int w = blockIdx.y;
   const Item I = items[R.item];
   if (R.w0 + w >= I.nw) return;
   const int2 bij = tiles[I.tile0 + R.tile];
-  const int t = threadIdx.x, li = t & 31, h = (t >> 5) & 1, wave = t >> 6;
-  double re[2][16], im[2][16];
+  const int t = threadIdx.x, i = t & 15, q = (t >> 4) & 3, wave = t >> 6;
+  double re[8][4], im[8][4];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int n = 0; n < 8; ++n)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) re[rt][e] = im[rt][e] = 0.0;
+    for (int e = 0; e < 4; ++e) re[n][e] = im[n][e] = 0.0;
   for (int u = 0; u < R.nu; ++u) {
-    const f16v* p =
-        reinterpret_cast<const f16v*>(part + ((size_t)(R.u0 + u) * 256 + t) * (kPF * 2 * 2 * 16)) + w * 4;
+    const f4* p = reinterpret_cast<const f4*>(part + ((size_t)(R.u0 + u) * 256 + t) * (kSF * 2 * 8 * 4)) + w * 16;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const f16v a = p[rt], b = p[2 + rt];
+    for (int n = 0; n < 8; ++n) {
+      const f4 a = p[n], b = p[8 + n];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        re[rt][e] += (double)a[e];
-        im[rt][e] += (double)b[e];
+      for (int e = 0; e < 4; ++e) {
+        re[n][e] += (double)a[e];
+        im[n][e] += (double)b[e];
       }
     }
   }
   double* m = I.chi0 + (size_t)(R.w0 + w) * I.ng * I.ng * 2;
-  const int Gp = bij.y * kPCols + 32 * wave + li;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int n = 0; n < 8; ++n)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int G = bij.x * kPRows + 32 * rt + 8 * (e >> 2) + 4 * h + (e & 3);
+    for (int e = 0; e < 4; ++e) {
+      const int G = bij.x * kSRows + 16 * wave + 4 * q + e, Gp = bij.y * kSCols + 16 * n + i;
       if (G >= I.ng || Gp >= I.ng || G > Gp) continue;
-      const double vr = -I.pref * re[rt][e];
-      const double vi = G == Gp ? 0.0 : -I.pref * im[rt][e];
-      const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
-      if (I.accumulate) {
-        m[up] += vr;
-        m[up + 1] += vi;
-        if (G != Gp) {
-          m[lo] += vr;
-          m[lo + 1] -= vi;
-        }
-      } else {
-        m[up] = vr;
-        m[up + 1] = vi;
-        if (G != Gp) {
-          m[lo] = vr;
-          m[lo + 1] = -vi;
-        }
-      }
+      put_pair(I, m, G, Gp, re[n][e], im[n][e]);
     }
 }
 
@@ -891,34 +878,17 @@ __global__ void __launch_bounds__(256) chi0_reduce_blocks(const Item* __restrict
     for (int e = 0; e < 4; ++e) {
       const int G = bij.x * kBlk + 16 * wave + 4 * q + e, Gp = bij.y * kBlk + 16 * n + i;
       if (G >= I.ng || Gp >= I.ng || G > Gp) continue;
-      const double vr = -I.pref * re[n][e];
-      const double vi = G == Gp ? 0.0 : -I.pref * im[n][e];
-      const size_t up = ((size_t)G * I.ng + Gp) * 2, lo = ((size_t)Gp * I.ng + G) * 2;
-      if (I.accumulate) {
-        m[up] += vr;
-        m[up + 1] += vi;
-        if (G != Gp) {
-          m[lo] += vr;
-          m[lo + 1] -= vi;
-        }
-      } else {
-        m[up] = vr;
-        m[up + 1] = vi;
-        if (G != Gp) {
-          m[lo] = vr;
-          m[lo + 1] = -vi;
-        }
-      }
+      put_pair(I, m, G, Gp, re[n][e], im[n][e]);
     }
 }
 
 // --------------------------------------------------------------- host side --
 
-// Default block form of the bf16 updates: the 64 x 64 blocks (4) unless XO_CHI0_FORM=panel
-// (the 64 x 128 panel, 8).
+// Default form of the bf16 updates: the 64 x 64 blocks (4) unless XO_CHI0_FORM=strips
+// (the 64 x 128 strips, 8).
 int default_block_form() {
   const char* e = std::getenv("XO_CHI0_FORM");
-  if (e && !std::strcmp(e, "panel")) return 8;
+  if (e && !std::strcmp(e, "strips")) return 8;
   return 4;
 }
 
@@ -1015,18 +985,18 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
   const int mode = prec == XO_FP64 ? MODE_F64 : (prec == XO_FP32 ? MODE_F32 : (prec == XO_BF16 ? MODE_BF16 : MODE_BF16X3));
   const size_t tsz = mode == MODE_F64 ? sizeof(double) : sizeof(float);
   const int nw = a[0].nw;
-  // bf16 forms: the 64 x 64 block form (nt_tiles 4) or the 64 x 128 panel form (nt_tiles 8)
-  // once there are four frequencies to share them; XO_CHI0_FORM=blocks|panel picks the
-  // default between the two
+  // bf16 forms: the 64 x 64 block form (nt_tiles 4, four frequencies per unit) or the
+  // 64 x 128 strip form (nt_tiles 8, two frequencies per unit) once there are four
+  // frequencies; XO_CHI0_FORM=blocks|strips picks the default between the two
   const int pick = (tune && tune->nt_tiles) ? tune->nt_tiles : (nw >= kBW ? default_block_form() : 1);
   const bool blk = is_bf(mode) && (pick == 4 || pick == 8);
-  const bool pnl = blk && pick == 8;
-  const int nwg = blk ? kBW : (nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1)));
+  const bool str = blk && pick == 8;
+  const int nwg = str ? kSF : (blk ? kBW : (nw >= 8 ? 8 : (nw >= 4 ? 4 : (nw >= 2 ? 2 : 1))));
   const int ngroups = (nw + nwg - 1) / nwg;
   const int nwpad = ngroups * nwg;
   const int NT = (tune && is_bf(mode) && tune->nt_tiles == 2) ? 2 : 1;
-  const int grid_per_cu = pnl ? 1 : ((tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4));
-  const int brow = pnl ? kPRows : (blk ? kBlk : kTile), bcol = pnl ? kPCols : (blk ? kBlk : kTile * NT);
+  const int grid_per_cu = (tune && tune->wg_per_cu > 0) ? tune->wg_per_cu : (blk ? 2 : 4);
+  const int brow = str ? kSRows : (blk ? kBlk : kTile), bcol = str ? kSCols : (blk ? kBlk : kTile * NT);
 
   // block pairs: brow-row block i, bcol-column block j, keeping those with a column >= a row
   std::vector<int2> tiles;
@@ -1088,11 +1058,11 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     const int2 b = tiles[items[u.item].tile0 + u.tile];
     const int ng = a[u.item].ng;
     int c = 0;
-    if (pnl) {  // 32 x 32 tiles, each worth four 16 x 16 ones
-      for (int w = 0; w < 4; ++w)
-        for (int rt = 0; rt < 2; ++rt) {
-          const int r0 = b.x * kPRows + 32 * rt, c0 = b.y * kPCols + 32 * w;
-          c += 4 * (r0 < ng && c0 < ng && c0 + 31 >= r0);
+    if (str) {
+      for (int r = 0; r < 4; ++r)
+        for (int m = 0; m < 8; ++m) {
+          const int r0 = b.x * kSRows + 16 * r, c0 = b.y * kSCols + 16 * m;
+          c += r0 < ng && c0 < ng && c0 >= r0;
         }
       return c;
     }
@@ -1136,7 +1106,7 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     qoff[8] = (int)queue.size();
   }
   const int nunits = (int)units.size();
-  const size_t per = pnl ? (size_t)kPPer * sizeof(float)
+  const size_t per = str ? (size_t)kSPer * sizeof(float)
                          : (blk ? (size_t)kBlkPer * sizeof(float) : (size_t)kWaves * nwg * 2 * NT * 256 * tsz);
   const size_t pbytes = per * nunits;
   bool any_check = false;
@@ -1219,19 +1189,10 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
     XO_RET(device_table(qoff, sizeof(qoff), s, &dqoff));
     hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, counter, 8);
     XO_CHECK_LAUNCH();
-    if (pnl) {
-      const size_t lds = mode == MODE_BF16 ? sizeof(PanelLds<1>) : sizeof(PanelLds<3>);
-      static bool attr = false;
-      if (!attr) {
-        XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&chi0_panel<1>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(PanelLds<1>)));
-        XO_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&chi0_panel<3>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(PanelLds<3>)));
-        attr = true;
-      }
+    if (str) {
       {
-        KernelTimer kt_(mode == MODE_BF16 ? "chi0_panel_bf16" : "chi0_panel_bf16x3", s);
-        hipLaunchKernelGGL(mode == MODE_BF16 ? chi0_panel<1> : chi0_panel<3>, dim3(grid), dim3(256), lds, s,
+        KernelTimer kt_(mode == MODE_BF16 ? "chi0_strips_bf16" : "chi0_strips_bf16x3", s);
+        hipLaunchKernelGGL(mode == MODE_BF16 ? chi0_strips<1> : chi0_strips<3>, dim3(grid), dim3(256), 0, s,
                            static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
                            static_cast<const Unit*>(dunits), static_cast<const int*>(dqueue),
                            static_cast<const int*>(dqoff), counter, static_cast<float*>(part));
@@ -1239,7 +1200,7 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
       XO_CHECK_LAUNCH();
       {
         KernelTimer kt_("chi0_reduce", s);
-        hipLaunchKernelGGL(chi0_reduce_panel, dim3(nreds, kPF), dim3(256), 0, s, static_cast<const Item*>(ditems),
+        hipLaunchKernelGGL(chi0_reduce_strips, dim3(nreds, kSF), dim3(256), 0, s, static_cast<const Item*>(ditems),
                            static_cast<const int2*>(dtiles), static_cast<const Red*>(dreds),
                            static_cast<const float*>(part));
       }
@@ -1387,7 +1348,7 @@ extern "C" int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best,
       for (int wpc : {1, 2, 4, 8}) {
         if (kper > 0 && kper / 2 > ntmax) continue;
         if ((wpc == 1) != (nt >= 4) && wpc < 2) continue;  // one workgroup per CU only for the block forms
-        if (nt == 8 && wpc != 1) continue;                  // the panel form runs one per CU
+        if (nt == 8 && wpc > 2) continue;                   // the strip form fits two per CU
         cands.push_back({nt, kper, wpc});
       }
   hipEvent_t e0, e1;

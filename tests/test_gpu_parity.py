@@ -257,8 +257,8 @@ def test_chi0_reduced_precision_random(prec, tol, nt, ng, nw):
                                            (300, 129, 4, (4, 0, 0))])
 def test_chi0_bf16_edges(prec, nt, ng, nw, tune):
     """Degenerate and ragged shapes of the bf16 forms: one transition, one G-vector, one
-    frequency in the 64 x 64 block form and the 64 x 128 panel form (three padded frequency
-    slots), G-sets one past a block edge, transition slices shorter than a step; within the
+    frequency in the 64 x 64 block form (three padded frequency slots) and the 64 x 128
+    strip form (one), G-sets one past a block edge, transition slices shorter than a step; within the
     bf16 rounding bound (plain) or 2e-4 (split), exactly Hermitian."""
     say(f"chi0 {prec} edge nt={nt} ng={ng} nw={nw} tune={tune}")
     M = random_complex(300 + nt, (nt, ng)).astype(np.complex64).astype(np.complex128)
@@ -483,9 +483,9 @@ def test_alloc_failure_is_reported_and_recovers():
 def test_chi0_batch_uneven_items(prec, tol, tune):
     """Items with different G-set sizes and transition counts in one persistent launch."""
     if prec == "fp64" and tune is not None and tune[0] in (2, 4, 8):
-        pytest.skip("two column tiles per wave and the block and panel forms exist for the bf16 forms only")
+        pytest.skip("two column tiles per wave and the block and strip forms exist for the bf16 forms only")
     if prec == "fp32" and tune is not None and tune[0] in (4, 8):
-        pytest.skip("the block and panel forms exist for the bf16 forms only (a 2-tile tune runs the 1-tile form)")
+        pytest.skip("the block and strip forms exist for the bf16 forms only (a 2-tile tune runs the 1-tile form)")
     say(f"chi0 batch {prec} tune={tune}")
     shapes = [(700, 17), (1300, 33), (96, 50), (2000, 41)]
     w = [0.0, 0.3, 1.0]
