@@ -31,3 +31,14 @@ def mlp_init(dims, seed):
 def flatten_params(params) -> np.ndarray:
     """Per layer W [out][in] row-major then b [out], as one FP32 vector."""
     return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in params]).astype(np.float32)
+
+
+def device_random_rho(seed: int, nt: int, ng: int, dtype, device, scale: float = 0.02):
+    """Seeded complex strengths [nt][ng] and pole energies [nt] (uniform in [0.05, 5.05) Ha)
+    generated on the device by torch's counter-based generator, for inputs too large to build
+    on the host (a full large-cell transition set). Real and imaginary parts ~ N(0, scale^2/2)."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(seed)
+    M = torch.randn((nt, ng), dtype=dtype, device=device, generator=g) * scale
+    dE = torch.rand(nt, dtype=torch.float64, device=device, generator=g) * 5.0 + 0.05
+    return M, dE

@@ -1,7 +1,8 @@
-"""The benchmark workload at full size (c2: 64 k-pairs, 16 + 200 bands, 36^3, NG = 400, 8
-frequencies, K = 204 800), in the launch configuration bench.py times: sampled columns of
-rho and of chi0 against the oracle computed column by column, and properties of eps~^-1
-that hold at any size."""
+"""The benchmark workloads at full size, in the launch configuration bench.py times: c2 (64
+k-pairs, 16 + 200 bands, 36^3, NG = 400, 8 frequencies, K = 204 800) with sampled columns of
+rho and of chi0 against the oracle computed column by column and properties of eps~^-1 that
+hold at any size; the large cell at its real G-set and grid with fewer bands; and chi0 at the
+large cell's full shape (K = 2 048 000, NG = 3000, 16 frequencies) on sampled elements."""
 
 import numpy as np
 import pytest
@@ -191,3 +192,41 @@ def test_c2_eps_every_form_vs_oracle(c2_oracle_eps, prec, gate):
     assert e_f <= gate
     if prec == "fp64":
         assert e_f < 1e-11
+
+
+# --------------------------------------------------------------------------------------
+# chi0 at the full large-cell shape (K = 2 048 000 transitions, NG = 3000, the 16 imaginary
+# frequencies of the workload), through the same call and automatic unit slicing bench.py
+# times. The strengths are seeded random numbers drawn on the device (49 GB in complex64);
+# the oracle sums all 2 048 000 transitions for the sampled (G, G') pairs, which span the
+# first and last 64-blocks, the diagonal and the ragged edge of the G-set. Tolerances as in
+# the random chi0 tests: FP64 1e-12, FP32 2e-5 and split bf16 2e-4 of the largest sampled
+# element. The whole result is exactly Hermitian.
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 2e-4), ("fp32", 2e-5), ("fp64", 1e-12)])
+def test_chi0_full_large_cell_shape_sampled(prec, tol):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from synth.rand import device_random_rho
+    from synth.crystal import frequencies
+    xo.lib()
+    K, NG = 2_048_000, 3000
+    w = frequencies(16)
+    dev = torch.device("cuda:0")
+    say(f"chi0 at the full large-cell shape, {prec}: K={K}, NG={NG}, 16 frequencies")
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    M, dE = device_random_rho(11, K, NG, dt, dev)
+    out = torch.empty((len(w), NG, NG), dtype=torch.complex128, device=dev)
+    xo.chi0(M, dE, w, 1.0, out=out, prec=prec, check_dE=False)
+    torch.cuda.synchronize()
+    herm = bool(torch.equal(out, out.conj().transpose(1, 2)))
+    Ms = M[:, C5S].cpu().numpy().astype(np.complex128)
+    dEs = dE.cpu().numpy()
+    got = out[:, C5S][:, :, C5S].cpu().numpy()
+    del M, dE, out
+    torch.cuda.empty_cache()
+    ref = chi0_from_rho(Ms, dEs, w, 1.0)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"  sampled chi0 err {err:.2e} (tolerance {tol:.0e}), exactly Hermitian: {herm}")
+    assert herm
+    assert err < tol
