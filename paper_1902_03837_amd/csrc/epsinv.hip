@@ -7,8 +7,9 @@
 // launches; the diagonal blocks are inverted without pivoting (positive definite
 // input) or, with XO_EPS_LU_FALLBACK (general eps~), with partial pivoting inside
 // the block. Per block column K (width b = 64):
-//   P = A_KK^-1                      diag_block: one workgroup per frequency, the
-//                                    block in registers, one barrier per pivot
+//   P = A_KK^-1                      diag_inverse: one workgroup per frequency, the
+//                                    block in registers, one barrier per pivot pair
+//                                    (one per pivot with pivoting)
 //   A_Kj = P A_Kj  (j outside K)     row_col: row half-tiles of the panel, and
 //   S_iK = A_iK,  A_iK = -A_iK P     column half-tiles (old column saved in S)
 //   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update, 32 x 32 tiles
@@ -77,15 +78,12 @@ __global__ void eps_absmax(const double* __restrict__ A, int n, unsigned long lo
 // In-place Gauss-Jordan inverse of the kb x kb diagonal block K of every matrix
 // (kb <= 64). 4096 / E threads per frequency: thread t holds row t / (64 / E),
 // columns E (t % (64 / E)) .. + E - 1 in registers (identity outside kb). Per
-// pivot k the owners publish column k and the pivot row (values before the step) in
-// LDS, double buffered, and every thread updates its own E entries. The pivot row
+// pivot k (per pivot pair in diag_block_pairs) the owners publish column k and the
+// pivot row (values before the step) in LDS, double buffered, and every thread updates its own E entries. The pivot row
 // is stored transposed ([j][column group]) so that a wave reads it without bank
 // conflicts.
 //
-// PIV = false (Hermitian positive definite eps~): the pivot of column k is row k,
-// one barrier per pivot; the pivots are the diagonal of eps~ = L D L^H, so a pivot
-// with non-positive real part proves eps~ is not positive definite (flagged).
-// PIV = true (general eps~, real frequencies): partial pivoting inside the block.
+// This form (general eps~, real frequencies) pivots partially inside the block.
 // The pivot of column k is the row of largest modulus among the rows not yet used;
 // rows stay in place (the sweep is applied to row p_k and column k), so the result
 // R holds R[p_k][j] = B^-1[k][p_j] (B the block) and is written back with that
@@ -94,13 +92,13 @@ __global__ void eps_absmax(const double* __restrict__ A, int n, unsigned long lo
 // (flagged): the blocked elimination has no pivoting across blocks, so the caller gets
 // an error instead of an inaccurate inverse.
 // The body runs on the kB * kB / E threads of a workgroup for the matrix A of frequency w.
-template <int E, bool PIV>
-__device__ __forceinline__ void diag_block(z* __restrict__ A, int n, int K, int kb, int check_sign, int w,
-                                           int* __restrict__ flag, const unsigned long long* __restrict__ gmax2) {
+template <int E>
+__device__ __forceinline__ void diag_block_lu(z* __restrict__ A, int n, int K, int kb, int w,
+                                              int* __restrict__ flag, const unsigned long long* __restrict__ gmax2) {
   constexpr int CG = kB / E;  // column groups
   __shared__ z pcol[2][kB];
   __shared__ z prow[2][E][CG];
-  __shared__ int perm[kB], inv[kB];   // PIV: pivot row of column k, and its inverse
+  __shared__ int perm[kB], inv[kB];   // pivot row of column k, and its inverse
   __shared__ double wmax[kB * kB / E / 64];
   const int o = K * kB;
   const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq, lane = t & 63;
@@ -110,49 +108,44 @@ __device__ __forceinline__ void diag_block(z* __restrict__ A, int n, int K, int 
   for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
     a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
-    if (PIV && r < kb && c < kb) amax = fmax(amax, a[j].x * a[j].x + a[j].y * a[j].y);
+    if (r < kb && c < kb) amax = fmax(amax, a[j].x * a[j].x + a[j].y * a[j].y);
   }
-  double thr2 = 0.0;  // PIV: squared singularity threshold
-  if constexpr (PIV) {
-    for (int m = 32; m >= 1; m >>= 1) amax = fmax(amax, __shfl_xor(amax, m, 64));
-    if (lane == 0) wmax[t >> 6] = amax;
-    __syncthreads();
-    amax = 0.0;
+  // squared singularity threshold
+  for (int m = 32; m >= 1; m >>= 1) amax = fmax(amax, __shfl_xor(amax, m, 64));
+  if (lane == 0) wmax[t >> 6] = amax;
+  __syncthreads();
+  amax = 0.0;
 #pragma unroll
-    for (int i = 0; i < kB * kB / E / 64; ++i) amax = fmax(amax, wmax[i]);
-    thr2 = 1e-26 * fmax(amax, __longlong_as_double(gmax2[w]));
-  }
-  uint64_t used = 0;  // PIV: rows already pivoted (the same in every wave)
+  for (int i = 0; i < kB * kB / E / 64; ++i) amax = fmax(amax, wmax[i]);
+  const double thr2 = 1e-26 * fmax(amax, __longlong_as_double(gmax2[w]));
+  uint64_t used = 0;  // rows already pivoted (the same in every wave)
   for (int kq = 0; kq < CG; ++kq) {
 #pragma unroll
     for (int kk = 0; kk < E; ++kk) {
       const int k = E * kq + kk;
       if (k >= kb) break;
       const int b = k & 1;
-      int p = k;
       if (cq == kq) pcol[b][r] = a[kk];
-      if constexpr (PIV) {
-        __syncthreads();
-        // every wave finds the pivot row: lane l looks at row l (rows past kb and used
-        // rows excluded), then a butterfly maximum; ties go to the lower row
-        const z v = pcol[b][lane];
-        double m2 = (lane < kb && !((used >> lane) & 1)) ? v.x * v.x + v.y * v.y : -1.0;
-        int idx = lane;
-        for (int m = 32; m >= 1; m >>= 1) {
-          const double om = __shfl_xor(m2, m, 64);
-          const int oi = __shfl_xor(idx, m, 64);
-          if (om > m2 || (om == m2 && oi < idx)) {
-            m2 = om;
-            idx = oi;
-          }
+      __syncthreads();
+      // every wave finds the pivot row: lane l looks at row l (rows past kb and used
+      // rows excluded), then a butterfly maximum; ties go to the lower row
+      const z v = pcol[b][lane];
+      double m2 = (lane < kb && !((used >> lane) & 1)) ? v.x * v.x + v.y * v.y : -1.0;
+      int idx = lane;
+      for (int m = 32; m >= 1; m >>= 1) {
+        const double om = __shfl_xor(m2, m, 64);
+        const int oi = __shfl_xor(idx, m, 64);
+        if (om > m2 || (om == m2 && oi < idx)) {
+          m2 = om;
+          idx = oi;
         }
-        p = __builtin_amdgcn_readfirstlane(idx);
-        used |= (uint64_t)1 << p;
-        if (t == 0) {
-          perm[k] = p;
-          inv[p] = k;
-          if (!(m2 > thr2)) atomicCAS(flag + w, 0, o + k + 1);  // first singular pivot of this frequency
-        }
+      }
+      const int p = __builtin_amdgcn_readfirstlane(idx);
+      used |= (uint64_t)1 << p;
+      if (t == 0) {
+        perm[k] = p;
+        inv[p] = k;
+        if (!(m2 > thr2)) atomicCAS(flag + w, 0, o + k + 1);  // first singular pivot of this frequency
       }
       if (r == p) {
 #pragma unroll
@@ -160,10 +153,6 @@ __device__ __forceinline__ void diag_block(z* __restrict__ A, int n, int K, int 
       }
       __syncthreads();
       const z piv = pcol[b][p];
-      if (!PIV && t == 0) {
-        const bool bad = check_sign ? !(piv.x > 0.0) : (piv.x == 0.0 && piv.y == 0.0);
-        if (bad) atomicCAS(flag + w, 0, o + k + 1);  // first bad pivot of this frequency
-      }
       const double den = piv.x * piv.x + piv.y * piv.y;
       const double rd = den > 0.0 ? 1.0 / den : 0.0;
       const z ip = z{piv.x * rd, -piv.y * rd};
@@ -182,25 +171,119 @@ __device__ __forceinline__ void diag_block(z* __restrict__ A, int n, int K, int 
       if (cq == kq) a[kk] = prow_p ? ip : z{-gr.x, -gr.y};
     }
   }
-  if constexpr (PIV) __syncthreads();  // perm and inv complete
+  __syncthreads();  // perm and inv complete
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int c = c0 + j;
-    if (r < kb && c < kb) {
-      if constexpr (PIV)
-        A[(size_t)(o + inv[r]) * n + o + perm[c]] = a[j];
-      else
-        A[(size_t)(o + r) * n + o + c] = a[j];
+    if (r < kb && c < kb) A[(size_t)(o + inv[r]) * n + o + perm[c]] = a[j];
+  }
+}
+
+// Hermitian positive definite form (imaginary frequencies): the pivots are the diagonal,
+// two per barrier. Per pair
+// (k, k + 1) the owners publish both pivot columns and both pivot rows (values before the
+// pair) and every thread applies the 2 x 2 block step, with P the pivot block and Q = P^-1:
+//   pivot rows   A[P][j] <- Q A[P][j],                    A[P][P] <- Q
+//   other rows   A[r][j] <- A[r][j] - (A[r][P] Q) A[P][j], A[r][P] <- -A[r][P] Q
+// In exact arithmetic this is the two scalar Gauss-Jordan steps of the pair. Their pivots are
+// p00 and the Schur complement det(P) / p00, the next two diagonal entries of eps~ = L D L^H,
+// so a non-positive real part of either proves eps~ is not positive definite (flagged: the
+// first bad pivot of the frequency, 1-based). An odd kb (< 64) pairs its last column with the identity padding, which the
+// step leaves as it is. Half as many barriers and LDS round trips as the scalar sweep.
+template <int E>
+__device__ __forceinline__ void diag_block_pairs(z* __restrict__ A, int n, int K, int kb, int w,
+                                                 int* __restrict__ flag) {
+  constexpr int CG = kB / E;  // column groups
+  static_assert(E % 2 == 0, "a pivot pair stays in one column group");
+  __shared__ z pcol[2][2][kB];     // [buffer][pivot column k, k + 1][row]
+  __shared__ z prow[2][2][E][CG];  // [buffer][pivot row k, k + 1][j][column group]
+  const int o = K * kB;
+  const int t = threadIdx.x, r = t / CG, cq = t % CG, c0 = E * cq;
+  z a[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int c = c0 + j;
+    a[j] = (r < kb && c < kb) ? A[(size_t)(o + r) * n + o + c] : z{r == c ? 1.0 : 0.0, 0.0};
+  }
+  for (int kq = 0; kq < CG; ++kq) {
+#pragma unroll
+    for (int kk = 0; kk < E; kk += 2) {
+      const int k = E * kq + kk;
+      if (k >= kb) break;
+      const int b = (k >> 1) & 1;
+      if (cq == kq) {
+        pcol[b][0][r] = a[kk];
+        pcol[b][1][r] = a[kk + 1];
+      }
+      if (r == k || r == k + 1) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) prow[b][r - k][j][cq] = a[j];
+      }
+      __syncthreads();
+      const z p00 = pcol[b][0][k], p01 = pcol[b][1][k], p10 = pcol[b][0][k + 1], p11 = pcol[b][1][k + 1];
+      const z pp = cmul(p00, p11), qq = cmul(p01, p10);
+      const z det = z{pp.x - qq.x, pp.y - qq.y};
+      if (t == 0) {
+        // Re(det / p00) has the sign of Re(det conj(p00)) once p00 has a positive real part
+        if (!(p00.x > 0.0))
+          atomicCAS(flag + w, 0, o + k + 1);  // first bad pivot of this frequency
+        else if (!(det.x * p00.x + det.y * p00.y > 0.0))
+          atomicCAS(flag + w, 0, o + k + 2);
+      }
+      const double den = det.x * det.x + det.y * det.y;
+      const double rd = den > 0.0 ? 1.0 / den : 0.0;
+      const z id = z{det.x * rd, -det.y * rd};
+      const z q00 = cmul(p11, id), q11 = cmul(p00, id);
+      const z m01 = cmul(p01, id), m10 = cmul(p10, id);
+      const z q01 = z{-m01.x, -m01.y}, q10 = z{-m10.x, -m10.y};
+      // one instruction stream for every row: a pivot row is 0 - (-Q[row]) A[P][j], any
+      // other row A[r][j] - (A[r][P] Q) A[P][j]; the pivot columns are set afterwards
+      const bool pv0 = r == k, pv1 = r == k + 1;
+      const z c0v = pcol[b][0][r], c1v = pcol[b][1][r];
+      z g0 = cmul(c0v, q00), g1 = cmul(c0v, q01);
+      cfma(g0, c1v, q10);
+      cfma(g1, c1v, q11);
+      if (pv0) {
+        g0 = z{-q00.x, -q00.y};
+        g1 = z{-q01.x, -q01.y};
+      }
+      if (pv1) {
+        g0 = z{-q10.x, -q10.y};
+        g1 = z{-q11.x, -q11.y};
+      }
+      const double keep = (pv0 || pv1) ? 0.0 : 1.0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const z r0 = prow[b][0][j][cq], r1 = prow[b][1][j][cq];
+        z v = z{keep * a[j].x, keep * a[j].y};
+        v.x = fma(-g0.x, r0.x, fma(g0.y, r0.y, v.x));
+        v.y = fma(-g0.x, r0.y, fma(-g0.y, r0.x, v.y));
+        v.x = fma(-g1.x, r1.x, fma(g1.y, r1.y, v.x));
+        v.y = fma(-g1.x, r1.y, fma(-g1.y, r1.x, v.y));
+        a[j] = v;
+      }
+      if (cq == kq) {
+        a[kk] = pv0 ? q00 : (pv1 ? q10 : z{-g0.x, -g0.y});
+        a[kk + 1] = pv0 ? q01 : (pv1 ? q11 : z{-g1.x, -g1.y});
+      }
     }
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int c = c0 + j;
+    if (r < kb && c < kb) A[(size_t)(o + r) * n + o + c] = a[j];
   }
 }
 
 template <int E, bool PIV>
 __global__ void __launch_bounds__(kB * kB / E) diag_inverse(double* __restrict__ Aall, int n, int K, int kb,
-                                                            int check_sign, int* __restrict__ flag,
+                                                            int* __restrict__ flag,
                                                             const unsigned long long* __restrict__ gmax2) {
   const int w = blockIdx.x;
-  diag_block<E, PIV>(reinterpret_cast<z*>(Aall) + (size_t)w * n * n, n, K, kb, check_sign, w, flag, gmax2);
+  if constexpr (PIV)
+    diag_block_lu<E>(reinterpret_cast<z*>(Aall) + (size_t)w * n * n, n, K, kb, w, flag, gmax2);
+  else
+    diag_block_pairs<E>(reinterpret_cast<z*>(Aall) + (size_t)w * n * n, n, K, kb, w, flag);
 }
 constexpr int kDiagE = 8;  // entries per thread of diag_inverse (512 threads: two waves per SIMD)
 
@@ -527,10 +610,10 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
       KernelTimer kt_("eps_diag_inverse", st);
       if (check_sign)
         hipLaunchKernelGGL((diag_inverse<kDiagE, false>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
-                           K, kb, check_sign, flag, gmax2);
+                           K, kb, flag, gmax2);
       else
         hipLaunchKernelGGL((diag_inverse<kDiagE, true>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
-                           K, kb, check_sign, flag, gmax2);
+                           K, kb, flag, gmax2);
     }
     XO_CHECK_LAUNCH();
     if (nblk > 1) {
