@@ -337,9 +337,12 @@ def test_epsinv_parity(name):
     assert rel_fro(out.cpu().numpy(), refn) < 1e-12
 
 
+@pytest.mark.parametrize("rank", ["valu", "mfma"])
 @pytest.mark.parametrize("ng", [1, 31, 32, 33, 63, 64, 65, 97, 128, 200])
-def test_epsinv_sizes_random_hpd(ng):
-    say(f"epsinv random HPD ng={ng}")
+def test_epsinv_sizes_random_hpd(ng, rank, monkeypatch):
+    # both rank-update kernels (32 x 32 VALU tiles, 64 x 64 FP64 matrix-core tiles)
+    monkeypatch.setenv("XO_EPS_RANK", rank)
+    say(f"epsinv random HPD ng={ng} rank update {rank}")
     X = random_complex(ng, (3 * ng + 2, ng))
     chi = -(X.conj().T @ X)[None] / (3 * ng)
     chi = np.concatenate([chi, 0.5 * chi])
@@ -380,13 +383,15 @@ def _chi_for_eps(M, qpg):
     return (np.eye(M.shape[-1])[None] - M) / (s[:, None] * s[None, :])[None]
 
 
+@pytest.mark.parametrize("rank", ["valu", "mfma"])
 @pytest.mark.parametrize("ng", [5, 64, 97, 200])
-def test_epsinv_lu_fallback_pivots_inside_blocks(ng):
+def test_epsinv_lu_fallback_pivots_inside_blocks(ng, rank, monkeypatch):
     """General (non-Hermitian) well-conditioned eps~ whose leading pivots are tiny or zero
     in the unpivoted order: frequency 0 has eps~_00 = 1e-14, frequency 1 has pairs of rows
     swapped inside each 64-block (zero diagonal where two rows meet), so elimination
     without pivoting fails or loses accuracy; the pivoted form matches numpy's LU inverse."""
-    say(f"epsinv LU fallback pivoting ng={ng}")
+    monkeypatch.setenv("XO_EPS_RANK", rank)
+    say(f"epsinv LU fallback pivoting ng={ng} rank update {rank}")
     g = np.random.default_rng(ng)
     base = np.eye(ng) + 0.3 * (g.standard_normal((ng, ng)) + 1j * g.standard_normal((ng, ng))) / np.sqrt(ng)
     m0 = base.copy()
