@@ -475,13 +475,20 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kU = 64;      // tile edge
 constexpr long kMfmaTiles = 2048;  // 64 x 64 tiles (all frequencies) from which this form is used
 constexpr int kUK = 32;     // pivot rows per LDS stage
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) rank_update_mfma(double* __restrict__ Aall, int n, int K, int kb,
-                                                       const double* __restrict__ Sall) {
-  if ((int)blockIdx.x == K || (int)blockIdx.y == K) return;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) rank_update_mfma(double* __restrict__ Aall, int n, int K, int kb, int nw,
+                                                                                                    const double* __restrict__ Sall) {
+  // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous range of the
+  // (tile row, tile column, frequency) space, tile row fastest: the tiles in flight on an
+  // XCD share their pivot rows and neighbouring S rows in its L2
+  const int nt = (n + kU - 1) / kU, ntiles = nt * nt * nw;
+  const int per = (ntiles + 7) >> 3;
+  const int L0 = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (L0 >= ntiles) return;
+  const int ti = L0 % nt, tj = (L0 / nt) % nt, w = L0 / (nt * nt);
+  if (ti == K || tj == K) return;
   __shared__ z L[kU][kUK + 1];   // S rows of the tile, this stage's pivot columns
   __shared__ z R[kUK][kU + 1];   // this stage's pivot rows, the tile's columns
-  const int w = blockIdx.z;
-  const int o = K * kB, i0 = blockIdx.x * kU, j0 = blockIdx.y * kU;
+  const int o = K * kB, i0 = ti * kU, j0 = tj * kU;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, wr = wave >> 1, wc = wave & 1;
@@ -734,8 +741,8 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
         const unsigned nt64 = (n + kU - 1) / kU, nt32 = (n + kT - 1) / kT;
         const int rf = rank_form();
         if (rf == 1 || (rf == 0 && (long)nt64 * nt64 * a->nw >= kMfmaTiles))
-          hipLaunchKernelGGL(rank_update_mfma, dim3(nt64, nt64, a->nw), dim3(256), 0, st, a->out, n, K, kb,
-                             static_cast<const double*>(S));
+          hipLaunchKernelGGL(rank_update_mfma, dim3(8 * ((nt64 * nt64 * a->nw + 7) / 8)), dim3(256), 0, st, a->out,
+                             n, K, kb, a->nw, static_cast<const double*>(S));
         else
           hipLaunchKernelGGL(rank_update, dim3(nt32, nt32, a->nw), dim3(256), 0, st, a->out, n, K, kb,
                              static_cast<const double*>(S));
