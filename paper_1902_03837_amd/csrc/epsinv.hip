@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, in
 // 32 (67 KB: two workgroups per CU); entries past kb and past n are staged as zero.
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kU = 64;      // tile edge
-constexpr long kMfmaTiles = 2048;  // 64 x 64 tiles (all frequencies) from which this form is used
+constexpr long kMfmaTiles = 1600;  // 64 x 64 tiles (all frequencies) from which this form is used
 constexpr int kUK = 32;     // pivot rows per LDS stage
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) rank_update_mfma(double* __restrict__ Aall, int n, int K, int kb, int nw,
                                                                                                     const double* __restrict__ Sall) {
