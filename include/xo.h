@@ -264,9 +264,8 @@ int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* be
  * XO_ERR_SINGULAR instead of an inaccurate inverse. With info NULL the call
  * synchronises the stream to read the pivot flags; with info set it does not
  * synchronise and leaves them to the caller. The trailing rank-64 updates run on
- * FP64 matrix cores once the 64 x 64 tiles of all frequencies number at least
- * 1600, else on VALU tiles; the environment variable XO_EPS_RANK=mfma or =valu,
- * read on each call, fixes that choice (results agree to FP64 rounding).
+ * FP64 matrix cores; the environment variable XO_EPS_RANK=valu, read on each
+ * call, runs them on VALU instead (results agree to FP64 rounding).
  * qpg: [host] [ng] |q+G| (at q = 0 the G = 0 entry is 1 and chi0's G = 0 row and
  *      column are the q-normalised head and wings).
  * chi0: [device] [nw][ng][ng] complex128 (read only); out: [device] same shape.

@@ -12,8 +12,8 @@
 //                                    (one per pivot with pivoting)
 //   A_Kj = P A_Kj  (j outside K)     row_col: row half-tiles of the panel, and
 //   S_iK = A_iK,  A_iK = -A_iK P     column half-tiles (old column saved in S)
-//   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update_mfma, 64 x 64 tiles on FP64 matrix cores
-//                                        (rank_update, 32 x 32 VALU tiles, for small inversions)
+//   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update_mfma, 32 x 32 tiles on FP64 matrix cores
+//                                        (rank_update: the same on VALU, XO_EPS_RANK=valu)
 // The pivots met inside the diagonal blocks are the diagonal of eps~ = L D L^H,
 // so a pivot with non-positive real part proves eps~ is not positive definite.
 // In the pivoted form a numerically singular diagonal block is reported instead.
@@ -462,103 +462,77 @@ __global__ void __launch_bounds__(256) rank_update(double* __restrict__ Aall, in
   update_tile(A, S, n, o, kb, i0, j0);
 }
 
-// The rank update on FP64 matrix cores (v_mfma_f64_16x16x4f64): one workgroup per 64 x 64 tile
-// (tile row blockIdx.x, tile column blockIdx.y) outside row and column block K; wave (wr, wc)
-// owns the 32 x 32 quadrant (wr, wc), four 16 x 16 output blocks with real and imaginary
-// accumulators. The complex product is taken in real arithmetic, two m per instruction: lane
-// (i, k) (i = lane % 16, k = lane / 16) supplies A[i][k] = Re or Im (k even or odd) of
-// S[row i][m + k / 2], and B[k][j] = (Re B, -Im B) for the real accumulator and (Im B, Re B)
-// for the imaginary one, B = A_Kj[m + k / 2][column j]; the instruction leaves D[lane / 16
-// + 4 r][lane % 16] in register r (the FP64 form's own order, unlike the FP32 16 x 16 forms). The kb pivot rows are staged through LDS in two halves of
-// 32 (67 KB: two workgroups per CU); entries past kb and past n are staged as zero.
+// The rank update on FP64 matrix cores (v_mfma_f64_16x16x4f64): one workgroup per 32 x 32 tile
+// outside row and column block K; wave (wr, wc) owns its 16 x 16 block (wr, wc) with a real
+// and an imaginary accumulator. The complex product is taken in real arithmetic, two m per
+// instruction: lane (i, k) (i = lane % 16, k = lane / 16) supplies A[i][k] = Re or Im (k even
+// or odd) of S[row i][m + k / 2], and B[k][j] = (Re B, -Im B) for the real accumulator and
+// (Im B, Re B) for the imaginary one, B = A_Kj[m + k / 2][column j]; the instruction leaves
+// D[lane / 16 + 4 r][lane % 16] in register r (the FP64 form's own order, unlike the FP32
+// 16 x 16 forms). The kb pivot rows are staged through LDS in two halves of 32 (34 KB, 72
+// registers: four workgroups per CU), the next half's loads issued before the current half's
+// products; entries past kb and past n are staged as zero. (64 x 64 tiles with four blocks per
+// wave, two workgroups per CU, measured slower at every size.)
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kU = 64;      // tile edge
-constexpr long kMfmaTiles = 1600;  // 64 x 64 tiles (all frequencies) from which this form is used
-constexpr int kUK = 32;     // pivot rows per LDS stage
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) rank_update_mfma(double* __restrict__ Aall, int n, int K, int kb, int nw,
-                                                                                                    const double* __restrict__ Sall) {
+constexpr int kMT = 32;   // tile edge
+constexpr int kUK = 32;   // pivot rows per LDS stage
+__global__ void __launch_bounds__(256) rank_update_mfma(double* __restrict__ Aall, int n, int K, int kb, int nw,
+                                                       const double* __restrict__ Sall) {
+  constexpr int FL = kMT * kUK / 256;  // staged entries per thread, each operand
   // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous range of the
   // (tile row, tile column, frequency) space, tile row fastest: the tiles in flight on an
   // XCD share their pivot rows and neighbouring S rows in its L2
-  const int nt = (n + kU - 1) / kU, ntiles = nt * nt * nw;
+  const int nt = (n + kMT - 1) / kMT, ntiles = nt * nt * nw;
   const int per = (ntiles + 7) >> 3;
   const int L0 = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
   if (L0 >= ntiles) return;
   const int ti = L0 % nt, tj = (L0 / nt) % nt, w = L0 / (nt * nt);
-  if (ti == K || tj == K) return;
-  __shared__ z L[kU][kUK + 1];   // S rows of the tile, this stage's pivot columns
-  __shared__ z R[kUK][kU + 1];   // this stage's pivot rows, the tile's columns
-  const int o = K * kB, i0 = ti * kU, j0 = tj * kU;
+  if (ti * kMT / kB == K || tj * kMT / kB == K) return;  // 32-tiles sit inside 64-blocks
+  __shared__ z L[kMT][kUK + 1];   // S rows of the tile, this stage's pivot columns
+  __shared__ z R[kUK][kMT + 1];   // this stage's pivot rows, the tile's columns
+  const int o = K * kB, i0 = ti * kMT, j0 = tj * kMT;
   z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
   const z* S = reinterpret_cast<const z*>(Sall) + (size_t)w * n * kB;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, wr = wave >> 1, wc = wave & 1;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, r0 = 16 * (wave >> 1), c0 = 16 * (wave & 1);
   const int li = lane & 15, lk = lane >> 4, half = lk >> 1, part = lk & 1;
-  d4 re[2][2], im[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      re[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-      im[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+  d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
   // stage loads: the next stage's are issued before the current stage's products
-  z vl[8], vr[8];
+  z vl[FL], vr[FL];
   auto load_stage = [&](int m0) {
 #pragma unroll
-    for (int f = 0; f < 8; ++f) {
-      const int e = t + 256 * f;
-      const int lr = e >> 5, lm = e & 31;   // L: 64 rows x 32
-      const int rm = e >> 6, rc = e & 63;   // R: 32 rows x 64
-      vl[f] = (i0 + lr < n && m0 + lm < kb) ? S[(size_t)(i0 + lr) * kB + m0 + lm] : z{0.0, 0.0};
-      vr[f] = (m0 + rm < kb && j0 + rc < n) ? A[(size_t)(o + m0 + rm) * n + j0 + rc] : z{0.0, 0.0};
+    for (int f = 0; f < FL; ++f) {
+      const int e = t + 256 * f, er = e / kUK, ec = e % kUK;  // L: 32 rows x 32; R: 32 rows x 32
+      vl[f] = (i0 + er < n && m0 + ec < kb) ? S[(size_t)(i0 + er) * kB + m0 + ec] : z{0.0, 0.0};
+      vr[f] = (m0 + er < kb && j0 + ec < n) ? A[(size_t)(o + m0 + er) * n + j0 + ec] : z{0.0, 0.0};
     }
   };
   load_stage(0);
   for (int m0 = 0; m0 < kb; m0 += kUK) {
     if (m0 > 0) __syncthreads();  // the previous stage's reads are done
 #pragma unroll
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < FL; ++f) {
       const int e = t + 256 * f;
-      L[e >> 5][e & 31] = vl[f];
-      R[e >> 6][e & 63] = vr[f];
+      L[e / kUK][e % kUK] = vl[f];
+      R[e / kUK][e % kUK] = vr[f];
     }
     __syncthreads();
     if (m0 + kUK < kb) load_stage(m0 + kUK);
     const int mk = min(kUK, kb - m0);
     for (int m = 0; m < mk; m += 2) {
-      double av[2], br[2], bi[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const z l = L[32 * wr + 16 * a + li][m + half];
-        av[a] = part ? l.y : l.x;
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const z r = R[m + half][32 * wc + 16 * b + li];
-        br[b] = part ? -r.y : r.x;
-        bi[b] = part ? r.x : r.y;
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], br[b], re[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bi[b], im[a][b], 0, 0, 0);
-        }
+      const z l = L[r0 + li][m + half], r = R[m + half][c0 + li];
+      const double av = part ? l.y : l.x, br = part ? -r.y : r.x, bi = part ? r.x : r.y;
+      re = __builtin_amdgcn_mfma_f64_16x16x4f64(av, br, re, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bi, im, 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 32 * wr + 16 * a + lk + 4 * r, j = j0 + 32 * wc + 16 * b + li;
-        if (i < n && j < n) {
-          z& x = A[(size_t)i * n + j];
-          x = z{x.x - re[a][b][r], x.y - im[a][b][r]};
-        }
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + r0 + lk + 4 * q, j = j0 + c0 + li;
+    if (i < n && j < n) {
+      z& x = A[(size_t)i * n + j];
+      x = z{x.x - re[q], x.y - im[q]};
+    }
+  }
 }
 
 __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ qpg, int n) {
@@ -578,14 +552,11 @@ __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ 
 
 namespace xo {
 namespace {
-// Rank-update kernel: 0 automatic (by tile count), 1 FP64 matrix cores, 2 VALU tiles; the
-// environment variable XO_EPS_RANK = mfma | valu fixes it (tests run both).
+// Rank-update kernel: FP64 matrix cores (default) or, with the environment variable
+// XO_EPS_RANK=valu, the VALU tiles (kept as a second implementation; the tests run both).
 int rank_form() {
   const char* e = std::getenv("XO_EPS_RANK");
-  if (!e) return 0;
-  if (!std::strcmp(e, "mfma")) return 1;
-  if (!std::strcmp(e, "valu")) return 2;
-  return 0;
+  return (e && !std::strcmp(e, "valu")) ? 2 : 1;
 }
 
 // Workspace of one call: the pivot flags and, with more than one block, the saved column panel.
@@ -738,14 +709,13 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
         KernelTimer kt_("eps_rank_update", st);
         // FP64 matrix cores on 64 x 64 tiles once there are enough of them to fill the
         // GPU; small inversions keep four times as many 32 x 32 VALU tiles in flight
-        const unsigned nt64 = (n + kU - 1) / kU, nt32 = (n + kT - 1) / kT;
-        const int rf = rank_form();
-        if (rf == 1 || (rf == 0 && (long)nt64 * nt64 * a->nw >= kMfmaTiles))
-          hipLaunchKernelGGL(rank_update_mfma, dim3(8 * ((nt64 * nt64 * a->nw + 7) / 8)), dim3(256), 0, st, a->out,
-                             n, K, kb, a->nw, static_cast<const double*>(S));
-        else
+        const unsigned nt32 = (n + 31) / 32;
+        if (rank_form() == 2)
           hipLaunchKernelGGL(rank_update, dim3(nt32, nt32, a->nw), dim3(256), 0, st, a->out, n, K, kb,
                              static_cast<const double*>(S));
+        else
+          hipLaunchKernelGGL(rank_update_mfma, dim3(8 * ((nt32 * nt32 * a->nw + 7) / 8)), dim3(256), 0, st, a->out,
+                             n, K, kb, a->nw, static_cast<const double*>(S));
       }
       XO_CHECK_LAUNCH();
     }
