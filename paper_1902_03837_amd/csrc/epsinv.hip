@@ -10,8 +10,9 @@
 //   P = A_KK^-1                      diag_inverse: one workgroup per frequency, the
 //                                    block in registers, one barrier per pivot pair
 //                                    (one per pivot with pivoting)
-//   A_Kj = P A_Kj  (j outside K)     row_col: row half-tiles of the panel, and
-//   S_iK = A_iK,  A_iK = -A_iK P     column half-tiles (old column saved in S)
+//   A_Kj = P A_Kj  (j outside K)     panel_mfma: row strips of the panel, and
+//   S_iK = A_iK,  A_iK = -A_iK P     column strips (old column saved in S), on FP64
+//                                    matrix cores (row_col: the same on VALU)
 //   A_ij -= S_iK A_Kj  (i, j outside K)  rank_update_mfma, 32 x 32 tiles on FP64 matrix cores
 //                                        (rank_update: the same on VALU, XO_EPS_RANK=valu)
 // The pivots met inside the diagonal blocks are the diagonal of eps~ = L D L^H,
@@ -535,6 +536,107 @@ __global__ void __launch_bounds__(256) rank_update_mfma(double* __restrict__ Aal
   }
 }
 
+// Panel of block column K on FP64 matrix cores, in strips of 16 (rows or columns) so that the
+// small, latency-bound launch has many workgroups. blockIdx.x = strip (row strips first).
+// Row strip s (columns x0 = 16 s .. + 15, outside block K): A_Kj <- P A_Kj over all kb rows of
+//   the panel, wave v computing rows 16 v .. + 15 (a strip's rows are read whole before any
+//   is written, and no other workgroup touches its columns).
+// Column strip s (rows x0 .. x0 + 15 outside block K): S_iK <- A_iK, A_iK <- -A_iK P over all kb
+//   pivot columns, wave v computing columns 16 v .. + 15.
+// Both are C = X Y with X (row strip: P, 64 rows; column strip: the strip's A_iK, 16 rows) and
+// Y (A_Kj, 16 columns; -P, 64 columns), taken as in rank_update_mfma: two m per instruction,
+// halves of 32 m staged through LDS (42.5 KB: three workgroups per CU).
+constexpr int kPS16 = 16;  // strip width
+__global__ void __launch_bounds__(256) panel_mfma(double* __restrict__ Aall, int n, int K, int kb, int ns,
+                                                 double* __restrict__ Sall) {
+  const int w = blockIdx.y;
+  const bool rowt = (int)blockIdx.x < ns;
+  const int sidx = rowt ? (int)blockIdx.x : (int)blockIdx.x - ns;
+  const int x0 = sidx * kPS16;
+  if (x0 / kB == K) return;  // strips sit inside 64-blocks
+  __shared__ z buf[64 * (kUK + 1) + kUK * (kPS16 + 1)];
+  // row strip: Xs [64][33] (P), Ys [32][17] (A_Kj); column strip: Xs [16][33] (A_iK), Ys [32][65] (P)
+  const int XL = kUK + 1, YL = rowt ? kPS16 + 1 : kB + 1;
+  z* Xs = buf;
+  z* Ys = buf + (rowt ? 64 : kPS16) * XL;
+  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
+  z* S = reinterpret_cast<z*>(Sall) + (size_t)w * n * kB;
+  const int o = K * kB;
+  const int t = threadIdx.x, lane = t & 63, v = t >> 6;
+  const int li = lane & 15, lk = lane >> 4, half = lk >> 1, part = lk & 1;
+  const int ax = rowt ? 16 * v : 0, by = rowt ? 0 : 16 * v;  // this wave's X rows and Y columns
+  const double sg = rowt ? 1.0 : -1.0;
+  d4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  // per stage and thread: 8 entries of the 64-wide operand (P), 2 of the 16-wide one
+  z vp[8], vq[2];
+  auto load_stage = [&](int m0) {
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int e = t + 256 * f;
+      if (rowt) {  // P[r][m0 + c], 64 x 32
+        const int r = e >> 5, c = e & 31;
+        vp[f] = (r < kb && m0 + c < kb) ? A[(size_t)(o + r) * n + o + m0 + c] : z{0.0, 0.0};
+      } else {     // P[m0 + r][c], 32 x 64
+        const int r = e >> 6, c = e & 63;
+        vp[f] = (m0 + r < kb && c < kb) ? A[(size_t)(o + m0 + r) * n + o + c] : z{0.0, 0.0};
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int e = t + 256 * f;
+      if (rowt) {  // A_Kj[m0 + r][x0 + c], 32 x 16
+        const int r = e >> 4, c = e & 15;
+        vq[f] = (m0 + r < kb && x0 + c < n) ? A[(size_t)(o + m0 + r) * n + x0 + c] : z{0.0, 0.0};
+      } else {     // A_iK[x0 + r][m0 + c], 16 x 32
+        const int r = e >> 5, c = e & 31;
+        vq[f] = (x0 + r < n && m0 + c < kb) ? A[(size_t)(x0 + r) * n + o + m0 + c] : z{0.0, 0.0};
+      }
+    }
+  };
+  load_stage(0);
+  for (int m0 = 0; m0 < kb; m0 += kUK) {
+    if (m0 > 0) __syncthreads();  // the previous stage's reads are done
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+      const int e = t + 256 * f;
+      if (rowt)
+        Xs[(e >> 5) * XL + (e & 31)] = vp[f];
+      else
+        Ys[(e >> 6) * YL + (e & 63)] = vp[f];
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int e = t + 256 * f;
+      if (rowt) {
+        Ys[(e >> 4) * YL + (e & 15)] = vq[f];
+      } else {
+        const int r = e >> 5, c = e & 31;
+        Xs[r * XL + c] = vq[f];
+        if (x0 + r < n && m0 + c < kb) S[(size_t)(x0 + r) * kB + m0 + c] = vq[f];  // the old column
+      }
+    }
+    __syncthreads();
+    if (m0 + kUK < kb) load_stage(m0 + kUK);
+    const int mk = min(kUK, kb - m0);
+    for (int m = 0; m < mk; m += 2) {
+      const z l = Xs[(ax + li) * XL + m + half], r = Ys[(m + half) * YL + by + li];
+      const double av = part ? l.y : l.x;
+      const double br = sg * (part ? -r.y : r.x), bi = sg * (part ? r.x : r.y);
+      re = __builtin_amdgcn_mfma_f64_16x16x4f64(av, br, re, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bi, im, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ax + lk + 4 * q, c = by + li;  // row and column of C
+    if (rowt) {
+      if (r < kb && x0 + c < n) A[(size_t)(o + r) * n + x0 + c] = z{re[q], im[q]};
+    } else {
+      if (x0 + r < n && c < kb) A[(size_t)(x0 + r) * n + o + c] = z{re[q], im[q]};
+    }
+  }
+}
+
 __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ qpg, int n) {
   const size_t w = blockIdx.y;
   const size_t nn = (size_t)n * n;
@@ -552,8 +654,9 @@ __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ 
 
 namespace xo {
 namespace {
-// Rank-update kernel: FP64 matrix cores (default) or, with the environment variable
-// XO_EPS_RANK=valu, the VALU tiles (kept as a second implementation; the tests run both).
+// Panel and rank-update kernels: FP64 matrix cores (default) or, with the environment
+// variable XO_EPS_RANK=valu, the VALU forms (kept as a second implementation; the tests
+// run both).
 int rank_form() {
   const char* e = std::getenv("XO_EPS_RANK");
   return (e && !std::strcmp(e, "valu")) ? 2 : 1;
@@ -702,13 +805,15 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
     if (nblk > 1) {
       {
         KernelTimer kt_("eps_row_col", st);
-        hipLaunchKernelGGL(row_col, dim3(4 * nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb, nblk, S);
+        const int ns = (n + kPS16 - 1) / kPS16;
+        if (rank_form() == 2)
+          hipLaunchKernelGGL(row_col, dim3(4 * nblk, a->nw), dim3(256), lds2, st, a->out, n, K, kb, nblk, S);
+        else
+          hipLaunchKernelGGL(panel_mfma, dim3(2 * ns, a->nw), dim3(256), 0, st, a->out, n, K, kb, ns, S);
       }
       XO_CHECK_LAUNCH();
       {
         KernelTimer kt_("eps_rank_update", st);
-        // FP64 matrix cores on 64 x 64 tiles once there are enough of them to fill the
-        // GPU; small inversions keep four times as many 32 x 32 VALU tiles in flight
         const unsigned nt32 = (n + 31) / 32;
         if (rank_form() == 2)
           hipLaunchKernelGGL(rank_update, dim3(nt32, nt32, a->nw), dim3(256), 0, st, a->out, n, K, kb,

@@ -340,7 +340,7 @@ def test_epsinv_parity(name):
 @pytest.mark.parametrize("rank", ["valu", "mfma"])
 @pytest.mark.parametrize("ng", [1, 31, 32, 33, 63, 64, 65, 97, 128, 200])
 def test_epsinv_sizes_random_hpd(ng, rank, monkeypatch):
-    # both rank-update kernels (32 x 32 tiles on FP64 matrix cores, the default, and on VALU)
+    # both forms of the panel and rank update (FP64 matrix cores, the default, and VALU)
     monkeypatch.setenv("XO_EPS_RANK", rank)
     say(f"epsinv random HPD ng={ng} rank update {rank}")
     X = random_complex(ng, (3 * ng + 2, ng))
