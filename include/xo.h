@@ -263,8 +263,9 @@ int xo_chi0_autotune(const xo_chi0_args* items, int n, xo_tune* best, double* be
  * singular block: the elimination does not pivot across blocks) returns
  * XO_ERR_SINGULAR instead of an inaccurate inverse. With info NULL the call
  * synchronises the stream to read the pivot flags; with info set it does not
- * synchronise and leaves them to the caller. The panel products and trailing
- * rank-64 updates run on FP64 matrix cores; the environment variable
+ * synchronise and leaves them to the caller. The diagonal-block sweeps (positive
+ * definite form), panel products and trailing rank-64 updates run on FP64 matrix
+ * cores; the environment variable
  * XO_EPS_RANK=valu, read on each call, runs them on VALU instead (results agree
  * to FP64 rounding).
  * qpg: [host] [ng] |q+G| (at q = 0 the G = 0 entry is 1 and chi0's G = 0 row and

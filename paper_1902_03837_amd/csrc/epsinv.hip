@@ -7,9 +7,10 @@
 // launches; the diagonal blocks are inverted without pivoting (positive definite
 // input) or, with XO_EPS_LU_FALLBACK (general eps~), with partial pivoting inside
 // the block. Per block column K (width b = 64):
-//   P = A_KK^-1                      diag_inverse: one workgroup per frequency, the
-//                                    block in registers, one barrier per pivot pair
-//                                    (one per pivot with pivoting)
+//   P = A_KK^-1                      diag_mfma: one workgroup per frequency, the block
+//                                    in registers, one barrier per pivot pair, the pair's
+//                                    update on FP64 matrix cores (diag_inverse: the same
+//                                    on VALU, and the pivoted form with one barrier per pivot)
 //   A_Kj = P A_Kj  (j outside K)     panel_mfma: row strips of the panel, and
 //   S_iK = A_iK,  A_iK = -A_iK P     column strips (old column saved in S), on FP64
 //                                    matrix cores (row_col: the same on VALU)
@@ -637,6 +638,109 @@ __global__ void __launch_bounds__(256) panel_mfma(double* __restrict__ Aall, int
   }
 }
 
+// Hermitian positive definite diagonal block on FP64 matrix cores: the two-pivot sweep of
+// diag_block_pairs with the rank-2 update of the whole 64 x 64 block as matrix-core products.
+// Wave v holds block row v (rows 16 v .. + 15) in the instruction's output layout: one 16 x 16
+// block per block column c, real and imaginary accumulators; lane (i, g), register q holds row
+// 16 v + g + 4 q, column 16 c + i. Every entry takes one update per pivot pair P = (k, k + 1):
+//   A <- A - G R,   G = A[:, P] Q outside the pivot rows, G = I - Q in them,
+//   R = A[P, :] + E  (E: ones at A[P_p][P_p]),
+// which leaves Q A[P, :] in the pivot rows, -A[r, P] Q in the pivot columns and Q at A[P, P]:
+// the pair's Gauss-Jordan step as one uniform product. G enters as the left operand (lane
+// (i, k): Re or Im of G[16 v + i][k / 2]), R as the right one ((Re, -Im) for the real
+// accumulator, (Im, Re) for the imaginary one), G negated. Per pair the owners publish the
+// pivot columns and rows (values before the pair) in LDS, double buffered, one barrier; the
+// pivots p00 and det P / p00 are flagged as in diag_block_pairs. Loops unrolled so that the
+// block column and register of every pivot are compile-time.
+__global__ void __launch_bounds__(256) diag_mfma(double* __restrict__ Aall, int n, int K, int kb,
+                                                int* __restrict__ flag) {
+  const int w = blockIdx.x;
+  z* A = reinterpret_cast<z*>(Aall) + (size_t)w * n * n;
+  __shared__ z pc[2][2][kB];  // [buffer][pivot column k, k + 1][row]
+  __shared__ z pr[2][2][kB];  // [buffer][pivot row k, k + 1][column]
+  const int o = K * kB;
+  const int t = threadIdx.x, lane = t & 63, v = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  d4 re[4], im[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * v + lg + 4 * q, col = 16 * c + li;
+      const z a = (row < kb && col < kb) ? A[(size_t)(o + row) * n + o + col] : z{row == col ? 1.0 : 0.0, 0.0};
+      re[c][q] = a.x;
+      im[c][q] = a.y;
+    }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 16 * c + 2 * j;
+      if (k >= kb) break;
+      const int b = j & 1;
+      // pivot columns k, k + 1: block column c, lane columns 2 j and 2 j + 1
+      if ((li >> 1) == j) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pc[b][li & 1][16 * v + lg + 4 * q] = z{re[c][q], im[c][q]};
+      }
+      // pivot rows k, k + 1: wave c, lane groups 2 (j & 1) and 2 (j & 1) + 1, register j / 2
+      if (v == c && (lg >> 1) == (j & 1)) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) pr[b][lg & 1][16 * cc + li] = z{re[cc][j >> 1], im[cc][j >> 1]};
+      }
+      __syncthreads();
+      const z p00 = pc[b][0][k], p01 = pc[b][1][k], p10 = pc[b][0][k + 1], p11 = pc[b][1][k + 1];
+      const z pp = cmul(p00, p11), qq = cmul(p01, p10);
+      const z det = z{pp.x - qq.x, pp.y - qq.y};
+      if (t == 0) {
+        if (!(p00.x > 0.0))
+          atomicCAS(flag + w, 0, o + k + 1);  // first bad pivot of this frequency
+        else if (!(det.x * p00.x + det.y * p00.y > 0.0))
+          atomicCAS(flag + w, 0, o + k + 2);
+      }
+      const double den = det.x * det.x + det.y * det.y;
+      const double rd = den > 0.0 ? 1.0 / den : 0.0;
+      const z id = z{det.x * rd, -det.y * rd};
+      const z q00 = cmul(p11, id), q11 = cmul(p00, id);
+      const z m01 = cmul(p01, id), m10 = cmul(p10, id);
+      const z q01 = z{-m01.x, -m01.y}, q10 = z{-m10.x, -m10.y};
+      // left operand: G of row 16 v + i, component k / 2, Re or Im
+      const int row = 16 * v + li;
+      const z c0v = pc[b][0][row], c1v = pc[b][1][row];
+      z g0 = cmul(c0v, q00), g1 = cmul(c0v, q01);
+      cfma(g0, c1v, q10);
+      cfma(g1, c1v, q11);
+      if (row == k) {
+        g0 = z{1.0 - q00.x, -q00.y};
+        g1 = z{-q01.x, -q01.y};
+      }
+      if (row == k + 1) {
+        g0 = z{-q10.x, -q10.y};
+        g1 = z{1.0 - q11.x, -q11.y};
+      }
+      const z gs = (lg >> 1) ? g1 : g0;
+      const double av = (lg & 1) ? -gs.y : -gs.x;
+      const int p = lg >> 1;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int col = 16 * cc + li;
+        z r = pr[b][p][col];
+        if (col == k + p) r.x += 1.0;
+        const double br = (lg & 1) ? -r.y : r.x, bi = (lg & 1) ? r.x : r.y;
+        re[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, br, re[cc], 0, 0, 0);
+        im[cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bi, im[cc], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 16 * v + lg + 4 * q, col = 16 * c + li;
+      if (row < kb && col < kb) A[(size_t)(o + row) * n + o + col] = z{re[c][q], im[c][q]};
+    }
+}
+
 __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ qpg, int n) {
   const size_t w = blockIdx.y;
   const size_t nn = (size_t)n * n;
@@ -654,9 +758,9 @@ __global__ void unsymmetrise(double* __restrict__ A, const double* __restrict__ 
 
 namespace xo {
 namespace {
-// Panel and rank-update kernels: FP64 matrix cores (default) or, with the environment
-// variable XO_EPS_RANK=valu, the VALU forms (kept as a second implementation; the tests
-// run both).
+// Diagonal-block (positive definite form), panel and rank-update kernels: FP64 matrix cores
+// (default) or, with the environment variable XO_EPS_RANK=valu, the VALU forms (kept as a
+// second implementation; the tests run both).
 int rank_form() {
   const char* e = std::getenv("XO_EPS_RANK");
   return (e && !std::strcmp(e, "valu")) ? 2 : 1;
@@ -794,7 +898,9 @@ int epsinv_run(const xo_eps_args* a, hipStream_t st, bool noalloc) {
     const int kb = std::min(kB, n - K * kB);
     {
       KernelTimer kt_("eps_diag_inverse", st);
-      if (check_sign)
+      if (check_sign && rank_form() != 2)
+        hipLaunchKernelGGL(diag_mfma, dim3(a->nw), dim3(256), 0, st, a->out, n, K, kb, flag);
+      else if (check_sign)
         hipLaunchKernelGGL((diag_inverse<kDiagE, false>), dim3(a->nw), dim3(kB * kB / kDiagE), 0, st, a->out, n,
                            K, kb, flag, gmax2);
       else
