@@ -705,12 +705,12 @@ def main():
         return run_c3(args)
     if args.workload == "c5":
         return run_c5(args)
-    if args.workload != "c2":
-        raise SystemExit(f"bench.py: unknown workload {args.workload}")
     if args.workload == "sigma":
         return run_sigma(args)
     if args.workload == "real":
         return run_real(args)
+    if args.workload != "c2":
+        raise SystemExit(f"bench.py: unknown workload {args.workload}")
     t0 = time.perf_counter()
     cr = crystal_for(args.workload)
     t_fix = time.perf_counter() - t0
