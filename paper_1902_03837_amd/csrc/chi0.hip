@@ -367,33 +367,36 @@ __global__ void chi0_reduce(const Item* __restrict__ items, const int2* __restri
   }
 }
 
-// Block form of the bf16 update (NP = 3 split, 1 plain). A workgroup owns a 64 x 64 output block
-// and four frequencies per unit; wave r owns rows 16 r .. 16 r + 15 and all four
-// 16-column tiles. Each step of 16 transitions stages the raw left rows, the
-// frequency factors and the right operand (split once, in fragment order) in LDS,
-// double buffered with one barrier per step: the next step's values are loaded
-// into registers before the current step's products and stored after them.
 constexpr int kBlk = 64;
 constexpr int kBW = 4;  // frequencies per unit in the block form
 constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 
+// Block form of the bf16 update (NP = 3 split, 1 plain). A unit is a 64 x 64 output block of the
+// Hermitian half, four frequencies and a transition slice; one workgroup of eight waves runs two
+// units of the same block and slice that hold consecutive frequency groups (waves 0-3 the first,
+// 4-7 the second), so the raw left rows and the split right operand are loaded from the fabric
+// and staged in LDS once for both. Wave r of a half owns rows 16 r .. 16 r + 15 and the four
+// 16-column tiles (those inside the G-set and, in a diagonal block, on or above the diagonal).
+// Each step of 16 transitions stages the raw left rows, the frequency factors of both groups
+// and the right operand (split once, in fragment order), double buffered with one barrier per
+// step: the next step's values are loaded into registers before the current step's products
+// and stored after them. Each half writes its unit's partials (per thread, contiguous:
+// [frequency][re, im][column tile] x 4 rows). A queue entry is a pair (u, v) of units, v = -1
+// for a lone unit (its second half computes on the first unit's frequencies and writes nothing).
 template <int NP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
-            const int* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
-            float* __restrict__ part) {
+           const int2* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
+           float* __restrict__ part) {
   __shared__ u4 Bs[2][2][4][4][16];        // [buffer][hi, lo][column tile][q][column]
   __shared__ float4 As[2][kBlk][9];        // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
-  __shared__ float4 Ws[2][kBW][4];         // [buffer][frequency][transition quad]
+  __shared__ float4 Ws[2][2 * kBW][4];     // [buffer][frequency of the pair][transition quad]
   __shared__ int su;
   const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int fn = tid >> 6, fq = (tid >> 4) & 3, fj = tid & 15;  // right-operand slot filled by this thread
-  const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition quad
-  // The queue has one segment per XCD (qoff[x] .. qoff[x + 1]), holding the units whose
-  // transition slices were given to XCD x. Workgroup b runs on XCD b mod 8 (launch order),
-  // starts on that segment and moves to the next once it is exhausted; it stops after
-  // finding all eight exhausted in a row. Every counter only grows, so all workgroups stop.
+  const int w8 = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int half = w8 >> 2, wave = w8 & 3;                       // frequency group of the pair, row tile
+  const int fn = (tid >> 6) & 3, fq = (tid >> 4) & 3, fj = tid & 15, fh = tid >> 8;  // right-operand slot
+  const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition pair
   int home = blockIdx.x & 7, misses = 0;
   for (;;) {
     if (tid == 0) {
@@ -414,72 +417,59 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     const int qpos = __builtin_amdgcn_readfirstlane(su);
     __syncthreads();
     if (qpos < 0) break;
-    const int uid = queue[qpos];
-    const Unit U = units[uid];
+    const int2 pr = queue[qpos];
+    const Unit U = units[pr.x];
+    const int w0b = pr.y >= 0 ? units[pr.y].w0 : U.w0;
     const Item I = items[U.item];
     const int2 bij = tiles[I.tile0 + U.tile];
     const int ng = I.ng, len = U.k1 - U.k0;
     const int nsteps = (len + 15) / 16;
-    // 16 x 16 tiles this wave computes: its row tile and the column tiles inside
-    // the G-set, and in a diagonal block only those on or above the diagonal
     int nmask = 0;
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       if (bij.x * kBlk + 16 * wave < ng && bij.y * kBlk + 16 * n < ng && (bij.x != bij.y || n >= wave))
         nmask |= 1 << n;
-    // Loads address the unit's transition slice by 32-bit byte offsets (the host
-    // keeps len * ng * 8 below 2^31). Rows past the slice and G past the G-set are
-    // clamped to valid entries: the former carry a zero weight, the latter land
-    // in outputs the reduction drops.
     const char* rbase = static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v);
-    const char* wbase = static_cast<const char*>(I.W) + ((size_t)U.k0 * I.nwpad + U.w0) * sizeof(float);
     const unsigned rstep = 16u * ng * sizeof(f2v), wstep = 16u * I.nwpad * sizeof(float);
     const unsigned Ga = min(bij.x * kBlk + ar, ng - 1), Gb = min(bij.y * kBlk + 16 * fn + fj, ng - 1);
     const unsigned amax = ((unsigned)(len - 1) * ng + Ga) * sizeof(f2v);
     const unsigned bmax = ((unsigned)(len - 1) * ng + Gb) * sizeof(f2v);
-    unsigned oa[4], ob[4];
+    unsigned oa[2], ob[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      oa[u] = ((unsigned)(4 * aq + u) * ng + Ga) * sizeof(f2v);
-      ob[u] = ((unsigned)(4 * fq + u) * ng + Gb) * sizeof(f2v);
+    for (int u = 0; u < 2; ++u) {
+      oa[u] = ((unsigned)(2 * aq + u) * ng + Ga) * sizeof(f2v);
+      ob[u] = ((unsigned)(4 * fq + 2 * fh + u) * ng + Gb) * sizeof(f2v);
     }
-    // frequency factors: transition wt of the step, frequency wf (read by every wave, so
-    // that all waves issue the same loads; wave 0 stores them); rows past the slice read
-    // its last row and are zeroed when stored
-    const int wt = tid & 15, wf = (tid >> 4) & 3;
-    const unsigned ow = ((unsigned)wt * I.nwpad + wf) * sizeof(float);
-    const unsigned wmax = ((unsigned)(len - 1) * I.nwpad + wf) * sizeof(float);
-
-    // Plain form: two register sets (A, B) of staged loads; step s + 1 is stored to LDS
-    // while step s + 2 is in flight, so each load has two steps of products to arrive.
-    // Loads are unconditional (clamped addresses), so the wait before a store counts
-    // exactly the other set's loads.
-    f2v raA[4], rbA[4], raB[4], rbB[4];
-    float wvA = 0.f, wvB = 0.f;
-    // ---- load step s into register set (ra, rb, wv)
-#define CHI0_BLK_LOAD(s_, ra_, rb_, wv_)                                                      \
-    {                                                                                         \
-      const unsigned d_ = (unsigned)(s_) * rstep;                                             \
-      _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                         \
-        ra_[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                     \
-        rb_[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                     \
-      }                                                                                       \
-      wv_ = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));                       \
+    // frequency factors: transition wt, frequency wf of the pair (threads 0..127 load and store)
+    const int wt = tid & 15, wf = (tid >> 4) & 7;
+    const int wcol = (wf >> 2 ? w0b : U.w0) + (wf & 3);
+    const char* wbase = static_cast<const char*>(I.W) + ((size_t)U.k0 * I.nwpad + wcol) * sizeof(float);
+    const unsigned ow = (unsigned)wt * I.nwpad * sizeof(float);
+    const unsigned wmax = (unsigned)(len - 1) * I.nwpad * sizeof(float);
+    f2v raA[2], rbA[2];
+    float wvA = 0.f;
+#define CHI0_PAIR_LOAD(s_, ra_, rb_, wv_)                                                    \
+    {                                                                                        \
+      const unsigned d_ = (unsigned)(s_) * rstep;                                            \
+      _Pragma("unroll") for (int u = 0; u < 2; ++u) {                                        \
+        ra_[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                    \
+        rb_[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                    \
+      }                                                                                      \
+      wv_ = gld<float>(wbase + min(ow + (unsigned)(s_) * wstep, wmax));                      \
     }
-    // ---- store step s from register set (ra, rb, wv) into buffer b. Split form: hi and
-    // lo of the right operand; plain form: hi and its rotation (-im, re)
-#define CHI0_BLK_STORE(b_, s_, ra_, rb_, wv_)                                                 \
-    {                                                                                         \
-      uint32_t h_[4], l_[4];                                                                  \
-      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
-      Bs[b_][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                                 \
-      if constexpr (NP == 3)                                                                  \
-        Bs[b_][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                               \
-      else                                                                                    \
-        Bs[b_][1][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])}; \
-      As[b_][ar][2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);                \
-      As[b_][ar][2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y);            \
-      if (wave == 0) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 16 * (s_) + wt < len ? wv_ : 0.f; \
+#define CHI0_PAIR_STORE(b_, s_, ra_, rb_, wv_)                                               \
+    {                                                                                        \
+      uint32_t h_[2], l_[2];                                                                 \
+      _Pragma("unroll") for (int u = 0; u < 2; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
+      uint2* bh_ = reinterpret_cast<uint2*>(&Bs[b_][0][fn][fq][fj]) + fh;                    \
+      uint2* bl_ = reinterpret_cast<uint2*>(&Bs[b_][1][fn][fq][fj]) + fh;                    \
+      *bh_ = make_uint2(h_[0], h_[1]);                                                       \
+      if constexpr (NP == 3)                                                                 \
+        *bl_ = make_uint2(l_[0], l_[1]);                                                     \
+      else                                                                                   \
+        *bl_ = make_uint2(rot_neg(h_[0]), rot_neg(h_[1]));                                   \
+      As[b_][ar][aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);                  \
+      if (tid < 128) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 16 * (s_) + wt < len ? wv_ : 0.f; \
     }
     f4 acc[kBW][2][4];
 #pragma unroll
@@ -488,15 +478,13 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[w][r][n] = f4{0.f, 0.f, 0.f, 0.f};
-    // products of the step held in buffer buf
     auto products = [&](int buf) {
       if (!nmask) return;
-      // weighted left operand of every frequency, converted once and shared by the column tiles
       const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
       u4 ah[kBW], al[kBW];
 #pragma unroll
       for (int w = 0; w < kBW; ++w) {
-        const float4 wq = Ws[buf][w][q];
+        const float4 wq = Ws[buf][4 * half + w][q];
         uint32_t h[4], l[4];
         split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
         split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
@@ -505,9 +493,6 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         ah[w] = u4{h[0], h[1], h[2], h[3]};
         al[w] = u4{l[0], l[1], l[2], l[3]};
       }
-      // column tiles: Re through the right operand, Im through its rotation (-im, re)
-      // (split form: rotated in registers; plain form: read from LDS); the next tile's
-      // operands are read ahead of the products
       u4 b0 = Bs[buf][0][0][q][i], b1 = Bs[buf][1][0][q][i];
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
@@ -541,46 +526,28 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         b1 = nb1;
       }
     };
-    CHI0_BLK_LOAD(0, raA, rbA, wvA);
-    CHI0_BLK_STORE(0, 0, raA, rbA, wvA);
-    if constexpr (NP == 1) {
-      // step k sits in buffer k % 2; entering an even k, step k + 1 is in set B and
-      // step k + 2 in set A
-      CHI0_BLK_LOAD(1, raB, rbB, wvB);
-      CHI0_BLK_LOAD(2, raA, rbA, wvA);
+    CHI0_PAIR_LOAD(0, raA, rbA, wvA);
+    CHI0_PAIR_STORE(0, 0, raA, rbA, wvA);
+    __syncthreads();
+    for (int k = 0; k < nsteps; ++k) {
+      const int buf = k & 1;
+      if (k + 1 < nsteps) CHI0_PAIR_LOAD(k + 1, raA, rbA, wvA);
+      products(buf);
+      if (k + 1 < nsteps) CHI0_PAIR_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
       __syncthreads();
-      for (int k = 0; k < nsteps; k += 2) {
-        products(0);
-        if (k + 1 < nsteps) CHI0_BLK_STORE(1, k + 1, raB, rbB, wvB);
-        __syncthreads();
-        if (k + 1 >= nsteps) break;
-        CHI0_BLK_LOAD(k + 3, raB, rbB, wvB);
-        products(1);
-        if (k + 2 < nsteps) CHI0_BLK_STORE(0, k + 2, raA, rbA, wvA);
-        __syncthreads();
-        CHI0_BLK_LOAD(k + 4, raA, rbA, wvA);
-      }
-    } else {
-      // the split form has no registers for a second set: one step ahead
-      __syncthreads();
-      for (int k = 0; k < nsteps; ++k) {
-        const int buf = k & 1;
-        if (k + 1 < nsteps) CHI0_BLK_LOAD(k + 1, raA, rbA, wvA);
-        products(buf);
-        if (k + 1 < nsteps) CHI0_BLK_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
-        __syncthreads();
-      }
     }
-#undef CHI0_BLK_LOAD
-#undef CHI0_BLK_STORE
-    // partials of this thread, contiguous: [frequency][re, im][column tile] x 4 rows
-    f4* out = reinterpret_cast<f4*>(part + ((size_t)uid * 256 + tid) * (kBW * 2 * 4 * 4));
+#undef CHI0_PAIR_LOAD
+#undef CHI0_PAIR_STORE
+    const int uid = half ? pr.y : pr.x;
+    if (uid >= 0) {
+      f4* out = reinterpret_cast<f4*>(part + ((size_t)uid * 256 + (tid & 255)) * (kBW * 2 * 4 * 4));
 #pragma unroll
-    for (int w = 0; w < kBW; ++w)
+      for (int w = 0; w < kBW; ++w)
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) out[(w * 2 + r) * 4 + n] = acc[w][r][n];
+          for (int n = 0; n < 4; ++n) out[(w * 2 + r) * 4 + n] = acc[w][r][n];
+    }
   }
 }
 
@@ -1207,18 +1174,39 @@ static int chi0_batch_run(const xo_chi0_args* a, int n, const xo_tune* tune, hip
       XO_CHECK_LAUNCH();
       return XO_OK;
     }
-    if (mode == MODE_BF16) {
-      KernelTimer kt_("chi0_blocks_bf16", s);
-      hipLaunchKernelGGL(chi0_blocks<1>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
-                         static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
-                         static_cast<const int*>(dqueue), static_cast<const int*>(dqoff), counter,
-                         static_cast<float*>(part));
-    } else {
-      KernelTimer kt_("chi0_blocks_bf16x3", s);
-      hipLaunchKernelGGL(chi0_blocks<3>, dim3(grid), dim3(256), 0, s, static_cast<const Item*>(ditems),
-                         static_cast<const int2*>(dtiles), static_cast<const Unit*>(dunits),
-                         static_cast<const int*>(dqueue), static_cast<const int*>(dqoff), counter,
-                         static_cast<float*>(part));
+    // pair the units of one block and slice that hold consecutive frequency groups (adjacent in
+    // each XCD segment of the queue)
+    std::vector<int2> pq;
+    int qoff2[9];
+    for (int x = 0; x < 8; ++x) {
+      qoff2[x] = (int)pq.size();
+      for (int i = qoff[x]; i < qoff[x + 1];) {
+        const int u = queue[i];
+        if (i + 1 < qoff[x + 1]) {
+          const int v = queue[i + 1];
+          if (units[v].item == units[u].item && units[v].tile == units[u].tile && units[v].k0 == units[u].k0 &&
+              units[v].w0 == units[u].w0 + kBW) {
+            pq.push_back(make_int2(u, v));
+            i += 2;
+            continue;
+          }
+        }
+        pq.push_back(make_int2(u, -1));
+        ++i;
+      }
+    }
+    qoff2[8] = (int)pq.size();
+    const void *dpq = nullptr, *dqoff2 = nullptr;
+    XO_RET(device_table(pq.data(), pq.size() * sizeof(int2), s, &dpq));
+    XO_RET(device_table(qoff2, sizeof(qoff2), s, &dqoff2));
+    // eight-wave workgroups: half as many per CU as the four-wave forms
+    const int grid2 = std::min((int)pq.size(), num_cus() * std::max(1, grid_per_cu / 2));
+    {
+      KernelTimer kt_(mode == MODE_BF16 ? "chi0_blocks_bf16" : "chi0_blocks_bf16x3", s);
+      hipLaunchKernelGGL(mode == MODE_BF16 ? chi0_blocks<1> : chi0_blocks<3>, dim3(grid2), dim3(512), 0, s,
+                         static_cast<const Item*>(ditems), static_cast<const int2*>(dtiles),
+                         static_cast<const Unit*>(dunits), static_cast<const int2*>(dpq),
+                         static_cast<const int*>(dqoff2), counter, static_cast<float*>(part));
     }
     XO_CHECK_LAUNCH();
     {
