@@ -377,10 +377,10 @@ constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 // 4-7 the second), so the raw left rows and the split right operand are loaded from the fabric
 // and staged in LDS once for both. Wave r of a half owns rows 16 r .. 16 r + 15 and the four
 // 16-column tiles (those inside the G-set and, in a diagonal block, on or above the diagonal).
-// Each step of 16 transitions stages the raw left rows, the frequency factors of both groups
-// and the right operand (split once, in fragment order), double buffered with one barrier per
-// step: the next step's values are loaded into registers before the current step's products
-// and stored after them. Each half writes its unit's partials (per thread, contiguous:
+// Each step of 32 transitions (two products deep) stages the raw left rows, the frequency
+// factors of both groups and the right operand (split once, in fragment order), double buffered
+// with one barrier per step: the next step's values are loaded into registers before the
+// current step's products and stored after them. Each half writes its unit's partials (per thread, contiguous:
 // [frequency][re, im][column tile] x 4 rows). A queue entry is a pair (u, v) of units, v = -1
 // for a lone unit (its second half computes on the first unit's frequencies and writes nothing).
 template <int NP>
@@ -388,15 +388,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
            const int2* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
            float* __restrict__ part) {
-  __shared__ u4 Bs[2][2][4][4][16];        // [buffer][hi, lo][column tile][q][column]
-  __shared__ float4 As[2][kBlk][9];        // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
-  __shared__ float4 Ws[2][2 * kBW][4];     // [buffer][frequency of the pair][transition quad]
+  __shared__ u4 Bs[2][2][2][4][4][16];     // [buffer][half step][hi, lo][column tile][q][column]
+  __shared__ float4 As[2][kBlk][17];       // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
+  __shared__ float4 Ws[2][2 * kBW][8];     // [buffer][frequency of the pair][transition quad]
   __shared__ int su;
   const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
   const int w8 = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = w8 >> 2, wave = w8 & 3;                       // frequency group of the pair, row tile
   const int fn = (tid >> 6) & 3, fq = (tid >> 4) & 3, fj = tid & 15, fh = tid >> 8;  // right-operand slot
-  const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition pair
+  const int ar = tid & 63, aq = tid >> 6;                        // left-operand row and transition quad
   int home = blockIdx.x & 7, misses = 0;
   for (;;) {
     if (tid == 0) {
@@ -423,35 +423,35 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     const Item I = items[U.item];
     const int2 bij = tiles[I.tile0 + U.tile];
     const int ng = I.ng, len = U.k1 - U.k0;
-    const int nsteps = (len + 15) / 16;
+    const int nsteps = (len + 31) / 32;  // steps of 32 transitions, two products deep
     int nmask = 0;
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       if (bij.x * kBlk + 16 * wave < ng && bij.y * kBlk + 16 * n < ng && (bij.x != bij.y || n >= wave))
         nmask |= 1 << n;
     const char* rbase = static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v);
-    const unsigned rstep = 16u * ng * sizeof(f2v), wstep = 16u * I.nwpad * sizeof(float);
+    const unsigned rstep = 32u * ng * sizeof(f2v), wstep = 32u * I.nwpad * sizeof(float);
     const unsigned Ga = min(bij.x * kBlk + ar, ng - 1), Gb = min(bij.y * kBlk + 16 * fn + fj, ng - 1);
     const unsigned amax = ((unsigned)(len - 1) * ng + Ga) * sizeof(f2v);
     const unsigned bmax = ((unsigned)(len - 1) * ng + Gb) * sizeof(f2v);
-    unsigned oa[2], ob[2];
+    unsigned oa[4], ob[4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      oa[u] = ((unsigned)(2 * aq + u) * ng + Ga) * sizeof(f2v);
-      ob[u] = ((unsigned)(4 * fq + 2 * fh + u) * ng + Gb) * sizeof(f2v);
+    for (int u = 0; u < 4; ++u) {
+      oa[u] = ((unsigned)(4 * aq + u) * ng + Ga) * sizeof(f2v);
+      ob[u] = ((unsigned)(16 * fh + 4 * fq + u) * ng + Gb) * sizeof(f2v);
     }
-    // frequency factors: transition wt, frequency wf of the pair (threads 0..127 load and store)
-    const int wt = tid & 15, wf = (tid >> 4) & 7;
+    // frequency factors: transition wt, frequency wf of the pair (threads 0..255 load and store)
+    const int wt = tid & 31, wf = (tid >> 5) & 7;
     const int wcol = (wf >> 2 ? w0b : U.w0) + (wf & 3);
     const char* wbase = static_cast<const char*>(I.W) + ((size_t)U.k0 * I.nwpad + wcol) * sizeof(float);
     const unsigned ow = (unsigned)wt * I.nwpad * sizeof(float);
     const unsigned wmax = (unsigned)(len - 1) * I.nwpad * sizeof(float);
-    f2v raA[2], rbA[2];
+    f2v raA[4], rbA[4];
     float wvA = 0.f;
 #define CHI0_PAIR_LOAD(s_, ra_, rb_, wv_)                                                    \
     {                                                                                        \
       const unsigned d_ = (unsigned)(s_) * rstep;                                            \
-      _Pragma("unroll") for (int u = 0; u < 2; ++u) {                                        \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                        \
         ra_[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                    \
         rb_[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                    \
       }                                                                                      \
@@ -459,17 +459,16 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     }
 #define CHI0_PAIR_STORE(b_, s_, ra_, rb_, wv_)                                               \
     {                                                                                        \
-      uint32_t h_[2], l_[2];                                                                 \
-      _Pragma("unroll") for (int u = 0; u < 2; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
-      uint2* bh_ = reinterpret_cast<uint2*>(&Bs[b_][0][fn][fq][fj]) + fh;                    \
-      uint2* bl_ = reinterpret_cast<uint2*>(&Bs[b_][1][fn][fq][fj]) + fh;                    \
-      *bh_ = make_uint2(h_[0], h_[1]);                                                       \
+      uint32_t h_[4], l_[4];                                                                 \
+      _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
+      Bs[b_][fh][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                            \
       if constexpr (NP == 3)                                                                 \
-        *bl_ = make_uint2(l_[0], l_[1]);                                                     \
+        Bs[b_][fh][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                          \
       else                                                                                   \
-        *bl_ = make_uint2(rot_neg(h_[0]), rot_neg(h_[1]));                                   \
-      As[b_][ar][aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);                  \
-      if (tid < 128) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 16 * (s_) + wt < len ? wv_ : 0.f; \
+        Bs[b_][fh][1][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])}; \
+      As[b_][ar][2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);              \
+      As[b_][ar][2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y);          \
+      if (tid < 256) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 32 * (s_) + wt < len ? wv_ : 0.f; \
     }
     f4 acc[kBW][2][4];
 #pragma unroll
@@ -478,13 +477,13 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[w][r][n] = f4{0.f, 0.f, 0.f, 0.f};
-    auto products = [&](int buf) {
+    auto products = [&](int buf, int hs) {
       if (!nmask) return;
-      const float4 a01 = As[buf][16 * wave + i][2 * q], a23 = As[buf][16 * wave + i][2 * q + 1];
+      const float4 a01 = As[buf][16 * wave + i][8 * hs + 2 * q], a23 = As[buf][16 * wave + i][8 * hs + 2 * q + 1];
       u4 ah[kBW], al[kBW];
 #pragma unroll
       for (int w = 0; w < kBW; ++w) {
-        const float4 wq = Ws[buf][4 * half + w][q];
+        const float4 wq = Ws[buf][4 * half + w][4 * hs + q];
         uint32_t h[4], l[4];
         split2(wq.x * a01.x, wq.x * a01.y, h[0], l[0]);
         split2(wq.y * a01.z, wq.y * a01.w, h[1], l[1]);
@@ -493,13 +492,13 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         ah[w] = u4{h[0], h[1], h[2], h[3]};
         al[w] = u4{l[0], l[1], l[2], l[3]};
       }
-      u4 b0 = Bs[buf][0][0][q][i], b1 = Bs[buf][1][0][q][i];
+      u4 b0 = Bs[buf][hs][0][0][q][i], b1 = Bs[buf][hs][1][0][q][i];
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
         u4 nb0 = b0, nb1 = b1;
         if (n < 3) {
-          nb0 = Bs[buf][0][n + 1][q][i];
-          nb1 = Bs[buf][1][n + 1][q][i];
+          nb0 = Bs[buf][hs][0][n + 1][q][i];
+          nb1 = Bs[buf][hs][1][n + 1][q][i];
         }
         if (nmask & (1 << n)) {
           if constexpr (NP == 3) {
@@ -532,7 +531,8 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     for (int k = 0; k < nsteps; ++k) {
       const int buf = k & 1;
       if (k + 1 < nsteps) CHI0_PAIR_LOAD(k + 1, raA, rbA, wvA);
-      products(buf);
+      products(buf, 0);
+      products(buf, 1);
       if (k + 1 < nsteps) CHI0_PAIR_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
       __syncthreads();
     }
