@@ -377,10 +377,10 @@ constexpr int kBlkPer = kBW * 2 * kBlk * kBlk;  // partial values per unit
 // 4-7 the second), so the raw left rows and the split right operand are loaded from the fabric
 // and staged in LDS once for both. Wave r of a half owns rows 16 r .. 16 r + 15 and the four
 // 16-column tiles (those inside the G-set and, in a diagonal block, on or above the diagonal).
-// Each step of 32 transitions (two products deep) stages the raw left rows, the frequency
+// Each step of 64 transitions (four products deep) stages the raw left rows, the frequency
 // factors of both groups and the right operand (split once, in fragment order), double buffered
-// with one barrier per step: the next step's values are loaded into registers before the
-// current step's products and stored after them. Each half writes its unit's partials (per thread, contiguous:
+// (137 KB of LDS) with one barrier per step: the next step is loaded into registers and stored
+// in two halves of 32 transitions, each around two of the current step's four products. Each half writes its unit's partials (per thread, contiguous:
 // [frequency][re, im][column tile] x 4 rows). A queue entry is a pair (u, v) of units, v = -1
 // for a lone unit (its second half computes on the first unit's frequencies and writes nothing).
 template <int NP>
@@ -388,9 +388,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, const Unit* __restrict__ units,
            const int2* __restrict__ queue, const int* __restrict__ qoff, int* __restrict__ counters,
            float* __restrict__ part) {
-  __shared__ u4 Bs[2][2][2][4][4][16];     // [buffer][half step][hi, lo][column tile][q][column]
-  __shared__ float4 As[2][kBlk][17];       // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
-  __shared__ float4 Ws[2][2 * kBW][8];     // [buffer][frequency of the pair][transition quad]
+  __shared__ u4 Bs[2][4][2][4][4][16];     // [buffer][quarter step][hi, lo][column tile][q][column]
+  __shared__ float4 As[2][kBlk][33];       // [buffer][row][transition pair, + 1 pad]: raw rho of the block rows
+  __shared__ float4 Ws[2][2 * kBW][16];    // [buffer][frequency of the pair][transition quad]
   __shared__ int su;
   const int tid = threadIdx.x, lane = tid & 63, i = lane & 15, q = lane >> 4;
   const int w8 = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -423,14 +423,14 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     const Item I = items[U.item];
     const int2 bij = tiles[I.tile0 + U.tile];
     const int ng = I.ng, len = U.k1 - U.k0;
-    const int nsteps = (len + 31) / 32;  // steps of 32 transitions, two products deep
+    const int nsteps = (len + 63) / 64;  // steps of 64 transitions, four products deep, staged in two halves
     int nmask = 0;
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       if (bij.x * kBlk + 16 * wave < ng && bij.y * kBlk + 16 * n < ng && (bij.x != bij.y || n >= wave))
         nmask |= 1 << n;
     const char* rbase = static_cast<const char*>(I.rho) + (size_t)U.k0 * ng * sizeof(f2v);
-    const unsigned rstep = 32u * ng * sizeof(f2v), wstep = 32u * I.nwpad * sizeof(float);
+    const unsigned rstep = 32u * ng * sizeof(f2v), wstep = 32u * I.nwpad * sizeof(float);  // per half step
     const unsigned Ga = min(bij.x * kBlk + ar, ng - 1), Gb = min(bij.y * kBlk + 16 * fn + fj, ng - 1);
     const unsigned amax = ((unsigned)(len - 1) * ng + Ga) * sizeof(f2v);
     const unsigned bmax = ((unsigned)(len - 1) * ng + Gb) * sizeof(f2v);
@@ -450,7 +450,7 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     float wvA = 0.f;
 #define CHI0_PAIR_LOAD(s_, ra_, rb_, wv_)                                                    \
     {                                                                                        \
-      const unsigned d_ = (unsigned)(s_) * rstep;                                            \
+      const unsigned d_ = (unsigned)(s_) * rstep;  /* s_: half step */                      \
       _Pragma("unroll") for (int u = 0; u < 4; ++u) {                                        \
         ra_[u] = gld<f2v>(rbase + min(oa[u] + d_, amax));                                    \
         rb_[u] = gld<f2v>(rbase + min(ob[u] + d_, bmax));                                    \
@@ -459,16 +459,17 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
     }
 #define CHI0_PAIR_STORE(b_, s_, ra_, rb_, wv_)                                               \
     {                                                                                        \
+      const int hh_ = (s_) & 1;  /* half of the buffer */                                    \
       uint32_t h_[4], l_[4];                                                                 \
       _Pragma("unroll") for (int u = 0; u < 4; ++u) split2(rb_[u].x, rb_[u].y, h_[u], l_[u]); \
-      Bs[b_][fh][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                            \
+      Bs[b_][2 * hh_ + fh][0][fn][fq][fj] = u4{h_[0], h_[1], h_[2], h_[3]};                  \
       if constexpr (NP == 3)                                                                 \
-        Bs[b_][fh][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                          \
+        Bs[b_][2 * hh_ + fh][1][fn][fq][fj] = u4{l_[0], l_[1], l_[2], l_[3]};                \
       else                                                                                   \
-        Bs[b_][fh][1][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])}; \
-      As[b_][ar][2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);              \
-      As[b_][ar][2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y);          \
-      if (tid < 256) reinterpret_cast<float*>(&Ws[b_][wf][0])[wt] = 32 * (s_) + wt < len ? wv_ : 0.f; \
+        Bs[b_][2 * hh_ + fh][1][fn][fq][fj] = u4{rot_neg(h_[0]), rot_neg(h_[1]), rot_neg(h_[2]), rot_neg(h_[3])}; \
+      As[b_][ar][16 * hh_ + 2 * aq] = make_float4(ra_[0].x, ra_[0].y, ra_[1].x, ra_[1].y);   \
+      As[b_][ar][16 * hh_ + 2 * aq + 1] = make_float4(ra_[2].x, ra_[2].y, ra_[3].x, ra_[3].y); \
+      if (tid < 256) reinterpret_cast<float*>(&Ws[b_][wf][0])[32 * hh_ + wt] = 32 * (s_) + wt < len ? wv_ : 0.f; \
     }
     f4 acc[kBW][2][4];
 #pragma unroll
@@ -525,15 +526,23 @@ chi0_blocks(const Item* __restrict__ items, const int2* __restrict__ tiles, cons
         b1 = nb1;
       }
     };
+    // half steps 2 k and 2 k + 1 fill buffer k % 2; the next step's halves are loaded and
+    // stored one after the other around the current step's two pairs of products
     CHI0_PAIR_LOAD(0, raA, rbA, wvA);
     CHI0_PAIR_STORE(0, 0, raA, rbA, wvA);
+    CHI0_PAIR_LOAD(1, raA, rbA, wvA);
+    CHI0_PAIR_STORE(0, 1, raA, rbA, wvA);
     __syncthreads();
     for (int k = 0; k < nsteps; ++k) {
       const int buf = k & 1;
-      if (k + 1 < nsteps) CHI0_PAIR_LOAD(k + 1, raA, rbA, wvA);
-      products(buf, 0);
-      products(buf, 1);
-      if (k + 1 < nsteps) CHI0_PAIR_STORE(buf ^ 1, k + 1, raA, rbA, wvA);
+      const bool more = k + 1 < nsteps;
+#pragma unroll 1
+      for (int hh = 0; hh < 2; ++hh) {
+        if (more) CHI0_PAIR_LOAD(2 * k + 2 + hh, raA, rbA, wvA);
+        products(buf, 2 * hh);
+        products(buf, 2 * hh + 1);
+        if (more) CHI0_PAIR_STORE(buf ^ 1, 2 * k + 2 + hh, raA, rbA, wvA);
+      }
       __syncthreads();
     }
 #undef CHI0_PAIR_LOAD
