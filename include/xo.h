@@ -229,15 +229,17 @@ int xo_chi0_real(const xo_chi0_real_args* a, void* stream);
  * of the FP64 partial sums. Blocks: nt_tiles 1 or 2 gives 16-row x 16*nt_tiles-
  * column blocks with up to 8 frequencies per unit, one wave per transition
  * quarter; nt_tiles 4 (XO_BF16X3 and XO_BF16 only) gives 64 x 64 blocks with 4
- * frequencies per unit and the right operand converted once per workgroup in
- * LDS; nt_tiles 8 (same forms) gives 64 x 128 strips with 2 frequencies per unit
+ * frequencies per unit, two units of one block and slice per eight-wave
+ * workgroup (their rho strips staged once) and the right operand converted once
+ * per workgroup in LDS; nt_tiles 8 (same forms) gives 64 x 128 strips with 2 frequencies per unit
  * (half the left-operand conversion per product, twice the right-operand reads).
  * With nt_tiles 0 the bf16 forms take the 64 x 64 form when there are at least
  * four frequencies, every other case 16 x 16. items: [host] array. */
 typedef struct {
   int nt_tiles;   /* 0 (default), 1, 2, or 4 / 8 (XO_BF16X3 / XO_BF16 only)       */
   int kper;       /* transitions per unit; 0 = chosen to fill the chip            */
-  int wg_per_cu;  /* persistent workgroups per compute unit; 0 = 2 (64 x 64), 4   */
+  int wg_per_cu;  /* persistent four-wave workgroups per compute unit (the 64 x 64
+                     form runs half as many eight-wave ones); 0 = 2 (64 x 64), 4   */
 } xo_tune;
 
 int xo_chi0_batch(const xo_chi0_args* items, int n, const xo_tune* tune, void* stream);
