@@ -313,6 +313,25 @@ def copy_calibration():
     return 2 * a.numel() * 8
 
 
+def roofline_eps(kern, ng, nw):
+    """Roofline of the eps~^-1 rank update on FP64 matrix cores (rank_update_mfma): algorithmic
+    flops 8 (NG - kb)^2 kb per 64-wide block column and frequency (the complex multiply-adds of the
+    entries outside the block's rows and columns, Eq. X_rpa_inv by Gauss-Jordan), over the kernel's
+    event-timed time per step, against the FP64 matrix-core peak."""
+    k = kern.get("eps_rank_update")
+    if not k:
+        return None
+    fl = 0.0
+    for k0 in range(0, ng, 64):
+        kb = min(64, ng - k0)
+        fl += 8.0 * (ng - kb) ** 2 * kb
+    ach = fl * nw / (k["ms_per_step"] / 1e3) / 1e12
+    peak = PEAK["fp64_mfma"] / 1e12
+    return {"kernel": "rank_update_mfma", "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": None,
+            "note": "algorithmic FP64 flops 8 (NG - kb)^2 kb per block column and frequency"}
+
+
 def run_c5(args):
     """Headline: the large cell (32-site simple-cubic supercell, 2x2x2 k, q = b1/2, 128 occupied +
     2000 empty bands, 72^3 grid, NG = 3000, 16 frequencies, K = 2 048 000) in the split-bf16 form,
@@ -380,6 +399,7 @@ def run_c5(args):
     rk = [k for k in res_form["kernels"] if k.startswith("rho_gemm") or k in ("rho_yz", "rho_zy")]
     if rk and rk[0] != res["roofline"]["kernel"]:
         res["roofline_rho"] = roofline(cr, res_form, K, nw, ng, name=rk[0], summary="c5_hbm_traffic.txt")
+    res["roofline_eps"] = roofline_eps(res_form["kernels"], ng, nw)
     res["beside"] = {p: dict(ms_per_step=r["ms_per_step"], stage_ms={"rho": r["t_rho_ms"], "chi0": r["t_chi0_ms"],
                                                                       "eps": r["t_eps_ms"]},
                              note="timed for reference, not the reported form")

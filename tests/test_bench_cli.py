@@ -29,3 +29,16 @@ def test_unknown_workload_and_several_gpus_are_refused(monkeypatch, capsys):
     with pytest.raises(SystemExit) as e:
         bench.main()
     assert e.value.code == 2 and "one GPU" in capsys.readouterr().err
+
+
+def test_eps_roofline_counts_the_rank_updates():
+    # NG = 128: two 64-wide block columns, each updating the 64 x 64 entries outside its rows
+    # and columns with 64 complex multiply-adds (8 flops) per entry; two frequencies, 1 ms
+    r = bench.roofline_eps({"eps_rank_update": {"ms_per_step": 1.0}}, 128, 2)
+    flops = 2 * 2 * 8 * 64 * 64 * 64
+    assert r["achieved"] == pytest.approx(flops / 1e-3 / 1e12)
+    assert r["peak"] == 78.6 and r["frac"] == pytest.approx(r["achieved"] / 78.6)
+    # a ragged last block: NG = 100 has blocks of 64 and 36
+    r = bench.roofline_eps({"eps_rank_update": {"ms_per_step": 1.0}}, 100, 1)
+    assert r["achieved"] == pytest.approx(8 * (36 * 36 * 64 + 64 * 64 * 36) / 1e-3 / 1e12)
+    assert bench.roofline_eps({}, 100, 1) is None
