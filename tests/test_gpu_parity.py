@@ -254,11 +254,13 @@ def test_chi0_reduced_precision_random(prec, tol, nt, ng, nw):
                                            (700, 65, 3, (4, 256, 1)), (130, 129, 6, None),
                                            (1, 1, 1, (8, 0, 0)), (33, 17, 1, (8, 0, 0)), (700, 65, 3, (8, 256, 1)),
                                            (130, 129, 6, (8, 0, 0)), (517, 200, 5, (8, 64, 1)),
-                                           (300, 129, 4, (4, 0, 0))])
+                                           (300, 129, 4, (4, 0, 0)), (700, 130, 11, (4, 256, 1)),
+                                           (300, 70, 12, None)])
 def test_chi0_bf16_edges(prec, nt, ng, nw, tune):
     """Degenerate and ragged shapes of the bf16 forms: one transition, one G-vector, one
     frequency in the 64 x 64 block form (three padded frequency slots) and the 64 x 128
-    strip form (one), G-sets one past a block edge, transition slices shorter than a step; within the
+    strip form (one), G-sets one past a block edge, transition slices shorter than a step, three
+    frequency groups in the block form (two units in one workgroup, one alone); within the
     bf16 rounding bound (plain) or 2e-4 (split), exactly Hermitian."""
     say(f"chi0 {prec} edge nt={nt} ng={ng} nw={nw} tune={tune}")
     M = random_complex(300 + nt, (nt, ng)).astype(np.complex64).astype(np.complex128)
