@@ -643,6 +643,65 @@ def run_sigma(args):
     print(json.dumps(res), flush=True)
 
 
+def run_eps(args):
+    """The eps~^-1 stage alone (Eq. X_rpa_inv, blocked Gauss-Jordan in FP64): for each NG x
+    frequencies in --eps-sizes, a seeded synthetic chi0 = -0.05 B B^H / NG (B complex Gaussian,
+    so eps~ is Hermitian positive definite, formed on the GPU) and |q+G| spread over [0.5, 3];
+    the time per call (events over --steps calls after --warmup) and per kernel (the library's
+    brackets over as many calls), and the rank update's matrix-core roofline."""
+    import torch
+    from paper_1902_03837_amd import xo
+    sizes = []
+    for tok in args.eps_sizes.split(","):
+        a, b = tok.lower().split("x")
+        sizes.append((int(a), int(b)))
+    res = {}
+    for ng, nw in sizes:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(ng * 1000 + nw)
+        B = torch.randn((nw, ng, ng), dtype=torch.complex128, device="cuda", generator=gen) / np.sqrt(ng)
+        chi = -torch.matmul(B, B.conj().transpose(-1, -2).contiguous()) * 0.05
+        del B
+        q = np.linspace(0.5, 3.0, ng)
+        out = torch.empty_like(chi)
+        info = torch.zeros(nw, dtype=torch.int32, device="cuda")
+        for _ in range(args.warmup):
+            xo.epsinv(chi, q, out=out, info=info)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            xo.epsinv(chi, q, out=out, info=info)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        xo.timing_report()
+        xo.timing_enable(True)
+        for _ in range(args.steps):
+            xo.epsinv(chi, q, out=out, info=info)
+        torch.cuda.synchronize()
+        xo.timing_enable(False)
+        kern = {name: {"launches_per_call": n / args.steps, "ms_per_call": t / args.steps, "avg_launch_ms": t / n}
+                for name, (n, t) in xo.timing_report().items()}
+        flags = int(info.max().item())
+        if flags:
+            raise SystemExit(f"bench.py: eps~ of NG={ng} not positive definite (flag {flags})")
+        roof = roofline_eps({"eps_rank_update": {"ms_per_step": kern["eps_rank_update"]["ms_per_call"]}}, ng, nw) \
+            if "eps_rank_update" in kern else None
+        res[f"{ng}x{nw}"] = {"ng": ng, "nw": nw, "ms_per_call": ms, "kernels": kern, "roofline_rank_update": roof}
+        print(f"[bench] eps NG={ng} x {nw}: {ms:.3f} ms per call", file=sys.stderr, flush=True)
+        del chi, out
+    first = res[f"{sizes[0][0]}x{sizes[0][1]}"]
+    print(json.dumps({"metric": "eps~^-1 time per call (all frequencies)", "value": first["ms_per_call"], "unit": "ms",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": first["ms_per_call"],
+                      "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": "eps: seeded Hermitian positive definite eps~ at NG x frequencies "
+                                             + ", ".join(f"{a} x {b}" for a, b in sizes),
+                                 "parallelism": "single GPU"},
+                      "sizes": res}), flush=True)
+
+
 def run_real(args):
     """Real-axis workload: the c2 crystal (fcc 4x4x4 k, q = b1/4, 16 occupied + 200 empty bands,
     36^3, NG = 400, K = 204 800) at 100 real frequencies spread evenly over [0, max dE] with
@@ -710,6 +769,7 @@ def main():
     ap.add_argument("--fixture-cache", default=None, help="directory to keep generated crystals in (npz)")
     ap.add_argument("--real-forms", default="bf16,bf16x3,fp64", help="real: forms (fp64 gives the error reference)")
     ap.add_argument("--real-nw", type=int, default=100, help="real: number of real frequencies")
+    ap.add_argument("--eps-sizes", default="400x8,900x16,3000x16", help="eps: NGxfrequencies, comma list")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -729,6 +789,8 @@ def main():
         return run_sigma(args)
     if args.workload == "real":
         return run_real(args)
+    if args.workload == "eps":
+        return run_eps(args)
     if args.workload != "c2":
         raise SystemExit(f"bench.py: unknown workload {args.workload}")
     t0 = time.perf_counter()

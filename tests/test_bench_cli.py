@@ -10,10 +10,10 @@ import bench  # noqa: E402
 
 
 @pytest.mark.parametrize("workload,runner", [("c3", "run_c3"), ("c5", "run_c5"), ("sigma", "run_sigma"),
-                                             ("real", "run_real")])
+                                             ("real", "run_real"), ("eps", "run_eps")])
 def test_each_workload_reaches_its_runner(workload, runner, monkeypatch):
     seen = []
-    for name in ("run_c3", "run_c5", "run_sigma", "run_real"):
+    for name in ("run_c3", "run_c5", "run_sigma", "run_real", "run_eps"):
         monkeypatch.setattr(bench, name, lambda args, name=name: seen.append(name))
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", workload])
     bench.main()
